@@ -1,0 +1,98 @@
+/* Test-only CPU oracle for block Lanczos with warm start (BLWS) singular value
+ * thresholding inside inexact-ALM nuclear-norm solvers.
+ *
+ * TEST INFRASTRUCTURE: only tests, the smoke check and the bench's CPU baseline
+ * call this library. It shares no code with the GPU library.
+ *
+ * All matrices are dense, row-major, FP64, element (i, j) at p[i * cols + j]
+ * (no leading-dimension argument: rows are packed). Every entry point returns 0
+ * on success and a negative value on a bad argument or allocation failure.
+ */
+#ifndef BLWS_ORACLE_H
+#define BLWS_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* The (counter + 1)-th output of SplitMix64 seeded with `seed`, mapped to
+ * [-1, 1) as ((z >> 11) * 2^-53) * 2 - 1. Exact in binary64. */
+double orc_uniform(uint64_t seed, uint64_t counter);
+
+/* Fill X (rows x cols) with orc_uniform(seed, stream * 2^40 + i * 4096 + j). */
+void orc_fill_uniform(int rows, int cols, uint64_t seed, uint64_t stream, double* X);
+
+/* Thin SVD W = U diag(S) V^T by one-sided (Hestenes) Jacobi. p = min(m, n).
+ * U: m x p, S: p (descending), V: n x p. Returns the number of sweeps. */
+int orc_jacobi_svd(int m, int n, const double* W, double* U, double* S, double* V);
+
+/* Eq. (4): A = T_eps(W) computed from the full Jacobi SVD. S_all (p values,
+ * may be NULL) receives all singular values; *rank = #{sigma_i > eps}. */
+int orc_svt_exact(int m, int n, const double* W, double eps, double* A, double* S_all,
+                  int* rank);
+
+/* One BLWS step (block Lanczos, k = 2, warm start from U, V; split Rayleigh-Ritz).
+ * U (m x b) and V (n x b) hold orthonormal columns on entry and the top-b Ritz
+ * vectors on exit. S (b) receives the Ritz values (descending); *rank =
+ * #{S_i > eps}; A (m x n, may be NULL) receives U_r diag(S_r - eps) V_r^T. */
+int orc_blws_step(int m, int n, const double* W, double eps, int b, double* U, double* V,
+                  double* S, double* A, int* rank);
+
+/* Cold start block: V = orth(random n x b), then `pow_steps` pairs
+ * U = orth(W V), V = orth(W^T U). With pow_steps = 0, U = orth(random m x b).
+ * Streams: V uses stream_v, U uses stream_v + 1. */
+int orc_cold_block(int m, int n, const double* W, int b, int pow_steps, uint64_t seed,
+                   uint64_t stream_v, double* U, double* V);
+
+/* Spectral norm by repeated BLWS steps from a cold block of width bs. */
+double orc_spectral_norm_blws(int m, int n, const double* W, int bs, int pow_steps,
+                              uint64_t seed, double rtol, int max_steps, int* steps_out);
+
+typedef struct {
+    double tol;            /* stop when ||D - A - E||_F / ||D||_F < tol            */
+    int max_iter;
+    double rho;            /* mu <- min(rho * mu, mu_bar)                          */
+    double mu0_scale;      /* mu0 = mu0_scale / ||D||_2                            */
+    double mu_max_factor;  /* mu_bar = mu_max_factor * mu0                         */
+    int sv0;               /* initial predicted rank                                */
+    double sv_step_frac;   /* rank-prediction increment, as a fraction of min(m,n) */
+    int b_round;           /* Lanczos block width = sv rounded up to this          */
+    int pow_steps;         /* power half-step pairs in the cold start               */
+    uint64_t seed;
+    int norm_steps;        /* max BLWS steps for ||D||_2                            */
+    double norm_rtol;
+} orc_alm_opts;
+
+typedef struct {
+    int iters;
+    int rank;
+    int b_final;
+    long long nnz_E;
+    double rel_residual;
+    double norm2_D;
+    int status;            /* 0 converged, 1 max_iter reached */
+} orc_info;
+
+void orc_default_opts(orc_alm_opts* o);
+
+/* mode: 0 = exact SVT (full Jacobi SVD each iteration, the plain form),
+ *       1 = BLWS SVT.
+ * Y (m x n, may be NULL) receives the final multiplier. sv_trace (may be NULL,
+ * length max_iter) receives the per-iteration svp. */
+int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* opts,
+             int mode, double* A, double* E, double* Y, int* svp_trace, orc_info* info);
+
+/* Matrix completion by inexact ALM: min ||A||_* s.t. P_Omega(A) = P_Omega(M).
+ * Omega as CSR (row_ptr m+1, col_idx nnz). mode as for orc_rpca; the exact mode
+ * forms W densely. Output: factors U (m x r_cap, row stride r_cap), V (n x r_cap),
+ * S (r_cap) of the final A = U diag(S) V^T (the first min(*rank, r_cap) columns). */
+int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
+           const double* values, const orc_alm_opts* opts, int mode, int r_cap,
+           double* U, double* S, double* V, int* rank, orc_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

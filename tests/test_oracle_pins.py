@@ -1,0 +1,312 @@
+"""Pins for the CPU oracle against facts the paper and the mathematics fix.
+
+Nothing here compares the oracle with itself: every check uses a closed form,
+an invariant, an independent numpy computation of the definition, or a number
+printed in the paper (Table 1). These run on the CPU only.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# --------------------------------------------------------------------------
+# counter-based generator
+# --------------------------------------------------------------------------
+def test_uniform_generator_range_and_moments():
+    X = oracle.fill_uniform(300, 40, seed=7, stream=5)
+    assert X.min() >= -1.0 and X.max() < 1.0
+    assert abs(X.mean()) < 0.02 and abs(X.var() - 1.0 / 3.0) < 0.01
+    # counter-based: entry (i, j) depends only on (seed, stream, i, j)
+    Y = oracle.fill_uniform(10, 40, seed=7, stream=5)
+    assert np.array_equal(X[:10], Y)
+    assert oracle.uniform(7, (5 << 40) + 3 * 4096 + 2) == X[3, 2]
+    assert not np.array_equal(X[:10], oracle.fill_uniform(10, 40, seed=7, stream=6))
+    # values are multiples of 2^-52 (53-bit mantissa draws mapped to [-1, 1))
+    assert np.all(np.mod(X * 2.0**52, 1.0) == 0.0)
+
+
+# --------------------------------------------------------------------------
+# one-sided Jacobi SVD
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m,n", [(40, 30), (30, 40), (64, 64), (17, 5)])
+def test_jacobi_prescribed_spectrum(m, n):
+    p = min(m, n)
+    sigma = np.geomspace(1e3, 1e-6, p)
+    W, q1, q2 = synth.prescribed_spectrum(m, n, sigma, seed=11 + m + n)
+    U, S, V = oracle.jacobi_svd(W)
+    assert np.all(np.diff(S) <= 0)
+    err = np.abs(S - sigma)
+    assert np.all(err <= 1e-13 * sigma[0] + 1e-12 * sigma), err.max()
+    assert np.abs(U.T @ U - np.eye(p)).max() < 1e-13
+    assert np.abs(V.T @ V - np.eye(p)).max() < 1e-13
+    assert np.linalg.norm(U * S @ V.T - W) <= 1e-13 * np.linalg.norm(W)
+
+
+def test_jacobi_2x2_closed_form():
+    a, b, d = 3.0, -7.5, 0.25
+    U, S, V = oracle.jacobi_svd(np.array([[a, b], [0.0, d]]))
+    # sigma1 * sigma2 = |det|, sigma1^2 + sigma2^2 = ||W||_F^2
+    assert S[0] * S[1] == pytest.approx(abs(a * d), rel=1e-14)
+    assert S[0] ** 2 + S[1] ** 2 == pytest.approx(a * a + b * b + d * d, rel=1e-14)
+
+
+def test_jacobi_brute_force_tiny():
+    g = np.random.default_rng(3)
+    for shape in [(3, 3), (4, 2), (2, 5), (6, 6), (1, 4), (5, 1)]:
+        W = g.standard_normal(shape)
+        _, S, _ = oracle.jacobi_svd(W)
+        ref = np.linalg.svd(W, compute_uv=False)
+        assert np.allclose(S, ref, rtol=0, atol=1e-14 * ref[0])
+
+
+def test_jacobi_rank_deficient_and_zero():
+    g = np.random.default_rng(5)
+    W = g.standard_normal((9, 3)) @ g.standard_normal((3, 7))
+    U, S, V = oracle.jacobi_svd(W)
+    assert np.all(S[3:] <= 1e-13 * S[0])
+    assert np.abs(U.T @ U - np.eye(7)).max() < 1e-12
+    assert np.abs(V.T @ V - np.eye(7)).max() < 1e-12
+    U, S, V = oracle.jacobi_svd(np.zeros((5, 4)))
+    assert np.all(S == 0)
+    assert np.abs(U.T @ U - np.eye(4)).max() < 1e-15
+    assert np.abs(V.T @ V - np.eye(4)).max() < 1e-15
+
+
+def test_jacobi_sign_convention():
+    W = synth.gaussian((12, 8), seed=9)
+    U, S, V = oracle.jacobi_svd(W)
+    for k in range(8):
+        assert U[np.argmax(np.abs(U[:, k])), k] > 0
+
+
+# --------------------------------------------------------------------------
+# singular value thresholding, Eq. (4)
+# --------------------------------------------------------------------------
+def test_svt_closed_form_prescribed_spectrum():
+    sigma = np.array([50.0, 20.0, 9.0, 4.0, 1.5, 0.5, 0.1])
+    W, q1, q2 = synth.prescribed_spectrum(30, 20, sigma, seed=2)
+    eps = 3.0
+    A, S, r = oracle.svt_exact(W, eps)
+    ref = (q1 * np.maximum(sigma - eps, 0.0)) @ q2.T
+    assert r == 4
+    assert np.linalg.norm(A - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_svt_is_the_prox_of_the_nuclear_norm():
+    """Eq. (3): A minimises eps ||A||_* + 0.5 ||A - W||_F^2 (checked with numpy)."""
+    g = np.random.default_rng(8)
+    W = g.standard_normal((15, 12)) * 3.0
+    eps = 2.0
+    A, _, r = oracle.svt_exact(W, eps)
+
+    def f(X):
+        return eps * np.linalg.svd(X, compute_uv=False).sum() + 0.5 * np.sum((X - W) ** 2)
+
+    f0 = f(A)
+    for _ in range(50):
+        H = g.standard_normal(W.shape)
+        for t in (1e-2, 1e-4):
+            assert f(A + t * H) >= f0 - 1e-12
+    # KKT: W - A = eps (U_r V_r^T + Z), U_r^T Z = 0, Z V_r = 0, ||Z||_2 <= 1
+    Ua, Sa, Vat = np.linalg.svd(A)
+    Ur, Vr = Ua[:, :r], Vat[:r].T
+    Z = (W - A) / eps - Ur @ Vr.T
+    assert np.abs(Ur.T @ Z).max() < 1e-12 and np.abs(Z @ Vr).max() < 1e-12
+    assert np.linalg.norm(Z, 2) <= 1.0 + 1e-12
+
+
+def test_svt_threshold_above_spectrum_gives_zero():
+    W = synth.gaussian((10, 10), seed=1)
+    A, S, r = oracle.svt_exact(W, S_max := np.linalg.norm(W, 2) * 1.01)
+    assert r == 0 and np.all(A == 0)
+
+
+# --------------------------------------------------------------------------
+# BLWS step (Algorithms 2-3 with k = 2, warm start)
+# --------------------------------------------------------------------------
+def _warm(W, b, delta, seed):
+    U0, _, V0t = np.linalg.svd(W, full_matrices=False)
+    g = np.random.default_rng(seed)
+    m, n = W.shape
+    Ui = np.linalg.qr(U0[:, :b] + delta * g.standard_normal((m, b)))[0]
+    Vi = np.linalg.qr(V0t[:b].T + delta * g.standard_normal((n, b)))[0]
+    return Ui, Vi
+
+
+def _spectrum_case():
+    sigma = np.r_[np.linspace(100, 50, 5), np.geomspace(5, 0.01, 45)]
+    W, _, _ = synth.prescribed_spectrum(60, 50, sigma, seed=3)
+    return W, sigma
+
+
+def test_blws_matches_rayleigh_ritz_definition():
+    """Ritz values = singular values of the projection of W on the block
+    Krylov spaces span[U, W V] x span[V, W^T U], computed with numpy."""
+    g = np.random.default_rng(12)
+    W = g.standard_normal((45, 38))
+    b = 6
+    U = np.linalg.qr(g.standard_normal((45, b)))[0]
+    V = np.linalg.qr(g.standard_normal((38, b)))[0]
+    Un, Vn, S, A, r = oracle.blws_step(W, 1.5, U, V)
+    Qu = np.linalg.qr(np.hstack([U, W @ V]))[0]
+    Qv = np.linalg.qr(np.hstack([V, W.T @ U]))[0]
+    Ub, sb, Vbt = np.linalg.svd(Qu.T @ W @ Qv)
+    assert np.allclose(S, sb[:b], rtol=1e-12, atol=1e-13 * sb[0])
+    rr = int(np.sum(sb[:b] > 1.5))
+    Aref = (Qu @ Ub[:, :rr] * (sb[:rr] - 1.5)) @ (Qv @ Vbt[:rr].T).T
+    assert r == rr
+    assert np.linalg.norm(A - Aref) <= 1e-12 * np.linalg.norm(Aref)
+    assert np.abs(Un.T @ Un - np.eye(b)).max() < 1e-13
+    assert np.abs(Vn.T @ Vn - np.eye(b)).max() < 1e-13
+
+
+def test_blws_equals_literal_block_lanczos_on_augmented_matrix():
+    """Algorithm 2 with k = 2 on W~ = [[0, W], [W^T, 0]] from the start block
+    blockdiag(U, V), then Algorithm 3: the positive Ritz values are the BLWS
+    Ritz values (Theorem 1 applied to the projected matrix)."""
+    g = np.random.default_rng(21)
+    m, n, b = 20, 16, 3
+    W = g.standard_normal((m, n))
+    U = np.linalg.qr(g.standard_normal((m, b)))[0]
+    V = np.linalg.qr(g.standard_normal((n, b)))[0]
+    Wt = np.block([[np.zeros((m, m)), W], [W.T, np.zeros((n, n))]])
+    X1 = np.zeros((m + n, 2 * b))
+    X1[:m, :b] = U
+    X1[m:, b:] = V
+    M1 = X1.T @ Wt @ X1
+    R1 = Wt @ X1 - X1 @ M1
+    X2, B1 = np.linalg.qr(R1)
+    M2 = X2.T @ Wt @ X2
+    T2 = np.block([[M1, B1.T], [B1, M2]])
+    lam = np.sort(np.linalg.eigvalsh(T2))[::-1]
+    _, _, S, _, _ = oracle.blws_step(W, 0.0, U, V, want_A=False)
+    assert np.allclose(S, lam[:b], rtol=1e-12)
+    # Theorem 1 on the explicit augmented matrix
+    ev = np.sort(np.linalg.eigvalsh(Wt))
+    sv = np.linalg.svd(W, compute_uv=False)
+    expect = np.sort(np.r_[sv, -sv, np.zeros(m - n)])
+    assert np.allclose(ev, expect, atol=1e-12)
+
+
+def test_blws_exact_warm_start_is_exact():
+    """With the exact top-b subspaces the new Krylov directions vanish (R_1 = 0);
+    the Householder completion keeps the block orthonormal and the step returns
+    the exact top-b singular values and T_eps(W)."""
+    W, sigma = _spectrum_case()
+    U0, _, V0t = np.linalg.svd(W, full_matrices=False)
+    b = 8
+    Un, Vn, S, A, r = oracle.blws_step(W, 3.5, U0[:, :b], V0t[:b].T)
+    assert np.allclose(S, sigma[:b], rtol=1e-12)
+    Aex, _, rex = oracle.svt_exact(W, 3.5)
+    assert r == rex == 8
+    assert np.linalg.norm(A - Aex) <= 1e-12 * np.linalg.norm(Aex)
+    assert np.abs(Un.T @ Un - np.eye(b)).max() < 1e-13
+
+
+def test_blws_warm_start_convergence_is_quadratic_in_sigma():
+    W, sigma = _spectrum_case()
+    b = 8
+    errs = []
+    for d in (1e-3, 1e-4, 1e-5):
+        U, V = _warm(W, b, d, seed=0)
+        _, _, S, _, _ = oracle.blws_step(W, 3.5, U, V, want_A=False)
+        errs.append(np.abs(S - sigma[:b]).max() / sigma[0])
+        # Ritz values interlace from below
+        assert np.all(S <= sigma[:b] * (1 + 1e-13))
+    assert errs[0] / errs[1] > 30 and errs[1] / errs[2] > 30, errs
+
+
+def test_blws_rank_deficient_w():
+    g = np.random.default_rng(4)
+    W = g.standard_normal((30, 4)) @ g.standard_normal((4, 26))
+    U = np.linalg.qr(g.standard_normal((30, 6)))[0]
+    V = np.linalg.qr(g.standard_normal((26, 6)))[0]
+    Un, Vn, S, A, r = oracle.blws_step(W, 0.0, U, V)
+    sv = np.linalg.svd(W, compute_uv=False)
+    assert np.allclose(S[:4], sv[:4], rtol=1e-11)
+    assert np.all(S[4:] <= 1e-12 * sv[0])
+    assert np.abs(Un.T @ Un - np.eye(6)).max() < 1e-12
+    assert np.abs(Vn.T @ Vn - np.eye(6)).max() < 1e-12
+
+
+def test_spectral_norm_by_blws():
+    # a clear top gap: converged to rounding
+    sigma = np.r_[10.0, np.linspace(8.0, 0.1, 59)]
+    W, _, _ = synth.prescribed_spectrum(120, 90, sigma, seed=6)
+    s, steps = oracle.spectral_norm_blws(W, bs=8)
+    assert s == pytest.approx(10.0, rel=1e-13)
+    # a Gaussian matrix (clustered top of the spectrum): converges from below
+    g = np.random.default_rng(6)
+    W = g.standard_normal((120, 90))
+    s, steps = oracle.spectral_norm_blws(W, bs=8)
+    ref = np.linalg.norm(W, 2)
+    assert ref * (1 - 1e-9) <= s <= ref * (1 + 1e-14)
+    U, V = oracle.cold_block(W, 8, 2, seed=1)
+    assert np.abs(U.T @ U - np.eye(8)).max() < 1e-13
+    assert np.abs(V.T @ V - np.eye(8)).max() < 1e-13
+
+
+# --------------------------------------------------------------------------
+# inexact ALM for RPCA
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_rpca_exact_recovery_small(seed):
+    inst = synth.rpca_instance(200, 200, 10, 0.05, 50.0, seed)
+    ex = oracle.rpca(inst["D"], mode="exact", want_Y=True)
+    bl = oracle.rpca(inst["D"], mode="blws", want_Y=True)
+    nA0 = np.linalg.norm(inst["A0"])
+    for out in (ex, bl):
+        info = out["info"]
+        assert info["status"] == 0 and info["rel_residual"] < 1e-7
+        assert info["rank"] == 10
+        assert np.linalg.norm(out["A"] - inst["A0"]) / nA0 < 2e-6
+        assert abs(info["nnz_E"] - inst["nnz"]) <= 10
+        lam = 1.0 / np.sqrt(200)
+        Y, E = out["Y"], out["E"]
+        # E-step optimality: |Y| <= lambda with equality (and sign) on supp(E)
+        # (the dual update Y + mu Z cancels in floating point: mu reaches 1e7 mu_0)
+        assert np.abs(Y).max() <= lam * (1 + 1e-9)
+        on = E != 0
+        assert np.allclose(Y[on], lam * np.sign(E[on]), rtol=0, atol=1e-9 * lam)
+        # dual feasibility for the nuclear norm at the optimum
+        assert np.linalg.norm(Y, 2) <= 1.0 + 1e-3
+    assert np.linalg.norm(ex["A"] - bl["A"]) / np.linalg.norm(ex["A"]) < 1e-6
+
+
+def test_rpca_table1_m500_row():
+    """Table 1, m = 500: rank(A^) = 50, ||E^||_0 within a few dozen of the
+    25000 corruptions, relative error of order 1e-5, about 30 iterations."""
+    inst = synth.rpca_instance(500, 500, 50, 0.10, 500.0, 0)
+    out = oracle.rpca(inst["D"], mode="blws")
+    info = out["info"]
+    assert info["rank"] == 50
+    assert 25000 <= info["nnz_E"] <= 25100
+    err = np.linalg.norm(out["A"] - inst["A0"]) / np.linalg.norm(inst["A0"])
+    assert err < 5e-5
+    assert 15 <= info["iters"] <= 40
+
+
+# --------------------------------------------------------------------------
+# ALM matrix completion
+# --------------------------------------------------------------------------
+def test_mc_recovers_planted_low_rank():
+    inst = synth.mc_instance(120, 100, 4, 0.45, seed=3)
+    M = inst["L"] @ inst["R"].T
+    res = {}
+    for mode in ("exact", "blws"):
+        out = oracle.mc(120, 100, inst["row_ptr"], inst["col_idx"], inst["values"], mode=mode,
+                        r_cap=40, rho=1.1, tol=1e-8)
+        A = out["U"] * out["S"] @ out["V"].T
+        assert out["info"]["status"] == 0
+        assert out["rank"] == 4
+        assert np.linalg.norm(A - M) / np.linalg.norm(M) < 1e-6
+        res[mode] = A
+    assert np.linalg.norm(res["exact"] - res["blws"]) / np.linalg.norm(M) < 1e-6
