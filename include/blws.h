@@ -1,0 +1,160 @@
+/* blws.h - C ABI of the MI355X BLWS singular-value-thresholding library.
+ *
+ * The library computes the singular value thresholding step of nuclear norm
+ * minimisation, A = T_eps(W) = U Theta_eps(S) V^T (Lin & Wei, Eq. (3)-(4)),
+ * with a partial SVD by block Lanczos with a warm start (BLWS: Sec. 4,
+ * Algorithms 2-3 with k = 2 as in Sec. 4.1, block width following the
+ * predicted rank as in Sec. 4.2), and the inexact-ALM solvers that host it:
+ * robust PCA (Eq. (1) relaxed to nuclear + l1 norms) and matrix completion
+ * (Eq. (2) relaxed to the nuclear norm), as in the experiments of Sec. 5.
+ *
+ * Conventions for every call:
+ *  - Matrices are dense and row-major: element (i, j) at p[i * ld + j], with
+ *    ld >= number of columns. All matrix and vector pointers are DEVICE pointers
+ *    unless a parameter says "host". The caller owns every buffer it passes; the
+ *    library owns only the context's workspace.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream). Work is
+ *    queued on it; the solvers block the calling thread until their result is
+ *    complete, blws_svt returns as soon as its work is queued.
+ *  - Element type of the W/D/U/V/A/E buffers: double for BLWS_FP64, float for
+ *    BLWS_FP32. Singular values S are always double.
+ *  - Return value: a blws_status. Arguments are validated before any work is
+ *    queued, so an error leaves every output untouched. No call aborts, exits
+ *    or throws. blws_last_error() gives a detail message for the last failure.
+ *  - Threads: a context may be used by one host thread at a time.
+ */
+#ifndef BLWS_H
+#define BLWS_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct blws_ctx_s* blws_ctx;
+
+typedef enum { BLWS_FP64 = 0, BLWS_FP32 = 1, BLWS_BF16 = 2 } blws_precision;
+
+typedef enum {
+    BLWS_OK = 0,
+    BLWS_NOT_CONVERGED = 1, /* iteration cap reached; outputs hold the last iterate */
+    BLWS_EINVAL = -1,       /* bad argument (nothing was queued)                   */
+    BLWS_ENOMEM = -2,       /* device workspace allocation failed                  */
+    BLWS_EDEVICE = -3,      /* a HIP call failed                                   */
+    BLWS_ENUMERIC = -4,     /* NaN or Inf met in the data or a residual            */
+    BLWS_EUNSUPPORTED = -5  /* precision or size not supported by this build       */
+} blws_status;
+
+/* Options of one BLWS call. */
+typedef struct {
+    int pow_steps;            /* cold start only: power half-step pairs on V (2)     */
+    unsigned long long seed;  /* cold start: seed of the counter-based generator     */
+} blws_svt_opts;
+
+/* Options of the inexact-ALM solvers. Defaults from blws_default_alm_opts. */
+typedef struct {
+    double tol;               /* stop when ||D - A - E||_F / ||D||_F < tol (1e-7)      */
+    int max_iter;             /* 1000                                                   */
+    double rho;               /* mu <- min(rho mu, mu_bar) (1.5)                        */
+    double mu0_scale;         /* mu_0 = mu0_scale / ||D||_2 (1.25)                      */
+    double mu_max_factor;     /* mu_bar = mu_max_factor * mu_0 (1e7)                    */
+    int sv0;                  /* initial predicted rank (10)                            */
+    double sv_step_frac;      /* rank-prediction increment as a fraction of min(m,n)    */
+    int b_round;              /* Lanczos block width = predicted rank rounded up (16)   */
+    int pow_steps;            /* power half-step pairs of the first (cold) block (2)    */
+    unsigned long long seed;  /* counter-based generator seed                           */
+    int norm_steps;           /* max BLWS steps for ||D||_2 (60)                        */
+    double norm_rtol;         /* relative change that stops the ||D||_2 steps (1e-13)   */
+    int b_max;                /* upper bound on the block width, <= 256 (256)           */
+} blws_alm_opts;
+
+typedef struct {
+    int status;               /* BLWS_OK or BLWS_NOT_CONVERGED                          */
+    int iters;                /* ALM iterations (= SVT calls)                           */
+    int rank;                 /* rank of the returned A                                 */
+    int b_final;              /* Lanczos block width of the last iteration              */
+    int fallbacks;            /* columns replaced after an orthonormalisation breakdown */
+    long long nnz_E;          /* nonzeros of the returned E (RPCA)                      */
+    double rel_residual;      /* final ||D - A - E||_F / ||D||_F                        */
+    double norm2_D;           /* ||D||_2 used for mu_0                                  */
+    double seconds;           /* wall time of the solve, measured on the host           */
+} blws_solve_info;
+
+/* Create a context on HIP device `device` (its workspace grows on demand). */
+int blws_create(blws_ctx* out, int device);
+int blws_destroy(blws_ctx ctx);
+const char* blws_status_string(int status);
+/* Detail of the last failure on this context (never NULL). */
+const char* blws_last_error(blws_ctx ctx);
+void blws_default_alm_opts(blws_alm_opts* opts);
+void blws_default_svt_opts(blws_svt_opts* opts);
+
+/* A = T_eps(W) by one BLWS step (Eq. (4) with the partial SVD of Sec. 4).
+ *   W: m x n (ldw). b: block width, 1 <= b <= min(m, n) / 2.
+ *   warm = 1: U (m x b, ldu) and V (n x b, ldv) hold orthonormal columns (the
+ *             previous principal subspaces) on entry.
+ *   warm = 0: U, V are ignored on entry; a cold block is drawn (opts->seed).
+ *   On exit U, V hold the top-b Ritz vectors (orthonormal), S (device double[b])
+ *   the Ritz values in decreasing order, rank_dev (device int, may be NULL) the
+ *   count of S_i > eps, and A (m x n, lda; may be NULL) = U_r diag(S_r - eps) V_r^T.
+ *   eps >= 0. prec: BLWS_FP64 or BLWS_FP32. Asynchronous on `stream`. */
+int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, int ldw,
+             double eps, int b, void* U, int ldu, void* V, int ldv, int warm, double* S,
+             int* rank_dev, void* A, int lda, const blws_svt_opts* opts);
+
+/* Robust PCA: min ||A||_* + lambda ||E||_1 s.t. D = A + E, by inexact ALM with
+ * one BLWS step per iteration (Sec. 5). lambda <= 0 selects 1/sqrt(max(m, n)).
+ * D (m x n, ldd) is read only; A (lda) and E (lde) receive the solution; E is
+ * also used as iteration state. opts may be NULL (defaults); info is a HOST
+ * struct (may be NULL). Blocks until the result is complete.
+ * Returns BLWS_OK, BLWS_NOT_CONVERGED, or an error. */
+int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const void* D,
+                    int ldd, double lambda, const blws_alm_opts* opts, void* A, int lda,
+                    void* E, int lde, blws_solve_info* info);
+
+/* ---------------------------------------------------------------------- */
+/* Diagnostics (used by the parity tests and the bench).                   */
+/* ---------------------------------------------------------------------- */
+
+/* X (rows x cols, ldx, device double) = the counter-based uniform generator:
+ * X[i][j] = u(seed, stream_id * 2^40 + i * 4096 + j), u = the (counter+1)-th
+ * SplitMix64 output mapped to [-1, 1) as ((z >> 11) * 2^-53) * 2 - 1. */
+int blws_fill_uniform(blws_ctx ctx, void* stream, int rows, int cols, double* X, int ldx,
+                      unsigned long long seed, unsigned long long stream_id);
+
+/* C (M x N, ldc) = alpha * op(A) * B + beta * C, op(A) = A (trans_a = 0, A is
+ * M x K) or A^T (trans_a = 1, A is K x M); B is K x N. All double. This is the
+ * library's skinny-GEMM kernel family (MFMA, split-K, deterministic). */
+int blws_gemm_f64(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K, double alpha,
+                  const double* A, int lda, const double* B, int ldb, double beta, double* C,
+                  int ldc);
+
+/* SVD of a small dense N x N FP64 matrix B (ldb) on the device: U_B (N x N),
+ * V_B (N x N) row-major with ld = N, S (N) decreasing, sign chosen so that the
+ * largest-magnitude entry of each left vector is positive. */
+int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int ldb,
+                       double* UB, double* S, double* VB);
+
+/* The cold start block of blws_svt (warm = 0) on its own: V = orth(random
+ * n x b drawn from generator stream `stream_v`) refined by `pow_steps` power
+ * half-step pairs V <- orth(W^T orth(W V)); U = orth(random m x b, stream
+ * stream_v + 1), independent of V. U (m x b, ldu), V (n x b, ldv) receive
+ * orthonormal columns. FP64 or FP32 per prec. */
+int blws_cold_block(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, int ldw,
+                    int b, int pow_steps, unsigned long long seed, unsigned long long stream_v,
+                    void* U, int ldu, void* V, int ldv);
+
+/* Per-kernel timing with HIP events on the launching stream. enable = 1 starts
+ * recording (and clears the totals); 0 stops. */
+int blws_timing_enable(blws_ctx ctx, int enable);
+/* Totals for the kernel family `name` ("gemm_w", "gemm_ts", "alm_epilogue",
+ * "small_svd", "chol", ...): launches and summed milliseconds, and the summed
+ * algorithmic flop and byte counts of those launches. Synchronises the device. */
+int blws_timing_get(blws_ctx ctx, const char* name, long long* launches, double* ms,
+                    double* flops, double* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

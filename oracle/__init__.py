@@ -44,6 +44,7 @@ class AlmOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("norm_steps", ctypes.c_int),
         ("norm_rtol", ctypes.c_double),
+        ("b_max", ctypes.c_int),
     ]
 
 

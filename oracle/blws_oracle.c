@@ -577,16 +577,18 @@ static int cold_block_op(const orc_op* op, int b, int pow_steps, uint64_t seed,
     if (!X) return -2;
     orc_fill_uniform(n, b, seed, stream_v, X);
     orth(n, b, X, V);
-    if (pow_steps <= 0) {
-        orc_fill_uniform(m, b, seed, stream_v + 1, X);
-        orth(m, b, X, U);
-    }
+    /* power half-step pairs refine V only: V <- orth(W^T orth(W V)) */
     for (int t = 0; t < pow_steps; ++t) {
         op_apply(op, b, V, X);
         orth(m, b, X, U);
         op_apply_t(op, b, U, X);
         orth(n, b, X, V);
     }
+    /* U is an independent random block: were U = orth(W V), W V would lie in
+     * span(U) and the first Lanczos block would have no new left directions
+     * (likewise V = orth(W^T U) on the right) */
+    orc_fill_uniform(m, b, seed, stream_v + 1, X);
+    orth(m, b, X, U);
     free(X);
     return 0;
 }
@@ -652,13 +654,16 @@ void orc_default_opts(orc_alm_opts* o)
     o->seed = 20101202ULL;
     o->norm_steps = 60;
     o->norm_rtol = 1e-13;
+    o->b_max = 256;
 }
 
-/* Block width for a predicted rank sv: rounded up, at most floor(p / 2). */
-static int block_width(int sv, int b_round, int p)
+/* Block width for a predicted rank sv: rounded up, at most floor(p / 2) and
+ * at most b_max. */
+static int block_width(int sv, int b_round, int p, int b_max)
 {
     int b = ((sv + b_round - 1) / b_round) * b_round;
     if (b > p / 2) b = p / 2;
+    if (b > b_max) b = b_max;
     if (b < 1) b = 1;
     return b;
 }
@@ -751,7 +756,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
         if (mode == 0) {
             orc_svt_exact(m, n, W, eps, A, NULL, &svp);
         } else {
-            int bn = block_width(sv, o.b_round, p);
+            int bn = block_width(sv, o.b_round, p, o.b_max);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);
@@ -872,7 +877,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
             w.Ul = Ua;
             w.Vl = Va;
             w.th = th;
-            int bn = block_width(sv, o.b_round, p);
+            int bn = block_width(sv, o.b_round, p, o.b_max);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);

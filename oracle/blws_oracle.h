@@ -40,9 +40,9 @@ int orc_svt_exact(int m, int n, const double* W, double eps, double* A, double* 
 int orc_blws_step(int m, int n, const double* W, double eps, int b, double* U, double* V,
                   double* S, double* A, int* rank);
 
-/* Cold start block: V = orth(random n x b), then `pow_steps` pairs
- * U = orth(W V), V = orth(W^T U). With pow_steps = 0, U = orth(random m x b).
- * Streams: V uses stream_v, U uses stream_v + 1. */
+/* Cold start block: V = orth(random n x b) refined by `pow_steps` power
+ * half-step pairs V <- orth(W^T orth(W V)); U = orth(random m x b), drawn
+ * independently. Streams: V uses stream_v, U uses stream_v + 1. */
 int orc_cold_block(int m, int n, const double* W, int b, int pow_steps, uint64_t seed,
                    uint64_t stream_v, double* U, double* V);
 
@@ -63,6 +63,7 @@ typedef struct {
     uint64_t seed;
     int norm_steps;        /* max BLWS steps for ||D||_2                            */
     double norm_rtol;
+    int b_max;             /* upper bound on the Lanczos block width                */
 } orc_alm_opts;
 
 typedef struct {

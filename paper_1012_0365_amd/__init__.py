@@ -1,0 +1,181 @@
+"""MI355X-native BLWS singular value thresholding and the nuclear-norm solvers
+that host it (Lin & Wei, block Lanczos with warm start).
+
+Python surface over the C ABI of libblws.so: torch tensors supply device memory
+and the current HIP stream; every computation runs in the library's kernels.
+
+    import torch, paper_1012_0365_amd as blws
+    ctx = blws.Context()
+    A, E, info = ctx.rpca_solve(D)                 # robust PCA (inexact ALM + BLWS)
+    S, rank = ctx.svt(W, eps, U, V, A=A_out)       # one BLWS SVT step, U/V updated in place
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+from . import _native
+from ._native import AlmOpts, BlwsError, SolveInfo, SvtOpts
+
+__all__ = ["Context", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo", "default_alm_opts"]
+
+
+def _torch():
+    import torch  # plumbing only: device memory and streams
+
+    return torch
+
+
+def _prec_of(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return _native.BLWS_FP64
+    if t.dtype == torch.float32:
+        return _native.BLWS_FP32
+    raise TypeError(f"unsupported dtype {t.dtype}: use float64 or float32")
+
+
+def _check_mat(t, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dim() != 2 or t.stride(1) != 1:
+        raise ValueError(f"{name} must be a 2-D row-major tensor (unit column stride)")
+    return t.stride(0)
+
+
+def default_alm_opts(**kw) -> AlmOpts:
+    o = AlmOpts()
+    _native.lib().blws_default_alm_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Context:
+    """One library context on a HIP device (owns the device workspace)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = _native.lib()
+        h = ctypes.c_void_p()
+        _native.check(self._lib.blws_create(ctypes.byref(h), device))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.blws_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _stream(self):
+        return ctypes.c_void_p(_torch().cuda.current_stream(self.device).cuda_stream)
+
+    def _check(self, status):
+        return _native.check(status, self.handle)
+
+    # -- the BLWS SVT step ---------------------------------------------------
+    def svt(self, W, eps: float, U, V, warm: bool = True, A=None, S=None, seed: int = 20101202,
+            pow_steps: int = 2):
+        """A = T_eps(W) by one BLWS step. U (m x b), V (n x b) are updated in
+        place with the top-b Ritz vectors. Returns (S, rank) as device tensors."""
+        torch = _torch()
+        prec = _prec_of(W)
+        ldw = _check_mat(W, "W")
+        ldu = _check_mat(U, "U")
+        ldv = _check_mat(V, "V")
+        m, n = W.shape
+        b = U.shape[1]
+        if U.shape != (m, b) or V.shape != (n, b) or U.dtype != W.dtype or V.dtype != W.dtype:
+            raise ValueError("U must be m x b and V n x b, with W's dtype")
+        if S is None:
+            S = torch.empty(b, dtype=torch.float64, device=W.device)
+        rank = torch.zeros(1, dtype=torch.int32, device=W.device)
+        lda = 0
+        if A is not None:
+            lda = _check_mat(A, "A")
+            if A.shape != (m, n) or A.dtype != W.dtype:
+                raise ValueError("A must be m x n with W's dtype")
+        o = SvtOpts(pow_steps, seed)
+        self._check(self._lib.blws_svt(
+            self.handle, self._stream(), prec, m, n, W.data_ptr(), ldw, float(eps), b,
+            U.data_ptr(), ldu, V.data_ptr(), ldv, int(bool(warm)), S.data_ptr(),
+            rank.data_ptr(), A.data_ptr() if A is not None else None, lda, ctypes.byref(o)))
+        return S, rank
+
+    # -- robust PCA ----------------------------------------------------------
+    def rpca_solve(self, D, lam: float | None = None, opts: AlmOpts | None = None, A=None,
+                   E=None):
+        """min ||A||_* + lam ||E||_1 s.t. D = A + E by inexact ALM with BLWS.
+        Returns (A, E, info dict)."""
+        torch = _torch()
+        prec = _prec_of(D)
+        ldd = _check_mat(D, "D")
+        m, n = D.shape
+        if A is None:
+            A = torch.empty_like(D)
+        if E is None:
+            E = torch.empty_like(D)
+        lda = _check_mat(A, "A")
+        lde = _check_mat(E, "E")
+        info = SolveInfo()
+        st = self._lib.blws_rpca_solve(
+            self.handle, self._stream(), prec, m, n, D.data_ptr(), ldd,
+            -1.0 if lam is None else float(lam), ctypes.byref(opts) if opts is not None else None,
+            A.data_ptr(), lda, E.data_ptr(), lde, ctypes.byref(info))
+        self._check(st)
+        return A, E, info.as_dict()
+
+    # -- diagnostics -----------------------------------------------------------
+    def fill_uniform(self, X, seed: int, stream_id: int):
+        ld = _check_mat(X, "X")
+        self._check(self._lib.blws_fill_uniform(self.handle, self._stream(), X.shape[0],
+                                                X.shape[1], X.data_ptr(), ld, seed, stream_id))
+
+    def gemm_f64(self, A, B, C, trans_a: bool = False, alpha: float = 1.0, beta: float = 0.0):
+        lda, ldb, ldc = _check_mat(A, "A"), _check_mat(B, "B"), _check_mat(C, "C")
+        M, N = C.shape
+        K = B.shape[0]
+        self._check(self._lib.blws_gemm_f64(self.handle, self._stream(), int(trans_a), M, N, K,
+                                            alpha, A.data_ptr(), lda, B.data_ptr(), ldb, beta,
+                                            C.data_ptr(), ldc))
+
+    def small_svd_f64(self, B):
+        torch = _torch()
+        ldb = _check_mat(B, "B")
+        N = B.shape[0]
+        UB = torch.empty(N, N, dtype=torch.float64, device=B.device)
+        VB = torch.empty_like(UB)
+        S = torch.empty(N, dtype=torch.float64, device=B.device)
+        self._check(self._lib.blws_small_svd_f64(self.handle, self._stream(), N, B.data_ptr(),
+                                                 ldb, UB.data_ptr(), S.data_ptr(), VB.data_ptr()))
+        return UB, S, VB
+
+    def cold_block(self, W, b: int, pow_steps: int = 2, seed: int = 20101202,
+                   stream_v: int = 1):
+        """The cold start block of svt(warm=False): returns (U, V)."""
+        torch = _torch()
+        ldw = _check_mat(W, "W")
+        m, n = W.shape
+        U = torch.empty(m, b, dtype=W.dtype, device=W.device)
+        V = torch.empty(n, b, dtype=W.dtype, device=W.device)
+        self._check(self._lib.blws_cold_block(self.handle, self._stream(), _prec_of(W), m, n,
+                                              W.data_ptr(), ldw, b, pow_steps, seed, stream_v,
+                                              U.data_ptr(), b, V.data_ptr(), b))
+        return U, V
+
+    def timing(self, enable: bool):
+        self._check(self._lib.blws_timing_enable(self.handle, int(enable)))
+
+    def timing_get(self, name: str) -> dict:
+        n = ctypes.c_longlong()
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        self._check(self._lib.blws_timing_get(self.handle, name.encode(), ctypes.byref(n),
+                                              ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
+        return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}

@@ -1,0 +1,114 @@
+"""ctypes binding of libblws.so (the C ABI in include/blws.h).
+
+Argument marshalling only: every step of the computation runs in the library's
+HIP kernels. Loading fails loudly when the library has not been built; there is
+no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libblws.so")
+
+BLWS_FP64, BLWS_FP32, BLWS_BF16 = 0, 1, 2
+STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
+          -3: "device error", -4: "NaN or Inf encountered", -5: "unsupported"}
+
+
+class SvtOpts(ctypes.Structure):
+    _fields_ = [("pow_steps", ctypes.c_int), ("seed", ctypes.c_ulonglong)]
+
+
+class AlmOpts(ctypes.Structure):
+    _fields_ = [
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("rho", ctypes.c_double),
+        ("mu0_scale", ctypes.c_double),
+        ("mu_max_factor", ctypes.c_double),
+        ("sv0", ctypes.c_int),
+        ("sv_step_frac", ctypes.c_double),
+        ("b_round", ctypes.c_int),
+        ("pow_steps", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("norm_steps", ctypes.c_int),
+        ("norm_rtol", ctypes.c_double),
+        ("b_max", ctypes.c_int),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int),
+        ("iters", ctypes.c_int),
+        ("rank", ctypes.c_int),
+        ("b_final", ctypes.c_int),
+        ("fallbacks", ctypes.c_int),
+        ("nnz_E", ctypes.c_longlong),
+        ("rel_residual", ctypes.c_double),
+        ("norm2_D", ctypes.c_double),
+        ("seconds", ctypes.c_double),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# (name, restype, argtypes) for every exported entry point
+_vp, _i, _d, _ll, _ull = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, \
+    ctypes.c_ulonglong
+SIGNATURES = {
+    "blws_create": (_i, [ctypes.POINTER(_vp), _i]),
+    "blws_destroy": (_i, [_vp]),
+    "blws_status_string": (ctypes.c_char_p, [_i]),
+    "blws_last_error": (ctypes.c_char_p, [_vp]),
+    "blws_default_alm_opts": (None, [ctypes.POINTER(AlmOpts)]),
+    "blws_default_svt_opts": (None, [ctypes.POINTER(SvtOpts)]),
+    "blws_svt": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, _i, _vp, _i, _vp, _i, _i, _vp, _vp, _vp,
+                      _i, ctypes.POINTER(SvtOpts)]),
+    "blws_rpca_solve": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, ctypes.POINTER(AlmOpts), _vp, _i,
+                             _vp, _i, ctypes.POINTER(SolveInfo)]),
+    "blws_fill_uniform": (_i, [_vp, _vp, _i, _i, _vp, _i, _ull, _ull]),
+    "blws_gemm_f64": (_i, [_vp, _vp, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i]),
+    "blws_small_svd_f64": (_i, [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp]),
+    "blws_cold_block": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _i, _ull, _ull, _vp, _i, _vp,
+                             _i]),
+    "blws_timing_enable": (_i, [_vp, _i]),
+    "blws_timing_get": (_i, [_vp, ctypes.c_char_p, ctypes.POINTER(_ll), ctypes.POINTER(_d),
+                             ctypes.POINTER(_d), ctypes.POINTER(_d)]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libblws.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(
+                f"{LIB_PATH} is missing: build it with `python paper_1012_0365_amd/build.py` "
+                "(or __graft_entry__.build()); the library has no CPU fallback")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+class BlwsError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+
+
+def check(status: int, ctx=None) -> int:
+    if status < 0:
+        detail = lib().blws_last_error(ctx).decode() if ctx is not None else ""
+        raise BlwsError(status, detail)
+    return status

@@ -1,0 +1,129 @@
+// Internal declarations shared by the HIP translation units of libblws.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/blws.h"
+
+namespace blws {
+
+// ---------------------------------------------------------------------------
+// Error plumbing: every HIP call in host code goes through HIP_TRY, which turns
+// a failure into a BlwsError carrying BLWS_EDEVICE and the HIP message.
+// ---------------------------------------------------------------------------
+struct BlwsError {
+    int status;
+    std::string msg;
+};
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::blws::BlwsError{BLWS_EDEVICE, std::string(#expr) + ": " +           \
+                                                      hipGetErrorString(e_)};           \
+    } while (0)
+
+#define BLWS_REQUIRE(cond, status, text)                                               \
+    do {                                                                               \
+        if (!(cond)) throw ::blws::BlwsError{(status), (text)};                       \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// Kernel timing (HIP events on the launching stream) for the bench.
+// ---------------------------------------------------------------------------
+struct Timer;
+// Start/stop one timed launch of a kernel family; no-ops unless timing is on.
+struct TimedLaunch {
+    Timer* t;
+    int slot;
+    hipStream_t stream;
+    const char* fam;
+    TimedLaunch(Timer* timer, const char* family, hipStream_t s, double flops, double bytes);
+    ~TimedLaunch();
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (device code in k_*.hip). All take the stream last.
+// ---------------------------------------------------------------------------
+
+// Skinny GEMM: C (M x N, ldc) = alpha * op(A) * B + beta * Cin, with
+// op(A) = A (M x K, lda) or A^T (A is K x M). B is K x N (ldb). Cin may alias C.
+// Types: TA for A, TB for B, TC for C/Cin; compute type TM (double or float).
+// `partial` is a device scratch of at least gemm_partial_elems(...) doubles.
+template <typename TA, typename TB, typename TC>
+void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, double alpha,
+          const TA* A, int lda, const TB* B, int ldb, double beta, const TC* Cin, int ldcin,
+          TC* C, int ldc, double* partial, size_t partial_elems, hipStream_t s);
+size_t gemm_partial_elems(int M, int N, int K);
+
+// Scaled LDL^T / Cholesky with breakdown detection on an n x n Gram matrix:
+// writes Rinv (n x n, ld n) such that X * Rinv has orthonormal columns when
+// G = X^T X; columns whose scaled pivot is <= eta are flagged (flags[j] = 1)
+// and get a zero column in Rinv. nflag (device int) += number of flags.
+void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* flags,
+              int* nflag, double eta, double* scratch, hipStream_t s);
+size_t chol_scratch_elems(int n);
+
+// Fill flagged columns of X (rows x c, ldx) with the counter-based uniform draw.
+template <typename T>
+void fill_flagged(int rows, int c, T* X, int ldx, const int* flags, uint64_t seed,
+                  uint64_t stream_id, hipStream_t s);
+
+// X[i][j] = u(seed, stream_id * 2^40 + i * 4096 + j) for i < rows, j < cols.
+template <typename T>
+void fill_uniform(int rows, int cols, T* X, int ldx, uint64_t seed, uint64_t stream_id,
+                  hipStream_t s);
+
+// One-sided Jacobi SVD of the N x N matrix B (ldb): UB, VB (N x N, ld N), S (N).
+void small_svd(Timer* tm, int N, const double* B, int ldb, double* UB, double* S, double* VB,
+               double* scratch, hipStream_t s);
+size_t small_svd_scratch_elems(int N);
+
+// Copy a rows x cols block (types may differ).
+template <typename TS, typename TD>
+void copy2d(int rows, int cols, const TS* src, int lds, TD* dst, int ldd, hipStream_t s);
+
+// rank_out[0] = #{S_i > eps, i < b}.
+void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t s);
+
+// Sum of squares and max |.| of an m x n matrix: two-pass, deterministic.
+// out[0] = sum of squares, out[1] = max abs. scratch >= norms_scratch_elems().
+template <typename T>
+void norms(int m, int n, const T* X, int ldx, double* out, double* scratch, hipStream_t s);
+size_t norms_scratch_elems();
+
+// RPCA start: Y = D / J, E = 0, W = D - E + Y / mu (Y, W with ld = n).
+template <typename T>
+void rpca_init(int m, int n, const T* D, int ldd, double J, double mu, T* Y, T* E, int lde,
+               T* W, hipStream_t s);
+
+// Fused SVT reconstruction + inexact-ALM update for RPCA (one pass over D, Y):
+// a = sum_{k < r} U[i][k] (S[k] - eps) V[j][k] with r = #{S_k > eps} (k < b);
+// t = d - a + y / mu;  e = shrink(t, lam / mu);  z = d - a - e;
+// y' = y + mu z;  w' = d - e + y' / mu_next.
+// Writes E, Y, W, and per-workgroup partial sums of z^2 into `partials`
+// (size alm_partials(m, n)); A_out (may be null) receives a.
+template <typename T>
+void alm_epilogue(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
+                  const double* S, double eps, double lam, double mu, double mu_next,
+                  const T* D, int ldd, T* Y, T* E, int lde, T* W, T* A_out, int lda,
+                  double* partials, hipStream_t s);
+size_t alm_partials(int m, int n);
+// A = U_r diag(S_r - eps) V_r^T only.
+template <typename T>
+void svt_reconstruct(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
+                     const double* S, double eps, T* A, int lda, hipStream_t s);
+
+// out[0] = sum of partials[0..count) in a fixed order.
+void sum_partials(int count, const double* partials, double* out, hipStream_t s);
+
+// Count nonzeros of an m x n matrix into out (long long), deterministic.
+template <typename T>
+void count_nonzeros(int m, int n, const T* X, int ldx, long long* out, long long* scratch,
+                    hipStream_t s);
+
+}  // namespace blws

@@ -1,0 +1,396 @@
+// Small dense FP64 kernels of the BLWS step: the Cholesky factor of the Gram
+// matrix used to orthonormalise the new Lanczos block (the QR step
+// (X_{l+1}, B_l) = qr(R_l) of Algorithm 2, done as Cholesky-QR), and the SVD of
+// the 2b x 2b projected matrix whose singular values are the Ritz values
+// (Algorithm 3 with Theorem 1). Both run in one workgroup.
+#include "blws_common.h"
+
+namespace blws {
+namespace {
+
+constexpr int CHOL_LDS_MAX = 128;  // Gram matrices up to 128 x 128 live in LDS
+
+// Counter-based uniform draw: the (counter + 1)-th output of SplitMix64
+// (Steele, Lea & Flood 2014) seeded with `seed`, mapped to [-1, 1).
+__device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
+// Scaled LDL^T elimination of the Gram matrix G = X^T X, tracking L^{-1} in the
+// strictly lower triangle of the same array (the trailing matrix lives in the
+// upper triangle). With d the pivots and s_i = G_ii^{-1/2}:
+//   R^{-1}[r][c] = s_r * (L^{-1})[c][r] / sqrt(d_c),  r <= c,
+// so X R^{-1} has orthonormal columns. A pivot <= eta (the squared sine of the
+// angle between a scaled column and the span of the earlier ones) marks the
+// column as dependent: it is skipped and its R^{-1} column is zero.
+template <bool LDS>
+__global__ __launch_bounds__(1024) void chol_inv_kernel(int n, const double* __restrict__ G,
+                                                        int ldg, double* __restrict__ Rinv,
+                                                        int* flags, int* nflag, double eta,
+                                                        double* gscratch)
+{
+    __shared__ double lds[LDS ? CHOL_LDS_MAX * CHOL_LDS_MAX : 1];
+    __shared__ double scal[512];
+    __shared__ int flg[512];
+    double* S = LDS ? lds : gscratch;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int i = tid; i < n; i += nth) {
+        const double g = G[(size_t)i * ldg + i];
+        scal[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+        flg[i] = 0;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += nth) {
+        const int i = e / n, k = e - i * n;
+        S[e] = (k >= i) ? G[(size_t)i * ldg + k] * scal[i] * scal[k] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        const double piv = S[j * n + j];
+        if (!(piv > eta)) {
+            if (tid == 0) flg[j] = 1;
+        } else {
+            const double inv = 1.0 / piv;
+            const int rows = n - j - 1;
+            const int items = rows * n;
+            for (int e = tid; e < items; e += nth) {
+                const int i = j + 1 + e / n, col = e % n;
+                const double l = S[j * n + i] * inv;
+                if (col >= i) {
+                    S[i * n + col] -= l * S[j * n + col];
+                } else if (col < j) {
+                    S[i * n + col] -= l * S[j * n + col];
+                } else if (col == j) {
+                    S[i * n + j] = -l;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < n * n; e += nth) {
+        const int r = e / n, c = e - r * n;
+        double v = 0.0;
+        if (r <= c && !flg[c]) {
+            const double lic = (r == c) ? 1.0 : S[c * n + r];
+            v = scal[r] * lic / sqrt(S[c * n + c]);
+        }
+        Rinv[e] = v;
+    }
+    int cnt = 0;
+    for (int i = tid; i < n; i += nth) {
+        flags[i] = flg[i];
+        cnt += flg[i];
+    }
+    if (cnt) atomicAdd(nflag, cnt);
+}
+
+// One-sided (Hestenes) Jacobi SVD of the N x N matrix B in one workgroup.
+// Columns live column-major in global scratch (Ac, Vc). Each round of the
+// round-robin ordering pairs all columns disjointly; a group of G lanes owns
+// one pair, computes the three inner products with a shuffle reduction and
+// applies the rotation to the pair's columns of B and V.
+constexpr int SVD_MAXN = 512;
+
+__global__ __launch_bounds__(1024) void jacobi_svd_kernel(int N, const double* __restrict__ B,
+                                                          int ldb, double* __restrict__ UB,
+                                                          double* __restrict__ S,
+                                                          double* __restrict__ VB, double* Ac,
+                                                          double* Vc, double tol, int max_sweeps)
+{
+    __shared__ int rot_count;
+    __shared__ double sig[SVD_MAXN];
+    __shared__ int perm[SVD_MAXN];
+    __shared__ int ok[SVD_MAXN];
+    __shared__ double vtmp[SVD_MAXN];
+    __shared__ double dots[SVD_MAXN];
+    __shared__ double red;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    for (int e = tid; e < N * N; e += nth) {
+        const int j = e / N, i = e - j * N;
+        Ac[e] = B[(size_t)i * ldb + j];
+        Vc[e] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    const int Ne = N + (N & 1);
+    const int npairs = Ne / 2;
+    int G = 64;
+    while (G > 1 && G * npairs > nth) G >>= 1;
+    const int grp = tid / G, gl = tid % G;
+    for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
+        if (tid == 0) rot_count = 0;
+        __syncthreads();
+        for (int round = 0; round < Ne - 1; ++round) {
+            if (grp < npairs) {
+                int p, q;
+                if (grp == 0) {
+                    p = round;
+                    q = Ne - 1;
+                } else {
+                    p = (round + grp) % (Ne - 1);
+                    q = (round - grp + (Ne - 1)) % (Ne - 1);
+                }
+                if (p > q) {
+                    const int t = p;
+                    p = q;
+                    q = t;
+                }
+                if (q < N) {
+                    double* ap = Ac + (size_t)p * N;
+                    double* aq = Ac + (size_t)q * N;
+                    double al = 0.0, be = 0.0, ga = 0.0;
+                    for (int i = gl; i < N; i += G) {
+                        const double x = ap[i], y = aq[i];
+                        al += x * x;
+                        be += y * y;
+                        ga += x * y;
+                    }
+                    for (int off = G >> 1; off > 0; off >>= 1) {
+                        al += __shfl_xor(al, off, G);
+                        be += __shfl_xor(be, off, G);
+                        ga += __shfl_xor(ga, off, G);
+                    }
+                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double t =
+                            (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double c = 1.0 / sqrt(1.0 + t * t);
+                        const double s = c * t;
+                        for (int i = gl; i < N; i += G) {
+                            const double x = ap[i], y = aq[i];
+                            ap[i] = c * x - s * y;
+                            aq[i] = s * x + c * y;
+                        }
+                        double* vp = Vc + (size_t)p * N;
+                        double* vq = Vc + (size_t)q * N;
+                        for (int i = gl; i < N; i += G) {
+                            const double x = vp[i], y = vq[i];
+                            vp[i] = c * x - s * y;
+                            vq[i] = s * x + c * y;
+                        }
+                        if (gl == 0) atomicAdd(&rot_count, 1);
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        const int rc = rot_count;
+        __syncthreads();
+        if (rc == 0) break;
+    }
+    // singular values = column norms; left vectors = normalised columns
+    for (int j = tid; j < N; j += nth) {
+        const double* a = Ac + (size_t)j * N;
+        double s2 = 0.0;
+        for (int i = 0; i < N; ++i) s2 += a[i] * a[i];
+        sig[j] = sqrt(s2);
+        ok[j] = sig[j] > 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < N * N; e += nth) {
+        const int j = e / N;
+        if (ok[j]) Ac[e] /= sig[j];
+    }
+    __syncthreads();
+    // complete exactly-zero columns with unit vectors orthogonalised (twice)
+    // against the accepted columns
+    int cand = 0;
+    for (int zc = 0; zc < N; ++zc) {
+        if (ok[zc]) continue;  // uniform: ok[] is shared
+        for (; cand < N; ++cand) {
+            for (int i = tid; i < N; i += nth) vtmp[i] = (i == cand) ? 1.0 : 0.0;
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                for (int j = tid; j < N; j += nth) {
+                    double d = 0.0;
+                    if (ok[j])
+                        for (int i = 0; i < N; ++i) d += Ac[(size_t)j * N + i] * vtmp[i];
+                    dots[j] = d;
+                }
+                __syncthreads();
+                for (int i = tid; i < N; i += nth) {
+                    double v = vtmp[i];
+                    for (int j = 0; j < N; ++j)
+                        if (ok[j]) v -= dots[j] * Ac[(size_t)j * N + i];
+                    vtmp[i] = v;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                double s2 = 0.0;
+                for (int i = 0; i < N; ++i) s2 += vtmp[i] * vtmp[i];
+                red = sqrt(s2);
+            }
+            __syncthreads();
+            const double nv = red;
+            if (nv > 0.5) {
+                for (int i = tid; i < N; i += nth) Ac[(size_t)zc * N + i] = vtmp[i] / nv;
+                __syncthreads();
+                if (tid == 0) ok[zc] = 1;
+                __syncthreads();
+                ++cand;
+                break;
+            }
+            __syncthreads();
+        }
+    }
+    // decreasing order, ties by column index. The key maps NaN to -inf so the
+    // order is total and perm is a permutation whatever the data hold.
+    for (int j = tid; j < N; j += nth) {
+        const double kj = isnan(sig[j]) ? -INFINITY : sig[j];
+        int pos = 0;
+        for (int k = 0; k < N; ++k) {
+            const double kk = isnan(sig[k]) ? -INFINITY : sig[k];
+            pos += (kk > kj) || (kk == kj && k < j);
+        }
+        perm[pos] = j;
+    }
+    __syncthreads();
+    for (int t = tid; t < N; t += nth) {
+        int j = perm[t];
+        if (j < 0 || j >= N) j = t;  // unreachable when perm is a permutation
+        const double* u = Ac + (size_t)j * N;
+        int imax = 0;
+        for (int i = 1; i < N; ++i)
+            if (fabs(u[i]) > fabs(u[imax])) imax = i;
+        const double sg = u[imax] < 0.0 ? -1.0 : 1.0;
+        S[t] = sig[j];
+        for (int i = 0; i < N; ++i) {
+            UB[(size_t)i * N + t] = sg * u[i];
+            VB[(size_t)i * N + t] = sg * Vc[(size_t)j * N + i];
+        }
+    }
+}
+
+template <typename T>
+__global__ void fill_flagged_kernel(int rows, int c, T* X, int ldx, const int* flags,
+                                    uint64_t seed, uint64_t stream_id)
+{
+    const size_t total = (size_t)rows * c;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / c), j = (int)(e - (size_t)i * c);
+        if (flags[j])
+            X[(size_t)i * ldx + j] =
+                (T)uniform_pm1(seed, (stream_id << 40) + (uint64_t)i * 4096ULL + (uint64_t)j);
+    }
+}
+
+template <typename T>
+__global__ void fill_uniform_kernel(int rows, int cols, T* X, int ldx, uint64_t seed,
+                                    uint64_t stream_id)
+{
+    const size_t total = (size_t)rows * cols;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / cols), j = (int)(e - (size_t)i * cols);
+        X[(size_t)i * ldx + j] =
+            (T)uniform_pm1(seed, (stream_id << 40) + (uint64_t)i * 4096ULL + (uint64_t)j);
+    }
+}
+
+template <typename TS, typename TD>
+__global__ void copy2d_kernel(int rows, int cols, const TS* src, int lds, TD* dst, int ldd)
+{
+    const size_t total = (size_t)rows * cols;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / cols), j = (int)(e - (size_t)i * cols);
+        dst[(size_t)i * ldd + j] = (TD)src[(size_t)i * lds + j];
+    }
+}
+
+__global__ void count_above_kernel(int b, const double* S, double eps, int* out)
+{
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    int c = 0;
+    for (int i = threadIdx.x; i < b; i += blockDim.x) c += S[i] > eps;
+    if (c) atomicAdd(&cnt, c);
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = cnt;
+}
+
+int grid_for(size_t total)
+{
+    size_t b = (total + 255) / 256;
+    if (b > 4096) b = 4096;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+}  // namespace
+
+size_t chol_scratch_elems(int n) { return n > CHOL_LDS_MAX ? (size_t)n * n : 0; }
+
+void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* flags, int* nflag,
+              double eta, double* scratch, hipStream_t s)
+{
+    BLWS_REQUIRE(n >= 1 && n <= 512, BLWS_EUNSUPPORTED, "chol_inv: block width above 512");
+    TimedLaunch tl(tm, "chol", s, (double)n * n * n / 3.0, 16.0 * n * n);
+    if (n <= CHOL_LDS_MAX)
+        hipLaunchKernelGGL((chol_inv_kernel<true>), dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv,
+                           flags, nflag, eta, (double*)nullptr);
+    else
+        hipLaunchKernelGGL((chol_inv_kernel<false>), dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv,
+                           flags, nflag, eta, scratch);
+}
+
+size_t small_svd_scratch_elems(int N) { return 2 * (size_t)N * N; }
+
+void small_svd(Timer* tm, int N, const double* B, int ldb, double* UB, double* S, double* VB,
+               double* scratch, hipStream_t s)
+{
+    BLWS_REQUIRE(N >= 1 && N <= SVD_MAXN, BLWS_EUNSUPPORTED, "small_svd: size above 512");
+    TimedLaunch tl(tm, "small_svd", s, 10.0 * (double)N * N * N, 32.0 * N * N);
+    const double tol = sqrt((double)N) * 0x1.0p-53;
+    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, N, B, ldb, UB, S, VB, scratch,
+                       scratch + (size_t)N * N, tol, 60);
+}
+
+template <typename T>
+void fill_flagged(int rows, int c, T* X, int ldx, const int* flags, uint64_t seed,
+                  uint64_t stream_id, hipStream_t s)
+{
+    hipLaunchKernelGGL((fill_flagged_kernel<T>), dim3(grid_for((size_t)rows * c)), dim3(256), 0, s,
+                       rows, c, X, ldx, flags, seed, stream_id);
+}
+
+template <typename T>
+void fill_uniform(int rows, int cols, T* X, int ldx, uint64_t seed, uint64_t stream_id,
+                  hipStream_t s)
+{
+    hipLaunchKernelGGL((fill_uniform_kernel<T>), dim3(grid_for((size_t)rows * cols)), dim3(256), 0,
+                       s, rows, cols, X, ldx, seed, stream_id);
+}
+
+template <typename TS, typename TD>
+void copy2d(int rows, int cols, const TS* src, int lds, TD* dst, int ldd, hipStream_t s)
+{
+    if (rows <= 0 || cols <= 0) return;
+    hipLaunchKernelGGL((copy2d_kernel<TS, TD>), dim3(grid_for((size_t)rows * cols)), dim3(256), 0,
+                       s, rows, cols, src, lds, dst, ldd);
+}
+
+void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(count_above_kernel, dim3(1), dim3(256), 0, s, b, S, eps, rank_out);
+}
+
+template void fill_flagged<double>(int, int, double*, int, const int*, uint64_t, uint64_t,
+                                   hipStream_t);
+template void fill_flagged<float>(int, int, float*, int, const int*, uint64_t, uint64_t,
+                                  hipStream_t);
+template void fill_uniform<double>(int, int, double*, int, uint64_t, uint64_t, hipStream_t);
+template void fill_uniform<float>(int, int, float*, int, uint64_t, uint64_t, hipStream_t);
+template void copy2d<double, double>(int, int, const double*, int, double*, int, hipStream_t);
+template void copy2d<float, float>(int, int, const float*, int, float*, int, hipStream_t);
+template void copy2d<float, double>(int, int, const float*, int, double*, int, hipStream_t);
+template void copy2d<double, float>(int, int, const double*, int, float*, int, hipStream_t);
+
+}  // namespace blws

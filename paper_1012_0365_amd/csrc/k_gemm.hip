@@ -1,0 +1,230 @@
+// Skinny GEMMs on CDNA4 matrix cores.
+//
+// Every product of the BLWS step has one small dimension: the block products
+// W V, W^T U, W G (Algorithm 2: the products of the augmented matrix with the
+// Lanczos blocks) have N = b columns; the projections and Gram matrices
+// X^T Y have a b x b output and a long K; the block updates X S have K <= 2b.
+// One kernel family covers them all: C = alpha op(A) B + beta C with
+// op(A) = A or A^T, B row-major K x N. A workgroup owns a 64-row strip of C
+// and 16 * NT of its columns, four wavefronts each computing 16 rows with
+// v_mfma_f64_16x16x4f64 tiles. Tiles of op(A) and B are staged through LDS,
+// converted to the compute type on the way in. Long K is split across
+// workgroups (split-K); the partial sums are reduced in a fixed order by a
+// second kernel, so results do not depend on scheduling.
+#include "blws_common.h"
+
+namespace blws {
+namespace {
+
+constexpr int BM = 64;  // rows of C per workgroup (4 wavefronts x 16)
+constexpr int BK = 32;  // K per LDS stage (8 MFMA steps of 4)
+constexpr int NTHREADS = 256;
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ __forceinline__ double ld_d(const T* p) { return (double)(*p); }
+
+template <typename TA, typename TB, typename TC, bool TRANS, int NT>
+__global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
+    int M, int N, int K, int kchunk, double alpha, const TA* __restrict__ A, int lda,
+    const TB* __restrict__ B, int ldb, double beta, const TC* Cin, int ldcin, TC* C, int ldc,
+    double* __restrict__ partial)
+{
+    constexpr int BN = 16 * NT;
+    __shared__ double As[BK][BM + 1];
+    __shared__ double Bs[BK][BN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+
+    d4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
+
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            // op(A) = A (M x K): 4 threads read 32 consecutive k of one row.
+            const int row = tid >> 2, kq = (tid & 3) * 8;
+            const int gr = r0 + row;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int gk = k0 + kq + u;
+                As[kq + u][row] = (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
+            }
+        } else {
+            // op(A) = A^T, A is K x M: 8 threads read 64 consecutive columns of one row.
+            const int kr = tid >> 3, rq = (tid & 7) * 8;
+            const int gk = k0 + kr;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int gr = r0 + rq + u;
+                As[kr][rq + u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
+            }
+        }
+        for (int e = tid; e < BK * BN; e += NTHREADS) {
+            const int kr = e / BN, cc = e - kr * BN;
+            const int gk = k0 + kr, gc = c0 + cc;
+            Bs[kr][cc] = (gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const double a = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const double bv = Bs[kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+                acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+
+    // C layout of the FP64 16x16 tile (measured on gfx950): register i of lane l
+    // holds row (l / 16) + 4 i, column l % 16.
+    const int rbase = r0 + wave * 16 + (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int col = c0 + j * 16 + (lane & 15);
+        if (col >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = rbase + 4 * i;
+            if (row >= M) continue;
+            const double v = acc[j][i];
+            if (partial) {
+                partial[((size_t)blockIdx.z * M + row) * N + col] = v;
+            } else {
+                double out = alpha * v;
+                if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
+                C[(size_t)row * ldc + col] = (TC)out;
+            }
+        }
+    }
+}
+
+// C = alpha * sum_s partial[s] + beta * Cin, summed in split order.
+template <typename TC>
+__global__ void splitk_reduce_kernel(int M, int N, int S, double alpha, const double* partial,
+                                     double beta, const TC* Cin, int ldcin, TC* C, int ldc)
+{
+    const size_t total = (size_t)M * N;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < S; ++s) acc += partial[(size_t)s * total + e];
+        const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
+        double out = alpha * acc;
+        if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
+        C[(size_t)row * ldc + col] = (TC)out;
+    }
+}
+
+struct Plan {
+    int nt, gy, gx, splits, kchunk;
+};
+
+Plan make_plan(int M, int N, int K)
+{
+    Plan p;
+    p.nt = N >= 128 ? 8 : (N + 15) / 16;
+    if (p.nt < 1) p.nt = 1;
+    p.gy = (N + 16 * p.nt - 1) / (16 * p.nt);
+    p.gx = (M + BM - 1) / BM;
+    const long tiles = (long)p.gx * p.gy;
+    // Aim at ~512 workgroups, each split no shorter than 4 LDS stages, and
+    // keep the partial sums below 4M doubles.
+    long s = (512 + tiles - 1) / tiles;
+    const long smax_k = (K + 4 * BK - 1) / (4 * BK);
+    if (s > smax_k) s = smax_k;
+    const long smax_mem = (4L << 20) / ((long)M * N > 0 ? (long)M * N : 1);
+    if (s > smax_mem) s = smax_mem;
+    if (s < 1) s = 1;
+    int kchunk = (int)((K + s - 1) / s);
+    kchunk = ((kchunk + BK - 1) / BK) * BK;
+    if (kchunk < BK) kchunk = BK;
+    p.kchunk = kchunk;
+    p.splits = (K + kchunk - 1) / kchunk;
+    if (p.splits < 1) p.splits = 1;
+    return p;
+}
+
+template <typename TA, typename TB, typename TC, bool TRANS>
+void launch_nt(const Plan& p, int M, int N, int K, double alpha, const TA* A, int lda,
+               const TB* B, int ldb, double beta, const TC* Cin, int ldcin, TC* C, int ldc,
+               double* partial, hipStream_t s)
+{
+    dim3 grid(p.gx, p.gy, p.splits), block(NTHREADS);
+#define BLWS_GEMM_CASE(NTV)                                                                 \
+    case NTV:                                                                               \
+        hipLaunchKernelGGL((gemm_f64_kernel<TA, TB, TC, TRANS, NTV>), grid, block, 0, s, M, N, \
+                           K, p.kchunk, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,    \
+                           partial);                                                        \
+        break;
+    switch (p.nt) {
+        BLWS_GEMM_CASE(1)
+        BLWS_GEMM_CASE(2)
+        BLWS_GEMM_CASE(3)
+        BLWS_GEMM_CASE(4)
+        BLWS_GEMM_CASE(5)
+        BLWS_GEMM_CASE(6)
+        BLWS_GEMM_CASE(7)
+        default:
+            BLWS_GEMM_CASE(8)
+    }
+#undef BLWS_GEMM_CASE
+}
+
+}  // namespace
+
+size_t gemm_partial_elems(int M, int N, int K)
+{
+    Plan p = make_plan(M, N, K);
+    return p.splits > 1 ? (size_t)p.splits * M * N : 0;
+}
+
+template <typename TA, typename TB, typename TC>
+void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, double alpha,
+          const TA* A, int lda, const TB* B, int ldb, double beta, const TC* Cin, int ldcin,
+          TC* C, int ldc, double* partial, size_t partial_elems, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return;
+    if (K <= 0) {
+        // C = beta * Cin: a split-K reduce over zero partials
+        hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(256), dim3(256), 0, s, M, N, 0, 0.0,
+                           (const double*)nullptr, beta, Cin, ldcin, C, ldc);
+        return;
+    }
+    Plan p = make_plan(M, N, K);
+    const bool split = p.splits > 1;
+    BLWS_REQUIRE(!split || (partial && partial_elems >= (size_t)p.splits * M * N), BLWS_ENOMEM,
+                 "gemm: split-K scratch too small");
+    TimedLaunch tl(tm, family, s, 2.0 * M * N * (double)K,
+                   8.0 * ((double)M * K + (double)K * N + (double)M * N));
+    if (trans_a)
+        launch_nt<TA, TB, TC, true>(p, M, N, K, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,
+                                     split ? partial : nullptr, s);
+    else
+        launch_nt<TA, TB, TC, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,
+                                      split ? partial : nullptr, s);
+    if (split) {
+        const size_t total = (size_t)M * N;
+        int blocks = (int)((total + 255) / 256);
+        if (blocks > 2048) blocks = 2048;
+        hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(blocks), dim3(256), 0, s, M, N,
+                           p.splits, alpha, partial, beta, Cin, ldcin, C, ldc);
+    }
+}
+
+#define BLWS_GEMM_INST(TA, TB, TC)                                                           \
+    template void gemm<TA, TB, TC>(Timer*, const char*, bool, int, int, int, double, const TA*, \
+                                   int, const TB*, int, double, const TC*, int, TC*, int,     \
+                                   double*, size_t, hipStream_t);
+BLWS_GEMM_INST(double, double, double)
+BLWS_GEMM_INST(float, float, float)
+BLWS_GEMM_INST(float, float, double)
+BLWS_GEMM_INST(float, double, float)
+#undef BLWS_GEMM_INST
+
+}  // namespace blws

@@ -1,0 +1,95 @@
+"""GPU parity of the library's building blocks, called through the C ABI."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+
+    assert torch.cuda.is_available(), "these tests need a GPU"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch):
+    import paper_1012_0365_amd as blws
+
+    c = blws.Context(0)
+    yield c
+    c.close()
+
+
+def dev(torch, a, dtype=None):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def test_counter_generator_is_bit_exact(torch, ctx):
+    for rows, cols, seed, stream in [(1, 1, 0, 0), (37, 5, 20101202, 3), (300, 64, 7, 1 << 20)]:
+        X = torch.empty(rows, cols, dtype=torch.float64, device="cuda")
+        ctx.fill_uniform(X, seed, stream)
+        ref = oracle.fill_uniform(rows, cols, seed, stream)
+        assert np.array_equal(host(X), ref)
+
+
+@pytest.mark.parametrize("trans", [False, True])
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 16, 32), (130, 112, 2000), (2000, 112, 2000),
+                                   (17, 200, 45), (224, 224, 1999), (5, 3, 70000)])
+def test_gemm_matches_numpy(torch, ctx, trans, M, N, K):
+    g = np.random.default_rng(M * 7 + N * 3 + K)
+    A = g.standard_normal((K, M) if trans else (M, K))
+    B = g.standard_normal((K, N))
+    C0 = g.standard_normal((M, N))
+    ref = 0.75 * ((A.T if trans else A) @ B) - 0.5 * C0
+    C = dev(torch, C0)
+    ctx.gemm_f64(dev(torch, A), dev(torch, B), C, trans_a=trans, alpha=0.75, beta=-0.5)
+    torch.cuda.synchronize()
+    scale = np.abs(A).max() * np.abs(B).max() * K + np.abs(C0).max()
+    assert np.abs(host(C) - ref).max() <= 1e-14 * scale
+
+
+def test_gemm_is_deterministic(torch, ctx):
+    g = np.random.default_rng(1)
+    A, B = dev(torch, g.standard_normal((3000, 700))), dev(torch, g.standard_normal((3000, 96)))
+    outs = []
+    for _ in range(3):
+        C = torch.zeros(700, 96, dtype=torch.float64, device="cuda")
+        ctx.gemm_f64(A, B, C, trans_a=True)
+        outs.append(host(C))
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
+
+
+@pytest.mark.parametrize("N", [1, 2, 7, 32, 64, 224])
+def test_small_svd_matches_oracle_jacobi(torch, ctx, N):
+    g = np.random.default_rng(N)
+    B = g.standard_normal((N, N)) * np.geomspace(1.0, 1e-6, N)[None, :]
+    UB, S, VB = ctx.small_svd_f64(dev(torch, B))
+    torch.cuda.synchronize()
+    UB, S, VB = host(UB), host(S), host(VB)
+    _, So, _ = oracle.jacobi_svd(B)
+    assert np.all(np.abs(S - So) <= 1e-13 * So[0] + 1e-12 * So)
+    assert np.abs(UB.T @ UB - np.eye(N)).max() < 1e-13
+    assert np.abs(VB.T @ VB - np.eye(N)).max() < 1e-13
+    assert np.linalg.norm(UB * S @ VB.T - B) <= 1e-13 * np.linalg.norm(B)
+
+
+def test_small_svd_rank_deficient(torch, ctx):
+    g = np.random.default_rng(3)
+    B = g.standard_normal((40, 3)) @ g.standard_normal((3, 40))
+    B[:, 5] = 0.0
+    UB, S, VB = ctx.small_svd_f64(dev(torch, B))
+    torch.cuda.synchronize()
+    UB, S, VB = host(UB), host(S), host(VB)
+    assert np.all(S[3:] <= 1e-13 * S[0])
+    assert np.abs(UB.T @ UB - np.eye(40)).max() < 1e-12
+    assert np.abs(VB.T @ VB - np.eye(40)).max() < 1e-12
