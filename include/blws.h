@@ -64,9 +64,11 @@ typedef struct {
     int b_round;              /* Lanczos block width = predicted rank rounded up (16)   */
     int pow_steps;            /* power half-step pairs of the first (cold) block (2)    */
     unsigned long long seed;  /* counter-based generator seed                           */
-    int norm_steps;           /* max BLWS steps for ||D||_2 (60)                        */
+    int norm_steps;           /* max BLWS steps for the ||D||_2 estimate (8)            */
     double norm_rtol;         /* relative change that stops the ||D||_2 steps (1e-13)   */
     int b_max;                /* upper bound on the block width, <= 256 (256)           */
+    int b_soft;               /* beyond this width the block follows the previous count */
+                              /* of values above the threshold, not the prediction (112)*/
 } blws_alm_opts;
 
 typedef struct {

@@ -652,18 +652,27 @@ void orc_default_opts(orc_alm_opts* o)
     o->b_round = 16;
     o->pow_steps = 2;
     o->seed = 20101202ULL;
-    o->norm_steps = 60;
+    o->norm_steps = 8;
     o->norm_rtol = 1e-13;
     o->b_max = 256;
+    o->b_soft = 112;
 }
 
 /* Block width for a predicted rank sv: rounded up, at most floor(p / 2) and
- * at most b_max. */
-static int block_width(int sv, int b_round, int p, int b_max)
+ * at most b_max. Beyond b_soft the block grows only as far as the count of
+ * values above the threshold in the previous iteration (svp) requires, without
+ * the prediction's extra margin. */
+static int block_width(int sv, int svp, const orc_alm_opts* o, int p)
 {
-    int b = ((sv + b_round - 1) / b_round) * b_round;
+    int b = ((sv + o->b_round - 1) / o->b_round) * o->b_round;
+    if (b > o->b_soft) {
+        int need = ((svp + 1 + o->b_round - 1) / o->b_round) * o->b_round;
+        b = need > o->b_soft ? need : o->b_soft;
+        if (b > ((sv + o->b_round - 1) / o->b_round) * o->b_round)
+            b = ((sv + o->b_round - 1) / o->b_round) * o->b_round;
+    }
     if (b > p / 2) b = p / 2;
-    if (b > b_max) b = b_max;
+    if (b > o->b_max) b = o->b_max;
     if (b < 1) b = 1;
     return b;
 }
@@ -747,7 +756,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
         E[e] = 0.0;
     }
     double mu = o.mu0_scale / s1, mu_bar = mu * o.mu_max_factor;
-    int sv = o.sv0, b = 0, svp = 0, it = 0;
+    int sv = o.sv0, b = 0, svp = 0, svp_prev = 0, it = 0;
     double rel = INFINITY;
     double *U = NULL, *V = NULL, *S = NULL;
     for (it = 1; it <= o.max_iter; ++it) {
@@ -756,7 +765,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
         if (mode == 0) {
             orc_svt_exact(m, n, W, eps, A, NULL, &svp);
         } else {
-            int bn = block_width(sv, o.b_round, p, o.b_max);
+            int bn = block_width(sv, svp_prev, &o, p);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);
@@ -770,6 +779,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
             S = (double*)malloc(sizeof(double) * (size_t)b);
             orc_blws_step(m, n, W, eps, b, U, V, S, A, &svp);
             sv = predict_rank(svp, sv, o.sv_step_frac, p);
+            svp_prev = svp;
         }
         if (svp_trace) svp_trace[it - 1] = svp;
         /* E = S_{lambda/mu}(D - A + Y/mu); Z = D - A - E; Y += mu Z */
@@ -850,7 +860,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
         s1 = spectral_norm_op(&op, 16, o.pow_steps, o.seed, o.norm_rtol, o.norm_steps, NULL);
     }
     double mu = o.mu0_scale / s1, mu_bar = mu * o.mu_max_factor;
-    int sv = o.sv0, b = 0, r = 0, it = 0;
+    int sv = o.sv0, b = 0, r = 0, it = 0, svp_prev = 0;
     double rel = INFINITY;
     double *U = NULL, *V = NULL, *S = NULL, *th = NULL;
     double *Ua = NULL, *Va = NULL; /* factors of the current A (width r) */
@@ -877,7 +887,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
             w.Ul = Ua;
             w.Vl = Va;
             w.th = th;
-            int bn = block_width(sv, o.b_round, p, o.b_max);
+            int bn = block_width(sv, svp_prev, &o, p);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);
@@ -892,6 +902,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
             int svp = 0;
             blws_step_op(&w, eps, b, U, V, S, &svp);
             sv = predict_rank(svp, sv, o.sv_step_frac, p);
+            svp_prev = svp;
             /* new A = U_r diag(S_r - eps) V_r^T, kept as factors */
             r = svp;
             free(Ua); free(Va); free(th);

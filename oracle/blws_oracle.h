@@ -61,9 +61,10 @@ typedef struct {
     int b_round;           /* Lanczos block width = sv rounded up to this          */
     int pow_steps;         /* power half-step pairs in the cold start               */
     uint64_t seed;
-    int norm_steps;        /* max BLWS steps for ||D||_2                            */
+    int norm_steps;        /* max BLWS steps for the ||D||_2 estimate               */
     double norm_rtol;
     int b_max;             /* upper bound on the Lanczos block width                */
+    int b_soft;            /* beyond this width the block follows svp, not sv      */
 } orc_alm_opts;
 
 typedef struct {

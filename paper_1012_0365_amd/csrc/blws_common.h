@@ -79,9 +79,18 @@ void fill_uniform(int rows, int cols, T* X, int ldx, uint64_t seed, uint64_t str
                   hipStream_t s);
 
 // One-sided Jacobi SVD of the N x N matrix B (ldb): UB, VB (N x N, ld N), S (N).
-void small_svd(Timer* tm, int N, const double* B, int ldb, double* UB, double* S, double* VB,
-               double* scratch, hipStream_t s);
-size_t small_svd_scratch_elems(int N);
+void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, double* S,
+                      double* VB, double* scratch, hipStream_t s);
+size_t small_svd_jacobi_scratch_elems(int N);
+
+// Golub-Kahan bidiagonalisation + bisection / inverse iteration on the
+// Golub-Kahan tridiagonal (N <= 224): the top nv singular values S[0..nv) and
+// the first nv columns of UB, VB (N x N, ld N). The vectors of close values are
+// not yet orthogonalised (the caller polishes them).
+bool small_svd_gk_supported(int N);
+size_t small_svd_gk_scratch_elems(int N);
+void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
+                  double* VB, double* scratch, hipStream_t s);
 
 // Copy a rows x cols block (types may differ).
 template <typename TS, typename TD>

@@ -111,7 +111,7 @@ namespace {
 template <typename T>
 struct StepWs {
     T *UF, *PH, *VG, *Qb, *T1, *T2, *R;
-    double *Cp, *Gr, *Ri, *Bm, *UB, *VB, *Sall, *svd, *chol, *partial;
+    double *Cp, *Gr, *Ri, *Bm, *UB, *VB, *Sall, *svd, *chol, *partial, *D1, *D2;
     int *flags, *nflag;
     size_t partial_elems;
 
@@ -132,7 +132,12 @@ struct StepWs {
         UB = c.take<double>((size_t)b2 * b2);
         VB = c.take<double>((size_t)b2 * b2);
         Sall = c.take<double>((size_t)b2);
-        svd = c.take<double>(small_svd_scratch_elems(b2));
+        {
+            size_t e1 = small_svd_jacobi_scratch_elems(b2), e2 = small_svd_gk_scratch_elems(b2);
+            svd = c.take<double>(e1 > e2 ? e1 : e2);
+        }
+        D1 = c.take<double>((size_t)b2 * b);
+        D2 = c.take<double>((size_t)b2 * b);
         chol = c.take<double>(chol_scratch_elems(b) + 1);
         flags = c.take<int>((size_t)b);
         nflag = c.take<int>(4);
@@ -192,6 +197,54 @@ void orth_against(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b0, co
     }
 }
 
+// Two Cholesky-QR passes on the FP64 columns X (rows x c, ldx) in place;
+// dependent columns (scaled pivot <= CHOL_ETA) are replaced by random draws.
+void cholqr2_f64(Context& cx, hipStream_t s, int rows, int c, double* X, int ldx, double* T1,
+                 double* Gr, double* Ri, int* flags, int* nflag, double* chol_scratch,
+                 double* partial, size_t partial_elems, uint64_t seed)
+{
+    Timer* tm = &cx.timer;
+    for (int pass = 0; pass < 2; ++pass) {
+        const double* src = pass == 0 ? X : T1;
+        const int lds = pass == 0 ? ldx : c;
+        gemm<double, double, double>(tm, "gemm_ts", true, c, c, rows, 1.0, src, lds, src, lds, 0.0,
+                                     (const double*)nullptr, 0, Gr, c, partial, partial_elems, s);
+        chol_inv(tm, c, Gr, c, Ri, flags, nflag, CHOL_ETA, chol_scratch, s);
+        double* dst = pass == 0 ? T1 : X;
+        const int ldd = pass == 0 ? c : ldx;
+        gemm<double, double, double>(tm, "gemm_ts", false, rows, c, c, 1.0, src, lds, Ri, c, 0.0,
+                                     (const double*)nullptr, 0, dst, ldd, partial, partial_elems,
+                                     s);
+        if (pass == 0)
+            fill_flagged<double>(rows, c, T1, c, flags, seed, (1ULL << 20) + (++cx.fix_calls), s);
+    }
+}
+
+// SVD of the small projected matrix: the top nv values and vectors. Sizes up
+// to 224 use the Golub-Kahan path, whose leading vectors are then polished to
+// orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
+// values only nearly orthogonal); larger ones the one-sided Jacobi kernel.
+struct SvdScratch {
+    double *svd, *T1, *Gr, *Ri, *chol, *partial;
+    int *flags, *nflag;
+    size_t partial_elems;
+};
+
+void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double* B, int ldb,
+                        double* UB, double* S, double* VB, const SvdScratch& w, uint64_t seed)
+{
+    TimedLaunch tl(&cx.timer, "small_svd", s, 0.0, 0.0);
+    if (small_svd_gk_supported(N)) {
+        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, w.svd, s);
+        cholqr2_f64(cx, s, N, nv, UB, N, w.T1, w.Gr, w.Ri, w.flags, w.nflag, w.chol, w.partial,
+                    w.partial_elems, seed);
+        cholqr2_f64(cx, s, N, nv, VB, N, w.T1, w.Gr, w.Ri, w.flags, w.nflag, w.chol, w.partial,
+                    w.partial_elems, seed);
+    } else {
+        small_svd_jacobi(&cx.timer, N, B, ldb, UB, S, VB, w.svd, s);
+    }
+}
+
 // One BLWS step (Algorithms 2-3, k = 2) on W from the orthonormal block
 // (U, V); on return U, V hold the top-b Ritz vectors and S the Ritz values.
 //
@@ -224,7 +277,11 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const T* W
     // B = [U, F]^T [P, H] in FP64
     gemm<T, T, double>(tm, "gemm_ts", true, b2, b2, m, 1.0, w.UF, b2, w.PH, b2, 0.0,
                        (const double*)nullptr, 0, w.Bm, b2, w.partial, w.partial_elems, s);
-    small_svd(tm, b2, w.Bm, b2, w.UB, w.Sall, w.VB, w.svd, s);
+    {
+        SvdScratch sw{w.svd, w.D1, w.Gr, w.Ri, w.chol, w.partial, w.flags, w.nflag,
+                      w.partial_elems};
+        small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, sw, seed);
+    }
     // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b)
     gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
                        (const T*)nullptr, 0, U, ldu, w.partial, w.partial_elems, s);
@@ -270,11 +327,20 @@ void grow_block(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b_old, i
     orth_against<T>(cx, w, s, rows, b_old, X, ldx, w.R, c, c, X + b_old, ldx, seed);
 }
 
-int block_width(int sv, int b_round, int p, int b_max)
+// Block width for a predicted rank sv: rounded up, at most floor(p / 2) and
+// b_max. Beyond b_soft the block grows only as far as the previous count of
+// values above the threshold (svp) requires, without the prediction's margin.
+int block_width(int sv, int svp, const blws_alm_opts& o, int p)
 {
-    int b = ((sv + b_round - 1) / b_round) * b_round;
+    const int want = ((sv + o.b_round - 1) / o.b_round) * o.b_round;
+    int b = want;
+    if (b > o.b_soft) {
+        const int need = ((svp + 1 + o.b_round - 1) / o.b_round) * o.b_round;
+        b = need > o.b_soft ? need : o.b_soft;
+        if (b > want) b = want;
+    }
     if (b > p / 2) b = p / 2;
-    if (b > b_max) b = b_max;
+    if (b > o.b_max) b = o.b_max;
     if (b < 1) b = 1;
     return b;
 }
@@ -381,7 +447,7 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
     const int np = (int)alm_partials(m, n);
     for (it = 1; it <= o.max_iter; ++it) {
         eps = 1.0 / mu;
-        const int bn = block_width(sv, o.b_round, p, o.b_max);
+        const int bn = block_width(sv, svp, o, p);
         if (b == 0) {
             cold_block<T>(cx, w, s, m, n, Wb, n, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
         } else if (bn > b) {
@@ -542,9 +608,10 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->b_round = 16;
     o->pow_steps = 2;
     o->seed = 20101202ULL;
-    o->norm_steps = 60;
+    o->norm_steps = 8;
     o->norm_rtol = 1e-13;
     o->b_max = 256;
+    o->b_soft = 112;
 }
 
 void blws_default_svt_opts(blws_svt_opts* o)
@@ -597,7 +664,8 @@ int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
     if (opts) o = *opts;
     BLWS_REQUIRE(o.tol > 0.0 && o.max_iter >= 1 && o.rho >= 1.0 && o.mu0_scale > 0.0 &&
                      o.mu_max_factor >= 1.0 && o.sv0 >= 1 && o.b_round >= 1 &&
-                     o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1,
+                     o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
+                     o.b_soft >= 1,
                  BLWS_EINVAL, "blws_rpca_solve: bad options");
     BLWS_REQUIRE(o.b_max <= 256, BLWS_EUNSUPPORTED, "blws_rpca_solve: b_max above 256");
     hipStream_t s = (hipStream_t)stream;
@@ -646,8 +714,28 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
     ABI_BEGIN(ctx)
     BLWS_REQUIRE(N >= 1 && N <= 512 && B && UB && S && VB && ldb >= N, BLWS_EINVAL,
                  "blws_small_svd_f64: bad arguments");
-    cx.ensure(blws::small_svd_scratch_elems(N) * sizeof(double) + 256);
-    blws::small_svd(&cx.timer, N, B, ldb, UB, S, VB, (double*)cx.ws, (hipStream_t)stream);
+    auto layout = [&](Carver& c, blws::SvdScratch& w) {
+        size_t e1 = blws::small_svd_jacobi_scratch_elems(N), e2 = blws::small_svd_gk_scratch_elems(N);
+        w.svd = c.take<double>(e1 > e2 ? e1 : e2);
+        w.T1 = c.take<double>((size_t)N * N);
+        w.Gr = c.take<double>((size_t)N * N);
+        w.Ri = c.take<double>((size_t)N * N);
+        w.chol = c.take<double>(blws::chol_scratch_elems(N) + 1);
+        w.flags = c.take<int>((size_t)N);
+        w.nflag = c.take<int>(4);
+        size_t pe = blws::gemm_partial_elems(N, N, N);
+        w.partial_elems = pe;
+        w.partial = c.take<double>(pe + 1);
+    };
+    blws::SvdScratch w;
+    {
+        Carver dry(nullptr);
+        layout(dry, w);
+        cx.ensure(dry.off + 256);
+    }
+    Carver c(cx.ws);
+    layout(c, w);
+    blws::small_svd_dispatch(cx, (hipStream_t)stream, N, N, B, ldb, UB, S, VB, w, 20101202ULL);
     return BLWS_OK;
     ABI_END
 }

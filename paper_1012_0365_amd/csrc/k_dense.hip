@@ -89,6 +89,96 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(int n, const double* __r
     if (cnt) atomicAdd(nflag, cnt);
 }
 
+// The same elimination with the matrix in registers (n <= 128): thread
+// (tr, tc) of a 32 x 32 grid holds S[tr + 32a][tc + 32b], a, b < 4. Each step
+// broadcasts the pivot row through LDS; two barriers per step.
+__global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double* __restrict__ G,
+                                                            int ldg, double* __restrict__ Rinv,
+                                                            int* flags, int* nflag, double eta)
+{
+    __shared__ double scal[128];
+    __shared__ double row[128];
+    __shared__ double piv[128];
+    __shared__ int flg[128];
+    const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+    for (int i = tid; i < n; i += 1024) {
+        const double g = G[(size_t)i * ldg + i];
+        scal[i] = g > 0.0 ? 1.0 / sqrt(g) : 0.0;
+        flg[i] = 0;
+    }
+    __syncthreads();
+    double S[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = tr + 32 * a, c = tc + 32 * b;
+            S[a][b] = (i < n && c < n && c >= i) ? G[(size_t)i * ldg + c] * scal[i] * scal[c] : 0.0;
+        }
+    for (int j = 0; j < n; ++j) {
+        // the owners of row j publish it (upper part: the trailing matrix;
+        // lower part: the row of L^{-1} built so far)
+        if (tr == (j & 31)) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                if (a == (j >> 5))
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const int c = tc + 32 * b;
+                        if (c < n) row[c] = S[a][b];
+                    }
+        }
+        __syncthreads();
+        const double p = row[j];
+        const bool dep = !(p > eta);
+        if (tid == 0) {
+            piv[j] = p;
+            flg[j] = dep ? 1 : 0;
+        }
+        if (!dep) {
+            const double inv = 1.0 / p;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const int i = tr + 32 * a;
+                if (i <= j || i >= n) continue;
+                const double l = row[i] * inv;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int c = tc + 32 * b;
+                    if (c >= n) continue;
+                    if (c >= i || c < j)
+                        S[a][b] -= l * row[c];
+                    else if (c == j)
+                        S[a][b] = -l;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    // R^{-1}[r][c] = s_r (L^{-1})[c][r] / sqrt(d_c), r <= c; thread (i, col)
+    // holds (L^{-1})[i][col] for col < i and writes element (col, i).
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = tr + 32 * a, c = tc + 32 * b;
+            if (i >= n || c >= n) continue;
+            // element (r, cc) = (c, i) of R^{-1}: needs r <= cc, i.e. c <= i
+            double v = 0.0;
+            if (c <= i && !flg[i]) {
+                const double lic = (c == i) ? 1.0 : S[a][b];
+                v = scal[c] * lic / sqrt(piv[i]);
+            }
+            Rinv[(size_t)c * n + i] = v;
+        }
+    int cnt = 0;
+    for (int i = tid; i < n; i += 1024) {
+        flags[i] = flg[i];
+        cnt += flg[i];
+    }
+    if (cnt) atomicAdd(nflag, cnt);
+}
+
 // One-sided (Hestenes) Jacobi SVD of the N x N matrix B in one workgroup.
 // Columns live column-major in global scratch (Ac, Vc). Each round of the
 // round-robin ordering pairs all columns disjointly; a group of G lanes owns
@@ -333,7 +423,10 @@ void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* fla
 {
     BLWS_REQUIRE(n >= 1 && n <= 512, BLWS_EUNSUPPORTED, "chol_inv: block width above 512");
     TimedLaunch tl(tm, "chol", s, (double)n * n * n / 3.0, 16.0 * n * n);
-    if (n <= CHOL_LDS_MAX)
+    if (n <= 128)
+        hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv, flags,
+                           nflag, eta);
+    else if (n <= CHOL_LDS_MAX)
         hipLaunchKernelGGL((chol_inv_kernel<true>), dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv,
                            flags, nflag, eta, (double*)nullptr);
     else
@@ -341,13 +434,13 @@ void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* fla
                            flags, nflag, eta, scratch);
 }
 
-size_t small_svd_scratch_elems(int N) { return 2 * (size_t)N * N; }
+size_t small_svd_jacobi_scratch_elems(int N) { return 2 * (size_t)N * N; }
 
-void small_svd(Timer* tm, int N, const double* B, int ldb, double* UB, double* S, double* VB,
-               double* scratch, hipStream_t s)
+void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, double* S,
+                      double* VB, double* scratch, hipStream_t s)
 {
     BLWS_REQUIRE(N >= 1 && N <= SVD_MAXN, BLWS_EUNSUPPORTED, "small_svd: size above 512");
-    TimedLaunch tl(tm, "small_svd", s, 10.0 * (double)N * N * N, 32.0 * N * N);
+    TimedLaunch tl(tm, "jacobi_svd", s, 10.0 * (double)N * N * N, 32.0 * N * N);
     const double tol = sqrt((double)N) * 0x1.0p-53;
     hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, N, B, ldb, UB, S, VB, scratch,
                        scratch + (size_t)N * N, tol, 60);

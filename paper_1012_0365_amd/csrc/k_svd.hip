@@ -1,0 +1,541 @@
+// SVD of the small projected matrix B (N x N, FP64) of the BLWS step, whose
+// singular values are the Ritz values (Algorithm 3 with Theorem 1).
+//
+// 1. Golub-Kahan bidiagonalisation B = Q_L Bd Q_R^T in ONE workgroup, B held
+//    in registers: a 32 x 16 thread grid, thread (tr, tc) owning rows
+//    tr + 32a and columns tc + 16c, so N <= 224. Each step
+//    is a left and a right Householder reflection; their vectors are written to
+//    global memory for the back-transformation.
+// 2. Singular values of Bd by multisection on the Golub-Kahan tridiagonal
+//    T = tridiag(0; d0, e0, d1, e1, ..., d_{N-1}) of size 2N, whose eigenvalues
+//    are +-sigma (Theorem 1 applied to the bidiagonal): one wavefront per value,
+//    64 Sturm counts per step.
+// 3. Singular vectors by inverse iteration on T - sigma I: the eigenvector is
+//    (v0, u0, v1, u1, ...), so u and v come out paired.
+// 4. Back-transformation through the stored reflectors (one workgroup per
+//    column block).
+#include "blws_common.h"
+
+namespace blws {
+namespace {
+
+constexpr int GK_MAXN = 224;
+
+// Start vectors of the inverse iteration: SplitMix64 (Steele, Lea & Flood
+// 2014) outputs mapped to [-1, 1), distinct per value so that vectors of a
+// multiple singular value start independent.
+__device__ __forceinline__ double start_pm1(uint64_t counter)
+{
+    uint64_t z = 0x5DEECE66DULL + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+constexpr int GK_LD = GK_MAXN + 1;  // padded LDS row of the partial sums
+
+// Thread (tr, tc) of the 32 x 16 grid owns rows tr + 32a (a < NPR) and
+// columns tc + 16c (c < 2 NPR): 7 x 14 doubles at N = 224, which 512 threads
+// (two wavefronts per SIMD, 256 registers each) hold without spilling.
+template <int NPR>
+__global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __restrict__ B,
+                                                        int ldb, double* __restrict__ dout,
+                                                        double* __restrict__ eout,
+                                                        double* __restrict__ VL,
+                                                        double* __restrict__ tauL,
+                                                        double* __restrict__ VR,
+                                                        double* __restrict__ tauR)
+{
+    constexpr int NPC = 2 * NPR;
+    __shared__ double part[32 * GK_LD];
+    __shared__ double sx[GK_MAXN], svl[GK_MAXN], sw[GK_MAXN];
+    __shared__ double sy[GK_MAXN], svr[GK_MAXN], sz[GK_MAXN];
+    __shared__ double stauL, stauR;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tr = tid & 31, tc = tid >> 5;
+
+    double Br[NPR][NPC];
+#pragma unroll
+    for (int a = 0; a < NPR; ++a)
+#pragma unroll
+        for (int c = 0; c < NPC; ++c) {
+            const int i = tr + 32 * a, j = tc + 16 * c;
+            Br[a][c] = (i < N && j < N) ? B[(size_t)i * ldb + j] : 0.0;
+        }
+
+    for (int k = 0; k < N; ++k) {
+        // ---- left reflector: column k, rows k..N-1
+        if (tc == (k & 15)) {
+            const int kc = k >> 4;
+#pragma unroll
+            for (int a = 0; a < NPR; ++a) {
+                const int i = tr + 32 * a;
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c < NPC; ++c)
+                    if (c == kc) v = Br[a][c];
+                if (i >= k && i < N) sx[i] = v;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const double alpha = sx[k];
+            double s2 = 0.0;
+            for (int i = k + 1 + lane; i < N; i += 64) s2 += sx[i] * sx[i];
+            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (s2 > 0.0) {
+                const double nrm = sqrt(alpha * alpha + s2);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            for (int i = k + 1 + lane; i < N; i += 64) {
+                const double v = sx[i] * scale;
+                svl[i] = v;
+                VL[(size_t)k * N + i] = v;
+            }
+            if (lane == 0) {
+                svl[k] = 1.0;
+                VL[(size_t)k * N + k] = 1.0;
+                tauL[k] = tau;
+                dout[k] = beta;
+                stauL = tau;
+            }
+        }
+        __syncthreads();
+        const double tl = stauL;
+        if (tl != 0.0) {
+            // w_j = tau * sum_{i >= k} v_i B[i][j], j > k; v_i read once per row block
+            double vi[NPR];
+#pragma unroll
+            for (int a = 0; a < NPR; ++a) {
+                const int i = tr + 32 * a;
+                vi[a] = (32 * a + 31 >= k && i >= k && i < N) ? svl[i] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                if (16 * c + 15 < k + 1) continue;  // uniform: no column > k in this block
+                const int j = tc + 16 * c;
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 0; a < NPR; ++a) {
+                    if (32 * a + 31 < k) continue;  // uniform: no row >= k in this block
+                    acc += vi[a] * Br[a][c];
+                }
+                if (j < N) part[tr * GK_LD + j] = acc;
+            }
+            __syncthreads();
+            if (tid < N && tid > k) {
+                double s = 0.0;
+                for (int r = 0; r < 32; ++r) s += part[r * GK_LD + tid];
+                sw[tid] = tl * s;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                if (16 * c + 15 < k + 1) continue;
+                const int j = tc + 16 * c;
+                const double wj = (j > k && j < N) ? sw[j] : 0.0;
+#pragma unroll
+                for (int a = 0; a < NPR; ++a) {
+                    if (32 * a + 31 < k) continue;
+                    Br[a][c] -= vi[a] * wj;
+                }
+            }
+        }
+        if (k + 1 >= N) break;
+        // ---- right reflector: row k, columns k+1..N-1
+        if (tr == (k & 31)) {
+            const int ka = k >> 5;
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                const int j = tc + 16 * c;
+                double v = 0.0;
+#pragma unroll
+                for (int a = 0; a < NPR; ++a)
+                    if (a == ka) v = Br[a][c];
+                if (j > k && j < N) sy[j] = v;
+            }
+        }
+        __syncthreads();
+        if (wave == 0) {
+            const double alpha = sy[k + 1];
+            double s2 = 0.0;
+            for (int j = k + 2 + lane; j < N; j += 64) s2 += sy[j] * sy[j];
+            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (s2 > 0.0) {
+                const double nrm = sqrt(alpha * alpha + s2);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            for (int j = k + 2 + lane; j < N; j += 64) {
+                const double v = sy[j] * scale;
+                svr[j] = v;
+                VR[(size_t)k * N + j] = v;
+            }
+            if (lane == 0) {
+                svr[k + 1] = 1.0;
+                VR[(size_t)k * N + k + 1] = 1.0;
+                tauR[k] = tau;
+                eout[k] = beta;
+                stauR = tau;
+            }
+        }
+        __syncthreads();
+        const double tq = stauR;
+        if (tq != 0.0) {
+            // z_i = tau * sum_{j > k} B[i][j] v_j, i > k: column-outer loops so
+            // that only one accumulator per row block stays live
+            double acc[NPR];
+#pragma unroll
+            for (int a = 0; a < NPR; ++a) acc[a] = 0.0;
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                if (16 * c + 15 < k + 1) continue;
+                const int j = tc + 16 * c;
+                const double vj = (j > k && j < N) ? svr[j] : 0.0;
+#pragma unroll
+                for (int a = 0; a < NPR; ++a) {
+                    if (32 * a + 31 < k + 1) continue;
+                    acc[a] += Br[a][c] * vj;
+                }
+            }
+#pragma unroll
+            for (int a = 0; a < NPR; ++a) {
+                if (32 * a + 31 < k + 1) continue;
+                const int i = tr + 32 * a;
+                if (i < N) part[tc * GK_LD + i] = acc[a];
+            }
+            __syncthreads();
+            if (tid < N && tid > k) {
+                double sum = 0.0;
+                for (int t = 0; t < 16; ++t) sum += part[t * GK_LD + tid];
+                sz[tid] = tq * sum;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < NPR; ++a) {
+                const int i = tr + 32 * a;
+                acc[a] = (32 * a + 31 >= k + 1 && i > k && i < N) ? sz[i] : 0.0;
+            }
+#pragma unroll
+            for (int c = 0; c < NPC; ++c) {
+                if (16 * c + 15 < k + 1) continue;
+                const int j = tc + 16 * c;
+                const double vj = (j > k && j < N) ? svr[j] : 0.0;
+#pragma unroll
+                for (int a = 0; a < NPR; ++a) {
+                    if (32 * a + 31 < k + 1) continue;
+                    Br[a][c] -= acc[a] * vj;
+                }
+            }
+        }
+    }
+}
+
+// Number of singular values of the bidiagonal (d, e) that are >= x (x > 0),
+// from the Sturm count of the Golub-Kahan tridiagonal T (zero diagonal,
+// off-diagonals f2 squared): #{eig(T) < x} = N + #{sigma < x}. The LDL^T
+// recurrence q_j = -x - f_{j-1}^2 / q_{j-1} counts negative pivots.
+__device__ int count_ge(int N, const double* f2, double x, double pivmin)
+{
+    int neg = 0;
+    double q = -x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    neg += q < 0.0;
+    for (int j = 1; j < 2 * N; ++j) {
+        q = -x - f2[j - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        neg += q < 0.0;
+    }
+    return 2 * N - neg;  // = N - #{sigma < x}
+}
+
+// One wavefront per singular value: sigma_t, the t-th largest, by multisection.
+__global__ __launch_bounds__(64) void tgk_bisect_kernel(int N, const double* __restrict__ d,
+                                                        const double* __restrict__ e,
+                                                        double* __restrict__ sig)
+{
+    __shared__ double f2[2 * GK_MAXN];
+    __shared__ int cnt[64];
+    const int t = blockIdx.x, lane = threadIdx.x;
+    double bound = 0.0, fmax2 = 0.0;
+    for (int j = lane; j < 2 * N - 1; j += 64) {
+        const double f = (j & 1) ? e[j >> 1] : d[j >> 1];
+        f2[j] = f * f;
+    }
+    __syncthreads();
+    for (int j = 0; j < 2 * N - 1; ++j) fmax2 = fmax(fmax2, f2[j]);
+    // Gershgorin bound of T: max_j |f_{j-1}| + |f_j|
+    for (int j = 0; j < 2 * N; ++j) {
+        const double l = j > 0 ? sqrt(f2[j - 1]) : 0.0;
+        const double r = j < 2 * N - 1 ? sqrt(f2[j]) : 0.0;
+        bound = fmax(bound, l + r);
+    }
+    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, fmax2);
+    double lo = 0.0, hi = bound * (1.0 + 4.0 * 0x1.0p-52) + pivmin;
+    // invariant: #{sigma >= lo} >= t + 1 (lo = 0 counts every value), #{sigma >= hi} <= t
+    for (int step = 0; step < 14; ++step) {
+        // relative precision 2u, or absolute u * ||T|| for values near zero
+        if (hi - lo <= 2.0 * 0x1.0p-52 * fmax(fabs(lo), fabs(hi)) + pivmin ||
+            hi - lo <= 0x1.0p-52 * bound)
+            break;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        cnt[lane] = count_ge(N, f2, x, pivmin);
+        __syncthreads();
+        // largest point still holding >= t + 1 values
+        int best = -1;
+        for (int l = 0; l < 64; ++l)
+            if (cnt[l] >= t + 1) best = l;
+        const double nlo = best >= 0 ? lo + (hi - lo) * (double)(best + 1) / 65.0 : lo;
+        const double nhi = best < 63 ? lo + (hi - lo) * (double)(best + 2) / 65.0 : hi;
+        lo = nlo;
+        hi = nhi;
+        __syncthreads();
+    }
+    // a value the bracket cannot separate from zero is reported as zero
+    const bool zero = lo == 0.0 && hi <= 8.0 * 0x1.0p-52 * bound + 4.0 * pivmin;
+    if (lane == 0) sig[t] = zero ? 0.0 : 0.5 * (lo + hi);
+}
+
+// Inverse iteration for the eigenvector of T at +sigma_t: LU factorisation
+// with partial pivoting of the tridiagonal T - sigma I (row interchanges give
+// U a second superdiagonal), then three solves from a fixed +-1 start vector,
+// normalising each time. The eigenvector z = (v0, u0, v1, u1, ...) splits into
+// the bidiagonal's right and left singular vectors. Work arrays live in LDS;
+// one wavefront per value, the sequential recurrences on lane 0.
+__global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __restrict__ d,
+                                                       const double* __restrict__ e,
+                                                       const double* __restrict__ sig,
+                                                       double* __restrict__ ubd,
+                                                       double* __restrict__ vbd, int ldv)
+{
+    __shared__ double f[2 * GK_MAXN];
+    __shared__ double z[2 * GK_MAXN], dl[2 * GK_MAXN], dd[2 * GK_MAXN], du[2 * GK_MAXN],
+        du2[2 * GK_MAXN];
+    __shared__ unsigned char swp[2 * GK_MAXN];
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const int n = 2 * N;
+    for (int j = lane; j < n - 1; j += 64) f[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
+    __syncthreads();
+    if (lane == 0) {
+        const double s = sig[t];
+        double fm = fabs(s);
+        for (int j = 0; j < n - 1; ++j) fm = fmax(fm, fabs(f[j]));
+        const double tiny = fm * 0x1.0p-52 + 1e-300;
+        for (int j = 0; j < n; ++j) {
+            dd[j] = -s;
+            if (j < n - 1) {
+                dl[j] = f[j];
+                du[j] = f[j];
+            }
+            if (j < n - 2) du2[j] = 0.0;
+        }
+        for (int j = 0; j < n - 1; ++j) {
+            if (fabs(dd[j]) >= fabs(dl[j])) {
+                swp[j] = 0;
+                const double fact = dd[j] != 0.0 ? dl[j] / dd[j] : 0.0;
+                dl[j] = fact;
+                dd[j + 1] -= fact * du[j];
+                if (j < n - 2) du2[j] = 0.0;
+            } else {
+                swp[j] = 1;
+                const double fact = dd[j] / dl[j];
+                dd[j] = dl[j];
+                dl[j] = fact;
+                const double tmp = du[j];
+                du[j] = dd[j + 1];
+                dd[j + 1] = tmp - fact * dd[j + 1];
+                if (j < n - 2) {
+                    du2[j] = du[j + 1];
+                    du[j + 1] = -fact * du[j + 1];
+                }
+            }
+        }
+        for (int j = 0; j < n; ++j)
+            if (fabs(dd[j]) < tiny) dd[j] = dd[j] < 0.0 ? -tiny : tiny;
+        for (int j = 0; j < n; ++j)
+            z[j] = start_pm1((uint64_t)t * 4096ULL + (uint64_t)j);
+        for (int it = 0; it < 2; ++it) {
+            for (int j = 0; j < n - 1; ++j) {
+                if (!swp[j]) {
+                    z[j + 1] -= dl[j] * z[j];
+                } else {
+                    const double tmp = z[j];
+                    z[j] = z[j + 1];
+                    z[j + 1] = tmp - dl[j] * z[j];
+                }
+            }
+            z[n - 1] /= dd[n - 1];
+            if (n >= 2) z[n - 2] = (z[n - 2] - du[n - 2] * z[n - 1]) / dd[n - 2];
+            for (int j = n - 3; j >= 0; --j)
+                z[j] = (z[j] - du[j] * z[j + 1] - du2[j] * z[j + 2]) / dd[j];
+            double mx = 0.0;
+            for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(z[j]));
+            const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
+            for (int j = 0; j < n; ++j) z[j] *= inv;
+        }
+    }
+    __syncthreads();
+    // split and normalise each half to unit length
+    double nu = 0.0, nv = 0.0;
+    for (int i = lane; i < N; i += 64) {
+        nv += z[2 * i] * z[2 * i];
+        nu += z[2 * i + 1] * z[2 * i + 1];
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        nu += __shfl_xor(nu, off, 64);
+        nv += __shfl_xor(nv, off, 64);
+    }
+    nu = nu > 0.0 ? 1.0 / sqrt(nu) : 0.0;
+    nv = nv > 0.0 ? 1.0 / sqrt(nv) : 0.0;
+    for (int i = lane; i < N; i += 64) {
+        vbd[(size_t)i * ldv + t] = z[2 * i] * nv;
+        ubd[(size_t)i * ldv + t] = z[2 * i + 1] * nu;
+    }
+}
+
+// X (N x nv, ld) <- H_0 H_1 ... H_{nref-1} X for reflectors stored column-wise
+// in Vh (column k: entries k+off .. N-1, unit at k+off), tau[k]. One wavefront
+// per column of X (four per workgroup), the column in registers (N <= 256);
+// reflectors staged through LDS 16 at a time, applied last to first.
+constexpr int RCH = 16;
+__global__ __launch_bounds__(256) void reflect_apply_kernel(int N, int nref, int off,
+                                                            const double* __restrict__ Vh,
+                                                            const double* __restrict__ tau,
+                                                            double* __restrict__ X, int ldx,
+                                                            int nv)
+{
+    __shared__ double vs[RCH][GK_MAXN];
+    __shared__ double ts[RCH];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = blockIdx.x * 4 + wave;
+    double xr[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int i = lane + 64 * r;
+        xr[r] = (col < nv && i < N) ? X[(size_t)i * ldx + col] : 0.0;
+    }
+    for (int k1 = nref - 1; k1 >= 0; k1 -= RCH) {
+        const int k0 = k1 - RCH + 1 < 0 ? 0 : k1 - RCH + 1;
+        const int cnt = k1 - k0 + 1;
+        __syncthreads();
+        for (int e = tid; e < cnt * N; e += 256) {
+            const int q = e / N, i = e - q * N;
+            const int k = k0 + q;
+            vs[q][i] = (i >= k + off) ? Vh[(size_t)k * N + i] : 0.0;
+        }
+        if (tid < cnt) ts[tid] = tau[k0 + tid];
+        __syncthreads();
+        for (int q = cnt - 1; q >= 0; --q) {
+            const double tk = ts[q];
+            if (tk == 0.0) continue;
+            double dot = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = lane + 64 * r;
+                if (i < N) dot += vs[q][i] * xr[r];
+            }
+            for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
+            const double w = tk * dot;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = lane + 64 * r;
+                if (i < N) xr[r] -= vs[q][i] * w;
+            }
+        }
+    }
+    if (col < nv) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int i = lane + 64 * r;
+            if (i < N) X[(size_t)i * ldx + col] = xr[r];
+        }
+    }
+}
+
+// Sign convention: the largest-magnitude entry of each left vector positive
+// (the right vector flips with it).
+__global__ void sign_fix_kernel(int N, int nv, double* UB, double* VB, int ld)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nv) return;
+    int imax = 0;
+    double vmax = 0.0;
+    for (int i = 0; i < N; ++i) {
+        const double a = fabs(UB[(size_t)i * ld + t]);
+        if (a > vmax) {
+            vmax = a;
+            imax = i;
+        }
+    }
+    if (UB[(size_t)imax * ld + t] < 0.0)
+        for (int i = 0; i < N; ++i) {
+            UB[(size_t)i * ld + t] = -UB[(size_t)i * ld + t];
+            VB[(size_t)i * ld + t] = -VB[(size_t)i * ld + t];
+        }
+}
+
+}  // namespace
+
+bool small_svd_gk_supported(int N) { return N >= 2 && N <= GK_MAXN; }
+
+size_t small_svd_gk_scratch_elems(int N)
+{
+    // d, e, tauL, tauR and the reflector vectors VL, VR
+    return 4 * (size_t)N + 2 * (size_t)N * N;
+}
+
+// Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
+void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
+                  double* VB, double* scratch, hipStream_t s)
+{
+    BLWS_REQUIRE(small_svd_gk_supported(N) && nv >= 1 && nv <= N, BLWS_EUNSUPPORTED,
+                 "small_svd_gk: size out of range");
+    double* d = scratch;
+    double* e = d + N;
+    double* tL = e + N;
+    double* tR = tL + N;
+    double* VL = tR + N;
+    double* VR = VL + (size_t)N * N;
+    {
+        TimedLaunch tl(tm, "gk_bidiag", s, 8.0 / 3.0 * N * (double)N * N, 16.0 * N * N);
+        const int NP = (N + 31) / 32;
+#define BLWS_GK_CASE(P)                                                                      \
+    case P:                                                                                  \
+        hipLaunchKernelGGL((gk_bidiag_kernel<P>), dim3(1), dim3(512), 0, s, N, B, ldb, d, e, VL, \
+                           tL, VR, tR);                                                      \
+        break;
+        switch (NP) {
+            BLWS_GK_CASE(1)
+            BLWS_GK_CASE(2)
+            BLWS_GK_CASE(3)
+            BLWS_GK_CASE(4)
+            BLWS_GK_CASE(5)
+            BLWS_GK_CASE(6)
+            default:
+                BLWS_GK_CASE(7)
+        }
+#undef BLWS_GK_CASE
+    }
+    {
+        TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
+        hipLaunchKernelGGL(tgk_bisect_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S);
+        hipLaunchKernelGGL(tgk_invit_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S, UB, VB, N);
+    }
+    {
+        TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
+        const int blocks = (nv + 3) / 4;
+        hipLaunchKernelGGL(reflect_apply_kernel, dim3(blocks), dim3(256), 0, s, N, N, 0, VL, tL,
+                           UB, N, nv);
+        hipLaunchKernelGGL(reflect_apply_kernel, dim3(blocks), dim3(256), 0, s, N, N - 1, 1, VR,
+                           tR, VB, N, nv);
+        hipLaunchKernelGGL(sign_fix_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, N, nv, UB, VB,
+                           N);
+    }
+}
+
+}  // namespace blws
