@@ -115,6 +115,32 @@ int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
                     int ldd, double lambda, const blws_alm_opts* opts, void* A, int lda,
                     void* E, int lde, blws_solve_info* info);
 
+/* Defaults of the matrix-completion solver: those of blws_default_alm_opts
+ * with tol = 1e-6, rho = 1.1 and mu0_scale = 1.0 (mu_0 = 1/||P_Omega(M)||_2). */
+void blws_default_mc_opts(blws_alm_opts* opts);
+
+/* Matrix completion: min ||A||_* s.t. P_Omega(A) = P_Omega(M), by inexact ALM
+ * (Sec. 2, Eq. (2) and its ALM host, Sec. 5) with one BLWS step per iteration.
+ * The matrix W = A + P_Omega(D + Y/mu - A) whose SVT each iteration takes is
+ * low rank plus sparse and is applied to blocks without being formed.
+ *   Omega and the samples: CSR on the device, row_ptr (int32[m + 1]),
+ *   col_idx (int32[nnz]), values (nnz, type of prec; both may be NULL when
+ *   nnz = 0, which returns rank 0). Columns within a row may
+ *   come in any order; row_ptr must be nondecreasing from 0 to nnz and every
+ *   column index in [0, n), else BLWS_EINVAL (checked on the device before
+ *   any other use). Read only.
+ *   Output: A = U diag(S) V^T with rank r = info->rank; the first
+ *   min(r, r_cap) columns of U (m x r_cap, ldu >= r_cap), V (n x r_cap,
+ *   ldv >= r_cap) and entries of S (device double[r_cap]) are written.
+ *   Stop at ||P_Omega(M) - P_Omega(A)||_F / ||P_Omega(M)||_F < tol.
+ *   opts may be NULL (blws_default_mc_opts); info is a HOST struct (may be
+ *   NULL). prec: BLWS_FP64 or BLWS_FP32. Blocks until the result is complete.
+ * Returns BLWS_OK, BLWS_NOT_CONVERGED, or an error. */
+int blws_mc_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
+                  const int* row_ptr, const int* col_idx, const void* values,
+                  const blws_alm_opts* opts, int r_cap, void* U, int ldu, double* S, void* V,
+                  int ldv, blws_solve_info* info);
+
 /* ---------------------------------------------------------------------- */
 /* Diagnostics (used by the parity tests and the bench).                   */
 /* ---------------------------------------------------------------------- */

@@ -7,6 +7,7 @@ and the current HIP stream; every computation runs in the library's kernels.
     import torch, paper_1012_0365_amd as blws
     ctx = blws.Context()
     A, E, info = ctx.rpca_solve(D)                 # robust PCA (inexact ALM + BLWS)
+    U, S, V, info = ctx.mc_solve(m, n, row_ptr, col_idx, values)  # matrix completion
     S, rank = ctx.svt(W, eps, U, V, A=A_out)       # one BLWS SVT step, U/V updated in place
 """
 
@@ -17,7 +18,8 @@ import ctypes
 from . import _native
 from ._native import AlmOpts, BlwsError, SolveInfo, SvtOpts
 
-__all__ = ["Context", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo", "default_alm_opts"]
+__all__ = ["Context", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo", "default_alm_opts",
+           "default_mc_opts"]
 
 
 def _torch():
@@ -46,6 +48,16 @@ def _check_mat(t, name: str):
 def default_alm_opts(**kw) -> AlmOpts:
     o = AlmOpts()
     _native.lib().blws_default_alm_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def default_mc_opts(**kw) -> AlmOpts:
+    o = AlmOpts()
+    _native.lib().blws_default_mc_opts(ctypes.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
@@ -131,6 +143,35 @@ class Context:
             A.data_ptr(), lda, E.data_ptr(), lde, ctypes.byref(info))
         self._check(st)
         return A, E, info.as_dict()
+
+    # -- matrix completion -----------------------------------------------------
+    def mc_solve(self, m: int, n: int, row_ptr, col_idx, values, opts: AlmOpts | None = None,
+                 r_cap: int = 256):
+        """min ||A||_* s.t. A agrees with the samples on Omega (CSR: row_ptr int32[m+1],
+        col_idx int32[nnz], values float64/float32[nnz], all device tensors), by
+        inexact ALM with BLWS. Returns (U, S, V, info) with A = U diag(S) V^T."""
+        torch = _torch()
+        prec = _prec_of(values)
+        for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx"), (values, "values")):
+            if not t.is_cuda or t.dim() != 1 or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous 1-D device tensor")
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr and col_idx must be int32")
+        if row_ptr.numel() != m + 1 or col_idx.numel() != values.numel():
+            raise ValueError("row_ptr must hold m + 1 entries and col_idx one per value")
+        nnz = values.numel()
+        U = torch.zeros(m, r_cap, dtype=values.dtype, device=values.device)
+        V = torch.zeros(n, r_cap, dtype=values.dtype, device=values.device)
+        S = torch.zeros(r_cap, dtype=torch.float64, device=values.device)
+        info = SolveInfo()
+        st = self._lib.blws_mc_solve(
+            self.handle, self._stream(), prec, m, n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
+            values.data_ptr(), ctypes.byref(opts) if opts is not None else None, r_cap,
+            U.data_ptr(), r_cap, S.data_ptr(), V.data_ptr(), r_cap, ctypes.byref(info))
+        self._check(st)
+        d = info.as_dict()
+        r = min(d["rank"], r_cap)
+        return U[:, :r], S[:r], V[:, :r], d
 
     # -- diagnostics -----------------------------------------------------------
     def fill_uniform(self, X, seed: int, stream_id: int):

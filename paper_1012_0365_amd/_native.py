@@ -72,6 +72,9 @@ SIGNATURES = {
                       _i, ctypes.POINTER(SvtOpts)]),
     "blws_rpca_solve": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, ctypes.POINTER(AlmOpts), _vp, _i,
                              _vp, _i, ctypes.POINTER(SolveInfo)]),
+    "blws_default_mc_opts": (None, [ctypes.POINTER(AlmOpts)]),
+    "blws_mc_solve": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp, ctypes.POINTER(AlmOpts), _i,
+                           _vp, _i, _vp, _vp, _i, ctypes.POINTER(SolveInfo)]),
     "blws_fill_uniform": (_i, [_vp, _vp, _i, _i, _vp, _i, _ull, _ull]),
     "blws_gemm_f64": (_i, [_vp, _vp, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i]),
     "blws_small_svd_f64": (_i, [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp]),

@@ -84,13 +84,15 @@ void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, do
 size_t small_svd_jacobi_scratch_elems(int N);
 
 // Golub-Kahan bidiagonalisation + bisection / inverse iteration on the
-// Golub-Kahan tridiagonal (N <= 224): the top nv singular values S[0..nv) and
+// Golub-Kahan tridiagonal (N <= 512): the top nv singular values S[0..nv) and
 // the first nv columns of UB, VB (N x N, ld N). The vectors of close values are
-// not yet orthogonalised (the caller polishes them).
+// not yet orthogonalised (the caller polishes them). Above N = 224 the
+// bidiagonalisation is a cooperative launch; *err (device int, zeroed by the
+// caller) is set if one of its barrier waits timed out.
 bool small_svd_gk_supported(int N);
 size_t small_svd_gk_scratch_elems(int N);
 void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
-                  double* VB, double* scratch, hipStream_t s);
+                  double* VB, double* scratch, int* err, hipStream_t s);
 
 // Copy a rows x cols block (types may differ).
 template <typename TS, typename TD>
@@ -134,5 +136,38 @@ void sum_partials(int count, const double* partials, double* out, hipStream_t s)
 template <typename T>
 void count_nonzeros(int m, int n, const T* X, int ldx, long long* out, long long* scratch,
                     hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Matrix-completion operator (k_sparse.hip).
+// ---------------------------------------------------------------------------
+
+// flag[0] = 0, then |= 1 if row_ptr is not nondecreasing from 0 to nnz, |= 2 if
+// a column index lies outside [0, n).
+void csr_check(int m, int n, int nnz, const int* row_ptr, const int* col_idx, int* flag,
+               hipStream_t s);
+// Transposed pattern: col_ptr (n + 1), csc_row / csc_perm (nnz): for position
+// q of column j, the row and the CSR index of the entry, rows ascending.
+// maxcnt[0] = longest column. scratch >= csc_scratch_ints(n, nnz) ints.
+size_t csc_scratch_ints(int n, int nnz);
+void csc_build(int m, int n, int nnz, const int* row_ptr, const int* col_idx, int* col_ptr,
+               int* csc_row, int* csc_perm, int* maxcnt, int* scratch, hipStream_t s);
+// out (rows x c, ldo) = sparse (rows, pattern ptr/idx, values val or val[perm]) * X.
+template <typename T>
+void spmm(Timer* tm, const char* family, int rows, int c, const int* ptr, const int* idx,
+          const int* perm, const T* val, const T* X, int ldx, T* out, int ldo, long long nnz,
+          hipStream_t s);
+// Row k of C (r x c) times S[k] - eps.
+void lr_scale(int r, int c, const double* S, double eps, double* C, int ldc, hipStream_t s);
+// Fused update over Omega (A_Omega from the factors, multiplier, residual,
+// next sparse part); partials has mc_partials(m) entries.
+size_t mc_partials(int m);
+template <typename T>
+void mc_update(Timer* tm, int m, long long nnz, const int* row_ptr, const int* col_idx,
+               const T* d, T* y, T* sv, const T* U, int ldu, const T* V, int ldv, const double* S,
+               double eps, const int* rank_dev, int rmax, double mu, double mu_next,
+               double* partials, hipStream_t s);
+template <typename T>
+void mc_init(long long nnz, const T* d, T* y, T* sv, hipStream_t s);
+void theta_out(int r, const double* S, double eps, double* Sout, hipStream_t s);
 
 }  // namespace blws

@@ -1,5 +1,6 @@
 // Host side of libblws: workspace, the BLWS step, the inexact-ALM RPCA loop,
 // kernel timing and the C ABI declared in include/blws.h.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -154,25 +155,55 @@ struct StepWs {
     }
 };
 
-// Orthonormalise `In` (rows x c) against the orthonormal block X (rows x b0,
-// may be null) into Out: the QR step of the block Lanczos procedure
-// (Algorithm 2) by two Cholesky-QR passes, X projected out before each.
+// Scratch of one orthonormalisation: T1, T2 (rows x 128), Cp (b x 128, b the
+// widest block projected against), Gr, Ri (128 x 128), the Cholesky scratch,
+// the breakdown flags (nflag[0] counts them) and the split-K partials.
+template <typename T>
+struct OrthWs {
+    T *T1, *T2;
+    double *Cp, *Gr, *Ri, *chol, *partial;
+    size_t partial_elems;
+    int *flags, *nflag;
+};
+
+constexpr int ORTH_CHUNK = 128;  // widest Cholesky-QR block (register Cholesky)
+
+// dst (rows x c, ld c) = src minus its components in span(X_0), span(X_1), ...,
+// block after block (each X_q rows x bx[q], orthonormal columns).
+template <typename T>
+void project_out(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx,
+                 const T* const* X, const int* ldx, const int* bx, const T* src, int lds, T* dst,
+                 int c)
+{
+    Timer* tm = &cx.timer;
+    if (nx == 0) {
+        copy2d<T, T>(rows, c, src, lds, dst, c, s);
+        return;
+    }
+    const T* cur = src;
+    int ldcur = lds;
+    for (int q = 0; q < nx; ++q) {
+        gemm<T, T, double>(tm, "gemm_ts", true, bx[q], c, rows, 1.0, X[q], ldx[q], cur, ldcur, 0.0,
+                           (const double*)nullptr, 0, w.Cp, c, w.partial, w.partial_elems, s);
+        gemm<T, double, T>(tm, "gemm_ts", false, rows, c, bx[q], -1.0, X[q], ldx[q], w.Cp, c, 1.0,
+                           cur, ldcur, dst, c, w.partial, w.partial_elems, s);
+        cur = dst;
+        ldcur = c;
+    }
+}
+
+// One block of at most ORTH_CHUNK columns: project In out of the X blocks,
+// then two Cholesky-QR passes, the X blocks projected out again between them.
 // Columns found dependent in the first pass are replaced by counter-based
 // random draws, which the second projection and pass orthonormalise.
 template <typename T>
-void orth_against(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b0, const T* X,
-                  int ldx, const T* In, int ldin, int c, T* Out, int ldout, uint64_t seed)
+void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx,
+                const T* const* X, const int* ldx, const int* bx, const T* In, int ldin, int c,
+                T* Out, int ldout, uint64_t seed)
 {
     Timer* tm = &cx.timer;
+    project_out<T>(cx, w, s, rows, nx, X, ldx, bx, In, ldin, w.T1, c);
     T* cur = w.T1;
-    if (X) {
-        gemm<T, T, double>(tm, "gemm_ts", true, b0, c, rows, 1.0, X, ldx, In, ldin, 0.0,
-                           (const double*)nullptr, 0, w.Cp, c, w.partial, w.partial_elems, s);
-        gemm<T, double, T>(tm, "gemm_ts", false, rows, c, b0, -1.0, X, ldx, w.Cp, c, 1.0, In,
-                           ldin, cur, c, w.partial, w.partial_elems, s);
-    } else {
-        copy2d<T, T>(rows, c, In, ldin, cur, c, s);
-    }
     for (int pass = 0; pass < 2; ++pass) {
         gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, cur, c, cur, c, 0.0,
                            (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
@@ -183,12 +214,8 @@ void orth_against(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b0, co
                            (const T*)nullptr, 0, dst, ldd, w.partial, w.partial_elems, s);
         if (pass == 0) {
             fill_flagged<T>(rows, c, w.T2, c, w.flags, seed, (1ULL << 20) + (++cx.fix_calls), s);
-            if (X) {
-                gemm<T, T, double>(tm, "gemm_ts", true, b0, c, rows, 1.0, X, ldx, w.T2, c, 0.0,
-                                   (const double*)nullptr, 0, w.Cp, c, w.partial,
-                                   w.partial_elems, s);
-                gemm<T, double, T>(tm, "gemm_ts", false, rows, c, b0, -1.0, X, ldx, w.Cp, c, 1.0,
-                                   w.T2, c, w.T1, c, w.partial, w.partial_elems, s);
+            if (nx > 0) {
+                project_out<T>(cx, w, s, rows, nx, X, ldx, bx, w.T2, c, w.T1, c);
                 cur = w.T1;
             } else {
                 cur = w.T2;
@@ -197,51 +224,115 @@ void orth_against(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b0, co
     }
 }
 
-// Two Cholesky-QR passes on the FP64 columns X (rows x c, ldx) in place;
-// dependent columns (scaled pivot <= CHOL_ETA) are replaced by random draws.
-void cholqr2_f64(Context& cx, hipStream_t s, int rows, int c, double* X, int ldx, double* T1,
-                 double* Gr, double* Ri, int* flags, int* nflag, double* chol_scratch,
-                 double* partial, size_t partial_elems, uint64_t seed)
+// Orthonormalise `In` (rows x c, ldin) against the orthonormal block X (rows x b0,
+// may be null) into Out: the QR step of the block Lanczos procedure
+// (Algorithm 2). Blocks of ORTH_CHUNK columns are orthonormalised in turn,
+// each against X and the blocks before it (block Gram-Schmidt), so that every
+// Cholesky factorisation is at most ORTH_CHUNK wide. In may equal Out.
+template <typename T>
+void orth_against(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int b0, const T* X,
+                  int ldx, const T* In, int ldin, int c, T* Out, int ldout, uint64_t seed)
 {
-    Timer* tm = &cx.timer;
-    for (int pass = 0; pass < 2; ++pass) {
-        const double* src = pass == 0 ? X : T1;
-        const int lds = pass == 0 ? ldx : c;
-        gemm<double, double, double>(tm, "gemm_ts", true, c, c, rows, 1.0, src, lds, src, lds, 0.0,
-                                     (const double*)nullptr, 0, Gr, c, partial, partial_elems, s);
-        chol_inv(tm, c, Gr, c, Ri, flags, nflag, CHOL_ETA, chol_scratch, s);
-        double* dst = pass == 0 ? T1 : X;
-        const int ldd = pass == 0 ? c : ldx;
-        gemm<double, double, double>(tm, "gemm_ts", false, rows, c, c, 1.0, src, lds, Ri, c, 0.0,
-                                     (const double*)nullptr, 0, dst, ldd, partial, partial_elems,
-                                     s);
-        if (pass == 0)
-            fill_flagged<double>(rows, c, T1, c, flags, seed, (1ULL << 20) + (++cx.fix_calls), s);
+    for (int c0 = 0; c0 < c; c0 += ORTH_CHUNK) {
+        const int cc = (c - c0) < ORTH_CHUNK ? (c - c0) : ORTH_CHUNK;
+        const T* Xs[2];
+        int lds[2], bs[2], nx = 0;
+        if (X && b0 > 0) {
+            Xs[nx] = X;
+            lds[nx] = ldx;
+            bs[nx++] = b0;
+        }
+        if (c0 > 0) {
+            Xs[nx] = Out;
+            lds[nx] = ldout;
+            bs[nx++] = c0;
+        }
+        orth_chunk<T>(cx, w, s, rows, nx, Xs, lds, bs, In + c0, ldin, cc, Out + c0, ldout, seed);
     }
 }
 
-// SVD of the small projected matrix: the top nv values and vectors. Sizes up
-// to 224 use the Golub-Kahan path, whose leading vectors are then polished to
-// orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
-// values only nearly orthogonal); larger ones the one-sided Jacobi kernel.
-struct SvdScratch {
-    double *svd, *T1, *Gr, *Ri, *chol, *partial;
-    int *flags, *nflag;
-    size_t partial_elems;
-};
+template <typename T>
+void orth_against(Context& cx, StepWs<T>& sw, hipStream_t s, int rows, int b0, const T* X,
+                  int ldx, const T* In, int ldin, int c, T* Out, int ldout, uint64_t seed)
+{
+    const OrthWs<T> w{sw.T1, sw.T2, sw.Cp, sw.Gr, sw.Ri, sw.chol, sw.partial, sw.partial_elems,
+                      sw.flags, sw.nflag};
+    orth_against<T>(cx, w, s, rows, b0, X, ldx, In, ldin, c, Out, ldout, seed);
+}
 
+// SVD of the small projected matrix: the top nv values and vectors, by the
+// Golub-Kahan path (N <= 512), whose leading vectors are then polished to
+// orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
+// values only nearly orthogonal). The one-sided Jacobi kernel serves larger N.
+// nflag[1] is set if the cooperative bidiagonalisation timed out.
 void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double* B, int ldb,
-                        double* UB, double* S, double* VB, const SvdScratch& w, uint64_t seed)
+                        double* UB, double* S, double* VB, double* svd_scratch,
+                        const OrthWs<double>& w, uint64_t seed)
 {
     TimedLaunch tl(&cx.timer, "small_svd", s, 0.0, 0.0);
     if (small_svd_gk_supported(N)) {
-        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, w.svd, s);
-        cholqr2_f64(cx, s, N, nv, UB, N, w.T1, w.Gr, w.Ri, w.flags, w.nflag, w.chol, w.partial,
-                    w.partial_elems, seed);
-        cholqr2_f64(cx, s, N, nv, VB, N, w.T1, w.Gr, w.Ri, w.flags, w.nflag, w.chol, w.partial,
-                    w.partial_elems, seed);
+        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s);
+        orth_against<double>(cx, w, s, N, 0, nullptr, 0, UB, N, nv, UB, N, seed);
+        orth_against<double>(cx, w, s, N, 0, nullptr, 0, VB, N, nv, VB, N, seed);
     } else {
-        small_svd_jacobi(&cx.timer, N, B, ldb, UB, S, VB, w.svd, s);
+        small_svd_jacobi(&cx.timer, N, B, ldb, UB, S, VB, svd_scratch, s);
+    }
+}
+
+// The matrix whose SVT is taken, seen only through its products with blocks.
+// Dense (RPCA: W stored), or low rank plus sparse (matrix completion:
+// W = Ul diag(S - eps) Vl^T + S_Omega with the low-rank part of rank r, never
+// formed).
+template <typename T>
+struct McOp {
+    int nnz = 0;
+    const int *row_ptr = nullptr, *col_idx = nullptr;                   // CSR pattern
+    const int *col_ptr = nullptr, *csc_row = nullptr, *csc_perm = nullptr;  // transposed
+    const T* sval = nullptr;  // sparse part, CSR order
+    int r = 0;                // rank of the low-rank part
+    const T *Ul = nullptr, *Vl = nullptr;
+    int ldl = 0;
+    const double* S = nullptr;  // theta_k = S[k] - eps
+    double eps = 0.0;
+    double* coef = nullptr;  // r x c scratch
+};
+
+template <typename T>
+struct Op {
+    const T* W = nullptr;
+    int ldw = 0;
+    const McOp<T>* mc = nullptr;
+};
+
+// out (rows x c) = W X (trans = false: X is n x c, rows = m) or W^T X
+// (trans = true: X is m x c, rows = n).
+template <typename T>
+void op_apply(Context& cx, StepWs<T>& w, hipStream_t s, const Op<T>& op, int m, int n,
+              bool trans, const T* X, int ldx, int c, T* out, int ldo)
+{
+    Timer* tm = &cx.timer;
+    const int rows = trans ? n : m, inner = trans ? m : n;
+    if (op.W) {
+        gemm<T, T, T>(tm, "gemm_w", trans, rows, c, inner, 1.0, op.W, op.ldw, X, ldx, 0.0,
+                      (const T*)nullptr, 0, out, ldo, w.partial, w.partial_elems, s);
+        return;
+    }
+    const McOp<T>& mc = *op.mc;
+    if (!trans)
+        spmm<T>(tm, "spmm", m, c, mc.row_ptr, mc.col_idx, nullptr, mc.sval, X, ldx, out, ldo,
+                mc.nnz, s);
+    else
+        spmm<T>(tm, "spmm", n, c, mc.col_ptr, mc.csc_row, mc.csc_perm, mc.sval, X, ldx, out, ldo,
+                mc.nnz, s);
+    if (mc.r > 0) {
+        // W X = Ul (theta o (Vl^T X)) + S X;  W^T X = Vl (theta o (Ul^T X)) + S^T X
+        const T* L = trans ? mc.Ul : mc.Vl;
+        const T* Rf = trans ? mc.Vl : mc.Ul;
+        gemm<T, T, double>(tm, "gemm_lr", true, mc.r, c, inner, 1.0, L, mc.ldl, X, ldx, 0.0,
+                           (const double*)nullptr, 0, mc.coef, c, w.partial, w.partial_elems, s);
+        lr_scale(mc.r, c, mc.S, mc.eps, mc.coef, c, s);
+        gemm<T, double, T>(tm, "gemm_lr", false, rows, c, mc.r, 1.0, Rf, mc.ldl, mc.coef, c, 1.0,
+                           out, ldo, out, ldo, w.partial, w.partial_elems, s);
     }
 }
 
@@ -255,7 +346,7 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
 // [[0, B], [B^T, 0]] with B = [U, F]^T W [V, G] = [U, F]^T [W V, W G], whose
 // SVD gives the Ritz values and vectors.
 template <typename T>
-void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const T* W, int ldw,
+void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
               double eps, int b, T* U, int ldu, T* V, int ldv, double* S, int* rank_dev,
               uint64_t seed)
 {
@@ -264,23 +355,20 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const T* W
     copy2d<T, T>(m, b, U, ldu, w.UF, b2, s);
     copy2d<T, T>(n, b, V, ldv, w.VG, b2, s);
     // products with the start block: P = W V, Q = W^T U
-    gemm<T, T, T>(tm, "gemm_w", false, m, b, n, 1.0, W, ldw, V, ldv, 0.0, (const T*)nullptr, 0,
-                  w.PH, b2, w.partial, w.partial_elems, s);
-    gemm<T, T, T>(tm, "gemm_w", true, n, b, m, 1.0, W, ldw, U, ldu, 0.0, (const T*)nullptr, 0,
-                  w.Qb, b, w.partial, w.partial_elems, s);
+    op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
+    op_apply<T>(cx, w, s, W, m, n, true, U, ldu, b, w.Qb, b);
     // new block: F = orth(P - U U^T P), G = orth(Q - V V^T Q)
     orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
     orth_against<T>(cx, w, s, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
     // the last product of the pass: H = W G
-    gemm<T, T, T>(tm, "gemm_w", false, m, b, n, 1.0, W, ldw, w.VG + b, b2, 0.0,
-                  (const T*)nullptr, 0, w.PH + b, b2, w.partial, w.partial_elems, s);
+    op_apply<T>(cx, w, s, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
     // B = [U, F]^T [P, H] in FP64
     gemm<T, T, double>(tm, "gemm_ts", true, b2, b2, m, 1.0, w.UF, b2, w.PH, b2, 0.0,
                        (const double*)nullptr, 0, w.Bm, b2, w.partial, w.partial_elems, s);
     {
-        SvdScratch sw{w.svd, w.D1, w.Gr, w.Ri, w.chol, w.partial, w.flags, w.nflag,
-                      w.partial_elems};
-        small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, sw, seed);
+        const OrthWs<double> ow{w.D1, w.D2, w.Cp, w.Gr, w.Ri, w.chol, w.partial,
+                                w.partial_elems, w.flags, w.nflag};
+        small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, w.svd, ow, seed);
     }
     // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b)
     gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
@@ -296,19 +384,15 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const T* W
 // (A U tied to V by U = orth(W V) would put W V inside span(U) and leave the
 // first Lanczos step without new left directions; likewise on the right.)
 template <typename T>
-void cold_block(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const T* W, int ldw,
-                int b, int pow_steps, uint64_t seed, uint64_t stream_v, T* U, int ldu, T* V,
-                int ldv)
+void cold_block(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W, int b,
+                int pow_steps, uint64_t seed, uint64_t stream_v, T* U, int ldu, T* V, int ldv)
 {
-    Timer* tm = &cx.timer;
     fill_uniform<T>(n, b, w.Qb, b, seed, stream_v, s);
     orth_against<T>(cx, w, s, n, 0, (const T*)nullptr, 0, w.Qb, b, b, V, ldv, seed);
     for (int t = 0; t < pow_steps; ++t) {
-        gemm<T, T, T>(tm, "gemm_w", false, m, b, n, 1.0, W, ldw, V, ldv, 0.0, (const T*)nullptr,
-                      0, w.PH, b, w.partial, w.partial_elems, s);
+        op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b);
         orth_against<T>(cx, w, s, m, 0, (const T*)nullptr, 0, w.PH, b, b, U, ldu, seed);
-        gemm<T, T, T>(tm, "gemm_w", true, n, b, m, 1.0, W, ldw, U, ldu, 0.0, (const T*)nullptr, 0,
-                      w.Qb, b, w.partial, w.partial_elems, s);
+        op_apply<T>(cx, w, s, W, m, n, true, U, ldu, b, w.Qb, b);
         orth_against<T>(cx, w, s, n, 0, (const T*)nullptr, 0, w.Qb, b, b, V, ldv, seed);
     }
     fill_uniform<T>(m, b, w.PH, b, seed, stream_v + 1, s);
@@ -358,6 +442,8 @@ struct Readback {
     int rank;
     int nflag;
     long long nnz;
+    int svd_err;
+    int pad2;
 };
 
 template <typename T>
@@ -401,7 +487,7 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
     Carver c(cx.ws);
     layout(c, Y, Wb, U, V, S, part, scal, rank_dev, nnz_scr, rb);
     Readback* hrb = (Readback*)cx.host_pinned;
-    HIP_TRY(hipMemsetAsync(w.nflag, 0, sizeof(int), s));
+    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
 
     // ||D||_F and ||D||_inf
     norms<T>(m, n, D, ldd, scal, part, s);
@@ -425,10 +511,11 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
 
     // ||D||_2 by BLWS steps from a cold block (generator stream 3)
     const int bs = bmax < 16 ? bmax : 16;
-    cold_block<T>(cx, w, s, m, n, D, ldd, bs, o.pow_steps, o.seed, 3, U, bs, V, bs);
+    const Op<T> opD{D, ldd, nullptr};
+    cold_block<T>(cx, w, s, m, n, opD, bs, o.pow_steps, o.seed, 3, U, bs, V, bs);
     double s1 = 0.0, prev = 0.0;
     for (int t = 0; t < o.norm_steps; ++t) {
-        svt_step<T>(cx, w, s, m, n, D, ldd, 0.0, bs, U, bs, V, bs, S, nullptr, o.seed);
+        svt_step<T>(cx, w, s, m, n, opD, 0.0, bs, U, bs, V, bs, S, nullptr, o.seed);
         HIP_TRY(hipMemcpyAsync(hrb, S, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         s1 = ((double*)hrb)[0];
@@ -445,24 +532,29 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
     int sv = o.sv0, b = 0, svp = 0, it = 0;
     double rel = INFINITY, eps = 0.0;
     const int np = (int)alm_partials(m, n);
+    const Op<T> opW{Wb, n, nullptr};
     for (it = 1; it <= o.max_iter; ++it) {
         eps = 1.0 / mu;
         const int bn = block_width(sv, svp, o, p);
         if (b == 0) {
-            cold_block<T>(cx, w, s, m, n, Wb, n, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
+            cold_block<T>(cx, w, s, m, n, opW, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
         } else if (bn > b) {
             grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)it);
             grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)it + 1);
         }
         b = bn;
-        svt_step<T>(cx, w, s, m, n, Wb, n, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         const double mu_next = (o.rho * mu < mu_bar) ? o.rho * mu : mu_bar;
         alm_epilogue<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, lambda, mu, mu_next, D, ldd,
                         Y, E, lde, Wb, (T*)nullptr, 0, part, s);
         sum_partials(np, part, &rb->zz, s);
         HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(&rb->svd_err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToDevice,
+                               s));
         HIP_TRY(hipMemcpyAsync(hrb, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        BLWS_REQUIRE(hrb->svd_err == 0, BLWS_EDEVICE,
+                     "small SVD: a device-wide barrier wait timed out");
         svp = hrb->rank;
         BLWS_REQUIRE(std::isfinite(hrb->zz), BLWS_ENUMERIC, "rpca_solve: residual is not finite");
         sv = predict_rank(svp, sv, o.sv_step_frac, p);
@@ -504,9 +596,181 @@ void svt_call_t(Context& cx, hipStream_t s, int m, int n, const T* W, int ldw, d
     }
     Carver c(cx.ws);
     w.carve(c, m, n, b);
-    if (!warm) cold_block<T>(cx, w, s, m, n, W, ldw, b, o.pow_steps, o.seed, 1, U, ldu, V, ldv);
-    svt_step<T>(cx, w, s, m, n, W, ldw, eps, b, U, ldu, V, ldv, S, rank_dev, o.seed);
+    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+    const Op<T> op{W, ldw, nullptr};
+    if (!warm) cold_block<T>(cx, w, s, m, n, op, b, o.pow_steps, o.seed, 1, U, ldu, V, ldv);
+    svt_step<T>(cx, w, s, m, n, op, eps, b, U, ldu, V, ldv, S, rank_dev, o.seed);
     if (A) svt_reconstruct<T>(&cx.timer, m, n, b, U, ldu, V, ldv, S, eps, A, lda, s);
+}
+
+// Inexact ALM for matrix completion: W = A + P_Omega(D + Y/mu - A), A = T_{1/mu}(W),
+// Y_Omega += mu (d - A_Omega), with A kept as the factors of the last BLWS step
+// and W applied as low rank plus sparse (never formed).
+template <typename T>
+int mc_solve_t(Context& cx, hipStream_t s, int m, int n, int nnz, const int* row_ptr,
+               const int* col_idx, const T* d, const blws_alm_opts& o, int r_cap, T* Uout,
+               int ldu, double* Sout, T* Vout, int ldv, blws_solve_info* info)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    const int p = m < n ? m : n;
+    const int bmax = (p / 2 < o.b_max) ? p / 2 : o.b_max;
+
+    StepWs<T> w;
+    T *U, *V, *y, *sv;
+    double *S, *coef, *part, *scal;
+    int *col_ptr, *csc_row, *csc_perm, *csc_scr, *flag, *rank_dev;
+    Readback* rb;
+    const size_t np = std::max(mc_partials(m), norms_scratch_elems());
+    auto layout = [&](Carver& c) {
+        w.carve(c, m, n, bmax);
+        U = c.take<T>((size_t)m * bmax);
+        V = c.take<T>((size_t)n * bmax);
+        S = c.take<double>(bmax);
+        y = c.take<T>((size_t)nnz + 1);
+        sv = c.take<T>((size_t)nnz + 1);
+        coef = c.take<double>((size_t)bmax * bmax);
+        part = c.take<double>(np);
+        scal = c.take<double>(16);
+        col_ptr = c.take<int>((size_t)n + 1);
+        csc_row = c.take<int>((size_t)nnz + 1);
+        csc_perm = c.take<int>((size_t)nnz + 1);
+        csc_scr = c.take<int>(csc_scratch_ints(n, nnz));
+        flag = c.take<int>(4);
+        rank_dev = c.take<int>(4);
+        rb = c.take<Readback>(1);
+    };
+    {
+        Carver dry(nullptr);
+        layout(dry);
+        cx.ensure(dry.off + 256);
+    }
+    Carver c(cx.ws);
+    layout(c);
+    Readback* hrb = (Readback*)cx.host_pinned;
+    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+
+    // the pattern must be valid before any kernel indexes with it
+    csr_check(m, n, nnz, row_ptr, col_idx, flag, s);
+    HIP_TRY(hipMemcpyAsync(&hrb->rank, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    BLWS_REQUIRE(hrb->rank == 0, BLWS_EINVAL,
+                 (hrb->rank & 1) ? "mc_solve: row_ptr is not nondecreasing from 0 to nnz"
+                                 : "mc_solve: a column index lies outside [0, n)");
+    csc_build(m, n, nnz, row_ptr, col_idx, col_ptr, csc_row, csc_perm, flag + 1, csc_scr, s);
+
+    double dnorm = 0.0;
+    if (nnz > 0) {
+        norms<T>(1, nnz, d, nnz, scal, part, s);
+        HIP_TRY(hipMemcpyAsync(hrb, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        dnorm = std::sqrt(((double*)hrb)[0]);
+        BLWS_REQUIRE(std::isfinite(dnorm), BLWS_ENUMERIC, "mc_solve: values hold NaN or Inf");
+    }
+    if (dnorm == 0.0) {
+        if (info) {
+            std::memset(info, 0, sizeof(*info));
+            info->seconds =
+                std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        }
+        HIP_TRY(hipStreamSynchronize(s));
+        return BLWS_OK;
+    }
+
+    McOp<T> mo;
+    mo.nnz = nnz;
+    mo.row_ptr = row_ptr;
+    mo.col_idx = col_idx;
+    mo.col_ptr = col_ptr;
+    mo.csc_row = csc_row;
+    mo.csc_perm = csc_perm;
+    mo.Ul = U;
+    mo.Vl = V;
+    mo.ldl = bmax;
+    mo.S = S;
+    mo.coef = coef;
+    const Op<T> op{nullptr, 0, &mo};
+
+    // ||D||_2 of the sampled matrix alone, by BLWS steps from a cold block
+    mo.sval = d;
+    mo.r = 0;
+    const int bs = bmax < 16 ? bmax : 16;
+    cold_block<T>(cx, w, s, m, n, op, bs, o.pow_steps, o.seed, 3, U, bs, V, bs);
+    double s1 = 0.0, prev = 0.0;
+    for (int t = 0; t < o.norm_steps; ++t) {
+        svt_step<T>(cx, w, s, m, n, op, 0.0, bs, U, bs, V, bs, S, nullptr, o.seed);
+        HIP_TRY(hipMemcpyAsync(hrb, S, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        s1 = ((double*)hrb)[0];
+        BLWS_REQUIRE(std::isfinite(s1) && s1 > 0.0, BLWS_ENUMERIC,
+                     "mc_solve: ||D||_2 is not finite");
+        if (t > 0 && std::fabs(s1 - prev) <= o.norm_rtol * s1) break;
+        prev = s1;
+    }
+
+    double mu = o.mu0_scale / s1;
+    const double mu_bar = mu * o.mu_max_factor;
+    mc_init<T>(nnz, d, y, sv, s);
+    mo.sval = sv;
+
+    int sv_pred = o.sv0, b = 0, svp = 0, it = 0;
+    double rel = INFINITY, eps = 0.0, eps_prev = 0.0;
+    const int npart = (int)mc_partials(m);
+    for (it = 1; it <= o.max_iter; ++it) {
+        eps = 1.0 / mu;
+        // the current A = U_r diag(S_r - eps_prev) V_r^T of the last step
+        mo.r = svp;
+        mo.eps = eps_prev;
+        const int bn = block_width(sv_pred, svp, o, p);
+        if (b == 0) {
+            cold_block<T>(cx, w, s, m, n, op, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
+        } else if (bn > b) {
+            grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)it);
+            grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)it + 1);
+        }
+        b = bn;
+        svt_step<T>(cx, w, s, m, n, op, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        const double mu_next = (o.rho * mu < mu_bar) ? o.rho * mu : mu_bar;
+        mc_update<T>(&cx.timer, m, nnz, row_ptr, col_idx, d, y, sv, U, bmax, V, bmax, S, eps,
+                     rank_dev, b, mu, mu_next, part, s);
+        sum_partials(npart, part, &rb->zz, s);
+        HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(&rb->svd_err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToDevice,
+                               s));
+        HIP_TRY(hipMemcpyAsync(hrb, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        BLWS_REQUIRE(hrb->svd_err == 0, BLWS_EDEVICE,
+                     "small SVD: a device-wide barrier wait timed out");
+        svp = hrb->rank;
+        BLWS_REQUIRE(std::isfinite(hrb->zz), BLWS_ENUMERIC, "mc_solve: residual is not finite");
+        sv_pred = predict_rank(svp, sv_pred, o.sv_step_frac, p);
+        mu = mu_next;
+        eps_prev = eps;
+        rel = std::sqrt(hrb->zz) / dnorm;
+        if (rel < o.tol) break;
+    }
+    if (it > o.max_iter) it = o.max_iter;
+    const int rc = svp < r_cap ? svp : r_cap;
+    if (rc > 0) {
+        copy2d<T, T>(m, rc, U, bmax, Uout, ldu, s);
+        copy2d<T, T>(n, rc, V, bmax, Vout, ldv, s);
+        theta_out(rc, S, eps, Sout, s);
+    }
+    HIP_TRY(hipMemcpyAsync(&rb->nflag, w.nflag, sizeof(int), hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipMemcpyAsync(hrb, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (info) {
+        info->status = rel < o.tol ? BLWS_OK : BLWS_NOT_CONVERGED;
+        info->iters = it;
+        info->rank = svp;
+        info->b_final = b;
+        info->fallbacks = hrb->nflag;
+        info->nnz_E = 0;
+        info->rel_residual = rel;
+        info->norm2_D = s1;
+        info->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return rel < o.tol ? BLWS_OK : BLWS_NOT_CONVERGED;
 }
 
 int fail(Context* cx, const BlwsError& e)
@@ -679,6 +943,47 @@ int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
     ABI_END
 }
 
+void blws_default_mc_opts(blws_alm_opts* o)
+{
+    if (!o) return;
+    blws_default_alm_opts(o);
+    o->tol = 1e-6;
+    o->rho = 1.1;
+    o->mu0_scale = 1.0;
+}
+
+int blws_mc_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
+                  const int* row_ptr, const int* col_idx, const void* values,
+                  const blws_alm_opts* opts, int r_cap, void* U, int ldu, double* S, void* V,
+                  int ldv, blws_solve_info* info)
+{
+    ABI_BEGIN(ctx)
+    BLWS_REQUIRE(m >= 2 && n >= 2 && nnz >= 0, BLWS_EINVAL, "blws_mc_solve: need m, n >= 2");
+    BLWS_REQUIRE(row_ptr && U && S && V && (nnz == 0 || (col_idx && values)), BLWS_EINVAL,
+                 "blws_mc_solve: null pointer argument");
+    BLWS_REQUIRE(r_cap >= 1 && ldu >= r_cap && ldv >= r_cap, BLWS_EINVAL,
+                 "blws_mc_solve: need r_cap >= 1 and ldu, ldv >= r_cap");
+    blws_alm_opts o;
+    blws_default_mc_opts(&o);
+    if (opts) o = *opts;
+    BLWS_REQUIRE(o.tol > 0.0 && o.max_iter >= 1 && o.rho >= 1.0 && o.mu0_scale > 0.0 &&
+                     o.mu_max_factor >= 1.0 && o.sv0 >= 1 && o.b_round >= 1 &&
+                     o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
+                     o.b_soft >= 1,
+                 BLWS_EINVAL, "blws_mc_solve: bad options");
+    BLWS_REQUIRE(o.b_max <= 256, BLWS_EUNSUPPORTED, "blws_mc_solve: b_max above 256");
+    hipStream_t s = (hipStream_t)stream;
+    if (prec == BLWS_FP64)
+        return blws::mc_solve_t<double>(cx, s, m, n, nnz, row_ptr, col_idx,
+                                        (const double*)values, o, r_cap, (double*)U, ldu, S,
+                                        (double*)V, ldv, info);
+    if (prec == BLWS_FP32)
+        return blws::mc_solve_t<float>(cx, s, m, n, nnz, row_ptr, col_idx, (const float*)values,
+                                       o, r_cap, (float*)U, ldu, S, (float*)V, ldv, info);
+    throw BlwsError{BLWS_EUNSUPPORTED, "blws_mc_solve: precision not supported"};
+    ABI_END
+}
+
 int blws_fill_uniform(blws_ctx ctx, void* stream, int rows, int cols, double* X, int ldx,
                       unsigned long long seed, unsigned long long stream_id)
 {
@@ -714,10 +1019,13 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
     ABI_BEGIN(ctx)
     BLWS_REQUIRE(N >= 1 && N <= 512 && B && UB && S && VB && ldb >= N, BLWS_EINVAL,
                  "blws_small_svd_f64: bad arguments");
-    auto layout = [&](Carver& c, blws::SvdScratch& w) {
+    double* svd = nullptr;
+    auto layout = [&](Carver& c, blws::OrthWs<double>& w) {
         size_t e1 = blws::small_svd_jacobi_scratch_elems(N), e2 = blws::small_svd_gk_scratch_elems(N);
-        w.svd = c.take<double>(e1 > e2 ? e1 : e2);
+        svd = c.take<double>(e1 > e2 ? e1 : e2);
         w.T1 = c.take<double>((size_t)N * N);
+        w.T2 = c.take<double>((size_t)N * N);
+        w.Cp = c.take<double>((size_t)N * N);
         w.Gr = c.take<double>((size_t)N * N);
         w.Ri = c.take<double>((size_t)N * N);
         w.chol = c.take<double>(blws::chol_scratch_elems(N) + 1);
@@ -727,7 +1035,7 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
         w.partial_elems = pe;
         w.partial = c.take<double>(pe + 1);
     };
-    blws::SvdScratch w;
+    blws::OrthWs<double> w;
     {
         Carver dry(nullptr);
         layout(dry, w);
@@ -735,7 +1043,13 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
     }
     Carver c(cx.ws);
     layout(c, w);
-    blws::small_svd_dispatch(cx, (hipStream_t)stream, N, N, B, ldb, UB, S, VB, w, 20101202ULL);
+    hipStream_t s = (hipStream_t)stream;
+    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+    blws::small_svd_dispatch(cx, s, N, N, B, ldb, UB, S, VB, svd, w, 20101202ULL);
+    int err = 0;
+    HIP_TRY(hipMemcpyAsync(&err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    BLWS_REQUIRE(err == 0, BLWS_EDEVICE, "small SVD: a device-wide barrier wait timed out");
     return BLWS_OK;
     ABI_END
 }
@@ -758,8 +1072,9 @@ int blws_cold_block(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
         cx.ensure(dry.off + 256);
         Carver c(cx.ws);
         w.carve(c, m, n, b);
-        blws::cold_block<double>(cx, w, s, m, n, (const double*)W, ldw, b, pow_steps, seed,
-                                 stream_v, (double*)U, ldu, (double*)V, ldv);
+        const blws::Op<double> op{(const double*)W, ldw, nullptr};
+        blws::cold_block<double>(cx, w, s, m, n, op, b, pow_steps, seed, stream_v, (double*)U,
+                                 ldu, (double*)V, ldv);
     } else if (prec == BLWS_FP32) {
         blws::StepWs<float> w;
         Carver dry(nullptr);
@@ -767,8 +1082,9 @@ int blws_cold_block(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
         cx.ensure(dry.off + 256);
         Carver c(cx.ws);
         w.carve(c, m, n, b);
-        blws::cold_block<float>(cx, w, s, m, n, (const float*)W, ldw, b, pow_steps, seed,
-                                stream_v, (float*)U, ldu, (float*)V, ldv);
+        const blws::Op<float> op{(const float*)W, ldw, nullptr};
+        blws::cold_block<float>(cx, w, s, m, n, op, b, pow_steps, seed, stream_v, (float*)U,
+                                ldu, (float*)V, ldv);
     } else {
         throw BlwsError{BLWS_EUNSUPPORTED, "blws_cold_block: precision not supported"};
     }

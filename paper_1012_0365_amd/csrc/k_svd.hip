@@ -1,11 +1,13 @@
 // SVD of the small projected matrix B (N x N, FP64) of the BLWS step, whose
 // singular values are the Ritz values (Algorithm 3 with Theorem 1).
 //
-// 1. Golub-Kahan bidiagonalisation B = Q_L Bd Q_R^T in ONE workgroup, B held
-//    in registers: a 32 x 16 thread grid, thread (tr, tc) owning rows
-//    tr + 32a and columns tc + 16c, so N <= 224. Each step
-//    is a left and a right Householder reflection; their vectors are written to
-//    global memory for the back-transformation.
+// 1. Golub-Kahan bidiagonalisation B = Q_L Bd Q_R^T. Up to N = 224 in ONE
+//    workgroup, B held in registers: a 32 x 16 thread grid, thread (tr, tc)
+//    owning rows tr + 32a and columns tc + 16c. Up to N = 512 across
+//    ceil(N / 32) co-resident workgroups holding 32-column slabs, with one
+//    device-wide barrier per column. Each step is a left and a right
+//    Householder reflection; their vectors are written to global memory for
+//    the back-transformation.
 // 2. Singular values of Bd by multisection on the Golub-Kahan tridiagonal
 //    T = tridiag(0; d0, e0, d1, e1, ..., d_{N-1}) of size 2N, whose eigenvalues
 //    are +-sigma (Theorem 1 applied to the bidiagonal): one wavefront per value,
@@ -19,7 +21,8 @@
 namespace blws {
 namespace {
 
-constexpr int GK_MAXN = 224;
+constexpr int GK_MAXN = 224;   // one-workgroup bidiagonalisation
+constexpr int SVD_MAXN = 512;  // cooperative bidiagonalisation and the later stages
 
 // Start vectors of the inverse iteration: SplitMix64 (Steele, Lea & Flood
 // 2014) outputs mapped to [-1, 1), distinct per value so that vectors of a
@@ -236,6 +239,237 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Cooperative Golub-Kahan bidiagonalisation for GK_MAXN < N <= SVD_MAXN.
+//
+// P = ceil(N / 32) workgroups, all resident at once (cooperative launch).
+// Workgroup p holds columns 32p .. 32p + 31 of B in registers: thread (g, c)
+// of a 16 x 32 grid owns column 32p + c and rows g + 16q (q < NQ). Per step k:
+//  - every workgroup forms the left reflector of column k on its own, from
+//    the column as published in the previous step, and applies it to its
+//    columns (no barrier needed);
+//  - for the right reflector of row k (x = row k beyond the superdiagonal)
+//    each workgroup publishes the sum of squares of its part of x and its
+//    part of sum_j B[i][j] x_j, and the owner of column k + 1 publishes that
+//    column; after ONE device-wide barrier every workgroup forms the
+//    reflector, z = B v and the next column from these in a fixed order
+//    (so all workgroups hold bit-identical copies) and updates its columns.
+// The barrier waits are bounded: on a timeout the error flag is set and every
+// workgroup leaves the kernel.
+// ---------------------------------------------------------------------------
+constexpr unsigned CO_SPIN_LIMIT = 1u << 22;
+
+struct CoopBuf {
+    double* colpub;  // 2 x N: column k + 1 before the right update
+    double* nrm;     // 2 x P: partial sums of squares of row k
+    double* part;    // 2 x P x N: partial products B x
+    unsigned* ctr;   // barrier arrivals (zero at launch)
+    int* err;        // set on a barrier timeout
+};
+
+__device__ __forceinline__ double ld_agent(double* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_agent(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-wide barrier among the co-resident workgroups: release of this
+// workgroup's writes, arrival count, bounded wait, acquire.
+__device__ bool coop_barrier(unsigned* ctr, unsigned target, int* err, int* ok_lds)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 1;
+        unsigned spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+                ++spins > CO_SPIN_LIMIT) {
+                __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        *ok_lds = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return *ok_lds != 0;
+}
+
+template <int NQ>
+__global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
+    int N, const double* __restrict__ B, int ldb, double* __restrict__ dout,
+    double* __restrict__ eout, double* __restrict__ VL, double* __restrict__ tauL,
+    double* __restrict__ VR, double* __restrict__ tauR, CoopBuf cb)
+{
+    __shared__ double xcol[SVD_MAXN];  // column k, then the left vector
+    __shared__ double zs[SVD_MAXN];    // z = B v of the right reflector
+    __shared__ double red[16][33];
+    __shared__ double wcol[32];
+    __shared__ double rowk[32];
+    __shared__ double sc[4];
+    __shared__ int okl;
+    const int P = gridDim.x, p = blockIdx.x;
+    const int tid = threadIdx.x, c = tid & 31, g = tid >> 5, lane = tid & 63, wave = tid >> 6;
+    const int j = 32 * p + c;
+    const bool jv = j < N;
+
+    double a[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int i = g + 16 * q;
+        a[q] = (i < N && jv) ? B[(size_t)i * ldb + j] : 0.0;
+    }
+    for (int i = tid; i < N; i += 512) xcol[i] = B[(size_t)i * ldb];
+    __syncthreads();
+
+    for (int k = 0; k < N; ++k) {
+        // ---- left reflector of column k (rows k..N-1), formed by every workgroup
+        if (wave == 0) {
+            const double alpha = xcol[k];
+            double s2 = 0.0;
+            for (int i = k + 1 + lane; i < N; i += 64) s2 += xcol[i] * xcol[i];
+            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (s2 > 0.0) {
+                const double nrm = sqrt(alpha * alpha + s2);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            for (int i = k + 1 + lane; i < N; i += 64) {
+                const double v = xcol[i] * scale;
+                xcol[i] = v;
+                if (p == 0) VL[(size_t)k * N + i] = v;
+            }
+            if (lane == 0) {
+                xcol[k] = 1.0;
+                sc[0] = tau;
+                if (p == 0) {
+                    VL[(size_t)k * N + k] = 1.0;
+                    tauL[k] = tau;
+                    dout[k] = beta;
+                }
+            }
+        }
+        __syncthreads();
+        const double tl = sc[0];
+        if (tl != 0.0) {
+            // w_j = tau sum_{i >= k} u_i B[i][j] for own columns j > k
+            double pw = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (16 * q + 15 < k) continue;  // uniform
+                const int i = g + 16 * q;
+                if (i >= k && i < N) pw += xcol[i] * a[q];
+            }
+            red[g][c] = pw;
+            __syncthreads();
+            if (tid < 32) {
+                double w = 0.0;
+                for (int gg = 0; gg < 16; ++gg) w += red[gg][tid];
+                wcol[tid] = tl * w;
+            }
+            __syncthreads();
+            const double wj = (jv && j > k) ? wcol[c] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (16 * q + 15 < k) continue;
+                const int i = g + 16 * q;
+                if (i >= k && i < N) a[q] -= xcol[i] * wj;
+            }
+        }
+        if (k + 1 >= N) break;
+
+        // ---- right reflector of row k: this workgroup's partials
+        const int slot = k & 1;
+        if (g == (k & 15)) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q)
+                if (q == (k >> 4)) v = a[q];
+            rowk[c] = jv ? v : 0.0;
+        }
+        __syncthreads();
+        {
+            const double xj = (jv && j >= k + 2) ? rowk[c] : 0.0;
+            double* prow = cb.part + ((size_t)slot * P + p) * N;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (16 * q + 15 < k + 1) continue;  // uniform
+                const int i = g + 16 * q;
+                double sq = a[q] * xj;
+                for (int off = 16; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+                if (c == 0 && i >= k + 1 && i < N) st_agent(prow + i, sq);
+            }
+        }
+        if (tid == 0) {
+            double s2 = 0.0;
+            for (int cc = 0; cc < 32; ++cc) {
+                const int jj = 32 * p + cc;
+                if (jj >= k + 2 && jj < N) s2 += rowk[cc] * rowk[cc];
+            }
+            st_agent(cb.nrm + slot * P + p, s2);
+        }
+        if (p == ((k + 1) >> 5) && c == ((k + 1) & 31)) {
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int i = g + 16 * q;
+                if (i >= k && i < N) st_agent(cb.colpub + (size_t)slot * N + i, a[q]);
+            }
+        }
+        if (!coop_barrier(cb.ctr, (unsigned)(k + 1) * (unsigned)P, cb.err, &okl)) return;
+
+        // ---- the reflector, z = B v and the next column, from the partials
+        if (tid == 0) {
+            const double alpha = ld_agent(cb.colpub + (size_t)slot * N + k);
+            double s2 = 0.0;
+            for (int q = 0; q < P; ++q) s2 += ld_agent(cb.nrm + slot * P + q);
+            double tau = 0.0, beta = alpha, scale = 0.0;
+            if (s2 > 0.0) {
+                const double nrm = sqrt(alpha * alpha + s2);
+                beta = alpha >= 0.0 ? -nrm : nrm;
+                tau = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+            sc[1] = tau;
+            sc[2] = scale;
+            if (p == 0) {
+                tauR[k] = tau;
+                eout[k] = beta;
+            }
+        }
+        __syncthreads();
+        const double tq = sc[1], scl = sc[2];
+        for (int i = k + 1 + tid; i < N; i += 512) {
+            double acc = 0.0;
+            for (int q = 0; q < P; ++q) acc += ld_agent(cb.part + ((size_t)slot * P + q) * N + i);
+            const double cp = ld_agent(cb.colpub + (size_t)slot * N + i);
+            const double z = cp + scl * acc;
+            zs[i] = z;
+            xcol[i] = cp - tq * z;
+        }
+        if (g == 0 && jv && j >= k + 1) VR[(size_t)k * N + j] = (j == k + 1) ? 1.0 : rowk[c] * scl;
+        __syncthreads();
+        if (tq != 0.0) {
+            const double vj = (jv && j >= k + 1) ? ((j == k + 1) ? 1.0 : rowk[c] * scl) : 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (16 * q + 15 < k + 1) continue;
+                const int i = g + 16 * q;
+                if (i >= k + 1 && i < N) a[q] -= tq * zs[i] * vj;
+            }
+        }
+        __syncthreads();  // rowk, zs and sc are rewritten in the next step
+    }
+}
+
 // Number of singular values of the bidiagonal (d, e) that are >= x (x > 0),
 // from the Sturm count of the Golub-Kahan tridiagonal T (zero diagonal,
 // off-diagonals f2 squared): #{eig(T) < x} = N + #{sigma < x}. The LDL^T
@@ -259,7 +493,7 @@ __global__ __launch_bounds__(64) void tgk_bisect_kernel(int N, const double* __r
                                                         const double* __restrict__ e,
                                                         double* __restrict__ sig)
 {
-    __shared__ double f2[2 * GK_MAXN];
+    __shared__ double f2[2 * SVD_MAXN];
     __shared__ int cnt[64];
     const int t = blockIdx.x, lane = threadIdx.x;
     double bound = 0.0, fmax2 = 0.0;
@@ -313,10 +547,10 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
                                                        double* __restrict__ ubd,
                                                        double* __restrict__ vbd, int ldv)
 {
-    __shared__ double f[2 * GK_MAXN];
-    __shared__ double z[2 * GK_MAXN], dl[2 * GK_MAXN], dd[2 * GK_MAXN], du[2 * GK_MAXN],
-        du2[2 * GK_MAXN];
-    __shared__ unsigned char swp[2 * GK_MAXN];
+    __shared__ double f[2 * SVD_MAXN];
+    __shared__ double z[2 * SVD_MAXN], dl[2 * SVD_MAXN], dd[2 * SVD_MAXN], du[2 * SVD_MAXN],
+        du2[2 * SVD_MAXN];
+    __shared__ unsigned char swp[2 * SVD_MAXN];
     const int t = blockIdx.x, lane = threadIdx.x;
     const int n = 2 * N;
     for (int j = lane; j < n - 1; j += 64) f[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
@@ -400,22 +634,22 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
 
 // X (N x nv, ld) <- H_0 H_1 ... H_{nref-1} X for reflectors stored column-wise
 // in Vh (column k: entries k+off .. N-1, unit at k+off), tau[k]. One wavefront
-// per column of X (four per workgroup), the column in registers (N <= 256);
-// reflectors staged through LDS 16 at a time, applied last to first.
-constexpr int RCH = 16;
+// per column of X (four per workgroup), the column in registers (N <= 64 R);
+// reflectors staged through LDS RCH at a time, applied last to first.
+template <int MAXN, int RCH, int R>
 __global__ __launch_bounds__(256) void reflect_apply_kernel(int N, int nref, int off,
                                                             const double* __restrict__ Vh,
                                                             const double* __restrict__ tau,
                                                             double* __restrict__ X, int ldx,
                                                             int nv)
 {
-    __shared__ double vs[RCH][GK_MAXN];
+    __shared__ double vs[RCH][MAXN];
     __shared__ double ts[RCH];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = blockIdx.x * 4 + wave;
-    double xr[4];
+    double xr[R];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < R; ++r) {
         const int i = lane + 64 * r;
         xr[r] = (col < nv && i < N) ? X[(size_t)i * ldx + col] : 0.0;
     }
@@ -435,14 +669,14 @@ __global__ __launch_bounds__(256) void reflect_apply_kernel(int N, int nref, int
             if (tk == 0.0) continue;
             double dot = 0.0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int i = lane + 64 * r;
                 if (i < N) dot += vs[q][i] * xr[r];
             }
             for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
             const double w = tk * dot;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
+            for (int r = 0; r < R; ++r) {
                 const int i = lane + 64 * r;
                 if (i < N) xr[r] -= vs[q][i] * w;
             }
@@ -450,7 +684,7 @@ __global__ __launch_bounds__(256) void reflect_apply_kernel(int N, int nref, int
     }
     if (col < nv) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int r = 0; r < R; ++r) {
             const int i = lane + 64 * r;
             if (i < N) X[(size_t)i * ldx + col] = xr[r];
         }
@@ -481,17 +715,19 @@ __global__ void sign_fix_kernel(int N, int nv, double* UB, double* VB, int ld)
 
 }  // namespace
 
-bool small_svd_gk_supported(int N) { return N >= 2 && N <= GK_MAXN; }
+bool small_svd_gk_supported(int N) { return N >= 2 && N <= SVD_MAXN; }
 
 size_t small_svd_gk_scratch_elems(int N)
 {
-    // d, e, tauL, tauR and the reflector vectors VL, VR
-    return 4 * (size_t)N + 2 * (size_t)N * N;
+    // d, e, tauL, tauR, the reflector vectors VL, VR, and for the cooperative
+    // bidiagonalisation the published column, partials and barrier counter
+    const size_t P = (N + 31) / 32;
+    return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8;
 }
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
 void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
-                  double* VB, double* scratch, hipStream_t s)
+                  double* VB, double* scratch, int* err, hipStream_t s)
 {
     BLWS_REQUIRE(small_svd_gk_supported(N) && nv >= 1 && nv <= N, BLWS_EUNSUPPORTED,
                  "small_svd_gk: size out of range");
@@ -501,7 +737,26 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     double* tR = tL + N;
     double* VL = tR + N;
     double* VR = VL + (size_t)N * N;
-    {
+    if (N > GK_MAXN) {
+        TimedLaunch tl(tm, "gk_bidiag", s, 8.0 / 3.0 * N * (double)N * N, 16.0 * N * N);
+        const int P = (N + 31) / 32;
+        CoopBuf cb;
+        cb.colpub = VR + (size_t)N * N;
+        cb.nrm = cb.colpub + 2 * (size_t)N;
+        cb.part = cb.nrm + 2 * (size_t)P;
+        cb.ctr = (unsigned*)(cb.part + 2 * (size_t)P * N);
+        cb.err = err;
+        HIP_TRY(hipMemsetAsync(cb.ctr, 0, sizeof(unsigned), s));
+        void* args[] = {(void*)&N,  (void*)&B,  (void*)&ldb, (void*)&d,  (void*)&e,
+                        (void*)&VL, (void*)&tL, (void*)&VR,  (void*)&tR, (void*)&cb};
+        const void* fn = nullptr;
+        const int NQ = (N + 15) / 16;
+        if (NQ <= 20) fn = (const void*)gk_bidiag_coop_kernel<20>;
+        else if (NQ <= 24) fn = (const void*)gk_bidiag_coop_kernel<24>;
+        else if (NQ <= 28) fn = (const void*)gk_bidiag_coop_kernel<28>;
+        else fn = (const void*)gk_bidiag_coop_kernel<32>;
+        HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(P), dim3(512), args, 0, s));
+    } else {
         TimedLaunch tl(tm, "gk_bidiag", s, 8.0 / 3.0 * N * (double)N * N, 16.0 * N * N);
         const int NP = (N + 31) / 32;
 #define BLWS_GK_CASE(P)                                                                      \
@@ -529,10 +784,17 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     {
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
-        hipLaunchKernelGGL(reflect_apply_kernel, dim3(blocks), dim3(256), 0, s, N, N, 0, VL, tL,
-                           UB, N, nv);
-        hipLaunchKernelGGL(reflect_apply_kernel, dim3(blocks), dim3(256), 0, s, N, N - 1, 1, VR,
-                           tR, VB, N, nv);
+        if (N <= GK_MAXN) {
+            hipLaunchKernelGGL((reflect_apply_kernel<GK_MAXN, 16, 4>), dim3(blocks), dim3(256), 0,
+                               s, N, N, 0, VL, tL, UB, N, nv);
+            hipLaunchKernelGGL((reflect_apply_kernel<GK_MAXN, 16, 4>), dim3(blocks), dim3(256), 0,
+                               s, N, N - 1, 1, VR, tR, VB, N, nv);
+        } else {
+            hipLaunchKernelGGL((reflect_apply_kernel<SVD_MAXN, 8, 8>), dim3(blocks), dim3(256), 0,
+                               s, N, N, 0, VL, tL, UB, N, nv);
+            hipLaunchKernelGGL((reflect_apply_kernel<SVD_MAXN, 8, 8>), dim3(blocks), dim3(256), 0,
+                               s, N, N - 1, 1, VR, tR, VB, N, nv);
+        }
         hipLaunchKernelGGL(sign_fix_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, N, nv, UB, VB,
                            N);
     }

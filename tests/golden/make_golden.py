@@ -1,13 +1,14 @@
 """Write the stored expected values for the full-size parity tests.
 
-Calls only the CPU oracle (and the seeded input generator). For each case it
-runs the oracle's exact-SVT inexact ALM (the plain form: a full one-sided
-Jacobi SVD per iteration) and stores what a GPU run at the same size can be
-checked against without rerunning the oracle: seeded sampled entries of A and
-E, the singular values of A, norms, the nonzero count of E, the iteration
-count and rank.
+Calls only the CPU oracle (and the seeded input generator). RPCA cases run the
+oracle's exact-SVT inexact ALM (the plain form: a full one-sided Jacobi SVD per
+iteration); the matrix-completion case, whose dense exact form is out of reach
+at n = 5000, runs the oracle's BLWS ALM (pinned against the exact form at
+small sizes). Each stores what a GPU run at the same size can be checked
+against without rerunning the oracle: seeded sampled entries of the solution,
+singular values, norms, counts, the iteration count and rank.
 
-    python tests/golden/make_golden.py rpca_n2000_s0
+    python tests/golden/make_golden.py rpca_n2000_s0 mc_n5000_s0
 """
 
 from __future__ import annotations
@@ -30,6 +31,13 @@ CASES = {
     "rpca_n2000_s0": dict(m=2000, n=2000, r=100, frac=0.10, amp=500.0, seed=0, tol=1e-7),
     # smaller case in the same regime (Table 1, m = 500 row shape)
     "rpca_n500_s0": dict(m=500, n=500, r=50, frac=0.10, amp=500.0, seed=0, tol=1e-7),
+}
+
+MC_CASES = {
+    # matrix completion: n = 5000, L, R 5000 x 50 N(0, 1), 10% of entries sampled,
+    # stop at relative residual on Omega < 1e-6
+    "mc_n5000_s0": dict(m=5000, n=5000, r=50, frac=0.10, seed=0, tol=1e-6, rho=1.1,
+                        mu0_scale=1.0),
 }
 
 SAMPLES = 4096
@@ -68,9 +76,40 @@ def make(name: str) -> dict:
     }
 
 
+def make_mc(name: str) -> dict:
+    c = MC_CASES[name]
+    inst = synth.mc_instance(c["m"], c["n"], c["r"], c["frac"], c["seed"])
+    t0 = time.time()
+    out = oracle.mc(c["m"], c["n"], inst["row_ptr"], inst["col_idx"], inst["values"],
+                    mode="blws", r_cap=256, tol=c["tol"], rho=c["rho"], mu0_scale=c["mu0_scale"])
+    secs = time.time() - t0
+    U, S, V = out["U"], out["S"], out["V"]
+    pos = synth.sample_positions(c["m"], c["n"], SAMPLES, SAMPLE_SEED)
+    rows, cols = pos // c["n"], pos % c["n"]
+    a_s = np.einsum("ik,k,ik->i", U[rows], S, V[cols])
+    m_s = np.einsum("ik,ik->i", inst["L"][rows], inst["R"][cols])
+    info = out["info"]
+    return {
+        "case": name,
+        "source": "oracle BLWS inexact ALM for matrix completion (FP64)",
+        "params": c,
+        "nnz": int(inst["nnz"]),
+        "iters": info["iters"],
+        "rank": out["rank"],
+        "rel_residual": info["rel_residual"],
+        "norm2_D": info["norm2_D"],
+        "sigma_A": [float(x) for x in S],
+        "sample_seed": SAMPLE_SEED,
+        "sample_pos": [int(p) for p in pos],
+        "A_samples": [float(x) for x in a_s],
+        "M_samples": [float(x) for x in m_s],
+        "oracle_seconds": secs,
+    }
+
+
 if __name__ == "__main__":
-    for name in sys.argv[1:] or list(CASES):
-        g = make(name)
+    for name in sys.argv[1:] or list(CASES) + list(MC_CASES):
+        g = make_mc(name) if name in MC_CASES else make(name)
         path = os.path.join(os.path.dirname(os.path.abspath(__file__)), name + ".json")
         with open(path, "w") as f:
             json.dump(g, f, indent=0)
