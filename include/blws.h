@@ -17,7 +17,12 @@
  *    queued on it; the solvers block the calling thread until their result is
  *    complete, blws_svt returns as soon as its work is queued.
  *  - Element type of the W/D/U/V/A/E buffers: double for BLWS_FP64, float for
- *    BLWS_FP32. Singular values S are always double.
+ *    BLWS_FP32 and BLWS_BF16. Singular values S are always double. In BLWS_FP32
+ *    the products with W run on FP32 matrix cores; BLWS_BF16 (robust PCA only)
+ *    is the precision ladder: the products with W run in BF16 (FP32
+ *    accumulation) while the residual is large, then in FP32, and a last BF16
+ *    iterate is refined by one FP32 step. Gram matrices, Cholesky factors, the
+ *    projected SVD and the reconstruction of A are FP64 in every mode.
  *  - Return value: a blws_status. Arguments are validated before any work is
  *    queued, so an error leaves every output untouched. No call aborts, exits
  *    or throws. blws_last_error() gives a detail message for the last failure.
@@ -69,6 +74,8 @@ typedef struct {
     int b_max;                /* upper bound on the block width, <= 256 (256)           */
     int b_soft;               /* beyond this width the block follows the previous count */
                               /* of values above the threshold, not the prediction (112)*/
+    double ladder_tol;        /* BLWS_BF16 solves: W products in BF16 while the relative */
+                              /* residual is at or above this, FP32 below (1e-3)         */
 } blws_alm_opts;
 
 typedef struct {
@@ -81,6 +88,8 @@ typedef struct {
     double rel_residual;      /* final ||D - A - E||_F / ||D||_F                        */
     double norm2_D;           /* ||D||_2 used for mu_0                                  */
     double seconds;           /* wall time of the solve, measured on the host           */
+    int iters_bf16;           /* iterations whose W products ran in BF16 (BLWS_BF16)    */
+    int refined;              /* 1 if a final FP32 step refined a BF16 last iterate     */
 } blws_solve_info;
 
 /* Create a context on HIP device `device` (its workspace grows on demand). */
@@ -157,6 +166,14 @@ int blws_fill_uniform(blws_ctx ctx, void* stream, int rows, int cols, double* X,
 int blws_gemm_f64(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K, double alpha,
                   const double* A, int lda, const double* B, int ldb, double beta, double* C,
                   int ldc);
+
+/* Diagnostic: C (M x N, float) = op(A) B on the FP32 (bf16 = 0: A float) or
+ * BF16 (bf16 = 1: A holds BF16 bits as uint16, B is rounded to BF16 on the
+ * way in) matrix cores with FP32 accumulation: the kernel of the W products
+ * in the FP32 and BF16 modes. op(A) = A (M x K, lda) or A^T (A is K x M).
+ * B is K x N (ldb). Asynchronous on `stream`. */
+int blws_gemm_lp(blws_ctx ctx, void* stream, int bf16, int trans_a, int M, int N, int K,
+                 const void* A, int lda, const float* B, int ldb, float* C, int ldc);
 
 /* SVD of a small dense N x N FP64 matrix B (ldb) on the device: U_B (N x N),
  * V_B (N x N) row-major with ld = N, S (N) decreasing, sign chosen so that the

@@ -123,11 +123,17 @@ class Context:
 
     # -- robust PCA ----------------------------------------------------------
     def rpca_solve(self, D, lam: float | None = None, opts: AlmOpts | None = None, A=None,
-                   E=None):
+                   E=None, bf16: bool = False):
         """min ||A||_* + lam ||E||_1 s.t. D = A + E by inexact ALM with BLWS.
+        bf16=True (float32 D only) selects the precision ladder: BF16 W products
+        while the residual is large, then FP32, with a final FP32 refinement.
         Returns (A, E, info dict)."""
         torch = _torch()
         prec = _prec_of(D)
+        if bf16:
+            if prec != _native.BLWS_FP32:
+                raise TypeError("the BF16 ladder takes float32 D")
+            prec = _native.BLWS_BF16
         ldd = _check_mat(D, "D")
         m, n = D.shape
         if A is None:
@@ -186,6 +192,20 @@ class Context:
         self._check(self._lib.blws_gemm_f64(self.handle, self._stream(), int(trans_a), M, N, K,
                                             alpha, A.data_ptr(), lda, B.data_ptr(), ldb, beta,
                                             C.data_ptr(), ldc))
+
+    def gemm_lp(self, A, B, C, trans_a: bool = False):
+        """C = op(A) B on the FP32 (A float32) or BF16 (A int16 holding BF16 bits)
+        matrix cores, FP32 accumulation (B, C float32)."""
+        torch = _torch()
+        lda, ldb, ldc = _check_mat(A, "A"), _check_mat(B, "B"), _check_mat(C, "C")
+        bf = A.dtype == torch.int16
+        if not bf and A.dtype != torch.float32:
+            raise TypeError("A must be float32 or int16 (BF16 bits)")
+        M, N = C.shape
+        K = B.shape[0]
+        self._check(self._lib.blws_gemm_lp(self.handle, self._stream(), int(bf), int(trans_a),
+                                           M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
+                                           C.data_ptr(), ldc))
 
     def small_svd_f64(self, B):
         torch = _torch()

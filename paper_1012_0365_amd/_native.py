@@ -38,6 +38,7 @@ class AlmOpts(ctypes.Structure):
         ("norm_rtol", ctypes.c_double),
         ("b_max", ctypes.c_int),
         ("b_soft", ctypes.c_int),
+        ("ladder_tol", ctypes.c_double),
     ]
 
 
@@ -52,6 +53,8 @@ class SolveInfo(ctypes.Structure):
         ("rel_residual", ctypes.c_double),
         ("norm2_D", ctypes.c_double),
         ("seconds", ctypes.c_double),
+        ("iters_bf16", ctypes.c_int),
+        ("refined", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -77,6 +80,7 @@ SIGNATURES = {
                            _vp, _i, _vp, _vp, _i, ctypes.POINTER(SolveInfo)]),
     "blws_fill_uniform": (_i, [_vp, _vp, _i, _i, _vp, _i, _ull, _ull]),
     "blws_gemm_f64": (_i, [_vp, _vp, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i]),
+    "blws_gemm_lp": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i]),
     "blws_small_svd_f64": (_i, [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp]),
     "blws_cold_block": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _i, _ull, _ull, _vp, _i, _vp,
                              _i]),

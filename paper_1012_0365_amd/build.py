@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libblws.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("BLWS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["k_gemm.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "engine.hip"]
+SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "engine.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -36,7 +36,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJ, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
+    with ThreadPoolExecutor(max_workers=min(7, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]

@@ -60,6 +60,16 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
           TC* C, int ldc, double* partial, size_t partial_elems, hipStream_t s);
 size_t gemm_partial_elems(int M, int N, int K);
 
+// W-products in FP32 on FP32 MFMA (bf16 = false: A float) or BF16 MFMA
+// (bf16 = true: A holds BF16 bits, B is rounded to BF16), FP32 accumulation:
+// C (M x N, float) = op(A) B. `partial` holds gemm_lp_partial_elems floats.
+size_t gemm_lp_partial_elems(int M, int N, int K);
+void gemm_lp(Timer* tm, const char* family, bool bf16, bool trans_a, int M, int N, int K,
+             const void* A, int lda, const float* B, int ldb, float* C, int ldc, float* partial,
+             size_t partial_elems, hipStream_t s);
+// Y[e] = BF16(X[e]) for e < count (round to nearest even).
+void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s);
+
 // Scaled LDL^T / Cholesky with breakdown detection on an n x n Gram matrix:
 // writes Rinv (n x n, ld n) such that X * Rinv has orthonormal columns when
 // G = X^T X; columns whose scaled pivot is <= eta are flagged (flags[j] = 1)
@@ -116,13 +126,14 @@ void rpca_init(int m, int n, const T* D, int ldd, double J, double mu, T* Y, T* 
 // a = sum_{k < r} U[i][k] (S[k] - eps) V[j][k] with r = #{S_k > eps} (k < b);
 // t = d - a + y / mu;  e = shrink(t, lam / mu);  z = d - a - e;
 // y' = y + mu z;  w' = d - e + y' / mu_next.
-// Writes E, Y, W, and per-workgroup partial sums of z^2 into `partials`
+// Writes E, Y, W (and its BF16 copy Wh when non-null), and per-workgroup
+// partial sums of z^2 into `partials`
 // (size alm_partials(m, n)); A_out (may be null) receives a.
 template <typename T>
 void alm_epilogue(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
                   const double* S, double eps, double lam, double mu, double mu_next,
-                  const T* D, int ldd, T* Y, T* E, int lde, T* W, T* A_out, int lda,
-                  double* partials, hipStream_t s);
+                  const T* D, int ldd, T* Y, T* E, int lde, T* W, unsigned short* Wh, T* A_out,
+                  int lda, double* partials, hipStream_t s);
 size_t alm_partials(int m, int n);
 // A = U_r diag(S_r - eps) V_r^T only.
 template <typename T>

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <type_traits>
 #include <vector>
 
 #include "blws_common.h"
@@ -148,6 +149,9 @@ struct StepWs {
                                  {n, b, b}};
         for (auto& sh : shapes) {
             size_t e = gemm_partial_elems(sh[0], sh[1], sh[2]);
+            if (e > pe) pe = e;
+            // the FP32 / BF16 W-product kernels keep FP32 partials in the same buffer
+            e = (gemm_lp_partial_elems(sh[0], sh[1], sh[2]) + 1) / 2;
             if (e > pe) pe = e;
         }
         partial_elems = pe;
@@ -302,6 +306,7 @@ struct Op {
     const T* W = nullptr;
     int ldw = 0;
     const McOp<T>* mc = nullptr;
+    const unsigned short* Wh = nullptr;  // BF16 copy of W (ld ldw): products in BF16
 };
 
 // out (rows x c) = W X (trans = false: X is n x c, rows = m) or W^T X
@@ -313,8 +318,16 @@ void op_apply(Context& cx, StepWs<T>& w, hipStream_t s, const Op<T>& op, int m, 
     Timer* tm = &cx.timer;
     const int rows = trans ? n : m, inner = trans ? m : n;
     if (op.W) {
-        gemm<T, T, T>(tm, "gemm_w", trans, rows, c, inner, 1.0, op.W, op.ldw, X, ldx, 0.0,
-                      (const T*)nullptr, 0, out, ldo, w.partial, w.partial_elems, s);
+        if constexpr (std::is_same<T, float>::value) {
+            // FP32 or BF16 matrix cores, FP32 accumulation
+            const bool bf = op.Wh != nullptr;
+            gemm_lp(tm, "gemm_w", bf, trans, rows, c, inner,
+                    bf ? (const void*)op.Wh : (const void*)op.W, op.ldw, X, ldx, out, ldo,
+                    (float*)w.partial, 2 * w.partial_elems, s);
+        } else {
+            gemm<T, T, T>(tm, "gemm_w", trans, rows, c, inner, 1.0, op.W, op.ldw, X, ldx, 0.0,
+                          (const T*)nullptr, 0, out, ldo, w.partial, w.partial_elems, s);
+        }
         return;
     }
     const McOp<T>& mc = *op.mc;
@@ -448,7 +461,8 @@ struct Readback {
 
 template <typename T>
 int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, double lambda,
-                 const blws_alm_opts& o, T* A, int lda, T* E, int lde, blws_solve_info* info)
+                 const blws_alm_opts& o, T* A, int lda, T* E, int lde, blws_solve_info* info,
+                 bool ladder = false)
 {
     auto t0 = std::chrono::steady_clock::now();
     const int p = m < n ? m : n;
@@ -458,11 +472,13 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
 
     // workspace layout
     StepWs<T> w;
+    unsigned short* Wh = nullptr;  // BF16 copy of W (precision ladder)
     auto layout = [&](Carver& c, T*& Y, T*& Wb, T*& U, T*& V, double*& S, double*& part,
                       double*& scal, int*& rank_dev, long long*& nnz_scr, Readback*& rb) {
         w.carve(c, m, n, bmax);
         Y = c.take<T>(mn);
         Wb = c.take<T>(mn);
+        Wh = c.take<unsigned short>(ladder ? mn : 1);
         U = c.take<T>((size_t)m * bmax);
         V = c.take<T>((size_t)n * bmax);
         S = c.take<double>(bmax);
@@ -528,13 +544,22 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
     double mu = o.mu0_scale / s1;
     const double mu_bar = mu * o.mu_max_factor;
     rpca_init<T>(m, n, D, ldd, J, mu, Y, E, lde, Wb, s);
+    if constexpr (std::is_same<T, float>::value)
+        if (ladder) to_bf16((long long)mn, Wb, Wh, s);
 
     int sv = o.sv0, b = 0, svp = 0, it = 0;
-    double rel = INFINITY, eps = 0.0;
+    double rel = INFINITY, rel_prev = INFINITY, eps = 0.0;
     const int np = (int)alm_partials(m, n);
-    const Op<T> opW{Wb, n, nullptr};
+    // precision ladder: BF16 products while the residual is at or above
+    // ladder_tol (or until it stops decreasing), FP32 afterwards
+    bool bf = ladder, last_bf = false, refined = false;
+    int iters_bf = 0;
+    Op<T> opW{Wb, n, nullptr, nullptr};
     for (it = 1; it <= o.max_iter; ++it) {
         eps = 1.0 / mu;
+        opW.Wh = bf ? Wh : nullptr;
+        last_bf = bf;
+        iters_bf += bf ? 1 : 0;
         const int bn = block_width(sv, svp, o, p);
         if (b == 0) {
             cold_block<T>(cx, w, s, m, n, opW, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
@@ -546,7 +571,7 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
         svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         const double mu_next = (o.rho * mu < mu_bar) ? o.rho * mu : mu_bar;
         alm_epilogue<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, lambda, mu, mu_next, D, ldd,
-                        Y, E, lde, Wb, (T*)nullptr, 0, part, s);
+                        Y, E, lde, Wb, bf ? Wh : nullptr, (T*)nullptr, 0, part, s);
         sum_partials(np, part, &rb->zz, s);
         HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
         HIP_TRY(hipMemcpyAsync(&rb->svd_err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToDevice,
@@ -560,9 +585,34 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
         sv = predict_rank(svp, sv, o.sv_step_frac, p);
         mu = mu_next;
         rel = std::sqrt(hrb->zz) / dnorm;
-        if (rel < o.tol) break;
+        if (bf && (rel < o.ladder_tol || (it >= 3 && rel >= rel_prev))) bf = false;
+        rel_prev = rel;
+        if (rel < o.tol) {
+            if (last_bf) {
+                // refinement: the last iterate came from BF16 products; one more
+                // ALM step with FP32 products (FP64 Rayleigh-Ritz, FP64
+                // reconstruction)
+                refined = true;
+                eps = 1.0 / mu;
+                opW.Wh = nullptr;
+                svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+                const double mu_n2 = (o.rho * mu < mu_bar) ? o.rho * mu : mu_bar;
+                alm_epilogue<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, lambda, mu, mu_n2,
+                                D, ldd, Y, E, lde, Wb, nullptr, (T*)nullptr, 0, part, s);
+                sum_partials(np, part, &rb->zz, s);
+                HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice,
+                                       s));
+                HIP_TRY(hipMemcpyAsync(hrb, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
+                HIP_TRY(hipStreamSynchronize(s));
+                svp = hrb->rank;
+                rel = std::sqrt(hrb->zz) / dnorm;
+                mu = mu_n2;
+            }
+            break;
+        }
     }
-    if (it > o.max_iter) it = o.max_iter;
+    // ALM steps taken (the refinement step included)
+    const int steps = (it > o.max_iter ? o.max_iter : it) + (refined ? 1 : 0);
     svt_reconstruct<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, A, lda, s);
     count_nonzeros<T>(m, n, E, lde, &rb->nnz, nnz_scr, s);
     HIP_TRY(hipMemcpyAsync(&rb->nflag, w.nflag, sizeof(int), hipMemcpyDeviceToDevice, s));
@@ -570,11 +620,13 @@ int rpca_solve_t(Context& cx, hipStream_t s, int m, int n, const T* D, int ldd, 
     HIP_TRY(hipStreamSynchronize(s));
     if (info) {
         info->status = rel < o.tol ? BLWS_OK : BLWS_NOT_CONVERGED;
-        info->iters = it;
+        info->iters = steps;
         info->rank = svp;
         info->b_final = b;
         info->fallbacks = hrb->nflag;
         info->nnz_E = hrb->nnz;
+        info->iters_bf16 = iters_bf;
+        info->refined = refined ? 1 : 0;
         info->rel_residual = rel;
         info->norm2_D = s1;
         info->seconds =
@@ -765,6 +817,8 @@ int mc_solve_t(Context& cx, hipStream_t s, int m, int n, int nnz, const int* row
         info->b_final = b;
         info->fallbacks = hrb->nflag;
         info->nnz_E = 0;
+        info->iters_bf16 = 0;
+        info->refined = 0;
         info->rel_residual = rel;
         info->norm2_D = s1;
         info->seconds =
@@ -876,6 +930,7 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->norm_rtol = 1e-13;
     o->b_max = 256;
     o->b_soft = 112;
+    o->ladder_tol = 1e-3;
 }
 
 void blws_default_svt_opts(blws_svt_opts* o)
@@ -929,16 +984,17 @@ int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
     BLWS_REQUIRE(o.tol > 0.0 && o.max_iter >= 1 && o.rho >= 1.0 && o.mu0_scale > 0.0 &&
                      o.mu_max_factor >= 1.0 && o.sv0 >= 1 && o.b_round >= 1 &&
                      o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
-                     o.b_soft >= 1,
+                     o.b_soft >= 1 && o.ladder_tol >= 0.0,
                  BLWS_EINVAL, "blws_rpca_solve: bad options");
     BLWS_REQUIRE(o.b_max <= 256, BLWS_EUNSUPPORTED, "blws_rpca_solve: b_max above 256");
     hipStream_t s = (hipStream_t)stream;
     if (prec == BLWS_FP64)
         return blws::rpca_solve_t<double>(cx, s, m, n, (const double*)D, ldd, lambda, o,
                                           (double*)A, lda, (double*)E, lde, info);
-    if (prec == BLWS_FP32)
+    if (prec == BLWS_FP32 || prec == BLWS_BF16)
         return blws::rpca_solve_t<float>(cx, s, m, n, (const float*)D, ldd, lambda, o,
-                                         (float*)A, lda, (float*)E, lde, info);
+                                         (float*)A, lda, (float*)E, lde, info,
+                                         prec == BLWS_BF16);
     throw BlwsError{BLWS_EUNSUPPORTED, "blws_rpca_solve: precision not supported"};
     ABI_END
 }
@@ -1009,6 +1065,22 @@ int blws_gemm_f64(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K, 
     blws::gemm<double, double, double>(&cx.timer, "gemm_diag", trans_a != 0, M, N, K, alpha, A,
                                        lda, B, ldb, beta, C, ldc, C, ldc, (double*)cx.ws, pe + 1,
                                        (hipStream_t)stream);
+    return BLWS_OK;
+    ABI_END
+}
+
+int blws_gemm_lp(blws_ctx ctx, void* stream, int bf16, int trans_a, int M, int N, int K,
+                 const void* A, int lda, const float* B, int ldb, float* C, int ldc)
+{
+    ABI_BEGIN(ctx)
+    BLWS_REQUIRE(M >= 0 && N >= 0 && K >= 1 && A && B && C, BLWS_EINVAL,
+                 "blws_gemm_lp: bad arguments");
+    BLWS_REQUIRE(ldb >= N && ldc >= N && lda >= (trans_a ? M : K), BLWS_EINVAL,
+                 "blws_gemm_lp: leading dimension too small");
+    const size_t pe = blws::gemm_lp_partial_elems(M, N, K);
+    cx.ensure((pe + 1) * sizeof(float) + 256);
+    blws::gemm_lp(&cx.timer, "gemm_diag", bf16 != 0, trans_a != 0, M, N, K, A, lda, B, ldb, C,
+                  ldc, (float*)cx.ws, pe + 1, (hipStream_t)stream);
     return BLWS_OK;
     ABI_END
 }

@@ -22,6 +22,15 @@ __device__ __forceinline__ double rd(const T* p)
     return (double)(*p);
 }
 
+// FP32 -> BF16 bits, round to nearest even (the BF16 copy of W).
+__device__ __forceinline__ unsigned short bf16_rne(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -42,7 +51,8 @@ __global__ __launch_bounds__(256) void svt_tile_kernel(
     int m, int n, int b, const T* __restrict__ U, int ldu, const T* __restrict__ V, int ldv,
     const double* __restrict__ S, double eps, double lam, double mu, double mu_next,
     const T* __restrict__ D, int ldd, T* __restrict__ Y, T* __restrict__ E, int lde,
-    T* __restrict__ W, T* __restrict__ A_out, int lda, double* __restrict__ partials)
+    T* __restrict__ W, unsigned short* __restrict__ Wh, T* __restrict__ A_out, int lda,
+    double* __restrict__ partials)
 {
     __shared__ double Us[EBK][TILE + 1];
     __shared__ double Vs[EBK][TILE + 1];
@@ -113,7 +123,9 @@ __global__ __launch_bounds__(256) void svt_tile_kernel(
             const double y2 = y + mu * z;
             E[(size_t)row * lde + col] = (T)e;
             Y[ye] = (T)y2;
-            W[ye] = (T)(d - e + y2 / mu_next);
+            const T wn = (T)(d - e + y2 / mu_next);
+            W[ye] = wn;
+            if (Wh) Wh[ye] = bf16_rne((float)wn);
             if (A_out) A_out[(size_t)row * lda + col] = (T)a;
             zz += z * z;
         }
@@ -256,15 +268,15 @@ size_t alm_partials(int m, int n)
 template <typename T>
 void alm_epilogue(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
                   const double* S, double eps, double lam, double mu, double mu_next, const T* D,
-                  int ldd, T* Y, T* E, int lde, T* W, T* A_out, int lda, double* partials,
-                  hipStream_t s)
+                  int ldd, T* Y, T* E, int lde, T* W, unsigned short* Wh, T* A_out, int lda,
+                  double* partials, hipStream_t s)
 {
     dim3 grid((n + TILE - 1) / TILE, (m + TILE - 1) / TILE);
     // algorithmic traffic: read D, Y; write E, Y, W (A itself is never stored)
     TimedLaunch tl(tm, "alm_epilogue", s, 2.0 * m * (double)n * b,
                    5.0 * sizeof(T) * (double)m * n);
     hipLaunchKernelGGL((svt_tile_kernel<T, 0>), grid, dim3(256), 0, s, m, n, b, U, ldu, V, ldv, S,
-                       eps, lam, mu, mu_next, D, ldd, Y, E, lde, W, A_out, lda, partials);
+                       eps, lam, mu, mu_next, D, ldd, Y, E, lde, W, Wh, A_out, lda, partials);
 }
 
 template <typename T>
@@ -276,7 +288,7 @@ void svt_reconstruct(Timer* tm, int m, int n, int b, const T* U, int ldu, const 
                    sizeof(T) * (double)m * n);
     hipLaunchKernelGGL((svt_tile_kernel<T, 1>), grid, dim3(256), 0, s, m, n, b, U, ldu, V, ldv, S,
                        eps, 0.0, 1.0, 1.0, (const T*)nullptr, 0, (T*)nullptr, (T*)nullptr, 0,
-                       (T*)nullptr, A, lda, (double*)nullptr);
+                       (T*)nullptr, (unsigned short*)nullptr, A, lda, (double*)nullptr);
 }
 
 void sum_partials(int count, const double* partials, double* out, hipStream_t s)
@@ -298,7 +310,8 @@ void count_nonzeros(int m, int n, const T* X, int ldx, long long* out, long long
                                hipStream_t);                                                   \
     template void alm_epilogue<T>(Timer*, int, int, int, const T*, int, const T*, int,          \
                                   const double*, double, double, double, double, const T*, int, \
-                                  T*, T*, int, T*, T*, int, double*, hipStream_t);              \
+                                  T*, T*, int, T*, unsigned short*, T*, int, double*,           \
+                                  hipStream_t);                                                 \
     template void svt_reconstruct<T>(Timer*, int, int, int, const T*, int, const T*, int,       \
                                      const double*, double, T*, int, hipStream_t);             \
     template void count_nonzeros<T>(int, int, const T*, int, long long*, long long*,            \

@@ -1,0 +1,307 @@
+// Block products W X and W^T X in FP32 and BF16 on CDNA4 matrix cores.
+//
+// The products of the Lanczos block with W (Algorithm 2) are the only work of
+// the BLWS step that touches the big matrix. In the FP32 and BF16 precision
+// modes they run on v_mfma_f32_16x16x4f32 (FP32 inputs) or
+// v_mfma_f32_16x16x32_bf16 (W kept as a BF16 copy, the block rounded to BF16
+// on the way into LDS), accumulating in FP32. Tiling as the FP64 kernel: a
+// workgroup owns 64 rows of C (four wavefronts x 16) and 16 * NT columns;
+// long K is split across workgroups and the FP32 partials are summed in a
+// fixed order (in FP64) by a second kernel.
+#include "blws_common.h"
+
+namespace blws {
+namespace {
+
+constexpr int LBM = 64;
+constexpr int LNTHREADS = 256;
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef short s8 __attribute__((ext_vector_type(8)));
+
+// FP32 -> BF16 with round-to-nearest-even (finite inputs; NaN stays NaN).
+__device__ __forceinline__ unsigned short f2bf(float f)
+{
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u) return (unsigned short)((u >> 16) | ((u & 0xFFFF) ? 0x40 : 0));
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+template <typename T>
+__device__ __forceinline__ unsigned short to_bf(T v);
+template <>
+__device__ __forceinline__ unsigned short to_bf<float>(float v) { return f2bf(v); }
+template <>
+__device__ __forceinline__ unsigned short to_bf<unsigned short>(unsigned short v) { return v; }
+
+template <typename T>
+__device__ __forceinline__ float to_f(T v);
+template <>
+__device__ __forceinline__ float to_f<float>(float v) { return v; }
+
+// FP32 mode: A, B float; LDS k-major; BK = 32 (8 MFMA steps of k = 4).
+template <bool TRANS, int NT>
+__global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K, int kchunk,
+                                                             const float* __restrict__ A, int lda,
+                                                             const float* __restrict__ B, int ldb,
+                                                             float* __restrict__ C, int ldc,
+                                                             float* __restrict__ partial)
+{
+    constexpr int BK = 32, BN = 16 * NT;
+    __shared__ float As[BK][LBM + 1];
+    __shared__ float Bs[BK][BN + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * LBM, c0 = blockIdx.y * BN;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+    f4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            const int row = tid >> 2, kq = (tid & 3) * 8;
+            const int gr = r0 + row;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int gk = k0 + kq + u;
+                As[kq + u][row] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : 0.f;
+            }
+        } else {
+            const int kr = tid >> 3, rq = (tid & 7) * 8;
+            const int gk = k0 + kr;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int gr = r0 + rq + u;
+                As[kr][rq + u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : 0.f;
+            }
+        }
+        for (int e = tid; e < BK * BN; e += LNTHREADS) {
+            const int kr = e / BN, cc = e - kr * BN;
+            const int gk = k0 + kr, gc = c0 + cc;
+            Bs[kr][cc] = (gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 4; ++kk) {
+            const float a = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const float bv = Bs[kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // FP32 16x16 tile (measured on gfx950): register i of lane l holds row
+    // 4 (l / 16) + i, column l % 16.
+    const int rbase = r0 + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int col = c0 + j * 16 + (lane & 15);
+        if (col >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = rbase + i;
+            if (row >= M) continue;
+            if (partial)
+                partial[((size_t)blockIdx.z * M + row) * N + col] = acc[j][i];
+            else
+                C[(size_t)row * ldc + col] = acc[j][i];
+        }
+    }
+}
+
+// BF16 mode: A is BF16 bits (the W copy), B float rounded to BF16 into LDS.
+// LDS row-major in k (8 consecutive k per lane fragment); BK = 64 (2 MFMA
+// steps of k = 32).
+template <bool TRANS, int NT>
+__global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
+    int M, int N, int K, int kchunk, const unsigned short* __restrict__ A, int lda,
+    const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+    float* __restrict__ partial)
+{
+    constexpr int BK = 64, BN = 16 * NT, LDK = BK + 8;
+    __shared__ __attribute__((aligned(16))) unsigned short As[LBM][LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[BN][LDK];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * LBM, c0 = blockIdx.y * BN;
+    const int kb = blockIdx.z * kchunk;
+    const int ke = min(K, kb + kchunk);
+    f4 acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            const int row = tid >> 2, kq = (tid & 3) * 16;
+            const int gr = r0 + row;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int gk = k0 + kq + u;
+                As[row][kq + u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
+            }
+        } else {
+            const int kr = tid >> 2, rq = (tid & 3) * 16;
+            const int gk = k0 + kr;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int gr = r0 + rq + u;
+                As[rq + u][kr] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
+            }
+        }
+        for (int e = tid; e < BK * BN; e += LNTHREADS) {
+            const int kr = e / BN, cc = e - kr * BN;
+            const int gk = k0 + kr, gc = c0 + cc;
+            Bs[cc][kr] = (gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc]) : (unsigned short)0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK / 32; ++kk) {
+            const s8 a = *(const s8*)&As[wave * 16 + (lane & 15)][kk * 32 + 8 * (lane >> 4)];
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const s8 bv = *(const s8*)&Bs[j * 16 + (lane & 15)][kk * 32 + 8 * (lane >> 4)];
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    const int rbase = r0 + wave * 16 + 4 * (lane >> 4);
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int col = c0 + j * 16 + (lane & 15);
+        if (col >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = rbase + i;
+            if (row >= M) continue;
+            if (partial)
+                partial[((size_t)blockIdx.z * M + row) * N + col] = acc[j][i];
+            else
+                C[(size_t)row * ldc + col] = acc[j][i];
+        }
+    }
+}
+
+__global__ void reduce_f32_kernel(int M, int N, int S, const float* partial, float* C, int ldc)
+{
+    const size_t total = (size_t)M * N;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        double acc = 0.0;
+        for (int s = 0; s < S; ++s) acc += (double)partial[(size_t)s * total + e];
+        const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
+        C[(size_t)row * ldc + col] = (float)acc;
+    }
+}
+
+__global__ void to_bf16_kernel(long long count, const float* __restrict__ X,
+                               unsigned short* __restrict__ Y)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < count;
+         e += (long long)gridDim.x * blockDim.x)
+        Y[e] = f2bf(X[e]);
+}
+
+struct PlanLp {
+    int nt, gy, gx, splits, kchunk;
+};
+
+PlanLp make_plan_lp(int M, int N, int K, int BK)
+{
+    PlanLp p;
+    p.nt = N >= 128 ? 8 : (N + 15) / 16;
+    if (p.nt < 1) p.nt = 1;
+    p.gy = (N + 16 * p.nt - 1) / (16 * p.nt);
+    p.gx = (M + LBM - 1) / LBM;
+    const long tiles = (long)p.gx * p.gy;
+    long s = (512 + tiles - 1) / tiles;
+    const long smax_k = (K + 4 * BK - 1) / (4 * BK);
+    if (s > smax_k) s = smax_k;
+    const long smax_mem = (8L << 20) / ((long)M * N > 0 ? (long)M * N : 1);
+    if (s > smax_mem) s = smax_mem;
+    if (s < 1) s = 1;
+    int kchunk = (int)((K + s - 1) / s);
+    kchunk = ((kchunk + BK - 1) / BK) * BK;
+    if (kchunk < BK) kchunk = BK;
+    p.kchunk = kchunk;
+    p.splits = (K + kchunk - 1) / kchunk;
+    if (p.splits < 1) p.splits = 1;
+    return p;
+}
+
+}  // namespace
+
+size_t gemm_lp_partial_elems(int M, int N, int K)
+{
+    const PlanLp p1 = make_plan_lp(M, N, K, 32), p2 = make_plan_lp(M, N, K, 64);
+    const int s = p1.splits > p2.splits ? p1.splits : p2.splits;
+    return s > 1 ? (size_t)s * M * N : 0;
+}
+
+void gemm_lp(Timer* tm, const char* family, bool bf16, bool trans_a, int M, int N, int K,
+             const void* A, int lda, const float* B, int ldb, float* C, int ldc, float* partial,
+             size_t partial_elems, hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return;
+    BLWS_REQUIRE(K > 0, BLWS_EINVAL, "gemm_lp: K must be positive");
+    const PlanLp p = make_plan_lp(M, N, K, bf16 ? 64 : 32);
+    const bool split = p.splits > 1;
+    BLWS_REQUIRE(!split || (partial && partial_elems >= (size_t)p.splits * M * N), BLWS_ENOMEM,
+                 "gemm_lp: split-K scratch too small");
+    TimedLaunch tl(tm, family, s, 2.0 * M * N * (double)K,
+                   (bf16 ? 2.0 : 4.0) * (double)M * K + 4.0 * ((double)K * N + (double)M * N));
+    dim3 grid(p.gx, p.gy, p.splits), block(LNTHREADS);
+    float* part = split ? partial : nullptr;
+#define BLWS_LP_CASE(NTV)                                                                      \
+    case NTV:                                                                                  \
+        if (bf16) {                                                                            \
+            if (trans_a)                                                                       \
+                hipLaunchKernelGGL((gemm_bf16_kernel<true, NTV>), grid, block, 0, s, M, N, K,  \
+                                   p.kchunk, (const unsigned short*)A, lda, B, ldb, C, ldc,     \
+                                   part);                                                      \
+            else                                                                               \
+                hipLaunchKernelGGL((gemm_bf16_kernel<false, NTV>), grid, block, 0, s, M, N, K, \
+                                   p.kchunk, (const unsigned short*)A, lda, B, ldb, C, ldc,     \
+                                   part);                                                      \
+        } else {                                                                               \
+            if (trans_a)                                                                       \
+                hipLaunchKernelGGL((gemm_f32_kernel<true, NTV>), grid, block, 0, s, M, N, K,   \
+                                   p.kchunk, (const float*)A, lda, B, ldb, C, ldc, part);       \
+            else                                                                               \
+                hipLaunchKernelGGL((gemm_f32_kernel<false, NTV>), grid, block, 0, s, M, N, K,  \
+                                   p.kchunk, (const float*)A, lda, B, ldb, C, ldc, part);       \
+        }                                                                                      \
+        break;
+    switch (p.nt) {
+        BLWS_LP_CASE(1)
+        BLWS_LP_CASE(2)
+        BLWS_LP_CASE(3)
+        BLWS_LP_CASE(4)
+        BLWS_LP_CASE(5)
+        BLWS_LP_CASE(6)
+        BLWS_LP_CASE(7)
+        default:
+            BLWS_LP_CASE(8)
+    }
+#undef BLWS_LP_CASE
+    if (split) {
+        const size_t total = (size_t)M * N;
+        int blocks = (int)((total + 255) / 256);
+        if (blocks > 2048) blocks = 2048;
+        hipLaunchKernelGGL(reduce_f32_kernel, dim3(blocks), dim3(256), 0, s, M, N, p.splits,
+                           partial, C, ldc);
+    }
+}
+
+void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s)
+{
+    if (count <= 0) return;
+    long long blocks = (count + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((unsigned)blocks), dim3(256), 0, s, count, X, Y);
+}
+
+}  // namespace blws
