@@ -199,6 +199,69 @@ int blws_timing_enable(blws_ctx ctx, int enable);
 int blws_timing_get(blws_ctx ctx, const char* name, long long* launches, double* ms,
                     double* flops, double* bytes);
 
+/* ------------------------------------------------------------------------
+ * Request server (serving many solves on one GPU).
+ *
+ * RPCA and matrix-completion requests of any sizes are submitted at any time
+ * and run with continuous batching: a scheduler thread keeps up to max_slots
+ * solves in flight, each on its own stream with its own workspace (D, E, Y or
+ * the samples and multipliers, and the warm Lanczos block stay resident in
+ * HBM until the solve ends), and advances whichever solve's last step has
+ * finished, so the work of different requests overlaps on the device.
+ * Requests are admitted in submission order as soon as a slot is free and
+ * their workspace fits the memory budget next to the solves in flight (a
+ * request larger than the budget runs alone). Each request computes exactly
+ * what blws_rpca_solve / blws_mc_solve compute for the same arguments,
+ * whatever else is in flight.
+ *
+ * Buffers: the input buffers must hold their data when submit is called (the
+ * server's streams do not wait on the caller's streams) and, like the output
+ * buffers, stay valid and untouched until the request is reported done. Every
+ * request is retrieved once, by blws_server_poll or blws_server_wait.
+ * info->seconds is the latency from submit to completion.
+ * ------------------------------------------------------------------------ */
+typedef struct blws_server_s* blws_server;
+
+typedef struct {
+    int max_slots;     /* solves in flight at once, 1..16 (4)                          */
+    size_t mem_budget; /* device bytes the in-flight solves' workspaces may hold;      */
+                       /* 0 selects 80% of the free device memory at creation (0)       */
+} blws_server_opts;
+
+typedef struct {
+    long long submitted, completed, failed;
+    int active;        /* solves in flight now                                         */
+    int queued;        /* requests waiting for admission                               */
+    int max_active;    /* most solves in flight at once so far                         */
+    size_t mem_in_use, mem_peak, mem_budget;
+} blws_server_stats;
+
+void blws_default_server_opts(blws_server_opts* opts);
+/* Start a server on HIP device `device` (opts may be NULL). */
+int blws_server_create(blws_server* out, int device, const blws_server_opts* opts);
+/* Finish every submitted request, then release the server. */
+int blws_server_destroy(blws_server srv);
+/* Queue a robust-PCA solve (arguments as blws_rpca_solve; prec FP64, FP32 or
+ * BF16). Arguments are checked here: on an error nothing is queued. On
+ * success *ticket (host) identifies the request. */
+int blws_server_submit_rpca(blws_server srv, int prec, int m, int n, const void* D, int ldd,
+                            double lambda, const blws_alm_opts* opts, void* A, int lda, void* E,
+                            int lde, long long* ticket);
+/* Queue a matrix-completion solve (arguments as blws_mc_solve). */
+int blws_server_submit_mc(blws_server srv, int prec, int m, int n, int nnz, const int* row_ptr,
+                          const int* col_idx, const void* values, const blws_alm_opts* opts,
+                          int r_cap, void* U, int ldu, double* S, void* V, int ldv,
+                          long long* ticket);
+/* *done = 1 and the request's status returned (info filled, may be NULL) once
+ * it has finished; *done = 0 and BLWS_OK while it is queued or running.
+ * BLWS_EINVAL for an unknown or already retrieved ticket. */
+int blws_server_poll(blws_server srv, long long ticket, int* done, blws_solve_info* info);
+/* Block until the request has finished; returns its status. */
+int blws_server_wait(blws_server srv, long long ticket, blws_solve_info* info);
+int blws_server_get_stats(blws_server srv, blws_server_stats* stats);
+/* Detail of the last failure seen through this server (never NULL). */
+const char* blws_server_last_error(blws_server srv);
+
 #ifdef __cplusplus
 }
 #endif

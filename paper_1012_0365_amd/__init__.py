@@ -16,10 +16,10 @@ from __future__ import annotations
 import ctypes
 
 from . import _native
-from ._native import AlmOpts, BlwsError, SolveInfo, SvtOpts
+from ._native import AlmOpts, BlwsError, ServerOpts, ServerStats, SolveInfo, SvtOpts
 
-__all__ = ["Context", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo", "default_alm_opts",
-           "default_mc_opts"]
+__all__ = ["Context", "Server", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo",
+           "default_alm_opts", "default_mc_opts"]
 
 
 def _torch():
@@ -240,3 +240,115 @@ class Context:
         self._check(self._lib.blws_timing_get(self.handle, name.encode(), ctypes.byref(n),
                                               ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)))
         return {"launches": n.value, "ms": ms.value, "flops": fl.value, "bytes": by.value}
+
+
+class Server:
+    """Request server: RPCA and MC solves submitted at any time and run with
+    continuous batching (up to max_slots in flight, each on its own stream,
+    admitted by workspace footprint against mem_budget bytes; 0 = 80% of free
+    device memory). Results are those of Context.rpca_solve / mc_solve."""
+
+    def __init__(self, device: int = 0, max_slots: int = 4, mem_budget: int = 0):
+        self._lib = _native.lib()
+        o = ServerOpts()
+        self._lib.blws_default_server_opts(ctypes.byref(o))
+        o.max_slots = max_slots
+        o.mem_budget = mem_budget
+        h = ctypes.c_void_p()
+        st = self._lib.blws_server_create(ctypes.byref(h), device, ctypes.byref(o))
+        if st < 0:
+            raise BlwsError(st, self._lib.blws_server_last_error(None).decode())
+        self.handle = h
+        self.device = device
+        self._keep = {}  # ticket -> (kind, tensors kept alive until retrieved)
+
+    def _check(self, st):
+        if st < 0:
+            raise BlwsError(st, self._lib.blws_server_last_error(self.handle).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.blws_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit_rpca(self, D, lam: float | None = None, opts: AlmOpts | None = None,
+                    bf16: bool = False) -> int:
+        torch = _torch()
+        prec = _prec_of(D)
+        if bf16:
+            if prec != _native.BLWS_FP32:
+                raise TypeError("the BF16 ladder takes float32 D")
+            prec = _native.BLWS_BF16
+        ldd = _check_mat(D, "D")
+        m, n = D.shape
+        A = torch.empty(m, n, dtype=D.dtype, device=D.device)
+        E = torch.empty(m, n, dtype=D.dtype, device=D.device)
+        torch.cuda.current_stream(D.device).synchronize()  # inputs ready before the server reads
+        t = ctypes.c_longlong()
+        self._check(self._lib.blws_server_submit_rpca(
+            self.handle, prec, m, n, D.data_ptr(), ldd, -1.0 if lam is None else float(lam),
+            ctypes.byref(opts) if opts is not None else None, A.data_ptr(), n, E.data_ptr(), n,
+            ctypes.byref(t)))
+        self._keep[t.value] = ("rpca", D, A, E)
+        return t.value
+
+    def submit_mc(self, m: int, n: int, row_ptr, col_idx, values, opts: AlmOpts | None = None,
+                  r_cap: int = 256) -> int:
+        torch = _torch()
+        prec = _prec_of(values)
+        if row_ptr.dtype != torch.int32 or col_idx.dtype != torch.int32:
+            raise TypeError("row_ptr and col_idx must be int32")
+        if row_ptr.numel() != m + 1 or col_idx.numel() != values.numel():
+            raise ValueError("row_ptr must hold m + 1 entries and col_idx one per value")
+        U = torch.zeros(m, r_cap, dtype=values.dtype, device=values.device)
+        V = torch.zeros(n, r_cap, dtype=values.dtype, device=values.device)
+        S = torch.zeros(r_cap, dtype=torch.float64, device=values.device)
+        torch.cuda.current_stream(values.device).synchronize()
+        t = ctypes.c_longlong()
+        self._check(self._lib.blws_server_submit_mc(
+            self.handle, prec, m, n, values.numel(), row_ptr.data_ptr(), col_idx.data_ptr(),
+            values.data_ptr(), ctypes.byref(opts) if opts is not None else None, r_cap,
+            U.data_ptr(), r_cap, S.data_ptr(), V.data_ptr(), r_cap, ctypes.byref(t)))
+        self._keep[t.value] = ("mc", row_ptr, col_idx, values, U, S, V)
+        return t.value
+
+    def _result(self, ticket, st, info):
+        kept = self._keep.pop(ticket)
+        self._check(st)
+        d = info.as_dict()
+        if kept[0] == "rpca":
+            return kept[2], kept[3], d
+        U, S, V = kept[4], kept[5], kept[6]
+        r = min(d["rank"], U.shape[1])
+        return U[:, :r], S[:r], V[:, :r], d
+
+    def poll(self, ticket: int):
+        """None while the request runs, else its result (as wait)."""
+        done = ctypes.c_int()
+        info = SolveInfo()
+        st = self._lib.blws_server_poll(self.handle, ticket, ctypes.byref(done),
+                                        ctypes.byref(info))
+        if st < 0 and not done.value:
+            self._check(st)
+        if not done.value:
+            return None
+        return self._result(ticket, st, info)
+
+    def wait(self, ticket: int):
+        """(A, E, info) for RPCA, (U, S, V, info) for MC."""
+        info = SolveInfo()
+        st = self._lib.blws_server_wait(self.handle, ticket, ctypes.byref(info))
+        return self._result(ticket, st, info)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        self._check(self._lib.blws_server_get_stats(self.handle, ctypes.byref(st)))
+        return st.as_dict()

@@ -61,6 +61,27 @@ class SolveInfo(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int), ("mem_budget", ctypes.c_size_t)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_longlong),
+        ("completed", ctypes.c_longlong),
+        ("failed", ctypes.c_longlong),
+        ("active", ctypes.c_int),
+        ("queued", ctypes.c_int),
+        ("max_active", ctypes.c_int),
+        ("mem_in_use", ctypes.c_size_t),
+        ("mem_peak", ctypes.c_size_t),
+        ("mem_budget", ctypes.c_size_t),
+    ]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 # (name, restype, argtypes) for every exported entry point
 _vp, _i, _d, _ll, _ull = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_longlong, \
     ctypes.c_ulonglong
@@ -84,6 +105,17 @@ SIGNATURES = {
     "blws_small_svd_f64": (_i, [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp]),
     "blws_cold_block": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _i, _ull, _ull, _vp, _i, _vp,
                              _i]),
+    "blws_default_server_opts": (None, [ctypes.POINTER(ServerOpts)]),
+    "blws_server_create": (_i, [ctypes.POINTER(_vp), _i, ctypes.POINTER(ServerOpts)]),
+    "blws_server_destroy": (_i, [_vp]),
+    "blws_server_submit_rpca": (_i, [_vp, _i, _i, _i, _vp, _i, _d, ctypes.POINTER(AlmOpts), _vp,
+                                     _i, _vp, _i, ctypes.POINTER(_ll)]),
+    "blws_server_submit_mc": (_i, [_vp, _i, _i, _i, _i, _vp, _vp, _vp, ctypes.POINTER(AlmOpts),
+                                   _i, _vp, _i, _vp, _vp, _i, ctypes.POINTER(_ll)]),
+    "blws_server_poll": (_i, [_vp, _ll, ctypes.POINTER(_i), ctypes.POINTER(SolveInfo)]),
+    "blws_server_wait": (_i, [_vp, _ll, ctypes.POINTER(SolveInfo)]),
+    "blws_server_get_stats": (_i, [_vp, ctypes.POINTER(ServerStats)]),
+    "blws_server_last_error": (ctypes.c_char_p, [_vp]),
     "blws_timing_enable": (_i, [_vp, _i]),
     "blws_timing_get": (_i, [_vp, ctypes.c_char_p, ctypes.POINTER(_ll), ctypes.POINTER(_d),
                              ctypes.POINTER(_d), ctypes.POINTER(_d)]),

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libblws.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("BLWS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "engine.hip"]
+SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "engine.hip", "server.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
