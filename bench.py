@@ -6,7 +6,12 @@ stop at ||D - A - E||_F / ||D||_F < 1e-7).
 A step is one full solve (all ALM iterations, each one BLWS SVT step plus the
 fused epilogue), with D resident in HBM. Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--prec f64|f32] [--no-cpu] [--no-plain]
+    python bench.py [--steps K] [--warmup W] [--prec f64|f32|bf16] [--no-cpu] [--no-plain]
+    python bench.py --workload serving [--requests R]   # the request-server mix
+
+The roofline entry is for the kernel family with the largest total time in
+the timed region, from HIP events recorded around each launch on the stream
+it runs on; `kernels` lists every family.
 """
 
 from __future__ import annotations
@@ -30,21 +35,34 @@ SEED = 0
 
 # MI355X published peaks
 PEAK = {
-    "hbm_GBs": 8000.0,
-    "mfma_f64_TFs": 78.6,
-    "mfma_f32_TFs": 157.3,
-    "valu_f64_TFs": 78.6,
+    "hbm": 8000.0,        # GB/s
+    "mfma_f64": 78.6,     # TFLOP/s dense
+    "mfma_f32": 157.3,
+    "mfma_bf16": 2500.0,
+    "valu_f64": 78.6,
 }
 
-# kernel family -> (bound, peak key, unit) for the roofline report
+# kernel family -> (bound, peak key or None for "by precision", unit)
 FAMILY_BOUND = {
     "gemm_w": ("mfma", None, "TFLOP/s"),
-    "gemm_ts": ("mfma", None, "TFLOP/s"),
-    "alm_epilogue": ("hbm", "hbm_GBs", "GB/s"),
-    "svt_reconstruct": ("mfma", None, "TFLOP/s"),
-    "small_svd": ("alu", "valu_f64_TFs", "TFLOP/s"),
-    "chol": ("alu", "valu_f64_TFs", "TFLOP/s"),
+    "gemm_ts": ("mfma", "mfma_f64", "TFLOP/s"),
+    "gemm_lr": ("mfma", "mfma_f64", "TFLOP/s"),
+    "alm_epilogue": ("hbm", "hbm", "GB/s"),
+    "svt_reconstruct": ("hbm", "hbm", "GB/s"),
+    "spmm": ("hbm", "hbm", "GB/s"),
+    "mc_update": ("hbm", "hbm", "GB/s"),
 }
+COMPOSITE = {"small_svd"}  # timed around several other families
+
+
+def family_bound(name, prec):
+    if name in FAMILY_BOUND:
+        bound, key, unit = FAMILY_BOUND[name]
+    else:  # one-workgroup / latency-bound FP64 kernels: vector ALU
+        bound, key, unit = "alu", "valu_f64", "TFLOP/s"
+    if key is None:
+        key = {"f64": "mfma_f64", "f32": "mfma_f32", "bf16": "mfma_bf16"}[prec]
+    return bound, key, unit
 
 
 def parse():
@@ -52,11 +70,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--prec", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64")
+    ap.add_argument("--workload", choices=["rpca", "serving"], default="rpca")
+    ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the full-SVD comparator")
-    ap.add_argument("--cpu-iters", type=int, default=4,
-                    help="oracle iterations timed for the CPU baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="CPU baseline: repeat oracle solves until this much time has passed")
     return ap.parse_args()
 
 
@@ -65,28 +85,28 @@ def log(*a):
 
 
 def roofline_entry(name, rec, prec):
-    bound, key, unit = FAMILY_BOUND.get(name, ("alu", "valu_f64_TFs", "TFLOP/s"))
-    avg_s = rec["ms"] / max(1, rec["launches"]) / 1e3
+    bound, key, unit = family_bound(name, prec)
+    n = max(1, rec["launches"])
+    avg_s = rec["ms"] / n / 1e3
     if bound == "hbm":
-        achieved = rec["bytes"] / max(1, rec["launches"]) / avg_s / 1e9
-        peak = PEAK[key]
+        achieved = rec["bytes"] / n / avg_s / 1e9 if avg_s > 0 else 0.0
     else:
-        achieved = rec["flops"] / max(1, rec["launches"]) / avg_s / 1e12
-        if key is None:
-            key = "mfma_f64_TFs" if prec == "f64" else "mfma_f32_TFs"
-        peak = PEAK[key]
+        achieved = rec["flops"] / n / avg_s / 1e12 if avg_s > 0 else 0.0
+    peak = PEAK[key]
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None,
-            "launches_per_step": None, "avg_us": avg_s * 1e6}
+            "frac": achieved / peak, "traffic": None, "avg_us": avg_s * 1e6,
+            "algorithmic_per_launch": (rec["bytes"] if bound == "hbm" else rec["flops"]) / n}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is a "
-              "single-GPU path and no multi-GPU figure is produced", file=sys.stderr)
-        sys.exit(2)
+def pct(vals, p):
+    v = sorted(vals)
+    if not v:
+        return None
+    i = min(len(v) - 1, max(0, int(math.ceil(p / 100.0 * len(v))) - 1))
+    return v[i]
 
+
+def bench_rpca(args):
     import numpy as np
     import torch
 
@@ -94,6 +114,7 @@ def main():
     import synth
 
     dt = torch.float64 if args.prec == "f64" else torch.float32
+    bf16 = args.prec == "bf16"
     t0 = time.time()
     inst = synth.rpca_instance(M, N, RANK, FRAC, AMP, SEED)
     log(f"[bench] data generated in {time.time() - t0:.1f}s")
@@ -105,18 +126,17 @@ def main():
     ctx = blws.Context(0)
 
     for i in range(args.warmup):
-        _, _, info = ctx.rpca_solve(D, A=A, E=E)
+        _, _, info = ctx.rpca_solve(D, A=A, E=E, bf16=bf16)
         log(f"[bench] warmup {i}: {info['iters']} iters, {info['seconds']:.3f}s")
     torch.cuda.synchronize()
 
     ctx.timing(True)
-    lat = []
-    iters = []
+    lat, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
         t1 = time.perf_counter()
-        _, _, info = ctx.rpca_solve(D, A=A, E=E)
+        _, _, info = ctx.rpca_solve(D, A=A, E=E, bf16=bf16)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - t1)
         iters.append(info["iters"])
@@ -125,24 +145,27 @@ def main():
     total = time.perf_counter() - t_start
 
     fams = {}
-    for name in ["gemm_w", "gemm_ts", "chol", "small_svd", "alm_epilogue", "svt_reconstruct"]:
+    for name in ctx.timing_families():
         rec = ctx.timing_get(name)
         if rec["launches"]:
             fams[name] = rec
     ctx.timing(False)
-    kernel_ms = sum(r["ms"] for r in fams.values())
-    dominant = max(fams, key=lambda k: fams[k]["ms"])
-    roof = roofline_entry(dominant, fams[dominant], args.prec)
+    leaves = {k: v for k, v in fams.items() if k not in COMPOSITE}
+    kernel_ms = sum(r["ms"] for r in leaves.values())
+    dominant = max(leaves, key=lambda k: leaves[k]["ms"])
+    roof = roofline_entry(dominant, leaves[dominant], args.prec)
     roof["kernel"] = dominant
-    roof["launches_per_step"] = fams[dominant]["launches"] / args.steps
+    roof["launches_per_step"] = leaves[dominant]["launches"] / args.steps
     kernels = {}
-    for name, rec in fams.items():
+    for name, rec in sorted(fams.items(), key=lambda kv: -kv[1]["ms"]):
         e = roofline_entry(name, rec, args.prec)
         kernels[name] = {"ms_per_step": rec["ms"] / args.steps,
-                         "share": rec["ms"] / kernel_ms if kernel_ms else None,
+                         "share": (rec["ms"] / kernel_ms if kernel_ms and name not in COMPOSITE
+                                   else None),
                          "launches_per_step": rec["launches"] / args.steps,
                          "avg_us": e["avg_us"], "achieved": e["achieved"], "unit": e["unit"],
-                         "frac": e["frac"], "bound": e["bound"]}
+                         "frac": e["frac"], "bound": e["bound"],
+                         "composite": name in COMPOSITE}
 
     # accuracy of the last solve
     Ad = A.double()
@@ -150,19 +173,12 @@ def main():
     rel_oracle = None
     gpath = os.path.join(ROOT, "tests", "golden", "rpca_n2000_s0.json")
     if os.path.exists(gpath):
-        g = json.load(open(gpath))
+        with open(gpath) as f:
+            g = json.load(f)
         pos = torch.tensor(g["sample_pos"], device=dev)
         As = Ad.reshape(-1)[pos].cpu().numpy()
         ref = np.array(g["A_samples"])
         rel_oracle = float(np.linalg.norm(As - ref) / np.linalg.norm(ref))
-
-    lat_sorted = sorted(lat)
-
-    def pct(p):
-        if not lat_sorted:
-            return None
-        i = min(len(lat_sorted) - 1, max(0, int(math.ceil(p / 100.0 * len(lat_sorted))) - 1))
-        return lat_sorted[i]
 
     out = {
         "metric": METRIC,
@@ -177,12 +193,13 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": "rpca_inexact_alm_blws", "m": M, "n": N, "rank": RANK,
+        "config": {"workload": "rpca_inexact_alm_blws_n2000", "m": M, "n": N, "rank": RANK,
                    "corruption": FRAC, "corruption_amp": AMP, "lambda": 1.0 / math.sqrt(N),
                    "tol": 1e-7, "seed": SEED, "precision": args.prec},
-        "solve_s_p50": pct(50),
-        "solve_s_p99": pct(99),
+        "solve_s_p50": pct(lat, 50),
+        "solve_s_p99": pct(lat, 99),
         "iters": iters[-1],
+        "iters_bf16": info.get("iters_bf16"),
         "svt_calls_per_s": sum(iters) / total,
         "rel_err_vs_A0": rel_A0,
         "rel_err_vs_oracle_samples": rel_oracle,
@@ -193,7 +210,7 @@ def main():
 
     if not args.no_plain:
         # Plain comparator: the same ALM with a full SVD per iteration on the same
-        # GPU (torch.linalg.svd -> rocSOLVER). Bounded sample: two full SVDs of a
+        # GPU (torch.linalg.svd). Bounded sample: the best of two full SVDs of a
         # 2000 x 2000 matrix of the solve's type, times the iteration count.
         W = D.clone()
         torch.linalg.svd(W, full_matrices=False)
@@ -206,7 +223,7 @@ def main():
             ts.append(time.perf_counter() - t1)
         plain = min(ts) * iters[-1]
         out["plain_gpu_solve_s_est"] = plain
-        out["plain_sample"] = (f"torch.linalg.svd of one {M}x{N} {args.prec} matrix, best of 2, "
+        out["plain_sample"] = (f"torch.linalg.svd of one {M}x{N} {dt} matrix, best of 2, "
                                f"x {iters[-1]} iterations")
         out["speedup_vs_plain"] = plain / (total / args.steps)
 
@@ -217,18 +234,128 @@ def main():
         cores = len(os.sched_getaffinity(0))
         threads = int(os.environ.get("OMP_NUM_THREADS", cores))
         t1 = time.perf_counter()
-        res = oracle.rpca(inst["D"], mode="blws", max_iter=args.cpu_iters)
+        n_solves, n_it = 0, 0
+        while True:
+            res = oracle.rpca(inst["D"], mode="blws")
+            n_solves += 1
+            n_it = res["info"]["iters"]
+            if time.perf_counter() - t1 >= args.cpu_seconds:
+                break
         tc = time.perf_counter() - t1
-        n_it = res["info"]["iters"]
-        per_solve = tc / n_it * iters[-1]
         out["cpu_baseline"] = {
-            "value": 1.0 / per_solve, "unit": "solves/s", "cores": min(threads, cores),
+            "value": n_solves / tc, "unit": "solves/s", "cores": min(threads, cores),
             "kind": "oracle",
-            "sample": (f"oracle BLWS inexact ALM (FP64 plain loops), first {n_it} iterations "
-                       f"of the same n=2000 solve incl. ||D||_2 setup, {tc:.1f}s, scaled to "
-                       f"{iters[-1]} iterations"),
+            "sample": (f"oracle BLWS inexact ALM (FP64 plain loops, OpenMP), {n_solves} full "
+                       f"n=2000 solve(s) of {n_it} iterations in {tc:.1f}s"),
         }
+    return out
 
+
+def serving_mix(nreq, seed=2024):
+    """Seeded request mix: 70% RPCA / 30% MC, m ~ U[500, 3000], n = m U[0.75, 1.25]
+    rounded to 64, rank 0.05 min(m, n), RPCA corruption 5-10% U[-500, 500], MC
+    sampling 10-20%, Poisson arrivals."""
+    import numpy as np
+
+    g = np.random.default_rng(seed)
+    reqs = []
+    for i in range(nreq):
+        m = int(g.integers(500, 3001))
+        n = max(64, int(round(m * g.uniform(0.75, 1.25) / 64.0)) * 64)
+        r = max(1, int(round(0.05 * min(m, n))))
+        if g.uniform() < 0.7:
+            reqs.append(("rpca", m, n, r, float(g.uniform(0.05, 0.10)), 1000 + i))
+        else:
+            reqs.append(("mc", m, n, r, float(g.uniform(0.10, 0.20)), 1000 + i))
+    return reqs
+
+
+def bench_serving(args):
+    import torch
+
+    import paper_1012_0365_amd as blws
+    import synth
+
+    reqs = serving_mix(args.requests)
+    log(f"[bench] serving: generating {len(reqs)} requests")
+    data = []
+    for kind, m, n, r, frac, seed in reqs:
+        if kind == "rpca":
+            inst = synth.rpca_instance(m, n, r, frac, AMP, seed)
+            data.append((kind, m, n, torch.tensor(inst["D"], dtype=torch.float32, device="cuda")))
+        else:
+            inst = synth.mc_instance(m, n, r, frac, seed)
+            data.append((kind, m, n,
+                         torch.tensor(inst["row_ptr"], dtype=torch.int32, device="cuda"),
+                         torch.tensor(inst["col_idx"], dtype=torch.int32, device="cuda"),
+                         torch.tensor(inst["values"], dtype=torch.float32, device="cuda")))
+    torch.cuda.synchronize()
+    mc_opts = blws.default_mc_opts()
+    srv = blws.Server(0, max_slots=8)
+    # warm-up: one request of each kind
+    for item in data[:2]:
+        t = (srv.submit_rpca(item[3]) if item[0] == "rpca"
+             else srv.submit_mc(item[1], item[2], item[3], item[4], item[5], opts=mc_opts))
+        srv.wait(t)
+    import numpy as np
+
+    g = np.random.default_rng(7)
+    gaps = g.exponential(1.0, len(data))  # Poisson arrivals, rate set below
+    t_start = time.perf_counter()
+    tickets = []
+    # submit at the arrival times; mean gap 20 ms keeps the server loaded
+    arrival = 0.0
+    for (item, gap) in zip(data, gaps):
+        arrival += 0.02 * gap
+        while time.perf_counter() - t_start < arrival:
+            time.sleep(0.0005)
+        if item[0] == "rpca":
+            tickets.append(srv.submit_rpca(item[3]))
+        else:
+            tickets.append(srv.submit_mc(item[1], item[2], item[3], item[4], item[5],
+                                         opts=mc_opts))
+    lat, iters, fails = [], 0, 0
+    for t in tickets:
+        try:
+            res = srv.wait(t)
+            lat.append(res[-1]["seconds"])
+            iters += res[-1]["iters"]
+        except blws.BlwsError:
+            fails += 1
+    total = time.perf_counter() - t_start
+    st = srv.stats()
+    srv.close()
+    return {
+        "metric": "serving mix: solves/s with p50/p99 latency",
+        "value": len(lat) / total,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(reqs),
+        "warmup": 2,
+        "ms_per_step": 1e3 * total / max(1, len(lat)),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving_mix_rpca70_mc30", "requests": len(reqs),
+                   "m_range": [500, 3000], "arrivals": "poisson, mean gap 20 ms",
+                   "max_slots": 8},
+        "latency_s_p50": pct(lat, 50),
+        "latency_s_p99": pct(lat, 99),
+        "svt_calls_per_s": iters / total,
+        "failed": fails,
+        "server_stats": st,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is a "
+              "single-GPU path and no multi-GPU figure is produced", file=sys.stderr)
+        sys.exit(2)
+    out = bench_serving(args) if args.workload == "serving" else bench_rpca(args)
     print(json.dumps(out))
 
 

@@ -198,6 +198,9 @@ int blws_timing_enable(blws_ctx ctx, int enable);
  * algorithmic flop and byte counts of those launches. Synchronises the device. */
 int blws_timing_get(blws_ctx ctx, const char* name, long long* launches, double* ms,
                     double* flops, double* bytes);
+/* Comma-separated names of the kernel families recorded since timing was
+ * enabled, into buf (host, len bytes, NUL-terminated). */
+int blws_timing_list(blws_ctx ctx, char* buf, size_t len);
 
 /* ------------------------------------------------------------------------
  * Request server (serving many solves on one GPU).

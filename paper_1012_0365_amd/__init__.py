@@ -234,6 +234,13 @@ class Context:
     def timing(self, enable: bool):
         self._check(self._lib.blws_timing_enable(self.handle, int(enable)))
 
+    def timing_families(self) -> list:
+        """Names of the kernel families recorded since timing was enabled."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        self._check(self._lib.blws_timing_list(self.handle, buf, len(buf)))
+        v = buf.value.decode()
+        return v.split(",") if v else []
+
     def timing_get(self, name: str) -> dict:
         n = ctypes.c_longlong()
         ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()

@@ -342,6 +342,21 @@ int blws_timing_enable(blws_ctx ctx, int enable)
     ABI_END
 }
 
+int blws_timing_list(blws_ctx ctx, char* buf, size_t len)
+{
+    ABI_BEGIN(ctx)
+    BLWS_REQUIRE(buf && len > 0, BLWS_EINVAL, "blws_timing_list: null buffer");
+    std::string names;
+    for (auto& kv : cx.timer.fam) {
+        if (!names.empty()) names += ",";
+        names += kv.first;
+    }
+    BLWS_REQUIRE(names.size() < len, BLWS_EINVAL, "blws_timing_list: buffer too small");
+    std::memcpy(buf, names.c_str(), names.size() + 1);
+    return BLWS_OK;
+    ABI_END
+}
+
 int blws_timing_get(blws_ctx ctx, const char* name, long long* launches, double* ms,
                     double* flops, double* bytes)
 {

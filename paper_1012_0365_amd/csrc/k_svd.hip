@@ -737,8 +737,17 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     double* tR = tL + N;
     double* VL = tR + N;
     double* VR = VL + (size_t)N * N;
+    static const char* const coop_fam[4] = {"gk_bidiag_coop_q20", "gk_bidiag_coop_q24",
+                                            "gk_bidiag_coop_q28", "gk_bidiag_coop_q32"};
+    static const char* const one_fam[7] = {"gk_bidiag_p1", "gk_bidiag_p2", "gk_bidiag_p3",
+                                           "gk_bidiag_p4", "gk_bidiag_p5", "gk_bidiag_p6",
+                                           "gk_bidiag_p7"};
+    // bidiagonalisation flops: 4 N^3 - 4 N^3 / 3 (Householder, both sides)
+    const double bd_flops = 8.0 / 3.0 * N * (double)N * N;
     if (N > GK_MAXN) {
-        TimedLaunch tl(tm, "gk_bidiag", s, 8.0 / 3.0 * N * (double)N * N, 16.0 * N * N);
+        const int NQc = (N + 15) / 16;
+        const int qi = NQc <= 20 ? 0 : NQc <= 24 ? 1 : NQc <= 28 ? 2 : 3;
+        TimedLaunch tl(tm, coop_fam[qi], s, bd_flops, 16.0 * N * N);
         const int P = (N + 31) / 32;
         CoopBuf cb;
         cb.colpub = VR + (size_t)N * N;
@@ -757,8 +766,8 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         else fn = (const void*)gk_bidiag_coop_kernel<32>;
         HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(P), dim3(512), args, 0, s));
     } else {
-        TimedLaunch tl(tm, "gk_bidiag", s, 8.0 / 3.0 * N * (double)N * N, 16.0 * N * N);
         const int NP = (N + 31) / 32;
+        TimedLaunch tl(tm, one_fam[NP - 1], s, bd_flops, 16.0 * N * N);
 #define BLWS_GK_CASE(P)                                                                      \
     case P:                                                                                  \
         hipLaunchKernelGGL((gk_bidiag_kernel<P>), dim3(1), dim3(512), 0, s, N, B, ldb, d, e, VL, \
