@@ -71,7 +71,7 @@ typedef struct {
     unsigned long long seed;  /* counter-based generator seed                           */
     int norm_steps;           /* max BLWS steps for the ||D||_2 estimate (8)            */
     double norm_rtol;         /* relative change that stops the ||D||_2 steps (1e-13)   */
-    int b_max;                /* upper bound on the block width, <= 256 (256)           */
+    int b_max;                /* upper bound on the block width, <= 512 (512; MC 256)   */
     int b_soft;               /* beyond this width the block follows the previous count */
                               /* of values above the threshold, not the prediction (112)*/
     double ladder_tol;        /* BLWS_BF16 solves: W products in BF16 while the relative */

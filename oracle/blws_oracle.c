@@ -654,7 +654,7 @@ void orc_default_opts(orc_alm_opts* o)
     o->seed = 20101202ULL;
     o->norm_steps = 8;
     o->norm_rtol = 1e-13;
-    o->b_max = 256;
+    o->b_max = 512;
     o->b_soft = 112;
 }
 

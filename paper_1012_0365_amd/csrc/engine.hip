@@ -131,7 +131,7 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->seed = 20101202ULL;
     o->norm_steps = 8;
     o->norm_rtol = 1e-13;
-    o->b_max = 256;
+    o->b_max = 512;
     o->b_soft = 112;
     o->ladder_tol = 1e-3;
 }
@@ -155,7 +155,7 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
     BLWS_REQUIRE(ldw >= n && ldu >= b && ldv >= b && (!A || lda >= n), BLWS_EINVAL,
                  "blws_svt: leading dimension too small");
     BLWS_REQUIRE(std::isfinite(eps) && eps >= 0.0, BLWS_EINVAL, "blws_svt: eps must be >= 0");
-    BLWS_REQUIRE(2 * b <= 512, BLWS_EUNSUPPORTED, "blws_svt: b above 256");
+    BLWS_REQUIRE(2 * b <= 1024, BLWS_EUNSUPPORTED, "blws_svt: b above 512");
     blws_svt_opts o;
     blws_default_svt_opts(&o);
     if (opts) o = *opts;
@@ -192,6 +192,7 @@ void blws_default_mc_opts(blws_alm_opts* o)
     o->tol = 1e-6;
     o->rho = 1.1;
     o->mu0_scale = 1.0;
+    o->b_max = 256;
 }
 
 int blws_mc_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
@@ -257,7 +258,7 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
                        double* S, double* VB)
 {
     ABI_BEGIN(ctx)
-    BLWS_REQUIRE(N >= 1 && N <= 512 && B && UB && S && VB && ldb >= N, BLWS_EINVAL,
+    BLWS_REQUIRE(N >= 1 && N <= 1024 && B && UB && S && VB && ldb >= N, BLWS_EINVAL,
                  "blws_small_svd_f64: bad arguments");
     double* svd = nullptr;
     auto layout = [&](Carver& c, blws::OrthWs<double>& w) {

@@ -546,7 +546,7 @@ inline void check_alm_opts(const blws_alm_opts& o, const std::string& who)
                      o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
                      o.b_soft >= 1 && o.ladder_tol >= 0.0,
                  BLWS_EINVAL, who + ": bad options");
-    BLWS_REQUIRE(o.b_max <= 256, BLWS_EUNSUPPORTED, who + ": b_max above 256");
+    BLWS_REQUIRE(o.b_max <= 512, BLWS_EUNSUPPORTED, who + ": b_max above 512");
 }
 
 inline std::unique_ptr<Job> make_rpca_job(int prec, int m, int n, const void* D, int ldd,

@@ -10,6 +10,8 @@ namespace {
 
 constexpr int CHOL_LDS_MAX = 128;  // Gram matrices up to 128 x 128 live in LDS
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 // Counter-based uniform draw: the (counter + 1)-th output of SplitMix64
 // (Steele, Lea & Flood 2014) seeded with `seed`, mapped to [-1, 1).
 __device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t counter)
@@ -91,15 +93,12 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(int n, const double* __r
 
 // The same elimination with the matrix in registers (n <= 128): thread
 // (tr, tc) of a 32 x 32 grid holds S[tr + 32a][tc + 32b], a, b < 4. Each step
-// broadcasts the pivot row through LDS; two barriers per step.
-__global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double* __restrict__ G,
-                                                            int ldg, double* __restrict__ Rinv,
-                                                            int* flags, int* nflag, double eta)
+// broadcasts the pivot row through LDS; two barriers per step. G and Rinv
+// (leading dimension ld) may be global or LDS; Rinv may alias G (G is read
+// once into registers before Rinv is written). All 1024 threads call it.
+__device__ __forceinline__ void chol_inv_regs(int n, const double* G, int ldg, double* Rinv, int ldr, double eta,
+                              double* scal, double* row, double* piv, int* flg)
 {
-    __shared__ double scal[128];
-    __shared__ double row[128];
-    __shared__ double piv[128];
-    __shared__ int flg[128];
     const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
     for (int i = tid; i < n; i += 1024) {
         const double g = G[(size_t)i * ldg + i];
@@ -115,6 +114,7 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
             const int i = tr + 32 * a, c = tc + 32 * b;
             S[a][b] = (i < n && c < n && c >= i) ? G[(size_t)i * ldg + c] * scal[i] * scal[c] : 0.0;
         }
+    __syncthreads();  // G fully read before Rinv (which may alias it) is written
     for (int j = 0; j < n; ++j) {
         // the owners of row j publish it (upper part: the trailing matrix;
         // lower part: the row of L^{-1} built so far)
@@ -163,20 +163,133 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
         for (int b = 0; b < 4; ++b) {
             const int i = tr + 32 * a, c = tc + 32 * b;
             if (i >= n || c >= n) continue;
-            // element (r, cc) = (c, i) of R^{-1}: needs r <= cc, i.e. c <= i
             double v = 0.0;
             if (c <= i && !flg[i]) {
                 const double lic = (c == i) ? 1.0 : S[a][b];
                 v = scal[c] * lic / sqrt(piv[i]);
             }
-            Rinv[(size_t)c * n + i] = v;
+            Rinv[(size_t)c * ldr + i] = v;
         }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double* __restrict__ G,
+                                                            int ldg, double* __restrict__ Rinv,
+                                                            int* flags, int* nflag, double eta)
+{
+    __shared__ double scal[128];
+    __shared__ double row[128];
+    __shared__ double piv[128];
+    __shared__ int flg[128];
+    chol_inv_regs(n, G, ldg, Rinv, n, eta, scal, row, piv, flg);
     int cnt = 0;
-    for (int i = tid; i < n; i += 1024) {
+    for (int i = threadIdx.x; i < n; i += 1024) {
         flags[i] = flg[i];
         cnt += flg[i];
     }
     if (cnt) atomicAdd(nflag, cnt);
+}
+
+// Two Cholesky-QR passes on the columns of X (rows x c, ld; rows <= 512,
+// c <= 128) in ONE workgroup per matrix (blockIdx.x picks X0 or X1): the Gram
+// matrix by FP64 MFMA into LDS, the Cholesky inverse in registers (in place
+// in LDS), X <- X R^{-1} in place row by row. Columns found dependent in the
+// first pass are redrawn from the counter-based generator (stream ids sid0,
+// sid1) before the second; *nflag counts them.
+constexpr int CQ_LD = 129;
+
+__global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, double* X0, double* X1,
+                                                             int ld, int* nflag, double eta,
+                                                             uint64_t seed, uint64_t sid0,
+                                                             uint64_t sid1)
+{
+    __shared__ double G[128 * CQ_LD];
+    __shared__ double scal[128], row[128], piv[128];
+    __shared__ int flg[128];
+    double* X = blockIdx.x == 0 ? X0 : X1;
+    const uint64_t sid = blockIdx.x == 0 ? sid0 : sid1;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int T = (c + 15) / 16;
+    for (int pass = 0; pass < 2; ++pass) {
+        // Gram G = X^T X: 16 x 16 tiles, wavefront w takes tiles w + 16 u,
+        // two at a time (independent MFMA chains)
+        for (int u0 = 0; u0 < 4; u0 += 2) {
+            const int t0 = wave + 16 * u0, t1 = t0 + 16;
+            const bool v0 = t0 / 8 < T && t0 % 8 < T, v1 = t1 / 8 < T && t1 % 8 < T;
+            if (!v0 && !v1) continue;  // uniform per wavefront
+            const int ca0 = 16 * (t0 / 8) + (lane & 15), cb0 = 16 * (t0 % 8) + (lane & 15);
+            const int ca1 = 16 * (t1 / 8) + (lane & 15), cb1 = 16 * (t1 % 8) + (lane & 15);
+            d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+            for (int k0 = 0; k0 < rows; k0 += 4) {  // uniform trip count
+                const int k = k0 + (lane >> 4);
+                const bool kin = k < rows;
+                const double* xr = X + (size_t)(kin ? k : 0) * ld;
+                const double a0 = (kin && v0 && ca0 < c) ? xr[ca0] : 0.0;
+                const double b0 = (kin && v0 && cb0 < c) ? xr[cb0] : 0.0;
+                const double a1 = (kin && v1 && ca1 < c) ? xr[ca1] : 0.0;
+                const double b1 = (kin && v1 && cb1 < c) ? xr[cb1] : 0.0;
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r0 = 16 * (t0 / 8) + (lane >> 4) + 4 * i;
+                const int r1 = 16 * (t1 / 8) + (lane >> 4) + 4 * i;
+                if (v0 && r0 < c && cb0 < c) G[r0 * CQ_LD + cb0] = acc0[i];
+                if (v1 && r1 < c && cb1 < c) G[r1 * CQ_LD + cb1] = acc1[i];
+            }
+        }
+        __syncthreads();
+        chol_inv_regs(c, G, CQ_LD, G, CQ_LD, eta, scal, row, piv, flg);
+        // X <- X R^{-1} by MFMA: wavefront w owns row blocks w, w + 16, ... (16
+        // rows each, all column tiles), so each row block is read completely
+        // before it is overwritten
+        for (int rb = wave; rb * 16 < rows; rb += 16) {
+            d4 acc[8];
+#pragma unroll
+            for (int tj = 0; tj < 8; ++tj) acc[tj] = d4{0.0, 0.0, 0.0, 0.0};
+            const int ra = 16 * rb + (lane & 15);
+            const double* xa = X + (size_t)(ra < rows ? ra : 0) * ld;
+#pragma unroll 2
+            for (int k0 = 0; k0 < c; k0 += 4) {
+                const int k = k0 + (lane >> 4);
+                const double a = (ra < rows && k < c) ? xa[k] : 0.0;
+#pragma unroll
+                for (int tj = 0; tj < 8; ++tj) {
+                    if (tj >= T) break;  // uniform
+                    const int cb = 16 * tj + (lane & 15);
+                    const double b = (k < c && cb < c) ? G[k * CQ_LD + cb] : 0.0;
+                    acc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[tj], 0, 0, 0);
+                }
+            }
+#pragma unroll
+            for (int tj = 0; tj < 8; ++tj) {
+                if (tj >= T) break;
+                const int cb = 16 * tj + (lane & 15);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = 16 * rb + (lane >> 4) + 4 * i;
+                    if (r < rows && cb < c) X[(size_t)r * ld + cb] = acc[tj][i];
+                }
+            }
+        }
+        __syncthreads();
+        if (pass == 0) {
+            for (int e = tid; e < rows * c; e += 1024) {
+                const int i = e / c, j = e - i * c;
+                if (flg[j])
+                    X[(size_t)i * ld + j] =
+                        uniform_pm1(seed, (sid << 40) + (uint64_t)i * 4096ULL + (uint64_t)j);
+            }
+        }
+        if (tid == 0) {
+            int cnt = 0;
+            for (int j = 0; j < c; ++j) cnt += flg[j];
+            if (cnt) atomicAdd(nflag, cnt);
+        }
+        __syncthreads();
+    }
 }
 
 // One-sided (Hestenes) Jacobi SVD of the N x N matrix B in one workgroup.
@@ -432,6 +545,18 @@ void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* fla
     else
         hipLaunchKernelGGL((chol_inv_kernel<false>), dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv,
                            flags, nflag, eta, scratch);
+}
+
+bool cholqr2_small_supported(int rows, int c) { return rows >= 1 && rows <= 512 && c >= 1 && c <= 128; }
+
+void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, int* nflag,
+                   double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, hipStream_t s)
+{
+    BLWS_REQUIRE(cholqr2_small_supported(rows, c), BLWS_EUNSUPPORTED, "cholqr2_small: size");
+    TimedLaunch tl(tm, "svd_polish", s, 2.0 * 2.0 * (2.0 * rows * (double)c * c + c * (double)c * c / 3.0),
+                   0.0);
+    hipLaunchKernelGGL(cholqr2_small_kernel, dim3(2), dim3(1024), 0, s, rows, c, X0, X1, ld, nflag,
+                       eta, seed, sid0, sid1);
 }
 
 size_t small_svd_jacobi_scratch_elems(int N) { return 2 * (size_t)N * N; }

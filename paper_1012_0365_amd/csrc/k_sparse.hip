@@ -147,7 +147,7 @@ __global__ __launch_bounds__(256) void seg_sort_kernel(int n, const int* col_ptr
 }
 
 // out (rows x c, ldo) = sum over the entries of each row of val * X[idx, :].
-// One wavefront per row; lanes over the c columns (c <= 256); entries fetched
+// One wavefront per row; lanes over the c columns (c <= 512); entries fetched
 // 64 at a time and broadcast; sums in FP64 in entry order. With `perm` the
 // value of position e is val[perm[e]] (the transposed pattern).
 template <typename T>
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void spmm_kernel(int rows, int c, const int* p
     const int i = blockIdx.x * 4 + wave;
     if (i >= rows) return;  // no barriers below
     const int a = ptr[i], z = ptr[i + 1];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     for (int base = a; base < z; base += 64) {
         const int e = base + lane;
         int col = 0;
@@ -175,14 +175,14 @@ __global__ __launch_bounds__(256) void spmm_kernel(int rows, int c, const int* p
             const double vv = __shfl(v, t, 64);
             const T* xr = X + (size_t)cc * ldx;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
+            for (int q = 0; q < 8; ++q) {
                 const int jj = lane + 64 * q;
                 if (jj < c) acc[q] += vv * (double)xr[jj];
             }
         }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
         const int jj = lane + 64 * q;
         if (jj < c) out[(size_t)i * ldo + jj] = (T)acc[q];
     }
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(256) void mc_update_kernel(
     const T* V, int ldv, const double* S, double eps, const int* rank_dev, int rmax, double mu,
     double mu_next, double* part)
 {
-    __shared__ double coef[4][256];
+    __shared__ double coef[4][512];
     __shared__ double red[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + wave;
@@ -300,7 +300,7 @@ void spmm(Timer* tm, const char* family, int rows, int c, const int* ptr, const 
           hipStream_t s)
 {
     if (rows <= 0 || c <= 0) return;
-    BLWS_REQUIRE(c <= 256, BLWS_EUNSUPPORTED, "spmm: more than 256 columns");
+    BLWS_REQUIRE(c <= 512, BLWS_EUNSUPPORTED, "spmm: more than 512 columns");
     TimedLaunch tl(tm, family, s, 2.0 * (double)nnz * c,
                    (double)nnz * (sizeof(int) + sizeof(T) + (perm ? sizeof(int) : 0) +
                                   (double)c * sizeof(T)) +
@@ -323,7 +323,7 @@ void mc_update(Timer* tm, int m, long long nnz, const int* row_ptr, const int* c
                double eps, const int* rank_dev, int rmax, double mu, double mu_next,
                double* partials, hipStream_t s)
 {
-    BLWS_REQUIRE(rmax <= 256, BLWS_EUNSUPPORTED, "mc_update: rank above 256");
+    BLWS_REQUIRE(rmax <= 512, BLWS_EUNSUPPORTED, "mc_update: rank above 512");
     TimedLaunch tl(tm, "mc_update", s, 2.0 * (double)nnz * rmax,
                    (double)nnz * (sizeof(int) + 5.0 * sizeof(T)));
     hipLaunchKernelGGL((mc_update_kernel<T>), dim3((m + 3) / 4), dim3(256), 0, s, m, row_ptr,

@@ -3,7 +3,7 @@
 //
 // 1. Golub-Kahan bidiagonalisation B = Q_L Bd Q_R^T. Up to N = 224 in ONE
 //    workgroup, B held in registers: a 32 x 16 thread grid, thread (tr, tc)
-//    owning rows tr + 32a and columns tc + 16c. Up to N = 512 across
+//    owning rows tr + 32a and columns tc + 16c. Up to N = 1024 across
 //    ceil(N / 32) co-resident workgroups holding 32-column slabs, with one
 //    device-wide barrier per column. Each step is a left and a right
 //    Householder reflection; their vectors are written to global memory for
@@ -22,7 +22,7 @@ namespace blws {
 namespace {
 
 constexpr int GK_MAXN = 224;   // one-workgroup bidiagonalisation
-constexpr int SVD_MAXN = 512;  // cooperative bidiagonalisation and the later stages
+constexpr int SVD_MAXN = 1024;  // cooperative bidiagonalisation and the later stages
 
 // Start vectors of the inverse iteration: SplitMix64 (Steele, Lea & Flood
 // 2014) outputs mapped to [-1, 1), distinct per value so that vectors of a
@@ -35,11 +35,48 @@ __device__ __forceinline__ double start_pm1(uint64_t counter)
     z ^= z >> 31;
     return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
+// Sums across lanes. Within a row of 16 lanes the partial sums move by DPP
+// row rotations (VALU, a few cycles each); only the steps across rows use
+// ds_bpermute shuffles. Every lane ends with the total, so all lanes hold
+// the same bits.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const unsigned long long u = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffu), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+// row_ror:n is DPP control 0x120 + n
+__device__ __forceinline__ double row_sum16(double x)
+{
+    x += dpp_move<0x128>(x);
+    x += dpp_move<0x124>(x);
+    x += dpp_move<0x122>(x);
+    x += dpp_move<0x121>(x);
+    return x;
+}
+__device__ __forceinline__ double half_sum32(double x)  // over the 32 lanes of a half-wavefront
+{
+    x = row_sum16(x);
+    return x + __shfl_xor(x, 16, 64);
+}
+__device__ __forceinline__ double wave_sum64(double x)
+{
+    x = row_sum16(x);
+    x += __shfl_xor(x, 16, 64);
+    return x + __shfl_xor(x, 32, 64);
+}
+
 constexpr int GK_LD = GK_MAXN + 1;  // padded LDS row of the partial sums
 
 // Thread (tr, tc) of the 32 x 16 grid owns rows tr + 32a (a < NPR) and
-// columns tc + 16c (c < 2 NPR): 7 x 14 doubles at N = 224, which 512 threads
-// (two wavefronts per SIMD, 256 registers each) hold without spilling.
+// columns tc + 16c (c < 2 NPR): 7 x 14 doubles at N = 224. Per column step
+// four barriers: every wavefront forms each reflector itself from the
+// published column or row (bit-identical in all of them), the column dot
+// products of the left reflection are reduced over the 32 row-lanes of a
+// half-wavefront by shuffles, and only the row products of the right
+// reflection go through LDS.
 template <int NPR>
 __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __restrict__ B,
                                                         int ldb, double* __restrict__ dout,
@@ -50,11 +87,9 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
                                                         double* __restrict__ tauR)
 {
     constexpr int NPC = 2 * NPR;
-    __shared__ double part[32 * GK_LD];
-    __shared__ double sx[GK_MAXN], svl[GK_MAXN], sw[GK_MAXN];
-    __shared__ double sy[GK_MAXN], svr[GK_MAXN], sz[GK_MAXN];
-    __shared__ double stauL, stauR;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    __shared__ double part[16 * GK_LD];
+    __shared__ double sxc[GK_MAXN], sxr[GK_MAXN], sz[GK_MAXN];
+    const int tid = threadIdx.x, lane = tid & 63;
     const int tr = tid & 31, tc = tid >> 5;
 
     double Br[NPR][NPC];
@@ -77,15 +112,15 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
 #pragma unroll
                 for (int c = 0; c < NPC; ++c)
                     if (c == kc) v = Br[a][c];
-                if (i >= k && i < N) sx[i] = v;
+                if (i >= k && i < N) sxc[i] = v;
             }
         }
         __syncthreads();
-        if (wave == 0) {
-            const double alpha = sx[k];
+        {
+            const double alpha = sxc[k];
             double s2 = 0.0;
-            for (int i = k + 1 + lane; i < N; i += 64) s2 += sx[i] * sx[i];
-            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            for (int i = k + 1 + lane; i < N; i += 64) s2 += sxc[i] * sxc[i];
+            s2 = wave_sum64(s2);
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (s2 > 0.0) {
                 const double nrm = sqrt(alpha * alpha + s2);
@@ -93,57 +128,38 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
                 tau = (beta - alpha) / beta;
                 scale = 1.0 / (alpha - beta);
             }
-            for (int i = k + 1 + lane; i < N; i += 64) {
-                const double v = sx[i] * scale;
-                svl[i] = v;
-                VL[(size_t)k * N + i] = v;
-            }
-            if (lane == 0) {
-                svl[k] = 1.0;
-                VL[(size_t)k * N + k] = 1.0;
-                tauL[k] = tau;
-                dout[k] = beta;
-                stauL = tau;
-            }
-        }
-        __syncthreads();
-        const double tl = stauL;
-        if (tl != 0.0) {
-            // w_j = tau * sum_{i >= k} v_i B[i][j], j > k; v_i read once per row block
-            double vi[NPR];
-#pragma unroll
-            for (int a = 0; a < NPR; ++a) {
-                const int i = tr + 32 * a;
-                vi[a] = (32 * a + 31 >= k && i >= k && i < N) ? svl[i] : 0.0;
-            }
-#pragma unroll
-            for (int c = 0; c < NPC; ++c) {
-                if (16 * c + 15 < k + 1) continue;  // uniform: no column > k in this block
-                const int j = tc + 16 * c;
-                double acc = 0.0;
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) {
-                    if (32 * a + 31 < k) continue;  // uniform: no row >= k in this block
-                    acc += vi[a] * Br[a][c];
+            if (tid < 64) {
+                for (int i = k + 1 + lane; i < N; i += 64) VL[(size_t)k * N + i] = sxc[i] * scale;
+                if (lane == 0) {
+                    VL[(size_t)k * N + k] = 1.0;
+                    tauL[k] = tau;
+                    dout[k] = beta;
                 }
-                if (j < N) part[tr * GK_LD + j] = acc;
             }
-            __syncthreads();
-            if (tid < N && tid > k) {
-                double s = 0.0;
-                for (int r = 0; r < 32; ++r) s += part[r * GK_LD + tid];
-                sw[tid] = tl * s;
-            }
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < NPC; ++c) {
-                if (16 * c + 15 < k + 1) continue;
-                const int j = tc + 16 * c;
-                const double wj = (j > k && j < N) ? sw[j] : 0.0;
+            if (tau != 0.0) {
+                double va[NPR];
 #pragma unroll
                 for (int a = 0; a < NPR; ++a) {
-                    if (32 * a + 31 < k) continue;
-                    Br[a][c] -= vi[a] * wj;
+                    const int i = tr + 32 * a;
+                    va[a] = (i > k && i < N) ? sxc[i] * scale : (i == k ? 1.0 : 0.0);
+                }
+#pragma unroll
+                for (int c = 0; c < NPC; ++c) {
+                    if (16 * c + 15 <= k) continue;  // uniform: no column > k here
+                    double p = 0.0;
+#pragma unroll
+                    for (int a = 0; a < NPR; ++a) {
+                        if (32 * a + 31 < k) continue;  // uniform: no row >= k here
+                        p += va[a] * Br[a][c];
+                    }
+                    p = half_sum32(p);  // sum over the 32 row-lanes of this half-wavefront
+                    const int j = tc + 16 * c;
+                    const double wj = (j > k && j < N) ? tau * p : 0.0;
+#pragma unroll
+                    for (int a = 0; a < NPR; ++a) {
+                        if (32 * a + 31 < k) continue;
+                        Br[a][c] -= va[a] * wj;
+                    }
                 }
             }
         }
@@ -158,15 +174,15 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
 #pragma unroll
                 for (int a = 0; a < NPR; ++a)
                     if (a == ka) v = Br[a][c];
-                if (j > k && j < N) sy[j] = v;
+                if (j > k && j < N) sxr[j] = v;
             }
         }
         __syncthreads();
-        if (wave == 0) {
-            const double alpha = sy[k + 1];
+        {
+            const double alpha = sxr[k + 1];
             double s2 = 0.0;
-            for (int j = k + 2 + lane; j < N; j += 64) s2 += sy[j] * sy[j];
-            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            for (int j = k + 2 + lane; j < N; j += 64) s2 += sxr[j] * sxr[j];
+            s2 = wave_sum64(s2);
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (s2 > 0.0) {
                 const double nrm = sqrt(alpha * alpha + s2);
@@ -174,65 +190,61 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
                 tau = (beta - alpha) / beta;
                 scale = 1.0 / (alpha - beta);
             }
-            for (int j = k + 2 + lane; j < N; j += 64) {
-                const double v = sy[j] * scale;
-                svr[j] = v;
-                VR[(size_t)k * N + j] = v;
-            }
-            if (lane == 0) {
-                svr[k + 1] = 1.0;
-                VR[(size_t)k * N + k + 1] = 1.0;
-                tauR[k] = tau;
-                eout[k] = beta;
-                stauR = tau;
-            }
-        }
-        __syncthreads();
-        const double tq = stauR;
-        if (tq != 0.0) {
-            // z_i = tau * sum_{j > k} B[i][j] v_j, i > k: column-outer loops so
-            // that only one accumulator per row block stays live
-            double acc[NPR];
-#pragma unroll
-            for (int a = 0; a < NPR; ++a) acc[a] = 0.0;
-#pragma unroll
-            for (int c = 0; c < NPC; ++c) {
-                if (16 * c + 15 < k + 1) continue;
-                const int j = tc + 16 * c;
-                const double vj = (j > k && j < N) ? svr[j] : 0.0;
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) {
-                    if (32 * a + 31 < k + 1) continue;
-                    acc[a] += Br[a][c] * vj;
+            if (tid < 64) {
+                for (int j = k + 2 + lane; j < N; j += 64) VR[(size_t)k * N + j] = sxr[j] * scale;
+                if (lane == 0) {
+                    VR[(size_t)k * N + k + 1] = 1.0;
+                    tauR[k] = tau;
+                    eout[k] = beta;
                 }
             }
+            if (tau != 0.0) {
+                // z_i = tau sum_{j > k} B[i][j] v_j, i > k
+                double acc[NPR];
 #pragma unroll
-            for (int a = 0; a < NPR; ++a) {
-                if (32 * a + 31 < k + 1) continue;
-                const int i = tr + 32 * a;
-                if (i < N) part[tc * GK_LD + i] = acc[a];
-            }
-            __syncthreads();
-            if (tid < N && tid > k) {
-                double sum = 0.0;
-                for (int t = 0; t < 16; ++t) sum += part[t * GK_LD + tid];
-                sz[tid] = tq * sum;
-            }
-            __syncthreads();
+                for (int a = 0; a < NPR; ++a) acc[a] = 0.0;
 #pragma unroll
-            for (int a = 0; a < NPR; ++a) {
-                const int i = tr + 32 * a;
-                acc[a] = (32 * a + 31 >= k + 1 && i > k && i < N) ? sz[i] : 0.0;
-            }
+                for (int c = 0; c < NPC; ++c) {
+                    if (16 * c + 15 <= k) continue;
+                    const int j = tc + 16 * c;
+                    const double vj =
+                        (j > k + 1 && j < N) ? sxr[j] * scale : (j == k + 1 ? 1.0 : 0.0);
 #pragma unroll
-            for (int c = 0; c < NPC; ++c) {
-                if (16 * c + 15 < k + 1) continue;
-                const int j = tc + 16 * c;
-                const double vj = (j > k && j < N) ? svr[j] : 0.0;
+                    for (int a = 0; a < NPR; ++a) {
+                        if (32 * a + 31 <= k) continue;
+                        acc[a] += Br[a][c] * vj;
+                    }
+                }
 #pragma unroll
                 for (int a = 0; a < NPR; ++a) {
-                    if (32 * a + 31 < k + 1) continue;
-                    Br[a][c] -= acc[a] * vj;
+                    if (32 * a + 31 <= k) continue;
+                    const int i = tr + 32 * a;
+                    if (i < N) part[tc * GK_LD + i] = acc[a];
+                }
+                __syncthreads();
+                if (tid < N && tid > k) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int t = 0; t < 16; ++t) sum += part[t * GK_LD + tid];
+                    sz[tid] = tau * sum;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int a = 0; a < NPR; ++a) {
+                    const int i = tr + 32 * a;
+                    acc[a] = (32 * a + 31 > k && i > k && i < N) ? sz[i] : 0.0;
+                }
+#pragma unroll
+                for (int c = 0; c < NPC; ++c) {
+                    if (16 * c + 15 <= k) continue;
+                    const int j = tc + 16 * c;
+                    const double vj =
+                        (j > k + 1 && j < N) ? sxr[j] * scale : (j == k + 1 ? 1.0 : 0.0);
+#pragma unroll
+                    for (int a = 0; a < NPR; ++a) {
+                        if (32 * a + 31 <= k) continue;
+                        Br[a][c] -= acc[a] * vj;
+                    }
                 }
             }
         }
@@ -488,44 +500,57 @@ __device__ int count_ge(int N, const double* f2, double x, double pivmin)
     return 2 * N - neg;  // = N - #{sigma < x}
 }
 
-// One wavefront per singular value: sigma_t, the t-th largest, by multisection.
-__global__ __launch_bounds__(64) void tgk_bisect_kernel(int N, const double* __restrict__ d,
-                                                        const double* __restrict__ e,
-                                                        double* __restrict__ sig)
+// One workgroup of BS_PTS threads per singular value: sigma_t, the t-th
+// largest, by multisection with BS_PTS Sturm counts per step.
+constexpr int BS_PTS = 256;
+__global__ __launch_bounds__(BS_PTS) void tgk_bisect_kernel(int N, const double* __restrict__ d,
+                                                            const double* __restrict__ e,
+                                                            double* __restrict__ sig)
 {
     __shared__ double f2[2 * SVD_MAXN];
-    __shared__ int cnt[64];
+    __shared__ int cnt[BS_PTS];
+    __shared__ double bnd[2];
+    __shared__ int best_s;
     const int t = blockIdx.x, lane = threadIdx.x;
-    double bound = 0.0, fmax2 = 0.0;
-    for (int j = lane; j < 2 * N - 1; j += 64) {
+    for (int j = lane; j < 2 * N - 1; j += BS_PTS) {
         const double f = (j & 1) ? e[j >> 1] : d[j >> 1];
         f2[j] = f * f;
     }
     __syncthreads();
-    for (int j = 0; j < 2 * N - 1; ++j) fmax2 = fmax(fmax2, f2[j]);
-    // Gershgorin bound of T: max_j |f_{j-1}| + |f_j|
-    for (int j = 0; j < 2 * N; ++j) {
-        const double l = j > 0 ? sqrt(f2[j - 1]) : 0.0;
-        const double r = j < 2 * N - 1 ? sqrt(f2[j]) : 0.0;
-        bound = fmax(bound, l + r);
+    if (lane == 0) {
+        double fmax2 = 0.0, bound = 0.0;
+        for (int j = 0; j < 2 * N - 1; ++j) fmax2 = fmax(fmax2, f2[j]);
+        // Gershgorin bound of T: max_j |f_{j-1}| + |f_j|
+        for (int j = 0; j < 2 * N; ++j) {
+            const double l = j > 0 ? sqrt(f2[j - 1]) : 0.0;
+            const double r = j < 2 * N - 1 ? sqrt(f2[j]) : 0.0;
+            bound = fmax(bound, l + r);
+        }
+        bnd[0] = fmax2;
+        bnd[1] = bound;
     }
+    __syncthreads();
+    const double fmax2 = bnd[0], bound = bnd[1];
     const double pivmin = 2.2250738585072014e-308 * fmax(1.0, fmax2);
     double lo = 0.0, hi = bound * (1.0 + 4.0 * 0x1.0p-52) + pivmin;
     // invariant: #{sigma >= lo} >= t + 1 (lo = 0 counts every value), #{sigma >= hi} <= t
-    for (int step = 0; step < 14; ++step) {
+    for (int step = 0; step < 16; ++step) {
         // relative precision 2u, or absolute u * ||T|| for values near zero
         if (hi - lo <= 2.0 * 0x1.0p-52 * fmax(fabs(lo), fabs(hi)) + pivmin ||
             hi - lo <= 0x1.0p-52 * bound)
             break;
-        const double x = lo + (hi - lo) * (double)(lane + 1) / 65.0;
+        const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(BS_PTS + 1);
         cnt[lane] = count_ge(N, f2, x, pivmin);
+        if (lane == 0) best_s = -1;
         __syncthreads();
-        // largest point still holding >= t + 1 values
-        int best = -1;
-        for (int l = 0; l < 64; ++l)
-            if (cnt[l] >= t + 1) best = l;
-        const double nlo = best >= 0 ? lo + (hi - lo) * (double)(best + 1) / 65.0 : lo;
-        const double nhi = best < 63 ? lo + (hi - lo) * (double)(best + 2) / 65.0 : hi;
+        // the last point still holding >= t + 1 values
+        if (cnt[lane] >= t + 1) atomicMax(&best_s, lane);
+        __syncthreads();
+        const int best = best_s;
+        const double nlo = best >= 0 ? lo + (hi - lo) * (double)(best + 1) / (double)(BS_PTS + 1) : lo;
+        const double nhi = best < BS_PTS - 1
+                               ? lo + (hi - lo) * (double)(best + 2) / (double)(BS_PTS + 1)
+                               : hi;
         lo = nlo;
         hi = nhi;
         __syncthreads();
@@ -537,10 +562,11 @@ __global__ __launch_bounds__(64) void tgk_bisect_kernel(int N, const double* __r
 
 // Inverse iteration for the eigenvector of T at +sigma_t: LU factorisation
 // with partial pivoting of the tridiagonal T - sigma I (row interchanges give
-// U a second superdiagonal), then three solves from a fixed +-1 start vector,
-// normalising each time. The eigenvector z = (v0, u0, v1, u1, ...) splits into
-// the bidiagonal's right and left singular vectors. Work arrays live in LDS;
-// one wavefront per value, the sequential recurrences on lane 0.
+// U a second superdiagonal), then two solves from the counter-based start
+// vector, normalising each time. The eigenvector z = (v0, u0, v1, u1, ...)
+// splits into the bidiagonal's right and left singular vectors. One wavefront
+// per value; the recurrences run on lane 0 with their carried values in
+// registers, the factors in LDS.
 __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __restrict__ d,
                                                        const double* __restrict__ e,
                                                        const double* __restrict__ sig,
@@ -551,64 +577,88 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
     __shared__ double z[2 * SVD_MAXN], dl[2 * SVD_MAXN], dd[2 * SVD_MAXN], du[2 * SVD_MAXN],
         du2[2 * SVD_MAXN];
     __shared__ unsigned char swp[2 * SVD_MAXN];
+    __shared__ double fm_s;
     const int t = blockIdx.x, lane = threadIdx.x;
     const int n = 2 * N;
-    for (int j = lane; j < n - 1; j += 64) f[j] = (j & 1) ? e[j >> 1] : d[j >> 1];
+    const double s = sig[t];
+    double fm = 0.0;
+    for (int j = lane; j < n - 1; j += 64) {
+        const double v = (j & 1) ? e[j >> 1] : d[j >> 1];
+        f[j] = v;
+        fm = fmax(fm, fabs(v));
+    }
+    for (int j = lane; j < n; j += 64) z[j] = start_pm1((uint64_t)t * 4096ULL + (uint64_t)j);
+    for (int off = 32; off > 0; off >>= 1) fm = fmax(fm, __shfl_xor(fm, off, 64));
+    if (lane == 0) fm_s = fmax(fm, fabs(s));
     __syncthreads();
     if (lane == 0) {
-        const double s = sig[t];
-        double fm = fabs(s);
-        for (int j = 0; j < n - 1; ++j) fm = fmax(fm, fabs(f[j]));
-        const double tiny = fm * 0x1.0p-52 + 1e-300;
-        for (int j = 0; j < n; ++j) {
-            dd[j] = -s;
-            if (j < n - 1) {
-                dl[j] = f[j];
-                du[j] = f[j];
-            }
-            if (j < n - 2) du2[j] = 0.0;
-        }
+        const double tiny = fm_s * 0x1.0p-52 + 1e-300;
+        // LU of T - s I: carried (dd_j, du_j); dl_j, du_{j+1} come from f
+        double ddj = -s, duj = n > 1 ? f[0] : 0.0;
         for (int j = 0; j < n - 1; ++j) {
-            if (fabs(dd[j]) >= fabs(dl[j])) {
-                swp[j] = 0;
-                const double fact = dd[j] != 0.0 ? dl[j] / dd[j] : 0.0;
-                dl[j] = fact;
-                dd[j + 1] -= fact * du[j];
-                if (j < n - 2) du2[j] = 0.0;
+            const double dlj = f[j];
+            const double dun = (j + 1 < n - 1) ? f[j + 1] : 0.0;
+            double odd, odu, odu2 = 0.0, fact;
+            unsigned char osw;
+            if (fabs(ddj) >= fabs(dlj)) {
+                fact = ddj != 0.0 ? dlj / ddj : 0.0;
+                osw = 0;
+                odd = ddj;
+                odu = duj;
+                ddj = -s - fact * duj;
+                duj = dun;
             } else {
-                swp[j] = 1;
-                const double fact = dd[j] / dl[j];
-                dd[j] = dl[j];
-                dl[j] = fact;
-                const double tmp = du[j];
-                du[j] = dd[j + 1];
-                dd[j + 1] = tmp - fact * dd[j + 1];
+                fact = ddj / dlj;
+                osw = 1;
+                odd = dlj;
+                odu = -s;
+                ddj = duj + fact * s;
                 if (j < n - 2) {
-                    du2[j] = du[j + 1];
-                    du[j + 1] = -fact * du[j + 1];
-                }
-            }
-        }
-        for (int j = 0; j < n; ++j)
-            if (fabs(dd[j]) < tiny) dd[j] = dd[j] < 0.0 ? -tiny : tiny;
-        for (int j = 0; j < n; ++j)
-            z[j] = start_pm1((uint64_t)t * 4096ULL + (uint64_t)j);
-        for (int it = 0; it < 2; ++it) {
-            for (int j = 0; j < n - 1; ++j) {
-                if (!swp[j]) {
-                    z[j + 1] -= dl[j] * z[j];
+                    odu2 = dun;
+                    duj = -fact * dun;
                 } else {
-                    const double tmp = z[j];
-                    z[j] = z[j + 1];
-                    z[j + 1] = tmp - dl[j] * z[j];
+                    duj = dun;
                 }
             }
-            z[n - 1] /= dd[n - 1];
-            if (n >= 2) z[n - 2] = (z[n - 2] - du[n - 2] * z[n - 1]) / dd[n - 2];
-            for (int j = n - 3; j >= 0; --j)
-                z[j] = (z[j] - du[j] * z[j + 1] - du2[j] * z[j + 2]) / dd[j];
-            double mx = 0.0;
-            for (int j = 0; j < n; ++j) mx = fmax(mx, fabs(z[j]));
+            dd[j] = fabs(odd) < tiny ? (odd < 0.0 ? -tiny : tiny) : odd;
+            dl[j] = fact;
+            du[j] = odu;
+            du2[j] = odu2;
+            swp[j] = osw;
+        }
+        dd[n - 1] = fabs(ddj) < tiny ? (ddj < 0.0 ? -tiny : tiny) : ddj;
+        for (int it = 0; it < 2; ++it) {
+            // forward: L^{-1} with the row interchanges, z_j carried
+            double zj = z[0];
+            for (int j = 0; j < n - 1; ++j) {
+                const double zn = z[j + 1];
+                const double l = dl[j];
+                if (!swp[j]) {
+                    z[j] = zj;
+                    zj = zn - l * zj;
+                } else {
+                    z[j] = zn;
+                    zj = zj - l * zn;
+                }
+            }
+            // back substitution, z_{j+1}, z_{j+2} carried
+            double z1 = zj / dd[n - 1], z2 = 0.0;
+            z[n - 1] = z1;
+            double mx = fabs(z1);
+            if (n >= 2) {
+                const double z0 = (z[n - 2] - du[n - 2] * z1) / dd[n - 2];
+                z[n - 2] = z0;
+                z2 = z1;
+                z1 = z0;
+                mx = fmax(mx, fabs(z0));
+            }
+            for (int j = n - 3; j >= 0; --j) {
+                const double z0 = (z[j] - du[j] * z1 - du2[j] * z2) / dd[j];
+                z[j] = z0;
+                z2 = z1;
+                z1 = z0;
+                mx = fmax(mx, fabs(z0));
+            }
             const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
             for (int j = 0; j < n; ++j) z[j] *= inv;
         }
@@ -632,85 +682,186 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
     }
 }
 
-// X (N x nv, ld) <- H_0 H_1 ... H_{nref-1} X for reflectors stored column-wise
-// in Vh (column k: entries k+off .. N-1, unit at k+off), tau[k]. One wavefront
-// per column of X (four per workgroup), the column in registers (N <= 64 R);
-// reflectors staged through LDS RCH at a time, applied last to first.
-template <int MAXN, int RCH, int R>
-__global__ __launch_bounds__(256) void reflect_apply_kernel(int N, int nref, int off,
-                                                            const double* __restrict__ Vh,
-                                                            const double* __restrict__ tau,
-                                                            double* __restrict__ X, int ldx,
-                                                            int nv)
+// Back-transformation of the bidiagonal's singular vectors.
+//   UB(:, t) <- H_0 ... H_{N-1} UB(:, t)   (left reflectors: row k of VL, unit at k)
+//   VB(:, t) <- G_0 ... G_{N-2} VB(:, t)   (right reflectors: row k of VR, unit at k + 1)
+// Blocks of WY_RB consecutive reflectors are applied, last block first, in the
+// compact WY form H_k0 ... H_k1 = I - Y T Y^T (T upper triangular). The T of
+// every block is built once by wy_t_kernel (one workgroup per block, from
+// Y^T Y and the tau's); backtransform_kernel then applies the blocks with one
+// wavefront per column, so a column needs WY_RB independent dot products per
+// block instead of WY_RB dependent ones.
+constexpr int WY_RB = 16;
+
+// grid.x = block index over both sides (left blocks first); 256 threads.
+__global__ __launch_bounds__(256) void wy_t_kernel(int N, const double* __restrict__ VL,
+                                                   const double* __restrict__ tL,
+                                                   const double* __restrict__ VR,
+                                                   const double* __restrict__ tR,
+                                                   double* __restrict__ Tout)
 {
-    __shared__ double vs[RCH][MAXN];
-    __shared__ double ts[RCH];
+    __shared__ double Y[WY_RB][SVD_MAXN];
+    __shared__ double YtY[WY_RB][WY_RB + 1];
+    __shared__ double Tm[WY_RB][WY_RB + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int col = blockIdx.x * 4 + wave;
-    double xr[R];
+    const int nblkL = (N + WY_RB - 1) / WY_RB;
+    const bool left = (int)blockIdx.x < nblkL;
+    const int blk = left ? blockIdx.x : blockIdx.x - nblkL;
+    const double* Vh = left ? VL : VR;
+    const double* tau = left ? tL : tR;
+    const int nref = left ? N : N - 1, off = left ? 0 : 1;
+    const int k0 = blk * WY_RB;
+    const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
+    for (int q = 0; q < WY_RB; ++q)
+        for (int i = tid; i < N; i += 256)
+            Y[q][i] = (q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+    __syncthreads();
+    // Y^T Y: pair (p, q), p < q, on wavefront (pair index % 4), lanes over i
+    for (int base = wave * 8; base < WY_RB * WY_RB; base += 32) {
+        double s[8];
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = lane + 64 * r;
-        xr[r] = (col < nv && i < N) ? X[(size_t)i * ldx + col] : 0.0;
-    }
-    for (int k1 = nref - 1; k1 >= 0; k1 -= RCH) {
-        const int k0 = k1 - RCH + 1 < 0 ? 0 : k1 - RCH + 1;
-        const int cnt = k1 - k0 + 1;
-        __syncthreads();
-        for (int e = tid; e < cnt * N; e += 256) {
-            const int q = e / N, i = e - q * N;
-            const int k = k0 + q;
-            vs[q][i] = (i >= k + off) ? Vh[(size_t)k * N + i] : 0.0;
+        for (int u = 0; u < 8; ++u) {
+            const int pq = base + u, p = pq / WY_RB, q = pq % WY_RB;
+            double a = 0.0;
+            if (p < q)
+                for (int i = lane; i < N; i += 64) a += Y[p][i] * Y[q][i];
+            s[u] = a;
         }
-        if (tid < cnt) ts[tid] = tau[k0 + tid];
-        __syncthreads();
-        for (int q = cnt - 1; q >= 0; --q) {
-            const double tk = ts[q];
-            if (tk == 0.0) continue;
-            double dot = 0.0;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = lane + 64 * r;
-                if (i < N) dot += vs[q][i] * xr[r];
+        for (int u = 0; u < 8; ++u) s[u] = wave_sum64(s[u]);
+        if (lane == 0)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int pq = base + u, p = pq / WY_RB, q = pq % WY_RB;
+                if (p < q) YtY[p][q] = s[u];
             }
-            for (int o = 32; o > 0; o >>= 1) dot += __shfl_xor(dot, o, 64);
-            const double w = tk * dot;
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int i = lane + 64 * r;
-                if (i < N) xr[r] -= vs[q][i] * w;
-            }
-        }
     }
-    if (col < nv) {
+    __syncthreads();
+    // T (forward, columnwise): T[q][q] = tau_q, T[0:q, q] = -tau_q T[0:q, 0:q] Y^T y_q
+    if (wave == 0) {
+        for (int q = 0; q < WY_RB; ++q) {
+            const double tq = q < cnt ? tau[k0 + q] : 0.0;
+            double v = 0.0;
+            if (lane < q) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = lane + 64 * r;
-            if (i < N) X[(size_t)i * ldx + col] = xr[r];
+                for (int r = 0; r < WY_RB; ++r)
+                    if (r >= lane && r < q) v += Tm[lane][r] * YtY[r][q];
+                v *= -tq;
+            }
+            if (lane < WY_RB) Tm[lane][q] = lane < q ? v : (lane == q ? tq : 0.0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
         }
+        for (int e = lane; e < WY_RB * WY_RB; e += 64)
+            Tout[(size_t)blockIdx.x * WY_RB * WY_RB + e] = Tm[e / WY_RB][e % WY_RB];
     }
 }
 
-// Sign convention: the largest-magnitude entry of each left vector positive
-// (the right vector flips with it).
-__global__ void sign_fix_kernel(int N, int nv, double* UB, double* VB, int ld)
+template <int MAXN, int R>
+__global__ __launch_bounds__(256) void backtransform_kernel(
+    int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
+    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nv) return;
+    __shared__ double Y[WY_RB][MAXN];
+    __shared__ double Tm[WY_RB][WY_RB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int col = blockIdx.x * 4 + wave;
+    const int nblkL = (N + WY_RB - 1) / WY_RB;
+    double xr[R], yr[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        xr[r] = (col < nv && i < N) ? UB[(size_t)i * ld + col] : 0.0;
+        yr[r] = (col < nv && i < N) ? VB[(size_t)i * ld + col] : 0.0;
+    }
+    for (int side = 0; side < 2; ++side) {
+        const double* Vh = side == 0 ? VL : VR;
+        const int nref = side == 0 ? N : N - 1, off = side;
+        const int nblk = (nref + WY_RB - 1) / WY_RB;
+        for (int blk = nblk - 1; blk >= 0; --blk) {
+            const int k0 = blk * WY_RB;
+            const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
+            const int tb = side == 0 ? blk : nblkL + blk;
+            __syncthreads();
+            for (int q = 0; q < WY_RB; ++q)
+                for (int i = tid; i < N; i += 256)
+                    Y[q][i] = (q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+            Tm[tid >> 4][tid & 15] = Tall[(size_t)tb * WY_RB * WY_RB + tid];
+            __syncthreads();
+            // x <- x - Y (T (Y^T x))
+            double yx[WY_RB];
+#pragma unroll
+            for (int q = 0; q < WY_RB; ++q) {
+                double s = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int i = lane + 64 * r;
+                    if (i < N) s += Y[q][i] * (side == 0 ? xr[r] : yr[r]);
+                }
+                yx[q] = s;
+            }
+#pragma unroll
+            for (int q = 0; q < WY_RB; ++q) yx[q] = wave_sum64(yx[q]);
+            double wv[WY_RB];
+#pragma unroll
+            for (int p = 0; p < WY_RB; ++p) {
+                double s = 0.0;
+#pragma unroll
+                for (int q = 0; q < WY_RB; ++q)
+                    if (q >= p) s += Tm[p][q] * yx[q];
+                wv[p] = s;
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int i = lane + 64 * r;
+                if (i < N) {
+                    double s = 0.0;
+#pragma unroll
+                    for (int p = 0; p < WY_RB; ++p) s += Y[p][i] * wv[p];
+                    if (side == 0)
+                        xr[r] -= s;
+                    else
+                        yr[r] -= s;
+                }
+            }
+        }
+    }
+    // sign convention: the first largest-magnitude entry of the left vector positive
+    double vmax = -1.0;
     int imax = 0;
-    double vmax = 0.0;
-    for (int i = 0; i < N; ++i) {
-        const double a = fabs(UB[(size_t)i * ld + t]);
-        if (a > vmax) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = lane + 64 * r;
+        const double a = fabs(xr[r]);
+        if (i < N && a > vmax) {
             vmax = a;
             imax = i;
         }
     }
-    if (UB[(size_t)imax * ld + t] < 0.0)
-        for (int i = 0; i < N; ++i) {
-            UB[(size_t)i * ld + t] = -UB[(size_t)i * ld + t];
-            VB[(size_t)i * ld + t] = -VB[(size_t)i * ld + t];
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(vmax, o, 64);
+        const int oi = __shfl_xor(imax, o, 64);
+        if (ov > vmax || (ov == vmax && oi < imax)) {
+            vmax = ov;
+            imax = oi;
         }
+    }
+    double xv = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (lane + 64 * r == imax) xv = xr[r];
+    xv = wave_sum64(xv);
+    const double sg = xv < 0.0 ? -1.0 : 1.0;
+    if (col < nv) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            if (i < N) {
+                UB[(size_t)i * ld + col] = sg * xr[r];
+                VB[(size_t)i * ld + col] = sg * yr[r];
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -722,7 +873,9 @@ size_t small_svd_gk_scratch_elems(int N)
     // d, e, tauL, tauR, the reflector vectors VL, VR, and for the cooperative
     // bidiagonalisation the published column, partials and barrier counter
     const size_t P = (N + 31) / 32;
-    return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8;
+    const size_t nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
+    return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
+           nblk * WY_RB * WY_RB;
 }
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
@@ -737,8 +890,10 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     double* tR = tL + N;
     double* VL = tR + N;
     double* VR = VL + (size_t)N * N;
-    static const char* const coop_fam[4] = {"gk_bidiag_coop_q20", "gk_bidiag_coop_q24",
-                                            "gk_bidiag_coop_q28", "gk_bidiag_coop_q32"};
+    static const char* const coop_fam[8] = {"gk_bidiag_coop_q20", "gk_bidiag_coop_q24",
+                                            "gk_bidiag_coop_q28", "gk_bidiag_coop_q32",
+                                            "gk_bidiag_coop_q40", "gk_bidiag_coop_q48",
+                                            "gk_bidiag_coop_q56", "gk_bidiag_coop_q64"};
     static const char* const one_fam[7] = {"gk_bidiag_p1", "gk_bidiag_p2", "gk_bidiag_p3",
                                            "gk_bidiag_p4", "gk_bidiag_p5", "gk_bidiag_p6",
                                            "gk_bidiag_p7"};
@@ -746,7 +901,8 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     const double bd_flops = 8.0 / 3.0 * N * (double)N * N;
     if (N > GK_MAXN) {
         const int NQc = (N + 15) / 16;
-        const int qi = NQc <= 20 ? 0 : NQc <= 24 ? 1 : NQc <= 28 ? 2 : 3;
+        const int qi = NQc <= 20 ? 0 : NQc <= 24 ? 1 : NQc <= 28 ? 2 : NQc <= 32 ? 3
+                     : NQc <= 40 ? 4 : NQc <= 48 ? 5 : NQc <= 56 ? 6 : 7;
         TimedLaunch tl(tm, coop_fam[qi], s, bd_flops, 16.0 * N * N);
         const int P = (N + 31) / 32;
         CoopBuf cb;
@@ -763,7 +919,11 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         if (NQ <= 20) fn = (const void*)gk_bidiag_coop_kernel<20>;
         else if (NQ <= 24) fn = (const void*)gk_bidiag_coop_kernel<24>;
         else if (NQ <= 28) fn = (const void*)gk_bidiag_coop_kernel<28>;
-        else fn = (const void*)gk_bidiag_coop_kernel<32>;
+        else if (NQ <= 32) fn = (const void*)gk_bidiag_coop_kernel<32>;
+        else if (NQ <= 40) fn = (const void*)gk_bidiag_coop_kernel<40>;
+        else if (NQ <= 48) fn = (const void*)gk_bidiag_coop_kernel<48>;
+        else if (NQ <= 56) fn = (const void*)gk_bidiag_coop_kernel<56>;
+        else fn = (const void*)gk_bidiag_coop_kernel<64>;
         HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(P), dim3(512), args, 0, s));
     } else {
         const int NP = (N + 31) / 32;
@@ -787,25 +947,25 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     }
     {
         TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
-        hipLaunchKernelGGL(tgk_bisect_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S);
+        hipLaunchKernelGGL(tgk_bisect_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S);
         hipLaunchKernelGGL(tgk_invit_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S, UB, VB, N);
     }
     {
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
-        if (N <= GK_MAXN) {
-            hipLaunchKernelGGL((reflect_apply_kernel<GK_MAXN, 16, 4>), dim3(blocks), dim3(256), 0,
-                               s, N, N, 0, VL, tL, UB, N, nv);
-            hipLaunchKernelGGL((reflect_apply_kernel<GK_MAXN, 16, 4>), dim3(blocks), dim3(256), 0,
-                               s, N, N - 1, 1, VR, tR, VB, N, nv);
-        } else {
-            hipLaunchKernelGGL((reflect_apply_kernel<SVD_MAXN, 8, 8>), dim3(blocks), dim3(256), 0,
-                               s, N, N, 0, VL, tL, UB, N, nv);
-            hipLaunchKernelGGL((reflect_apply_kernel<SVD_MAXN, 8, 8>), dim3(blocks), dim3(256), 0,
-                               s, N, N - 1, 1, VR, tR, VB, N, nv);
-        }
-        hipLaunchKernelGGL(sign_fix_kernel, dim3((nv + 63) / 64), dim3(64), 0, s, N, nv, UB, VB,
-                           N);
+        const int nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
+        double* Tall = VR + (size_t)N * N + 2 * (size_t)N + 2 * (size_t)((N + 31) / 32) +
+                       2 * (size_t)((N + 31) / 32) * N + 8;
+        hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, N, VL, tL, VR, tR, Tall);
+        if (N <= 256)
+            hipLaunchKernelGGL((backtransform_kernel<256, 4>), dim3(blocks), dim3(256), 0, s, N,
+                               nv, VL, VR, Tall, UB, VB, N);
+        else if (N <= 512)
+            hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks), dim3(256), 0, s, N,
+                               nv, VL, VR, Tall, UB, VB, N);
+        else
+            hipLaunchKernelGGL((backtransform_kernel<SVD_MAXN, 16>), dim3(blocks), dim3(256), 0, s,
+                               N, nv, VL, VR, Tall, UB, VB, N);
     }
 }
 

@@ -247,7 +247,7 @@ void orth_against(Context& cx, StepWs<T>& sw, hipStream_t s, int rows, int b0, c
 }
 
 // SVD of the small projected matrix: the top nv values and vectors, by the
-// Golub-Kahan path (N <= 512), whose leading vectors are then polished to
+// Golub-Kahan path (N <= 1024), whose leading vectors are then polished to
 // orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
 // values only nearly orthogonal). The one-sided Jacobi kernel serves larger N.
 // nflag[1] is set if the cooperative bidiagonalisation timed out.
@@ -258,8 +258,14 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
     TimedLaunch tl(&cx.timer, "small_svd", s, 0.0, 0.0);
     if (small_svd_gk_supported(N)) {
         small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s);
-        orth_against<double>(cx, w, s, N, 0, nullptr, 0, UB, N, nv, UB, N, seed);
-        orth_against<double>(cx, w, s, N, 0, nullptr, 0, VB, N, nv, VB, N, seed);
+        if (cholqr2_small_supported(N, nv)) {
+            const uint64_t sid0 = (1ULL << 20) + (++cx.fix_calls);
+            const uint64_t sid1 = (1ULL << 20) + (++cx.fix_calls);
+            cholqr2_small(&cx.timer, N, nv, UB, VB, N, w.nflag, CHOL_ETA, seed, sid0, sid1, s);
+        } else {
+            orth_against<double>(cx, w, s, N, 0, nullptr, 0, UB, N, nv, UB, N, seed);
+            orth_against<double>(cx, w, s, N, 0, nullptr, 0, VB, N, nv, VB, N, seed);
+        }
     } else {
         small_svd_jacobi(&cx.timer, N, B, ldb, UB, S, VB, svd_scratch, s);
     }

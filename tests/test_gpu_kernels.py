@@ -69,7 +69,7 @@ def test_gemm_is_deterministic(torch, ctx):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
 
 
-@pytest.mark.parametrize("N", [1, 2, 7, 32, 64, 224, 225, 256, 300, 416, 512])
+@pytest.mark.parametrize("N", [1, 2, 7, 32, 64, 224, 225, 256, 300, 416, 512, 640, 1024])
 def test_small_svd_matches_oracle_jacobi(torch, ctx, N):
     g = np.random.default_rng(N)
     B = g.standard_normal((N, N)) * np.geomspace(1.0, 1e-6, N)[None, :]

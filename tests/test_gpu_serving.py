@@ -174,7 +174,7 @@ def test_submit_checks_arguments(torch, blws):
     assert e.value.status == -1
     D = torch.zeros(8, 8, dtype=torch.float64, device="cuda")
     with pytest.raises(blws.BlwsError) as e:
-        srv.submit_rpca(D, opts=blws.default_alm_opts(b_max=300))
+        srv.submit_rpca(D, opts=blws.default_alm_opts(b_max=600))
     assert e.value.status == -5
     assert srv.stats()["submitted"] == 0
     srv.close()
