@@ -279,26 +279,28 @@ struct CoopBuf {
     int* err;        // set on a barrier timeout
 };
 
-__device__ __forceinline__ double ld_agent(double* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_agent(double* p, double v)
-{
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
+// The partials are exchanged with plain stores and loads: the barrier's
+// agent-scope release (after the stores) and acquire (before the loads) make
+// them visible across the XCDs, and plain loads can all be in flight at once.
+__device__ __forceinline__ double ld_agent(const double* p) { return *p; }
+__device__ __forceinline__ void st_agent(double* p, double v) { *p = v; }
 
-// Device-wide barrier among the co-resident workgroups: release of this
-// workgroup's writes, arrival count, bounded wait, acquire.
+// Device-wide barrier among the co-resident workgroups. Every wavefront
+// first waits for its own stores to complete (so they sit in this XCD's L2);
+// after the workgroup barrier one thread makes them visible at agent scope
+// (release: L2 write-back), arrives, polls the counter with relaxed loads
+// (bounded), and invalidates the local caches once (acquire) before the
+// workgroup continues.
 __device__ bool coop_barrier(unsigned* ctr, unsigned target, int* err, int* ok_lds)
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int ok = 1;
         unsigned spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
             if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
                 ++spins > CO_SPIN_LIMIT) {
                 __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -307,11 +309,36 @@ __device__ bool coop_barrier(unsigned* ctr, unsigned target, int* err, int* ok_l
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         *ok_lds = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     return *ok_lds != 0;
+}
+
+// Butterfly transpose-reduction over the 32 lanes of a half-wavefront: lane
+// c holds v[0..32); on return v[0] of lane c is the sum over the 32 lanes of
+// their v[c]. Each level pairs lane c with c ^ s; the lane keeps the half of
+// its remaining values whose index bit matches its own lane bit and adds the
+// partner's copy of that half (31 shuffles in all, the adds independent).
+template <int S>
+__device__ __forceinline__ void transpose_level(double (&v)[32], bool hi)
+{
+#pragma unroll
+    for (int j = 0; j < S; ++j) {
+        const double keep = hi ? v[j + S] : v[j];
+        const double send = hi ? v[j] : v[j + S];
+        v[j] = keep + __shfl_xor(send, S, 64);
+    }
+}
+
+__device__ __forceinline__ void transpose_sum32(double (&v)[32], int c)
+{
+    transpose_level<16>(v, (c & 16) != 0);
+    transpose_level<8>(v, (c & 8) != 0);
+    transpose_level<4>(v, (c & 4) != 0);
+    transpose_level<2>(v, (c & 2) != 0);
+    transpose_level<1>(v, (c & 1) != 0);
 }
 
 template <int NQ>
@@ -347,7 +374,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
             const double alpha = xcol[k];
             double s2 = 0.0;
             for (int i = k + 1 + lane; i < N; i += 64) s2 += xcol[i] * xcol[i];
-            for (int off = 32; off > 0; off >>= 1) s2 += __shfl_xor(s2, off, 64);
+            s2 = wave_sum64(s2);
             double tau = 0.0, beta = alpha, scale = 0.0;
             if (s2 > 0.0) {
                 const double nrm = sqrt(alpha * alpha + s2);
@@ -374,19 +401,25 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
         const double tl = sc[0];
         if (tl != 0.0) {
             // w_j = tau sum_{i >= k} u_i B[i][j] for own columns j > k
-            double pw = 0.0;
+            double pw[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 if (16 * q + 15 < k) continue;  // uniform
                 const int i = g + 16 * q;
-                if (i >= k && i < N) pw += xcol[i] * a[q];
+                pw[q & 3] += (i >= k && i < N) ? xcol[i] * a[q] : 0.0;
             }
-            red[g][c] = pw;
+            red[g][c] = (pw[0] + pw[1]) + (pw[2] + pw[3]);
             __syncthreads();
             if (tid < 32) {
-                double w = 0.0;
-                for (int gg = 0; gg < 16; ++gg) w += red[gg][tid];
-                wcol[tid] = tl * w;
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < 16; gg += 4) {
+                    w0 += red[gg][tid];
+                    w1 += red[gg + 1][tid];
+                    w2 += red[gg + 2][tid];
+                    w3 += red[gg + 3][tid];
+                }
+                wcol[tid] = tl * ((w0 + w1) + (w2 + w3));
             }
             __syncthreads();
             const double wj = (jv && j > k) ? wcol[c] : 0.0;
@@ -410,15 +443,19 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
         }
         __syncthreads();
         {
+            // partial (B x)_i over this slab's columns, rows i = g + 16 q: the
+            // products of the 32 column-lanes summed by a transpose-reduction,
+            // after which lane c holds row g + 16 (q0 + c)
             const double xj = (jv && j >= k + 2) ? rowk[c] : 0.0;
             double* prow = cb.part + ((size_t)slot * P + p) * N;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (16 * q + 15 < k + 1) continue;  // uniform
-                const int i = g + 16 * q;
-                double sq = a[q] * xj;
-                for (int off = 16; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
-                if (c == 0 && i >= k + 1 && i < N) st_agent(prow + i, sq);
+            for (int q0 = 0; q0 < NQ; q0 += 32) {
+                double v[32];
+#pragma unroll
+                for (int u = 0; u < 32; ++u) v[u] = (q0 + u < NQ) ? a[q0 + u < NQ ? q0 + u : 0] * xj : 0.0;
+                transpose_sum32(v, c);
+                const int i = g + 16 * (q0 + c);
+                if (q0 + c < NQ && i >= k + 1 && i < N) st_agent(prow + i, v[0]);
             }
         }
         if (tid == 0) {
@@ -438,8 +475,11 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
         }
         if (!coop_barrier(cb.ctr, (unsigned)(k + 1) * (unsigned)P, cb.err, &okl)) return;
 
-        // ---- the reflector, z = B v and the next column, from the partials
-        if (tid == 0) {
+        // ---- the reflector, z = B v and the next column, from the partials;
+        // every thread loads the norms with its partials and forms the
+        // reflector itself (same loads, same order: the same bits everywhere)
+        double tq, scl;
+        {
             const double alpha = ld_agent(cb.colpub + (size_t)slot * N + k);
             double s2 = 0.0;
             for (int q = 0; q < P; ++q) s2 += ld_agent(cb.nrm + slot * P + q);
@@ -450,15 +490,13 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
                 tau = (beta - alpha) / beta;
                 scale = 1.0 / (alpha - beta);
             }
-            sc[1] = tau;
-            sc[2] = scale;
-            if (p == 0) {
+            tq = tau;
+            scl = scale;
+            if (p == 0 && tid == 0) {
                 tauR[k] = tau;
                 eout[k] = beta;
             }
         }
-        __syncthreads();
-        const double tq = sc[1], scl = sc[2];
         for (int i = k + 1 + tid; i < N; i += 512) {
             double acc = 0.0;
             for (int q = 0; q < P; ++q) acc += ld_agent(cb.part + ((size_t)slot * P + q) * N + i);

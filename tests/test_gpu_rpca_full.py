@@ -107,3 +107,41 @@ def test_rpca_n2000_fp32_error_stated(torch, ctx, golden, instance):
           f"residual={info['rel_residual']:.3e} sampled rel err A {err_a:.3e}")
     assert info["rank"] == golden["rank"]
     assert err_a < 1e-4
+
+
+# n = 4000, rank 200, 10% corruption U[-500, 500], rho = 1.2: the precision
+# variant's size. Stored values from the oracle's BLWS form (same algorithm).
+@pytest.fixture(scope="module")
+def golden4k():
+    with open(os.path.join(HERE, "golden", "rpca_n4000_s0.json")) as f:
+        return json.load(f)
+
+
+@pytest.mark.parametrize("mode", ["f64", "bf16"])
+def test_rpca_n4000_matches_oracle(torch, ctx, golden4k, mode):
+    import paper_1012_0365_amd as blws
+
+    p = golden4k["params"]
+    inst = synth.rpca_instance(p["m"], p["n"], p["r"], p["frac"], p["amp"], p["seed"])
+    D = torch.tensor(inst["D"], dtype=torch.float64 if mode == "f64" else torch.float32,
+                     device="cuda")
+    A, E, info = ctx.rpca_solve(D, opts=blws.default_alm_opts(rho=p["rho"]), bf16=mode == "bf16")
+    torch.cuda.synchronize()
+    pos = torch.tensor(golden4k["sample_pos"], device="cuda")
+    a_s = A.double().reshape(-1)[pos].cpu().numpy()
+    e_s = E.double().reshape(-1)[pos].cpu().numpy()
+    a_ref = np.array(golden4k["A_samples"])
+    e_ref = np.array(golden4k["E_samples"])
+    err_a = np.linalg.norm(a_s - a_ref) / np.linalg.norm(a_ref)
+    err_e = np.linalg.norm(e_s - e_ref) / np.linalg.norm(e_ref)
+    r = p["r"]
+    sA = torch.linalg.svdvals(A.double()).cpu().numpy()
+    sref = np.array(golden4k["sigma_A"])
+    err_s = np.max(np.abs(sA[:r] - sref[:r]) / sref[:r])
+    print(f"n4000 {mode}: iters={info['iters']} (oracle {golden4k['iters']}) rank={info['rank']} "
+          f"(oracle {golden4k['rank']}) bf16 iters={info['iters_bf16']} sampled rel err A "
+          f"{err_a:.3e} E {err_e:.3e}, top-{r} sigma {err_s:.3e}, {info['seconds']:.3f}s")
+    assert info["status"] == 0
+    assert abs(info["rank"] - golden4k["rank"]) <= 2
+    assert abs(info["iters"] - golden4k["iters"]) <= 2
+    assert err_a < 1e-6 and err_e < 1e-6 and err_s < 1e-6
