@@ -35,10 +35,11 @@ __device__ __forceinline__ double start_pm1(uint64_t counter)
     z ^= z >> 31;
     return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
-// Sums across lanes. Within a row of 16 lanes the partial sums move by DPP
-// row rotations (VALU, a few cycles each); only the steps across rows use
-// ds_bpermute shuffles. Every lane ends with the total, so all lanes hold
-// the same bits.
+// Sums across lanes, all on the VALU. Within a row of 16 lanes the partial
+// sums move by DPP row rotations; across rows by the gfx950 permlane swaps:
+// v_permlane16_swap on (x, x) yields (x0, x0, x2, x2) and (x1, x1, x3, x3)
+// for rows x0..x3, v_permlane32_swap yields (lo, lo) and (hi, hi) for the
+// two halves, so that adding the pair gives every lane the same bits.
 template <int CTRL>
 __device__ __forceinline__ double dpp_move(double x)
 {
@@ -46,6 +47,29 @@ __device__ __forceinline__ double dpp_move(double x)
     const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffffu), CTRL, 0xF, 0xF, false);
     const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double join_words(unsigned lo, unsigned hi)
+{
+    return __longlong_as_double(((unsigned long long)hi << 32) | lo);
+}
+// a + b with a from the even and b from the odd 16-lane row of each pair,
+// given in every lane of both rows
+__device__ __forceinline__ double rows_pair_sum(double x)
+{
+    const unsigned long long u = __double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane16_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
+}
+// lower-half value + upper-half value, in every lane
+__device__ __forceinline__ double halves_sum(double x)
+{
+    const unsigned long long u = __double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)u, (unsigned)u, false, false);
+    const auto hi =
+        __builtin_amdgcn_permlane32_swap((unsigned)(u >> 32), (unsigned)(u >> 32), false, false);
+    return join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
 }
 // row_ror:n is DPP control 0x120 + n
 __device__ __forceinline__ double row_sum16(double x)
@@ -58,25 +82,227 @@ __device__ __forceinline__ double row_sum16(double x)
 }
 __device__ __forceinline__ double half_sum32(double x)  // over the 32 lanes of a half-wavefront
 {
-    x = row_sum16(x);
-    return x + __shfl_xor(x, 16, 64);
+    return rows_pair_sum(row_sum16(x));
 }
 __device__ __forceinline__ double wave_sum64(double x)
 {
-    x = row_sum16(x);
-    x += __shfl_xor(x, 16, 64);
-    return x + __shfl_xor(x, 32, 64);
+    return halves_sum(rows_pair_sum(row_sum16(x)));
+}
+
+// Broadcast within each half-wavefront: every lane of lanes 0-31 gets v of
+// lane src, every lane of lanes 32-63 gets v of lane src + 32 (src uniform).
+__device__ __forceinline__ double bcast_half(double v, int src)
+{
+    const unsigned long long u = __double_as_longlong(v);
+    const int lo = (int)(u & 0xffffffffu), hi = (int)(u >> 32);
+    const int lo0 = __builtin_amdgcn_readlane(lo, src), hi0 = __builtin_amdgcn_readlane(hi, src);
+    const int lo1 = __builtin_amdgcn_readlane(lo, src + 32);
+    const int hi1 = __builtin_amdgcn_readlane(hi, src + 32);
+    const bool upper = (threadIdx.x & 32) != 0;
+    const int rlo = upper ? lo1 : lo0, rhi = upper ? hi1 : hi0;
+    return __longlong_as_double(((unsigned long long)(unsigned)rhi << 32) | (unsigned)rlo);
+}
+
+// Householder reflector H = I - tau v v^T with v_0 = 1 mapping (alpha, x)
+// to (beta, 0): from alpha and s2 = |x|^2; v = (1, x * scale).
+__device__ __forceinline__ void house(double alpha, double s2, double& tau, double& beta,
+                                      double& scale)
+{
+    tau = 0.0;
+    beta = alpha;
+    scale = 0.0;
+    if (s2 > 0.0) {
+        const double nrm = sqrt(alpha * alpha + s2);
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+    }
 }
 
 constexpr int GK_LD = GK_MAXN + 1;  // padded LDS row of the partial sums
 
-// Thread (tr, tc) of the 32 x 16 grid owns rows tr + 32a (a < NPR) and
-// columns tc + 16c (c < 2 NPR): 7 x 14 doubles at N = 224. Per column step
-// four barriers: every wavefront forms each reflector itself from the
-// published column or row (bit-identical in all of them), the column dot
-// products of the left reflection are reduced over the 32 row-lanes of a
-// half-wavefront by shuffles, and only the row products of the right
-// reflection go through LDS.
+struct GkShared {
+    double part[8 * GK_LD];  // per-wavefront partial products B x (right reflection)
+    double xc[GK_MAXN];      // the current column (rows >= k): the next left reflection
+    double cp[GK_MAXN];      // column k + 1 after the left reflection of step k
+    double zs[GK_MAXN];      // B v of the right reflection (without tau), rows > k
+    double sx[16 * 16];      // row k beyond k + 1, per half-wavefront: its own columns only
+    double sq[16 * 16];      // column sums of the left reflection, per half-wavefront
+    double pn[8];            // per-wavefront partial sums of squares of row k
+    double ax;               // B[k][k + 1] after the left reflection
+};
+
+struct GkOut {
+    int N;
+    double *d, *e, *VL, *tauL, *VR, *tauR;
+};
+
+// Steps k of column block KC (16 KC <= k < 16 KC + 16) of the one-workgroup
+// bidiagonalisation; row group KC / 2 and column group KC are compile-time,
+// so groups wholly above or left of the active trailing matrix cost nothing.
+// Per step two barriers:
+//  - left reflection of column k (from xc, every wavefront forms it itself):
+//    the column products q_j = sum_{i > k} xc_i B_ij are summed over the 32
+//    row-lanes of a half-wavefront while the norm is formed, and combined with
+//    row k (read across lanes) once the scale is known;
+//  - right reflection of row k: its entries are known in every lane after the
+//    left update; each wavefront publishes its share of |x|^2 and of B x, the
+//    owner of column k + 1 publishes that column (barrier 1); thread i forms
+//    z_i = (B v)_i and the next column (barrier 2), and every thread applies
+//    the rank-1 update to its part.
+template <int NPR, int KC>
+__device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
+                                         double (&Br)[NPR][2 * NPR])
+{
+    constexpr int NPC = 2 * NPR;
+    if constexpr (KC < NPC) {
+        constexpr int KA = KC / 2;
+        const int N = o.N;
+        const int tid = threadIdx.x, lane = tid & 63, tr = tid & 31, tc = tid >> 5;
+        const int kend = min(16 * KC + 16, N);
+        for (int k = 16 * KC; k < kend; ++k) {
+            // ---- left reflection of column k
+            const double alphaL = sh.xc[k];
+            double s2a = 0.0, s2b = 0.0;
+            {
+                int i = k + 1 + lane;
+                for (; i + 64 < N; i += 128) {
+                    const double u0 = sh.xc[i], u1 = sh.xc[i + 64];
+                    s2a += u0 * u0;
+                    s2b += u1 * u1;
+                }
+                if (i < N) s2a += sh.xc[i] * sh.xc[i];
+            }
+            double xa[NPR];
+#pragma unroll
+            for (int a = KA; a < NPR; ++a)  // rows > k (xc is zero beyond N)
+                xa[a] = (tr > k - 32 * a) ? sh.xc[tr + 32 * a] : 0.0;
+#pragma unroll
+            for (int c = KC; c < NPC; ++c) {
+                double p = 0.0;
+#pragma unroll
+                for (int a = KA; a < NPR; ++a) p += xa[a] * Br[a][c];
+                p = half_sum32(p);
+                if (tr == 0) sh.sq[tc * 16 + c] = p;
+            }
+            double tauLk, betaL, scaleL;
+            house(alphaL, wave_sum64(s2a + s2b), tauLk, betaL, scaleL);
+            if (tid > k && tid < N) o.VL[(size_t)k * N + tid] = sh.xc[tid] * scaleL;
+            if (tid == k) {
+                o.VL[(size_t)k * N + k] = 1.0;
+                o.tauL[k] = tauLk;
+                o.d[k] = betaL;
+            }
+            double va[NPR];
+#pragma unroll
+            for (int a = KA; a < NPR; ++a) va[a] = (tr == k - 32 * a) ? 1.0 : xa[a] * scaleL;
+            const int kl = k & 31;
+            double axv = 0.0;
+#pragma unroll
+            for (int c = KC; c < NPC; ++c) {  // column j = tc + 16 c; zero beyond N
+                const double rk = bcast_half(Br[KA][c], kl);  // B[k][j]
+                const double wj =
+                    (tc > k - 16 * c) ? tauLk * (rk + scaleL * sh.sq[tc * 16 + c]) : 0.0;
+#pragma unroll
+                for (int a = KA; a < NPR; ++a) Br[a][c] -= va[a] * wj;
+                const double xk = rk - wj;  // row k after the reflection
+                if (tr == 0) sh.sx[tc * 16 + c] = (tc >= k + 2 - 16 * c) ? xk : 0.0;
+                if (tc == k + 1 - 16 * c) axv = xk;
+            }
+            if (k + 1 >= N) break;
+            // ---- right reflection of row k: partial sums, column k + 1
+            // (sx is private to the half-wavefront: written and read back by
+            // the same wavefront, in order)
+            {
+                double xr[NPC];
+#pragma unroll
+                for (int c = KC; c < NPC; ++c) xr[c] = sh.sx[tc * 16 + c];
+                double pa = 0.0, pb = 0.0;
+#pragma unroll
+                for (int c = KC; c < NPC; ++c) {
+                    if ((c - KC) & 1)
+                        pb += xr[c] * xr[c];
+                    else
+                        pa += xr[c] * xr[c];
+                }
+                const double pnh = halves_sum(pa + pb);
+                if (lane == 0) sh.pn[tid >> 6] = pnh;
+                if (tc == ((k + 1) & 15)) {
+                    if (tr == 0) sh.ax = axv;
+                    const bool next = (k & 15) == 15;
+#pragma unroll
+                    for (int a = KA; a < NPR; ++a) {
+                        double v = Br[a][KC];
+                        if constexpr (KC + 1 < NPC)
+                            if (next) v = Br[a][KC + 1];
+                        if (tr > k - 32 * a) sh.cp[tr + 32 * a] = v;
+                    }
+                }
+                double acc[NPR];
+#pragma unroll
+                for (int a = KA; a < NPR; ++a) acc[a] = 0.0;
+#pragma unroll
+                for (int c = KC; c < NPC; ++c)
+#pragma unroll
+                    for (int a = KA; a < NPR; ++a) acc[a] += Br[a][c] * xr[c];
+#pragma unroll
+                for (int a = KA; a < NPR; ++a) {
+                    const double t = halves_sum(acc[a]);
+                    if (lane < 32) sh.part[(tid >> 6) * GK_LD + tr + 32 * a] = t;
+                }
+            }
+            __syncthreads();
+            double tauRk, betaR, scaleR;
+            {
+                double s2 = 0.0;
+#pragma unroll
+                for (int w = 0; w < 8; ++w) s2 += sh.pn[w];
+                house(sh.ax, s2, tauRk, betaR, scaleR);
+            }
+            if (tr < NPC - KC) {  // lane tr stores column tc + 16 (KC + tr) of row k
+                const int j = tc + 16 * (KC + tr);
+                if (j >= k + 2 && j < N) o.VR[(size_t)k * N + j] = sh.sx[tc * 16 + KC + tr] * scaleR;
+            }
+            if (tid == 0) {
+                o.VR[(size_t)k * N + k + 1] = 1.0;
+                o.tauR[k] = tauRk;
+                o.e[k] = betaR;
+            }
+            if (tid > k && tid < N) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int w = 0; w < 8; w += 2) {
+                    s0 += sh.part[w * GK_LD + tid];
+                    s1 += sh.part[(w + 1) * GK_LD + tid];
+                }
+                const double c0 = sh.cp[tid];
+                const double z = c0 + scaleR * (s0 + s1);
+                sh.zs[tid] = z;
+                sh.xc[tid] = c0 - tauRk * z;
+            }
+            __syncthreads();
+            // ---- right update: rows > k, columns > k
+            {
+                double zr[NPR];
+#pragma unroll
+                for (int a = KA; a < NPR; ++a)  // zs is zero beyond N
+                    zr[a] = (tr > k - 32 * a) ? tauRk * sh.zs[tr + 32 * a] : 0.0;
+#pragma unroll
+                for (int c = KC; c < NPC; ++c) {
+                    const double vj =
+                        (tc == k + 1 - 16 * c) ? 1.0 : sh.sx[tc * 16 + c] * scaleR;
+#pragma unroll
+                    for (int a = KA; a < NPR; ++a) Br[a][c] -= zr[a] * vj;
+                }
+            }
+        }
+        gk_block<NPR, KC + 1>(sh, o, Br);
+    }
+}
+
+// One-workgroup bidiagonalisation for N <= 32 NPR (NPR <= 7): thread
+// (tr, tc) of the 32 x 16 grid owns rows tr + 32a (a < NPR) and columns
+// tc + 16c (c < 2 NPR), 7 x 14 doubles at N = 224.
 template <int NPR>
 __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __restrict__ B,
                                                         int ldb, double* __restrict__ dout,
@@ -87,9 +313,8 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
                                                         double* __restrict__ tauR)
 {
     constexpr int NPC = 2 * NPR;
-    __shared__ double part[16 * GK_LD];
-    __shared__ double sxc[GK_MAXN], sxr[GK_MAXN], sz[GK_MAXN];
-    const int tid = threadIdx.x, lane = tid & 63;
+    __shared__ GkShared sh;
+    const int tid = threadIdx.x;
     const int tr = tid & 31, tc = tid >> 5;
 
     double Br[NPR][NPC];
@@ -100,155 +325,13 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
             const int i = tr + 32 * a, j = tc + 16 * c;
             Br[a][c] = (i < N && j < N) ? B[(size_t)i * ldb + j] : 0.0;
         }
-
-    for (int k = 0; k < N; ++k) {
-        // ---- left reflector: column k, rows k..N-1
-        if (tc == (k & 15)) {
-            const int kc = k >> 4;
-#pragma unroll
-            for (int a = 0; a < NPR; ++a) {
-                const int i = tr + 32 * a;
-                double v = 0.0;
-#pragma unroll
-                for (int c = 0; c < NPC; ++c)
-                    if (c == kc) v = Br[a][c];
-                if (i >= k && i < N) sxc[i] = v;
-            }
-        }
-        __syncthreads();
-        {
-            const double alpha = sxc[k];
-            double s2 = 0.0;
-            for (int i = k + 1 + lane; i < N; i += 64) s2 += sxc[i] * sxc[i];
-            s2 = wave_sum64(s2);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (s2 > 0.0) {
-                const double nrm = sqrt(alpha * alpha + s2);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            if (tid < 64) {
-                for (int i = k + 1 + lane; i < N; i += 64) VL[(size_t)k * N + i] = sxc[i] * scale;
-                if (lane == 0) {
-                    VL[(size_t)k * N + k] = 1.0;
-                    tauL[k] = tau;
-                    dout[k] = beta;
-                }
-            }
-            if (tau != 0.0) {
-                double va[NPR];
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) {
-                    const int i = tr + 32 * a;
-                    va[a] = (i > k && i < N) ? sxc[i] * scale : (i == k ? 1.0 : 0.0);
-                }
-#pragma unroll
-                for (int c = 0; c < NPC; ++c) {
-                    if (16 * c + 15 <= k) continue;  // uniform: no column > k here
-                    double p = 0.0;
-#pragma unroll
-                    for (int a = 0; a < NPR; ++a) {
-                        if (32 * a + 31 < k) continue;  // uniform: no row >= k here
-                        p += va[a] * Br[a][c];
-                    }
-                    p = half_sum32(p);  // sum over the 32 row-lanes of this half-wavefront
-                    const int j = tc + 16 * c;
-                    const double wj = (j > k && j < N) ? tau * p : 0.0;
-#pragma unroll
-                    for (int a = 0; a < NPR; ++a) {
-                        if (32 * a + 31 < k) continue;
-                        Br[a][c] -= va[a] * wj;
-                    }
-                }
-            }
-        }
-        if (k + 1 >= N) break;
-        // ---- right reflector: row k, columns k+1..N-1
-        if (tr == (k & 31)) {
-            const int ka = k >> 5;
-#pragma unroll
-            for (int c = 0; c < NPC; ++c) {
-                const int j = tc + 16 * c;
-                double v = 0.0;
-#pragma unroll
-                for (int a = 0; a < NPR; ++a)
-                    if (a == ka) v = Br[a][c];
-                if (j > k && j < N) sxr[j] = v;
-            }
-        }
-        __syncthreads();
-        {
-            const double alpha = sxr[k + 1];
-            double s2 = 0.0;
-            for (int j = k + 2 + lane; j < N; j += 64) s2 += sxr[j] * sxr[j];
-            s2 = wave_sum64(s2);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (s2 > 0.0) {
-                const double nrm = sqrt(alpha * alpha + s2);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
-            if (tid < 64) {
-                for (int j = k + 2 + lane; j < N; j += 64) VR[(size_t)k * N + j] = sxr[j] * scale;
-                if (lane == 0) {
-                    VR[(size_t)k * N + k + 1] = 1.0;
-                    tauR[k] = tau;
-                    eout[k] = beta;
-                }
-            }
-            if (tau != 0.0) {
-                // z_i = tau sum_{j > k} B[i][j] v_j, i > k
-                double acc[NPR];
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) acc[a] = 0.0;
-#pragma unroll
-                for (int c = 0; c < NPC; ++c) {
-                    if (16 * c + 15 <= k) continue;
-                    const int j = tc + 16 * c;
-                    const double vj =
-                        (j > k + 1 && j < N) ? sxr[j] * scale : (j == k + 1 ? 1.0 : 0.0);
-#pragma unroll
-                    for (int a = 0; a < NPR; ++a) {
-                        if (32 * a + 31 <= k) continue;
-                        acc[a] += Br[a][c] * vj;
-                    }
-                }
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) {
-                    if (32 * a + 31 <= k) continue;
-                    const int i = tr + 32 * a;
-                    if (i < N) part[tc * GK_LD + i] = acc[a];
-                }
-                __syncthreads();
-                if (tid < N && tid > k) {
-                    double sum = 0.0;
-#pragma unroll
-                    for (int t = 0; t < 16; ++t) sum += part[t * GK_LD + tid];
-                    sz[tid] = tau * sum;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int a = 0; a < NPR; ++a) {
-                    const int i = tr + 32 * a;
-                    acc[a] = (32 * a + 31 > k && i > k && i < N) ? sz[i] : 0.0;
-                }
-#pragma unroll
-                for (int c = 0; c < NPC; ++c) {
-                    if (16 * c + 15 <= k) continue;
-                    const int j = tc + 16 * c;
-                    const double vj =
-                        (j > k + 1 && j < N) ? sxr[j] * scale : (j == k + 1 ? 1.0 : 0.0);
-#pragma unroll
-                    for (int a = 0; a < NPR; ++a) {
-                        if (32 * a + 31 <= k) continue;
-                        Br[a][c] -= acc[a] * vj;
-                    }
-                }
-            }
-        }
+    if (tid < GK_MAXN) {  // beyond N these stay zero
+        sh.xc[tid] = tid < N ? B[(size_t)tid * ldb] : 0.0;
+        sh.zs[tid] = 0.0;
     }
+    __syncthreads();
+    const GkOut o{N, dout, eout, VL, tauL, VR, tauR};
+    gk_block<NPR, 0>(sh, o, Br);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,9 +415,24 @@ __device__ __forceinline__ void transpose_level(double (&v)[32], bool hi)
     }
 }
 
+// Level 16 by v_permlane16_swap on (v[j], v[j + 16]): the even row of each
+// pair ends with (own v[j], partner's v[j]), the odd row with (partner's
+// v[j + 16], own v[j + 16]).
+__device__ __forceinline__ void transpose_level16(double (&v)[32])
+{
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        const unsigned long long a = __double_as_longlong(v[j]), b = __double_as_longlong(v[j + 16]);
+        const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)a, (unsigned)b, false, false);
+        const auto hi =
+            __builtin_amdgcn_permlane16_swap((unsigned)(a >> 32), (unsigned)(b >> 32), false, false);
+        v[j] = join_words(lo[0], hi[0]) + join_words(lo[1], hi[1]);
+    }
+}
+
 __device__ __forceinline__ void transpose_sum32(double (&v)[32], int c)
 {
-    transpose_level<16>(v, (c & 16) != 0);
+    transpose_level16(v);
     transpose_level<8>(v, (c & 8) != 0);
     transpose_level<4>(v, (c & 4) != 0);
     transpose_level<2>(v, (c & 2) != 0);
