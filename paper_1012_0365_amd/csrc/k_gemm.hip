@@ -11,6 +11,8 @@
 // converted to the compute type on the way in. Long K is split across
 // workgroups (split-K); the partial sums are reduced in a fixed order by a
 // second kernel, so results do not depend on scheduling.
+#include <algorithm>
+
 #include "blws_common.h"
 
 namespace blws {
@@ -112,8 +114,17 @@ __global__ void splitk_reduce_kernel(int M, int N, int S, double alpha, const do
     const size_t total = (size_t)M * N;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
+        // eight loads in flight, the additions still in chunk order
         double acc = 0.0;
-        for (int s = 0; s < S; ++s) acc += partial[(size_t)s * total + e];
+        int s = 0;
+        for (; s + 8 <= S; s += 8) {
+            double v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(s + u) * total + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; s < S; ++s) acc += partial[(size_t)s * total + e];
         const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
         double out = alpha * acc;
         if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
@@ -176,12 +187,225 @@ void launch_nt(const Plan& p, int M, int N, int K, double alpha, const TA* A, in
 #undef BLWS_GEMM_CASE
 }
 
+
+// ---------------------------------------------------------------------------
+// Tall-skinny shapes. The generic kernel above gives a 64-row strip to each
+// workgroup and runs its K range in LDS stages: for the orthonormalisation
+// products (M ~ 2000, N ~ 112) that is ~32 workgroups on a 256-CU chip. Two
+// dedicated forms instead:
+//  - NN with K <= SK_MAXK: one workgroup per 16-row strip of C; the strip of
+//    A is staged once in LDS (transposed, so fragment reads are unit-stride),
+//    B fragments are read straight from L2 (every workgroup reads all of B),
+//    the four wavefronts take interleaved 16-column tiles;
+//  - TN with M, N <= TN_MAXMN and long K: a workgroup owns a 64 x 64 block of
+//    C and one K chunk (LDS stages of 32 rows); the chunks' partial blocks are
+//    summed in chunk order by the split-K reduction, so results do not depend
+//    on scheduling.
+// ---------------------------------------------------------------------------
+constexpr int SK_MAXK = 512;
+constexpr int TN_MAXMN = 512;
+constexpr int TN_BK = 32;
+
+template <typename TA, typename TB, typename TC, int NTW>
+__global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, double alpha,
+                                                         const TA* __restrict__ A, int lda,
+                                                         const TB* __restrict__ B, int ldb,
+                                                         double beta, const TC* Cin, int ldcin,
+                                                         TC* C, int ldc)
+{
+    __shared__ double AsT[SK_MAXK][16];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = blockIdx.x * 16;
+    const int K4 = (K + 3) & ~3;
+    for (int row = wave; row < 16; row += 4) {
+        const int gr = r0 + row;
+        for (int k = lane; k < K4; k += 64)
+            AsT[k][row] = (gr < M && k < K) ? ld_d(A + (size_t)gr * lda + k) : 0.0;
+    }
+    __syncthreads();
+    const int kq = lane >> 4, cl = lane & 15;
+    d4 acc[NTW];
+    int col[NTW];
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        col[t] = 16 * (wave + 4 * t) + cl;
+    }
+    // B fragments by groups of PF k-steps, the next group's loads in flight
+    // while the current one feeds the matrix cores
+    constexpr int PF = NTW >= 8 ? 2 : (NTW >= 4 ? 4 : (NTW >= 2 ? 8 : 16));
+    const int nst = K4 / 4, ng = (nst + PF - 1) / PF;
+    double b0[PF][NTW], b1[PF][NTW];
+    auto load = [&](int g, double (&bq)[PF][NTW]) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int k = 4 * (g * PF + u) + kq;
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+                bq[u][t] = (k < K && col[t] < N) ? ld_d(B + (size_t)k * ldb + col[t]) : 0.0;
+        }
+    };
+    auto compute = [&](int g, const double (&bq)[PF][NTW]) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            if (g * PF + u >= nst) break;  // uniform
+            const double a = AsT[4 * (g * PF + u) + kq][cl];
+#pragma unroll
+            for (int t = 0; t < NTW; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[u][t], acc[t], 0, 0, 0);
+        }
+    };
+    load(0, b0);
+    for (int g = 0; g < ng; g += 2) {
+        if (g + 1 < ng) load(g + 1, b1);
+        compute(g, b0);
+        if (g + 1 >= ng) break;
+        if (g + 2 < ng) load(g + 2, b0);
+        compute(g + 1, b1);
+    }
+#pragma unroll
+    for (int t = 0; t < NTW; ++t) {
+        if (col[t] >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int row = r0 + kq + 4 * i;
+            if (row >= M) continue;
+            double out = alpha * acc[t][i];
+            if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col[t]];
+            C[(size_t)row * ldc + col[t]] = (TC)out;
+        }
+    }
+}
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void gemm_tn_lk_kernel(int M, int N, int K, int kchunk,
+                                                         const TA* __restrict__ A, int lda,
+                                                         const TB* __restrict__ B, int ldb,
+                                                         double* __restrict__ partial)
+{
+    __shared__ double As[TN_BK][64 + 4];
+    __shared__ double Bs[TN_BK][64 + 4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
+    const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+    const int kq = lane >> 4, cl = lane & 15;
+    d4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+    // 4 rows of 64 per pass of the 256 threads, coalesced along M / N; the
+    // next stage is loaded into registers while the current one is used
+    constexpr int NU = TN_BK / 4;
+    double ra[NU], rb[NU];
+    const int gm = m0 + lane, gn = n0 + lane;
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int gk = k0 + 4 * u + wave;
+            ra[u] = (gk < ke && gm < M) ? ld_d(A + (size_t)gk * lda + gm) : 0.0;
+            rb[u] = (gk < ke && gn < N) ? ld_d(B + (size_t)gk * ldb + gn) : 0.0;
+        }
+    };
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += TN_BK) {
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            As[4 * u + wave][lane] = ra[u];
+            Bs[4 * u + wave][lane] = rb[u];
+        }
+        __syncthreads();
+        if (k0 + TN_BK < ke) fetch(k0 + TN_BK);
+#pragma unroll
+        for (int kk = 0; kk < TN_BK / 4; ++kk) {
+            const double a = As[4 * kk + kq][16 * wave + cl];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const double bv = Bs[4 * kk + kq][16 * t + cl];
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[t], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    double* pz = partial + (size_t)blockIdx.z * M * N;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = n0 + 16 * t + cl;
+        if (c >= N) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = m0 + 16 * wave + kq + 4 * i;
+            if (r < M) pz[(size_t)r * N + c] = acc[t][i];
+        }
+    }
+}
+
+struct TnPlan {
+    int gx, gy, splits, kchunk;
+};
+
+// about 256 workgroups, chunks of at least one LDS stage, partials below
+// min(4M, cap) doubles
+TnPlan make_tn_plan(int M, int N, int K, size_t cap = (size_t)4 << 20)
+{
+    TnPlan p;
+    p.gx = (M + 63) / 64;
+    p.gy = (N + 63) / 64;
+    const long blocks = (long)p.gx * p.gy;
+    long s = (256 + blocks - 1) / blocks;
+    const long smax_k = (K + TN_BK - 1) / TN_BK;
+    if (s > smax_k) s = smax_k;
+    const long smax_mem = (long)(std::min(cap, (size_t)4 << 20) / ((size_t)M * N));
+    if (s > smax_mem) s = smax_mem;
+    if (s < 1) s = 1;
+    int kchunk = (int)((K + s - 1) / s);
+    kchunk = ((kchunk + TN_BK - 1) / TN_BK) * TN_BK;
+    p.kchunk = kchunk;
+    p.splits = (K + kchunk - 1) / kchunk;  // <= s
+    return p;
+}
+
+bool use_nn_sk(bool trans_a, int N, int K) { return !trans_a && K <= SK_MAXK && N <= 512; }
+bool use_tn_lk(bool trans_a, int M, int N, int K)
+{
+    return trans_a && M <= TN_MAXMN && N <= TN_MAXMN && K >= 4 * TN_BK;
+}
+
+template <typename TA, typename TB, typename TC>
+void launch_nn_sk(int M, int N, int K, double alpha, const TA* A, int lda, const TB* B, int ldb,
+                  double beta, const TC* Cin, int ldcin, TC* C, int ldc, hipStream_t s)
+{
+    const int ntw = ((N + 15) / 16 + 3) / 4;
+    dim3 grid((M + 15) / 16), block(256);
+#define BLWS_NNSK_CASE(V)                                                                       \
+    case V:                                                                                     \
+        hipLaunchKernelGGL((gemm_nn_sk_kernel<TA, TB, TC, V>), grid, block, 0, s, M, N, K, alpha, \
+                           A, lda, B, ldb, beta, Cin, ldcin, C, ldc);                           \
+        break;
+    switch (ntw) {
+        BLWS_NNSK_CASE(1)
+        BLWS_NNSK_CASE(2)
+        BLWS_NNSK_CASE(3)
+        BLWS_NNSK_CASE(4)
+        BLWS_NNSK_CASE(5)
+        BLWS_NNSK_CASE(6)
+        BLWS_NNSK_CASE(7)
+        default:
+            BLWS_NNSK_CASE(8)
+    }
+#undef BLWS_NNSK_CASE
+}
+
 }  // namespace
 
 size_t gemm_partial_elems(int M, int N, int K)
 {
     Plan p = make_plan(M, N, K);
-    return p.splits > 1 ? (size_t)p.splits * M * N : 0;
+    size_t e = p.splits > 1 ? (size_t)p.splits * M * N : 0;
+    if (use_tn_lk(true, M, N, K)) {
+        const TnPlan q = make_tn_plan(M, N, K);
+        const size_t et = (size_t)q.splits * M * N;
+        if (et > e) e = et;
+    }
+    return e;
 }
 
 template <typename TA, typename TB, typename TC>
@@ -194,6 +418,25 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
         // C = beta * Cin: a split-K reduce over zero partials
         hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(256), dim3(256), 0, s, M, N, 0, 0.0,
                            (const double*)nullptr, beta, Cin, ldcin, C, ldc);
+        return;
+    }
+    if (use_nn_sk(trans_a, N, K)) {
+        TimedLaunch tl(tm, family, s, 2.0 * M * N * (double)K,
+                       8.0 * ((double)M * K + (double)K * N + (double)M * N));
+        launch_nn_sk<TA, TB, TC>(M, N, K, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc, s);
+        return;
+    }
+    if (use_tn_lk(trans_a, M, N, K) && partial && partial_elems >= (size_t)M * N) {
+        const TnPlan q = make_tn_plan(M, N, K, partial_elems);
+        TimedLaunch tl(tm, family, s, 2.0 * M * N * (double)K,
+                       8.0 * ((double)M * K + (double)K * N + (double)M * N));
+        hipLaunchKernelGGL((gemm_tn_lk_kernel<TA, TB>), dim3(q.gx, q.gy, q.splits), dim3(256), 0,
+                           s, M, N, K, q.kchunk, A, lda, B, ldb, partial);
+        const size_t total = (size_t)M * N;
+        int blocks = (int)((total + 255) / 256);
+        if (blocks > 2048) blocks = 2048;
+        hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(blocks), dim3(256), 0, s, M, N,
+                           q.splits, alpha, partial, beta, Cin, ldcin, C, ldc);
         return;
     }
     Plan p = make_plan(M, N, K);

@@ -44,7 +44,11 @@ def test_counter_generator_is_bit_exact(torch, ctx):
 
 @pytest.mark.parametrize("trans", [False, True])
 @pytest.mark.parametrize("M,N,K", [(1, 1, 1), (64, 16, 32), (130, 112, 2000), (2000, 112, 2000),
-                                   (17, 200, 45), (224, 224, 1999), (5, 3, 70000)])
+                                   (17, 200, 45), (224, 224, 1999), (5, 3, 70000),
+                                   # tall-skinny forms: NN with K <= 512, TN with M, N <= 512
+                                   (2000, 112, 112), (1999, 511, 512), (33, 300, 3),
+                                   (5000, 256, 224), (112, 112, 2000), (448, 448, 2001),
+                                   (512, 512, 4096), (100, 37, 130)])
 def test_gemm_matches_numpy(torch, ctx, trans, M, N, K):
     g = np.random.default_rng(M * 7 + N * 3 + K)
     A = g.standard_normal((K, M) if trans else (M, K))
@@ -58,12 +62,14 @@ def test_gemm_matches_numpy(torch, ctx, trans, M, N, K):
     assert np.abs(host(C) - ref).max() <= 1e-14 * scale
 
 
-def test_gemm_is_deterministic(torch, ctx):
+@pytest.mark.parametrize("M", [700, 224])
+def test_gemm_is_deterministic(torch, ctx, M):
+    # split-K sums are reduced in chunk order: the same bits on every call
     g = np.random.default_rng(1)
-    A, B = dev(torch, g.standard_normal((3000, 700))), dev(torch, g.standard_normal((3000, 96)))
+    A, B = dev(torch, g.standard_normal((3000, M))), dev(torch, g.standard_normal((3000, 96)))
     outs = []
     for _ in range(3):
-        C = torch.zeros(700, 96, dtype=torch.float64, device="cuda")
+        C = torch.zeros(M, 96, dtype=torch.float64, device="cuda")
         ctx.gemm_f64(A, B, C, trans_a=True)
         outs.append(host(C))
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2])
