@@ -90,6 +90,7 @@ int blws_destroy(blws_ctx ctx)
     (void)hipSetDevice(ctx->cx.device);
     (void)hipDeviceSynchronize();
     ctx->cx.timer.clear();
+    ctx->cx.release_aux();
     if (ctx->cx.ws) (void)hipFree(ctx->cx.ws);
     if (ctx->cx.host_pinned) (void)hipHostFree(ctx->cx.host_pinned);
     delete ctx;

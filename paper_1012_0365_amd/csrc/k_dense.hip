@@ -91,13 +91,82 @@ __global__ __launch_bounds__(1024) void chol_inv_kernel(int n, const double* __r
     if (cnt) atomicAdd(nflag, cnt);
 }
 
+// 1 / p from the hardware estimate and two Newton steps, e <- 1 - p r,
+// r <- r + r e (each squares the relative error); the same instruction
+// sequence in every thread, so all of them hold the same bits.
+__device__ __forceinline__ double recip_nr(double p)
+{
+    double r = __builtin_amdgcn_rcp(p);
+    double e = fma(-p, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-p, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Steps j of row group JB (32 JB <= j < 32 JB + 32) of the register
+// elimination below. The trailing matrix is kept in both triangles, so every
+// element takes the same update S[i][c] -= l_i row_j[c] (l_i = 0 for rows
+// i <= j): the upper copies are the Schur complement that later pivots are
+// taken from, the lower copies of columns c < j hold L^{-1} (column c is
+// overwritten with -l_i when it is eliminated), and the lower copies of
+// columns c > j are never read. Row groups above JB are finished and skipped
+// at compile time.
+template <int JB>
+__device__ __forceinline__ void chol_inv_steps(int n, double (&S)[4][4], double* rowbuf, double* piv,
+                                               int* flg, double eta)
+{
+    if constexpr (JB < 4) {
+        const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
+        const int jend = min(32 * JB + 32, n);
+        for (int j = 32 * JB; j < jend; ++j) {
+            double* row = rowbuf + 128 * (j & 1);
+            // the owners of row j (row group JB) publish it
+            if (tr == (j & 31)) {
+#pragma unroll
+                for (int b = 0; b < 4; ++b) row[tc + 32 * b] = S[JB][b];
+            }
+            __syncthreads();
+            const double p = row[j];
+            const bool dep = !(p > eta);
+            if (tid == 0) {
+                piv[j] = p;
+                flg[j] = dep ? 1 : 0;
+            }
+            if (!dep) {
+                const double inv = recip_nr(p);
+                double rc[4];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) rc[b] = row[tc + 32 * b];
+                const bool jcol = tc == (j & 31);  // column j is tc + 32 JB
+#pragma unroll
+                for (int a = JB; a < 4; ++a) {
+                    const int i = tr + 32 * a;
+                    const double l = (i > j) ? row[i] * inv : 0.0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b) {
+                        const double v = fma(-l, rc[b], S[a][b]);
+                        if (b == JB)
+                            S[a][b] = (jcol && i > j) ? -l : v;
+                        else
+                            S[a][b] = v;
+                    }
+                }
+            }
+        }
+        chol_inv_steps<JB + 1>(n, S, rowbuf, piv, flg, eta);
+    }
+}
+
 // The same elimination with the matrix in registers (n <= 128): thread
 // (tr, tc) of a 32 x 32 grid holds S[tr + 32a][tc + 32b], a, b < 4. Each step
-// broadcasts the pivot row through LDS; two barriers per step. G and Rinv
-// (leading dimension ld) may be global or LDS; Rinv may alias G (G is read
-// once into registers before Rinv is written). All 1024 threads call it.
+// broadcasts the pivot row through LDS, alternating between the two halves of
+// `rowbuf` (2 x 128 doubles): the barrier after step j + 1's broadcast also
+// orders every read of step j before step j + 2 overwrites that half, so one
+// barrier per step. G (full, symmetric) and Rinv (leading dimension ld) may be
+// global or LDS; Rinv may alias G (G is read once into registers before Rinv
+// is written). All 1024 threads call it.
 __device__ __forceinline__ void chol_inv_regs(int n, const double* G, int ldg, double* Rinv, int ldr, double eta,
-                              double* scal, double* row, double* piv, int* flg)
+                              double* scal, double* rowbuf, double* piv, int* flg)
 {
     const int tid = threadIdx.x, tr = tid >> 5, tc = tid & 31;
     for (int i = tid; i < n; i += 1024) {
@@ -112,64 +181,26 @@ __device__ __forceinline__ void chol_inv_regs(int n, const double* G, int ldg, d
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int i = tr + 32 * a, c = tc + 32 * b;
-            S[a][b] = (i < n && c < n && c >= i) ? G[(size_t)i * ldg + c] * scal[i] * scal[c] : 0.0;
+            S[a][b] = (i < n && c < n) ? G[(size_t)i * ldg + c] * scal[i] * scal[c] : 0.0;
         }
     __syncthreads();  // G fully read before Rinv (which may alias it) is written
-    for (int j = 0; j < n; ++j) {
-        // the owners of row j publish it (upper part: the trailing matrix;
-        // lower part: the row of L^{-1} built so far)
-        if (tr == (j & 31)) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-                if (a == (j >> 5))
-#pragma unroll
-                    for (int b = 0; b < 4; ++b) {
-                        const int c = tc + 32 * b;
-                        if (c < n) row[c] = S[a][b];
-                    }
-        }
-        __syncthreads();
-        const double p = row[j];
-        const bool dep = !(p > eta);
-        if (tid == 0) {
-            piv[j] = p;
-            flg[j] = dep ? 1 : 0;
-        }
-        if (!dep) {
-            const double inv = 1.0 / p;
-#pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const int i = tr + 32 * a;
-                if (i <= j || i >= n) continue;
-                const double l = row[i] * inv;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int c = tc + 32 * b;
-                    if (c >= n) continue;
-                    if (c >= i || c < j)
-                        S[a][b] -= l * row[c];
-                    else if (c == j)
-                        S[a][b] = -l;
-                }
-            }
-        }
-        __syncthreads();
-    }
+    chol_inv_steps<0>(n, S, rowbuf, piv, flg, eta);
+    __syncthreads();
     // R^{-1}[r][c] = s_r (L^{-1})[c][r] / sqrt(d_c), r <= c; thread (i, col)
     // holds (L^{-1})[i][col] for col < i and writes element (col, i).
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 4; ++a) {
+        const int i = tr + 32 * a;
+        if (i >= n) continue;
+        const double rs = flg[i] ? 0.0 : 1.0 / sqrt(piv[i]);  // one root per row
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = tr + 32 * a, c = tc + 32 * b;
-            if (i >= n || c >= n) continue;
-            double v = 0.0;
-            if (c <= i && !flg[i]) {
-                const double lic = (c == i) ? 1.0 : S[a][b];
-                v = scal[c] * lic / sqrt(piv[i]);
-            }
-            Rinv[(size_t)c * ldr + i] = v;
+            const int c = tc + 32 * b;
+            if (c >= n) continue;
+            const double lic = (c == i) ? 1.0 : S[a][b];
+            Rinv[(size_t)c * ldr + i] = (c <= i) ? scal[c] * lic * rs : 0.0;
         }
+    }
     __syncthreads();
 }
 
@@ -178,7 +209,7 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
                                                             int* flags, int* nflag, double eta)
 {
     __shared__ double scal[128];
-    __shared__ double row[128];
+    __shared__ double row[2 * 128];
     __shared__ double piv[128];
     __shared__ int flg[128];
     chol_inv_regs(n, G, ldg, Rinv, n, eta, scal, row, piv, flg);
@@ -204,7 +235,7 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
                                                              uint64_t sid1)
 {
     __shared__ double G[128 * CQ_LD];
-    __shared__ double scal[128], row[128], piv[128];
+    __shared__ double scal[128], row[2 * 128], piv[128];
     __shared__ int flg[128];
     double* X = blockIdx.x == 0 ? X0 : X1;
     const uint64_t sid = blockIdx.x == 0 ? sid0 : sid1;

@@ -283,6 +283,7 @@ int blws_server_destroy(blws_server srv)
         (void)hipEventDestroy(sl->ev);
         (void)hipStreamDestroy(sl->stream);
         sl->cx.timer.clear();
+        sl->cx.release_aux();
         if (sl->cx.ws) (void)hipFree(sl->cx.ws);
         if (sl->cx.host_pinned) (void)hipHostFree(sl->cx.host_pinned);
     }

@@ -71,6 +71,39 @@ struct Context {
     std::string last_error;
     Timer timer;
     uint64_t fix_calls = 0;  // stream ids for breakdown replacement draws
+    // second stream for independent halves of a step (default priority),
+    // forked from and joined back into the caller's stream by events
+    hipStream_t aux = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+    void ensure_aux()
+    {
+        if (aux) return;
+        HIP_TRY(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
+        HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+        HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+    }
+    void release_aux()
+    {
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (aux) (void)hipStreamDestroy(aux);
+        aux = nullptr;
+        ev_fork = ev_join = nullptr;
+    }
+    // cx.aux waits for the work queued so far on s
+    void fork(hipStream_t s)
+    {
+        ensure_aux();
+        HIP_TRY(hipEventRecord(ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(aux, ev_fork, 0));
+    }
+    // s waits for the work queued so far on cx.aux
+    void join(hipStream_t s)
+    {
+        HIP_TRY(hipEventRecord(ev_join, aux));
+        HIP_TRY(hipStreamWaitEvent(s, ev_join, 0));
+    }
 
     void ensure(size_t bytes)
     {
@@ -98,6 +131,11 @@ struct StepWs {
     double *Cp, *Gr, *Ri, *Bm, *UB, *VB, *Sall, *svd, *chol, *partial, *D1, *D2;
     int *flags, *nflag;
     size_t partial_elems;
+    // the same orthonormalisation scratch and split-K partials again, for work
+    // on the second stream (the breakdown counter nflag is shared: atomic)
+    T *T1b, *T2b;
+    double *Cpb, *Grb, *Rib, *cholb, *partialb;
+    int* flagsb;
 
     void carve(Carver& c, int m, int n, int b)
     {
@@ -138,6 +176,30 @@ struct StepWs {
         }
         partial_elems = pe;
         partial = c.take<double>(pe + 1);
+        T1b = c.take<T>((size_t)mx * b);
+        T2b = c.take<T>((size_t)mx * b);
+        Cpb = c.take<double>((size_t)b * b);
+        Grb = c.take<double>((size_t)b * b);
+        Rib = c.take<double>((size_t)b * b);
+        cholb = c.take<double>(chol_scratch_elems(b) + 1);
+        flagsb = c.take<int>((size_t)b);
+        partialb = c.take<double>(pe + 1);
+    }
+
+    // this scratch with the second set in place of the first (for the
+    // second stream)
+    StepWs aux_view() const
+    {
+        StepWs v = *this;
+        v.T1 = T1b;
+        v.T2 = T2b;
+        v.Cp = Cpb;
+        v.Gr = Grb;
+        v.Ri = Rib;
+        v.chol = cholb;
+        v.flags = flagsb;
+        v.partial = partialb;
+        return v;
     }
 };
 
@@ -355,12 +417,20 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     const int b2 = 2 * b;
     copy2d<T, T>(m, b, U, ldu, w.UF, b2, s);
     copy2d<T, T>(n, b, V, ldv, w.VG, b2, s);
-    // products with the start block: P = W V, Q = W^T U
+    // The left (U, P, F) and right (V, Q, G) halves until H are independent:
+    // the right half runs on the second stream with its own scratch.
+    StepWs<T> wb = w.aux_view();
+    cx.fork(s);
+    // products with the start block: P = W V, Q = W^T U (the low-rank
+    // coefficients of the matrix-completion operator have one buffer: there
+    // Q waits for P)
     op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
-    op_apply<T>(cx, w, s, W, m, n, true, U, ldu, b, w.Qb, b);
+    if (!W.W) cx.fork(s);
+    op_apply<T>(cx, wb, cx.aux, W, m, n, true, U, ldu, b, w.Qb, b);
     // new block: F = orth(P - U U^T P), G = orth(Q - V V^T Q)
     orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
-    orth_against<T>(cx, w, s, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
+    orth_against<T>(cx, wb, cx.aux, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
+    cx.join(s);
     // the last product of the pass: H = W G
     op_apply<T>(cx, w, s, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
     // B = [U, F]^T [P, H] in FP64
@@ -371,11 +441,13 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
                                 w.partial_elems, w.flags, w.nflag};
         small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, w.svd, ow, seed);
     }
-    // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b)
+    // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b), on the two streams
+    cx.fork(s);
     gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
                        (const T*)nullptr, 0, U, ldu, w.partial, w.partial_elems, s);
     gemm<T, double, T>(tm, "gemm_ts", false, n, b, b2, 1.0, w.VG, b2, w.VB, b2, 0.0,
-                       (const T*)nullptr, 0, V, ldv, w.partial, w.partial_elems, s);
+                       (const T*)nullptr, 0, V, ldv, wb.partial, wb.partial_elems, cx.aux);
+    cx.join(s);
     copy2d<double, double>(1, b, w.Sall, b2, S, b, s);
     if (rank_dev) count_above(b, S, eps, rank_dev, s);
 }
