@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64")
     ap.add_argument("--workload", choices=["rpca", "serving"], default="rpca")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
+    ap.add_argument("--slots", type=int, default=8, help="serving: solves in flight")
+    ap.add_argument("--no-group", action="store_true",
+                    help="serving: one launch per W-product instead of grouped launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-plain", action="store_true", help="skip the full-SVD comparator")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
@@ -291,7 +294,7 @@ def bench_serving(args):
                          torch.tensor(inst["values"], dtype=torch.float32, device="cuda")))
     torch.cuda.synchronize()
     mc_opts = blws.default_mc_opts()
-    srv = blws.Server(0, max_slots=8)
+    srv = blws.Server(0, max_slots=args.slots, group_products=not args.no_group)
     # warm-up: one request of each kind
     for item in data[:2]:
         t = (srv.submit_rpca(item[3]) if item[0] == "rpca"
@@ -325,6 +328,19 @@ def bench_serving(args):
     total = time.perf_counter() - t_start
     st = srv.stats()
     srv.close()
+    seq = None
+    if not args.no_plain:
+        # the same requests one at a time, blocking FP64 solves (no server)
+        ctx = blws.Context(0)
+        t0 = time.perf_counter()
+        for item in data:
+            if item[0] == "rpca":
+                ctx.rpca_solve(item[3].double())
+            else:
+                ctx.mc_solve(item[1], item[2], item[3], item[4], item[5].double(), opts=mc_opts)
+        torch.cuda.synchronize()
+        seq = len(data) / (time.perf_counter() - t0)
+        ctx.close()
     return {
         "metric": "serving mix: solves/s with p50/p99 latency",
         "value": len(lat) / total,
@@ -340,7 +356,9 @@ def bench_serving(args):
         "data": "synthetic",
         "config": {"workload": "serving_mix_rpca70_mc30", "requests": len(reqs),
                    "m_range": [500, 3000], "arrivals": "poisson, mean gap 20 ms",
-                   "max_slots": 8},
+                   "max_slots": args.slots, "grouped_products": not args.no_group},
+        "sequential_fp64_solves_per_s": seq,
+        "speedup_vs_sequential_fp64": (len(lat) / total) / seq if seq else None,
         "latency_s_p50": pct(lat, 50),
         "latency_s_p99": pct(lat, 99),
         "svt_calls_per_s": iters / total,

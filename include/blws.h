@@ -222,13 +222,24 @@ int blws_timing_list(blws_ctx ctx, char* buf, size_t len);
  * buffers, stay valid and untouched until the request is reported done. Every
  * request is retrieved once, by blws_server_poll or blws_server_wait.
  * info->seconds is the latency from submit to completion.
+ *
+ * Grouped launches (group_products = 1): the solves whose last step has
+ * finished are advanced together, their host logic on one thread per slot;
+ * the dense W-products of their BLWS steps (W V, W^T U, then W G) are handed
+ * to one collector, which queues all of them as one grouped launch per
+ * precision (each problem with the block grid and K split it has alone, so a
+ * result is the same bits grouped or not) once every solve of the round has
+ * either handed over its products or finished its step. A solve that becomes
+ * ready waits up to group_window_us for the others in flight to be ready too.
  * ------------------------------------------------------------------------ */
 typedef struct blws_server_s* blws_server;
 
 typedef struct {
-    int max_slots;     /* solves in flight at once, 1..16 (4)                          */
-    size_t mem_budget; /* device bytes the in-flight solves' workspaces may hold;      */
-                       /* 0 selects 80% of the free device memory at creation (0)       */
+    int max_slots;       /* solves in flight at once, 1..16 (4)                        */
+    size_t mem_budget;   /* device bytes the in-flight solves' workspaces may hold;    */
+                         /* 0 selects 80% of the free device memory at creation (0)     */
+    int group_products;  /* 1: grouped W-product launches across solves (1)            */
+    int group_window_us; /* wait for other solves to become ready, 0..10000 us (200)   */
 } blws_server_opts;
 
 typedef struct {
@@ -237,6 +248,9 @@ typedef struct {
     int queued;        /* requests waiting for admission                               */
     int max_active;    /* most solves in flight at once so far                         */
     size_t mem_in_use, mem_peak, mem_budget;
+    long long grouped_launches; /* grouped W-product launches queued                   */
+    long long grouped_products; /* W-products that went through them                   */
+    int max_group;              /* most W-products in one grouped launch               */
 } blws_server_stats;
 
 void blws_default_server_opts(blws_server_opts* opts);

@@ -253,14 +253,20 @@ class Server:
     """Request server: RPCA and MC solves submitted at any time and run with
     continuous batching (up to max_slots in flight, each on its own stream,
     admitted by workspace footprint against mem_budget bytes; 0 = 80% of free
-    device memory). Results are those of Context.rpca_solve / mc_solve."""
+    device memory). With group_products the dense W-products of the solves
+    stepping together go out as grouped launches (a solve waits up to
+    group_window_us for others to be ready). Results are those of
+    Context.rpca_solve / mc_solve, bit for bit."""
 
-    def __init__(self, device: int = 0, max_slots: int = 4, mem_budget: int = 0):
+    def __init__(self, device: int = 0, max_slots: int = 4, mem_budget: int = 0,
+                 group_products: bool = True, group_window_us: int = 200):
         self._lib = _native.lib()
         o = ServerOpts()
         self._lib.blws_default_server_opts(ctypes.byref(o))
         o.max_slots = max_slots
         o.mem_budget = mem_budget
+        o.group_products = 1 if group_products else 0
+        o.group_window_us = group_window_us
         h = ctypes.c_void_p()
         st = self._lib.blws_server_create(ctypes.byref(h), device, ctypes.byref(o))
         if st < 0:

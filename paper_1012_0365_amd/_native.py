@@ -62,7 +62,8 @@ class SolveInfo(ctypes.Structure):
 
 
 class ServerOpts(ctypes.Structure):
-    _fields_ = [("max_slots", ctypes.c_int), ("mem_budget", ctypes.c_size_t)]
+    _fields_ = [("max_slots", ctypes.c_int), ("mem_budget", ctypes.c_size_t),
+                ("group_products", ctypes.c_int), ("group_window_us", ctypes.c_int)]
 
 
 class ServerStats(ctypes.Structure):
@@ -76,6 +77,9 @@ class ServerStats(ctypes.Structure):
         ("mem_in_use", ctypes.c_size_t),
         ("mem_peak", ctypes.c_size_t),
         ("mem_budget", ctypes.c_size_t),
+        ("grouped_launches", ctypes.c_longlong),
+        ("grouped_products", ctypes.c_longlong),
+        ("max_group", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:

@@ -60,6 +60,33 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
           TC* C, int ldc, double* partial, size_t partial_elems, hipStream_t s);
 size_t gemm_partial_elems(int M, int N, int K);
 
+// One W-product C = op(A) B (op(A) = A^T if trans) for a grouped launch:
+// prec 0 = FP64 (A, B, C double, partial doubles), 1 = FP32 (float), 2 = BF16
+// (A holds BF16 bits, B and C float, partial floats). partial is the
+// problem's own split-K scratch. A grouped launch computes every problem with
+// the block grid and K split it gets alone, so the results are the same bits.
+constexpr int GEMM_GROUP_MAX = 16;
+struct WProduct {
+    int prec;
+    bool trans;
+    int M, N, K;
+    const void* A;
+    int lda;
+    const void* B;
+    int ldb;
+    void* C;
+    int ldc;
+    void* partial;
+    size_t partial_elems;
+};
+// FP64: true if the problem takes the generic split-K kernel (the only one
+// with a grouped form); FP32 / BF16: always (with enough partial scratch).
+bool wproduct_groupable(const WProduct& w);
+bool wproduct_lp_groupable(const WProduct& w);
+// n <= GEMM_GROUP_MAX groupable problems of one precision, on stream s.
+void gemm_f64_grouped(const WProduct* ps, int n, hipStream_t s);
+void gemm_lp_grouped(const WProduct* ps, int n, hipStream_t s);
+
 // W-products in FP32 on FP32 MFMA (bf16 = false: A float) or BF16 MFMA
 // (bf16 = true: A holds BF16 bits, B is rounded to BF16), FP32 accumulation:
 // C (M x N, float) = op(A) B. `partial` holds gemm_lp_partial_elems floats.

@@ -21,24 +21,30 @@ namespace {
 constexpr int BM = 64;  // rows of C per workgroup (4 wavefronts x 16)
 constexpr int BK = 32;  // K per LDS stage (8 MFMA steps of 4)
 constexpr int NTHREADS = 256;
+constexpr int GROUP_MAX = GEMM_GROUP_MAX;  // problems per grouped launch
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
 __device__ __forceinline__ double ld_d(const T* p) { return (double)(*p); }
 
+// One 64 x 16 nt block (nt <= NT column tiles, nt uniform) of C, K range of
+// split bz: the body shared by the single-problem kernel and the grouped one.
+// As is BK x (BM + 1), Bs is BK x ldbs (ldbs >= 16 nt + 1) doubles of LDS.
+// An element's products are accumulated in the same order whatever nt is.
 template <typename TA, typename TB, typename TC, bool TRANS, int NT>
-__global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
-    int M, int N, int K, int kchunk, double alpha, const TA* __restrict__ A, int lda,
-    const TB* __restrict__ B, int ldb, double beta, const TC* Cin, int ldcin, TC* C, int ldc,
-    double* __restrict__ partial)
+__device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs, int bx, int by,
+                                               int bz, int nt, int M, int N, int K, int kchunk,
+                                               double alpha, const TA* __restrict__ A, int lda,
+                                               const TB* __restrict__ B, int ldb, double beta,
+                                               const TC* Cin, int ldcin, TC* C, int ldc,
+                                               double* __restrict__ partial)
 {
-    constexpr int BN = 16 * NT;
-    __shared__ double As[BK][BM + 1];
-    __shared__ double Bs[BK][BN + 1];
+    constexpr int LDA_S = BM + 1;
+    const int BN = 16 * nt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = blockIdx.x * BM, c0 = blockIdx.y * BN;
-    const int kb = blockIdx.z * kchunk;
+    const int r0 = bx * BM, c0 = by * BN;
+    const int kb = bz * kchunk;
     const int ke = min(K, kb + kchunk);
 
     d4 acc[NT];
@@ -53,7 +59,8 @@ __global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gk = k0 + kq + u;
-                As[kq + u][row] = (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
+                As[(kq + u) * LDA_S + row] =
+                    (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
             }
         } else {
             // op(A) = A^T, A is K x M: 8 threads read 64 consecutive columns of one row.
@@ -62,21 +69,23 @@ __global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gr = r0 + rq + u;
-                As[kr][rq + u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
+                As[kr * LDA_S + rq + u] =
+                    (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
             }
         }
         for (int e = tid; e < BK * BN; e += NTHREADS) {
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[kr][cc] = (gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
+            Bs[kr * ldbs + cc] = (gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
-            const double a = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+            const double a = As[(kk * 4 + (lane >> 4)) * LDA_S + wave * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const double bv = Bs[kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+                if (j >= nt) break;  // uniform
+                const double bv = Bs[(kk * 4 + (lane >> 4)) * ldbs + j * 16 + (lane & 15)];
                 acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[j], 0, 0, 0);
             }
         }
@@ -88,6 +97,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
     const int rbase = r0 + wave * 16 + (lane >> 4);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
+        if (j >= nt) break;
         const int col = c0 + j * 16 + (lane & 15);
         if (col >= N) continue;
 #pragma unroll
@@ -96,7 +106,7 @@ __global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
             if (row >= M) continue;
             const double v = acc[j][i];
             if (partial) {
-                partial[((size_t)blockIdx.z * M + row) * N + col] = v;
+                partial[((size_t)bz * M + row) * N + col] = v;
             } else {
                 double out = alpha * v;
                 if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
@@ -104,6 +114,75 @@ __global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
             }
         }
     }
+}
+
+template <typename TA, typename TB, typename TC, bool TRANS, int NT>
+__global__ __launch_bounds__(NTHREADS) void gemm_f64_kernel(
+    int M, int N, int K, int kchunk, double alpha, const TA* __restrict__ A, int lda,
+    const TB* __restrict__ B, int ldb, double beta, const TC* Cin, int ldcin, TC* C, int ldc,
+    double* __restrict__ partial)
+{
+    __shared__ double As[BK * (BM + 1)];
+    __shared__ double Bs[BK * (16 * NT + 1)];
+    gemm_f64_block<TA, TB, TC, TRANS, NT>(As, Bs, 16 * NT + 1, blockIdx.x, blockIdx.y, blockIdx.z,
+                                          NT, M, N, K, kchunk, alpha, A, lda, B, ldb, beta, Cin,
+                                          ldcin, C, ldc, partial);
+}
+
+// Grouped W-products (FP64): up to GROUP_MAX problems C_q = op_q(A_q) B_q in
+// one launch, each with the block grid and K split it has alone (so the same
+// results, bit for bit); block b belongs to problem q with
+// start[q] <= b < start[q + 1].
+struct GroupF64 {
+    int n;
+    int start[GROUP_MAX + 1];
+    struct Prob {
+        int M, N, K, kchunk, gx, gy, nt, trans, lda, ldb, ldc, splits;
+        const double *A, *B;
+        double *C, *partial;
+    } p[GROUP_MAX];
+};
+
+__device__ __forceinline__ int group_find(const int* start, int n, int blk)
+{
+    int q = 0;
+    while (q + 1 < n && blk >= start[q + 1]) ++q;
+    return q;
+}
+
+__global__ __launch_bounds__(NTHREADS) void gemm_f64_grouped_kernel(GroupF64 g)
+{
+    __shared__ double As[BK * (BM + 1)];
+    __shared__ double Bs[BK * (16 * 8 + 1)];
+    const int q = group_find(g.start, g.n, blockIdx.x);
+    const GroupF64::Prob& P = g.p[q];
+    const int l = blockIdx.x - g.start[q], per = P.gx * P.gy;
+    const int bz = l / per, rem = l - bz * per, by = rem / P.gx, bx = rem - by * P.gx;
+    double* part = P.splits > 1 ? P.partial : nullptr;
+    if (P.trans)
+        gemm_f64_block<double, double, double, true, 8>(As, Bs, 16 * 8 + 1, bx, by, bz, P.nt, P.M,
+                                                        P.N, P.K, P.kchunk, 1.0, P.A, P.lda, P.B,
+                                                        P.ldb, 0.0, nullptr, 0, P.C, P.ldc, part);
+    else
+        gemm_f64_block<double, double, double, false, 8>(As, Bs, 16 * 8 + 1, bx, by, bz, P.nt, P.M,
+                                                         P.N, P.K, P.kchunk, 1.0, P.A, P.lda, P.B,
+                                                         P.ldb, 0.0, nullptr, 0, P.C, P.ldc, part);
+}
+
+// sum_s partial[s][e], s = 0 .. S-1 in order (eight loads in flight)
+__device__ __forceinline__ double sum_splits(const double* partial, size_t total, size_t e, int S)
+{
+    double acc = 0.0;
+    int s = 0;
+    for (; s + 8 <= S; s += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(s + u) * total + e];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; s < S; ++s) acc += partial[(size_t)s * total + e];
+    return acc;
 }
 
 // C = alpha * sum_s partial[s] + beta * Cin, summed in split order.
@@ -114,21 +193,36 @@ __global__ void splitk_reduce_kernel(int M, int N, int S, double alpha, const do
     const size_t total = (size_t)M * N;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        // eight loads in flight, the additions still in chunk order
-        double acc = 0.0;
-        int s = 0;
-        for (; s + 8 <= S; s += 8) {
-            double v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = partial[(size_t)(s + u) * total + e];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) acc += v[u];
-        }
-        for (; s < S; ++s) acc += partial[(size_t)s * total + e];
+        const double acc = sum_splits(partial, total, e, S);
         const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
         double out = alpha * acc;
         if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
         C[(size_t)row * ldc + col] = (TC)out;
+    }
+}
+
+// The split-K sums of a grouped launch: problem q owns blocks start[q] ..
+// start[q + 1] - 1 (the same sums, in the same order, as alone).
+struct GroupRedF64 {
+    int n;
+    int start[GROUP_MAX + 1];
+    struct Prob {
+        int M, N, S, ldc;
+        const double* partial;
+        double* C;
+    } p[GROUP_MAX];
+};
+
+__global__ void splitk_reduce_grouped_kernel(GroupRedF64 g)
+{
+    const int q = group_find(g.start, g.n, blockIdx.x);
+    const GroupRedF64::Prob& P = g.p[q];
+    const int nb = g.start[q + 1] - g.start[q], lb = blockIdx.x - g.start[q];
+    const size_t total = (size_t)P.M * P.N;
+    for (size_t e = lb * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)nb * blockDim.x) {
+        const double acc = sum_splits(P.partial, total, e, P.S);
+        const int row = (int)(e / P.N), col = (int)(e - (size_t)row * P.N);
+        P.C[(size_t)row * P.ldc + col] = 1.0 * acc;
     }
 }
 
@@ -406,6 +500,66 @@ size_t gemm_partial_elems(int M, int N, int K)
         if (et > e) e = et;
     }
     return e;
+}
+
+bool wproduct_groupable(const WProduct& w)
+{
+    if (w.prec != 0 || w.M <= 0 || w.N <= 0 || w.K <= 0) return false;
+    if (use_nn_sk(w.trans, w.N, w.K)) return false;
+    if (use_tn_lk(w.trans, w.M, w.N, w.K) && w.partial && w.partial_elems >= (size_t)w.M * w.N)
+        return false;
+    const Plan p = make_plan(w.M, w.N, w.K);
+    return p.splits == 1 || (w.partial && w.partial_elems >= (size_t)p.splits * w.M * w.N);
+}
+
+void gemm_f64_grouped(const WProduct* ps, int n, hipStream_t s)
+{
+    BLWS_REQUIRE(n >= 1 && n <= GROUP_MAX, BLWS_EINVAL, "gemm_f64_grouped: bad problem count");
+    GroupF64 g{};
+    GroupRedF64 r{};
+    g.n = n;
+    int blocks = 0, rblocks = 0, nr = 0;
+    for (int q = 0; q < n; ++q) {
+        const WProduct& w = ps[q];
+        BLWS_REQUIRE(wproduct_groupable(w), BLWS_EINVAL, "gemm_f64_grouped: problem not groupable");
+        const Plan p = make_plan(w.M, w.N, w.K);
+        GroupF64::Prob& P = g.p[q];
+        P.M = w.M;
+        P.N = w.N;
+        P.K = w.K;
+        P.kchunk = p.kchunk;
+        P.gx = p.gx;
+        P.gy = p.gy;
+        P.nt = p.nt;
+        P.trans = w.trans ? 1 : 0;
+        P.lda = w.lda;
+        P.ldb = w.ldb;
+        P.ldc = w.ldc;
+        P.splits = p.splits;
+        P.A = (const double*)w.A;
+        P.B = (const double*)w.B;
+        P.C = (double*)w.C;
+        P.partial = (double*)w.partial;
+        g.start[q] = blocks;
+        blocks += p.gx * p.gy * p.splits;
+        if (p.splits > 1) {
+            const size_t total = (size_t)w.M * w.N;
+            int nb = (int)((total + 255) / 256);
+            if (nb > 2048) nb = 2048;
+            r.p[nr] = GroupRedF64::Prob{w.M, w.N, p.splits, w.ldc, (const double*)w.partial,
+                                        (double*)w.C};
+            r.start[nr] = rblocks;
+            rblocks += nb;
+            ++nr;
+        }
+    }
+    g.start[n] = blocks;
+    hipLaunchKernelGGL(gemm_f64_grouped_kernel, dim3(blocks), dim3(NTHREADS), 0, s, g);
+    if (nr > 0) {
+        r.n = nr;
+        r.start[nr] = rblocks;
+        hipLaunchKernelGGL(splitk_reduce_grouped_kernel, dim3(rblocks), dim3(256), 0, s, r);
+    }
 }
 
 template <typename TA, typename TB, typename TC>

@@ -40,20 +40,24 @@ __device__ __forceinline__ float to_f(T v);
 template <>
 __device__ __forceinline__ float to_f<float>(float v) { return v; }
 
-// FP32 mode: A, B float; LDS k-major; BK = 32 (8 MFMA steps of k = 4).
+// FP32 mode: A, B float; LDS k-major; BK = 32 (8 MFMA steps of k = 4). One
+// 64 x 16 nt block (nt <= NT, uniform) of C over the K range of split bz: the
+// body of the single-problem kernel and of the grouped one (As: 32 x 65,
+// Bs: 32 x ldbs floats of LDS). An element's products are accumulated in the
+// same order whatever nt is.
 template <bool TRANS, int NT>
-__global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K, int kchunk,
-                                                             const float* __restrict__ A, int lda,
-                                                             const float* __restrict__ B, int ldb,
-                                                             float* __restrict__ C, int ldc,
-                                                             float* __restrict__ partial)
+__device__ __forceinline__ void gemm_f32_block(float* As, float* Bs, int ldbs, int bx, int by,
+                                               int bz, int nt, int M, int N, int K, int kchunk,
+                                               const float* __restrict__ A, int lda,
+                                               const float* __restrict__ B, int ldb,
+                                               float* __restrict__ C, int ldc,
+                                               float* __restrict__ partial)
 {
-    constexpr int BK = 32, BN = 16 * NT;
-    __shared__ float As[BK][LBM + 1];
-    __shared__ float Bs[BK][BN + 1];
+    constexpr int BK = 32, LDA_S = LBM + 1;
+    const int BN = 16 * nt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = blockIdx.x * LBM, c0 = blockIdx.y * BN;
-    const int kb = blockIdx.z * kchunk;
+    const int r0 = bx * LBM, c0 = by * BN;
+    const int kb = bz * kchunk;
     const int ke = min(K, kb + kchunk);
     f4 acc[NT];
 #pragma unroll
@@ -66,7 +70,7 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gk = k0 + kq + u;
-                As[kq + u][row] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : 0.f;
+                As[(kq + u) * LDA_S + row] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : 0.f;
             }
         } else {
             const int kr = tid >> 3, rq = (tid & 7) * 8;
@@ -74,21 +78,22 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gr = r0 + rq + u;
-                As[kr][rq + u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : 0.f;
+                As[kr * LDA_S + rq + u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : 0.f;
             }
         }
         for (int e = tid; e < BK * BN; e += LNTHREADS) {
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[kr][cc] = (gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
+            Bs[kr * ldbs + cc] = (gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
-            const float a = As[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+            const float a = As[(kk * 4 + (lane >> 4)) * LDA_S + wave * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const float bv = Bs[kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+                if (j >= nt) break;  // uniform
+                const float bv = Bs[(kk * 4 + (lane >> 4)) * ldbs + j * 16 + (lane & 15)];
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[j], 0, 0, 0);
             }
         }
@@ -99,6 +104,7 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K
     const int rbase = r0 + wave * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
+        if (j >= nt) break;
         const int col = c0 + j * 16 + (lane & 15);
         if (col >= N) continue;
 #pragma unroll
@@ -106,28 +112,43 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K
             const int row = rbase + i;
             if (row >= M) continue;
             if (partial)
-                partial[((size_t)blockIdx.z * M + row) * N + col] = acc[j][i];
+                partial[((size_t)bz * M + row) * N + col] = acc[j][i];
             else
                 C[(size_t)row * ldc + col] = acc[j][i];
         }
     }
 }
 
+template <bool TRANS, int NT>
+__global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K, int kchunk,
+                                                             const float* __restrict__ A, int lda,
+                                                             const float* __restrict__ B, int ldb,
+                                                             float* __restrict__ C, int ldc,
+                                                             float* __restrict__ partial)
+{
+    __shared__ float As[32 * (LBM + 1)];
+    __shared__ float Bs[32 * (16 * NT + 1)];
+    gemm_f32_block<TRANS, NT>(As, Bs, 16 * NT + 1, blockIdx.x, blockIdx.y, blockIdx.z, NT, M, N, K,
+                              kchunk, A, lda, B, ldb, C, ldc, partial);
+}
+
 // BF16 mode: A is BF16 bits (the W copy), B float rounded to BF16 into LDS.
 // LDS row-major in k (8 consecutive k per lane fragment); BK = 64 (2 MFMA
-// steps of k = 32).
+// steps of k = 32). As: 64 x 72, Bs: 16 nt x 72 shorts of LDS.
+constexpr int BF_BK = 64, BF_LDK = BF_BK + 8;
 template <bool TRANS, int NT>
-__global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
-    int M, int N, int K, int kchunk, const unsigned short* __restrict__ A, int lda,
-    const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
-    float* __restrict__ partial)
+__device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned short* Bs, int bx,
+                                                int by, int bz, int nt, int M, int N, int K,
+                                                int kchunk, const unsigned short* __restrict__ A,
+                                                int lda, const float* __restrict__ B, int ldb,
+                                                float* __restrict__ C, int ldc,
+                                                float* __restrict__ partial)
 {
-    constexpr int BK = 64, BN = 16 * NT, LDK = BK + 8;
-    __shared__ __attribute__((aligned(16))) unsigned short As[LBM][LDK];
-    __shared__ __attribute__((aligned(16))) unsigned short Bs[BN][LDK];
+    constexpr int BK = BF_BK, LDK = BF_LDK;
+    const int BN = 16 * nt;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int r0 = blockIdx.x * LBM, c0 = blockIdx.y * BN;
-    const int kb = blockIdx.z * kchunk;
+    const int r0 = bx * LBM, c0 = by * BN;
+    const int kb = bz * kchunk;
     const int ke = min(K, kb + kchunk);
     f4 acc[NT];
 #pragma unroll
@@ -140,7 +161,8 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gk = k0 + kq + u;
-                As[row][kq + u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
+                As[row * LDK + kq + u] =
+                    (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
             }
         } else {
             const int kr = tid >> 2, rq = (tid & 3) * 16;
@@ -148,21 +170,24 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gr = r0 + rq + u;
-                As[rq + u][kr] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
+                As[(rq + u) * LDK + kr] =
+                    (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
             }
         }
         for (int e = tid; e < BK * BN; e += LNTHREADS) {
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[cc][kr] = (gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc]) : (unsigned short)0;
+            Bs[cc * LDK + kr] =
+                (gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc]) : (unsigned short)0;
         }
         __syncthreads();
 #pragma unroll
         for (int kk = 0; kk < BK / 32; ++kk) {
-            const s8 a = *(const s8*)&As[wave * 16 + (lane & 15)][kk * 32 + 8 * (lane >> 4)];
+            const s8 a = *(const s8*)&As[(wave * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4)];
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
-                const s8 bv = *(const s8*)&Bs[j * 16 + (lane & 15)][kk * 32 + 8 * (lane >> 4)];
+                if (j >= nt) break;  // uniform
+                const s8 bv = *(const s8*)&Bs[(j * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4)];
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
             }
         }
@@ -171,6 +196,7 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
     const int rbase = r0 + wave * 16 + 4 * (lane >> 4);
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
+        if (j >= nt) break;
         const int col = c0 + j * 16 + (lane & 15);
         if (col >= N) continue;
 #pragma unroll
@@ -178,11 +204,31 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
             const int row = rbase + i;
             if (row >= M) continue;
             if (partial)
-                partial[((size_t)blockIdx.z * M + row) * N + col] = acc[j][i];
+                partial[((size_t)bz * M + row) * N + col] = acc[j][i];
             else
                 C[(size_t)row * ldc + col] = acc[j][i];
         }
     }
+}
+
+template <bool TRANS, int NT>
+__global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
+    int M, int N, int K, int kchunk, const unsigned short* __restrict__ A, int lda,
+    const float* __restrict__ B, int ldb, float* __restrict__ C, int ldc,
+    float* __restrict__ partial)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[LBM * BF_LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[16 * NT * BF_LDK];
+    gemm_bf16_block<TRANS, NT>(As, Bs, blockIdx.x, blockIdx.y, blockIdx.z, NT, M, N, K, kchunk, A,
+                               lda, B, ldb, C, ldc, partial);
+}
+
+// FP32 partial sums of split s, added in split order in FP64
+__device__ __forceinline__ double sum_splits_f32(const float* partial, size_t total, size_t e, int S)
+{
+    double acc = 0.0;
+    for (int s = 0; s < S; ++s) acc += (double)partial[(size_t)s * total + e];
+    return acc;
 }
 
 __global__ void reduce_f32_kernel(int M, int N, int S, const float* partial, float* C, int ldc)
@@ -190,10 +236,97 @@ __global__ void reduce_f32_kernel(int M, int N, int S, const float* partial, flo
     const size_t total = (size_t)M * N;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
-        double acc = 0.0;
-        for (int s = 0; s < S; ++s) acc += (double)partial[(size_t)s * total + e];
+        const double acc = sum_splits_f32(partial, total, e, S);
         const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
         C[(size_t)row * ldc + col] = (float)acc;
+    }
+}
+
+// Grouped W-products (FP32 or BF16, one precision per launch): problem q owns
+// blocks start[q] .. start[q + 1] - 1, with the block grid and K split it has
+// alone, so its results are the same bits.
+constexpr int GROUP_MAX = GEMM_GROUP_MAX;
+struct GroupLp {
+    int n;
+    int start[GROUP_MAX + 1];
+    struct Prob {
+        int M, N, K, kchunk, gx, gy, nt, trans, lda, ldb, ldc, splits;
+        const void* A;
+        const float* B;
+        float *C, *partial;
+    } p[GROUP_MAX];
+};
+
+__device__ __forceinline__ int group_find(const int* start, int n, int blk)
+{
+    int q = 0;
+    while (q + 1 < n && blk >= start[q + 1]) ++q;
+    return q;
+}
+
+__device__ __forceinline__ void group_block(const GroupLp& g, int& q, int& bx, int& by, int& bz)
+{
+    q = group_find(g.start, g.n, blockIdx.x);
+    const GroupLp::Prob& P = g.p[q];
+    const int l = blockIdx.x - g.start[q], per = P.gx * P.gy;
+    bz = l / per;
+    const int rem = l - bz * per;
+    by = rem / P.gx;
+    bx = rem - by * P.gx;
+}
+
+__global__ __launch_bounds__(LNTHREADS) void gemm_f32_grouped_kernel(GroupLp g)
+{
+    __shared__ float As[32 * (LBM + 1)];
+    __shared__ float Bs[32 * (16 * 8 + 1)];
+    int q, bx, by, bz;
+    group_block(g, q, bx, by, bz);
+    const GroupLp::Prob& P = g.p[q];
+    float* part = P.splits > 1 ? P.partial : nullptr;
+    if (P.trans)
+        gemm_f32_block<true, 8>(As, Bs, 16 * 8 + 1, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
+                                (const float*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+    else
+        gemm_f32_block<false, 8>(As, Bs, 16 * 8 + 1, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
+                                 (const float*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+}
+
+__global__ __launch_bounds__(LNTHREADS) void gemm_bf16_grouped_kernel(GroupLp g)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[LBM * BF_LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[16 * 8 * BF_LDK];
+    int q, bx, by, bz;
+    group_block(g, q, bx, by, bz);
+    const GroupLp::Prob& P = g.p[q];
+    float* part = P.splits > 1 ? P.partial : nullptr;
+    if (P.trans)
+        gemm_bf16_block<true, 8>(As, Bs, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
+                                 (const unsigned short*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+    else
+        gemm_bf16_block<false, 8>(As, Bs, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
+                                  (const unsigned short*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+}
+
+struct GroupRedLp {
+    int n;
+    int start[GROUP_MAX + 1];
+    struct Prob {
+        int M, N, S, ldc;
+        const float* partial;
+        float* C;
+    } p[GROUP_MAX];
+};
+
+__global__ void reduce_f32_grouped_kernel(GroupRedLp g)
+{
+    const int q = group_find(g.start, g.n, blockIdx.x);
+    const GroupRedLp::Prob& P = g.p[q];
+    const int nb = g.start[q + 1] - g.start[q], lb = blockIdx.x - g.start[q];
+    const size_t total = (size_t)P.M * P.N;
+    for (size_t e = lb * (size_t)blockDim.x + threadIdx.x; e < total; e += (size_t)nb * blockDim.x) {
+        const double acc = sum_splits_f32(P.partial, total, e, P.S);
+        const int row = (int)(e / P.N), col = (int)(e - (size_t)row * P.N);
+        P.C[(size_t)row * P.ldc + col] = (float)acc;
     }
 }
 
@@ -293,6 +426,68 @@ void gemm_lp(Timer* tm, const char* family, bool bf16, bool trans_a, int M, int 
         if (blocks > 2048) blocks = 2048;
         hipLaunchKernelGGL(reduce_f32_kernel, dim3(blocks), dim3(256), 0, s, M, N, p.splits,
                            partial, C, ldc);
+    }
+}
+
+bool wproduct_lp_groupable(const WProduct& w)
+{
+    if ((w.prec != 1 && w.prec != 2) || w.M <= 0 || w.N <= 0 || w.K <= 0) return false;
+    const PlanLp p = make_plan_lp(w.M, w.N, w.K, w.prec == 2 ? 64 : 32);
+    return p.splits == 1 || (w.partial && w.partial_elems >= (size_t)p.splits * w.M * w.N);
+}
+
+void gemm_lp_grouped(const WProduct* ps, int n, hipStream_t s)
+{
+    BLWS_REQUIRE(n >= 1 && n <= GEMM_GROUP_MAX, BLWS_EINVAL, "gemm_lp_grouped: bad problem count");
+    const int prec = ps[0].prec;
+    GroupLp g{};
+    GroupRedLp r{};
+    g.n = n;
+    int blocks = 0, rblocks = 0, nr = 0;
+    for (int q = 0; q < n; ++q) {
+        const WProduct& w = ps[q];
+        BLWS_REQUIRE(w.prec == prec && wproduct_lp_groupable(w), BLWS_EINVAL,
+                     "gemm_lp_grouped: problem not groupable");
+        const PlanLp p = make_plan_lp(w.M, w.N, w.K, prec == 2 ? 64 : 32);
+        GroupLp::Prob& P = g.p[q];
+        P.M = w.M;
+        P.N = w.N;
+        P.K = w.K;
+        P.kchunk = p.kchunk;
+        P.gx = p.gx;
+        P.gy = p.gy;
+        P.nt = p.nt;
+        P.trans = w.trans ? 1 : 0;
+        P.lda = w.lda;
+        P.ldb = w.ldb;
+        P.ldc = w.ldc;
+        P.splits = p.splits;
+        P.A = w.A;
+        P.B = (const float*)w.B;
+        P.C = (float*)w.C;
+        P.partial = (float*)w.partial;
+        g.start[q] = blocks;
+        blocks += p.gx * p.gy * p.splits;
+        if (p.splits > 1) {
+            const size_t total = (size_t)w.M * w.N;
+            int nb = (int)((total + 255) / 256);
+            if (nb > 2048) nb = 2048;
+            r.p[nr] = GroupRedLp::Prob{w.M, w.N, p.splits, w.ldc, (const float*)w.partial,
+                                       (float*)w.C};
+            r.start[nr] = rblocks;
+            rblocks += nb;
+            ++nr;
+        }
+    }
+    g.start[n] = blocks;
+    if (prec == 2)
+        hipLaunchKernelGGL(gemm_bf16_grouped_kernel, dim3(blocks), dim3(LNTHREADS), 0, s, g);
+    else
+        hipLaunchKernelGGL(gemm_f32_grouped_kernel, dim3(blocks), dim3(LNTHREADS), 0, s, g);
+    if (nr > 0) {
+        r.n = nr;
+        r.start[nr] = rblocks;
+        hipLaunchKernelGGL(reduce_f32_grouped_kernel, dim3(rblocks), dim3(256), 0, s, r);
     }
 }
 

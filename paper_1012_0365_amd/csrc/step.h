@@ -63,7 +63,19 @@ struct Carver {
 
 }  // namespace
 
+struct Context;
+
+// Rendezvous for the W-products of several solves stepping at the same time
+// (the request server): a solve hands over its products and returns once a
+// grouped launch holding them has been queued after the work already on the
+// given streams, with those streams made to wait for it.
+struct ProductGroup {
+    virtual ~ProductGroup() {}
+    virtual void submit(const WProduct* prods, const hipStream_t* streams, int n) = 0;
+};
+
 struct Context {
+    ProductGroup* group = nullptr;  // set by the request server while a solve steps
     int device = 0;
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -399,6 +411,30 @@ void op_apply(Context& cx, StepWs<T>& w, hipStream_t s, const Op<T>& op, int m, 
     }
 }
 
+// The dense W-product op_apply would launch, as a grouped-launch problem
+// (same kernel, same split-K scratch, hence the same result).
+template <typename T>
+WProduct dense_wproduct(const StepWs<T>& w, const Op<T>& op, int m, int n, bool trans,
+                        const T* X, int ldx, int c, T* out, int ldo)
+{
+    WProduct pr{};
+    const bool bf = std::is_same<T, float>::value && op.Wh != nullptr;
+    pr.prec = std::is_same<T, double>::value ? 0 : (bf ? 2 : 1);
+    pr.trans = trans;
+    pr.M = trans ? n : m;
+    pr.N = c;
+    pr.K = trans ? m : n;
+    pr.A = bf ? (const void*)op.Wh : (const void*)op.W;
+    pr.lda = op.ldw;
+    pr.B = X;
+    pr.ldb = ldx;
+    pr.C = out;
+    pr.ldc = ldo;
+    pr.partial = w.partial;
+    pr.partial_elems = std::is_same<T, double>::value ? w.partial_elems : 2 * w.partial_elems;
+    return pr;
+}
+
 // One BLWS step (Algorithms 2-3, k = 2) on W from the orthonormal block
 // (U, V); on return U, V hold the top-b Ritz vectors and S the Ritz values.
 //
@@ -424,15 +460,28 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     // products with the start block: P = W V, Q = W^T U (the low-rank
     // coefficients of the matrix-completion operator have one buffer: there
     // Q waits for P)
-    op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
-    if (!W.W) cx.fork(s);
-    op_apply<T>(cx, wb, cx.aux, W, m, n, true, U, ldu, b, w.Qb, b);
+    if (cx.group && W.W) {
+        // the request server groups these with other solves' products
+        const WProduct pr[2] = {dense_wproduct<T>(w, W, m, n, false, V, ldv, b, w.PH, b2),
+                                dense_wproduct<T>(wb, W, m, n, true, U, ldu, b, w.Qb, b)};
+        const hipStream_t st[2] = {s, cx.aux};
+        cx.group->submit(pr, st, 2);
+    } else {
+        op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
+        if (!W.W) cx.fork(s);
+        op_apply<T>(cx, wb, cx.aux, W, m, n, true, U, ldu, b, w.Qb, b);
+    }
     // new block: F = orth(P - U U^T P), G = orth(Q - V V^T Q)
     orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
     orth_against<T>(cx, wb, cx.aux, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
     cx.join(s);
     // the last product of the pass: H = W G
-    op_apply<T>(cx, w, s, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
+    if (cx.group && W.W) {
+        const WProduct pr = dense_wproduct<T>(w, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
+        cx.group->submit(&pr, &s, 1);
+    } else {
+        op_apply<T>(cx, w, s, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
+    }
     // B = [U, F]^T [P, H] in FP64
     gemm<T, T, double>(tm, "gemm_ts", true, b2, b2, m, 1.0, w.UF, b2, w.PH, b2, 0.0,
                        (const double*)nullptr, 0, w.Bm, b2, w.partial, w.partial_elems, s);

@@ -2,7 +2,8 @@
 
 Every request must compute exactly what the blocking solver computes for the
 same arguments, whatever else is in flight: results are compared bit for bit
-with solves run alone. Also checked: solves overlap (more than one in flight),
+with solves run alone, with the W-products of solves stepping together in
+grouped launches and without. Also checked: solves overlap (more than one in flight),
 admission by the memory budget (a budget below one request's workspace runs
 them one at a time), per-request errors, argument checks at submission, and
 polling.
@@ -108,6 +109,20 @@ def test_mix_results_equal_solves_alone(torch, blws, mix, alone):
     print("server stats", st)
     assert st["completed"] == len(mix) and st["failed"] == 0
     assert st["max_active"] >= 2  # solves overlapped on the device
+    # the dense W-products of solves stepping together went out grouped
+    assert st["grouped_launches"] > 0 and st["max_group"] >= 2
+    assert st["grouped_products"] >= st["grouped_launches"]
+    srv.close()
+
+
+def test_mix_without_grouping_is_the_same(torch, blws, mix, alone):
+    # one launch per product instead of grouped launches: the same bits
+    srv = blws.Server(0, max_slots=4, group_products=False)
+    tickets = [submit(srv, blws, r) for r in mix]
+    for t, (ref, _) in zip(tickets, alone):
+        assert same(torch, srv.wait(t)[:-1], ref)
+    st = srv.stats()
+    assert st["grouped_launches"] == 0 and st["completed"] == len(mix)
     srv.close()
 
 
