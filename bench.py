@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import re
 import math
 import os
 import sys
@@ -26,6 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+COPY_BYTES = 256 << 20  # counter calibration copy
 METRIC = "RPCA solve s & SVT calls/s at n=2000 vs plain (≤1e-6 rel err); p50/p99 lat"
 M = N = 2000
 RANK = 100
@@ -71,7 +73,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64")
-    ap.add_argument("--workload", choices=["rpca", "serving"], default="rpca")
+    ap.add_argument("--workload", choices=["rpca", "serving", "copy"], default="rpca",
+                    help="copy: one device copy of 256 MiB (counter calibration)")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="serving: solves in flight")
     ap.add_argument("--no-group", action="store_true",
@@ -87,6 +90,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(family):
+    """HBM bytes per launch of a kernel family from the committed rocprofv3 PMC
+    summaries (profiles/*_traffic.md, FETCH_SIZE and WRITE_SIZE scaled by a
+    copy of known size), or None when there is none or the kernel's source has
+    changed since the counters were taken."""
+    import glob
+    import hashlib
+
+    here = os.path.dirname(os.path.abspath(__file__))
+    pat = re.compile(r"^traffic: kernel=(\S+) bytes_per_launch=(\d+) source=(\S+) sha256=(\w+)")
+    for path in sorted(glob.glob(os.path.join(here, "profiles", "*_traffic.md"))):
+        for line in open(path):
+            m = pat.match(line.strip())
+            if not m or m.group(1) != family:
+                continue
+            src = os.path.join(here, m.group(3))
+            if not os.path.exists(src):
+                return None
+            if hashlib.sha256(open(src, "rb").read()).hexdigest() != m.group(4):
+                return None
+            return int(m.group(2))
+    return None
+
+
 def roofline_entry(name, rec, prec):
     bound, key, unit = family_bound(name, prec)
     n = max(1, rec["launches"])
@@ -97,7 +124,7 @@ def roofline_entry(name, rec, prec):
         achieved = rec["flops"] / n / avg_s / 1e12 if avg_s > 0 else 0.0
     peak = PEAK[key]
     return {"bound": bound, "achieved": achieved, "peak": peak, "unit": unit,
-            "frac": achieved / peak, "traffic": None, "avg_us": avg_s * 1e6,
+            "frac": achieved / peak, "traffic": measured_traffic(name), "avg_us": avg_s * 1e6,
             "algorithmic_per_launch": (rec["bytes"] if bound == "hbm" else rec["flops"]) / n}
 
 
@@ -367,13 +394,31 @@ def bench_serving(args):
     }
 
 
+def bench_copy():
+    """One device-to-device copy of COPY_BYTES: the reference for HBM byte
+    counters (FETCH_SIZE should read COPY_BYTES, WRITE_SIZE the same)."""
+    import torch
+
+    n = COPY_BYTES // 8
+    x = torch.arange(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    assert bool((y[-16:] == x[-16:]).all())
+    return {"workload": "copy", "bytes_read": COPY_BYTES, "bytes_written": COPY_BYTES}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the solve is a "
               "single-GPU path and no multi-GPU figure is produced", file=sys.stderr)
         sys.exit(2)
-    out = bench_serving(args) if args.workload == "serving" else bench_rpca(args)
+    if args.workload == "copy":
+        out = bench_copy()
+    else:
+        out = bench_serving(args) if args.workload == "serving" else bench_rpca(args)
     print(json.dumps(out))
 
 
