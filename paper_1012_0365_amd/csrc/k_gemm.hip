@@ -51,34 +51,57 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = kb; k0 < ke; k0 += BK) {
+    // The next stage's tiles are loaded into registers while the current
+    // one feeds the matrix cores: A 8 values per thread (NN: 4 threads read 32
+    // consecutive k of one row; TN: 8 threads read 64 consecutive columns of
+    // one row), B 2 NT values (element e = tid + 256 u of the BK x BN tile).
+    constexpr int NB = (BK * 16 * NT + NTHREADS - 1) / NTHREADS;
+    double ra[8], rb[NB];
+    auto fetch = [&](int k0) {
         if (!TRANS) {
-            // op(A) = A (M x K): 4 threads read 32 consecutive k of one row.
             const int row = tid >> 2, kq = (tid & 3) * 8;
             const int gr = r0 + row;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gk = k0 + kq + u;
-                As[(kq + u) * LDA_S + row] =
-                    (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
+                ra[u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
             }
         } else {
-            // op(A) = A^T, A is K x M: 8 threads read 64 consecutive columns of one row.
             const int kr = tid >> 3, rq = (tid & 7) * 8;
             const int gk = k0 + kr;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gr = r0 + rq + u;
-                As[kr * LDA_S + rq + u] =
-                    (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
+                ra[u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
             }
         }
-        for (int e = tid; e < BK * BN; e += NTHREADS) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + NTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[kr * ldbs + cc] = (gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
+            rb[u] = (e < BK * BN && gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
+        }
+    };
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            const int row = tid >> 2, kq = (tid & 3) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) As[(kq + u) * LDA_S + row] = ra[u];
+        } else {
+            const int kr = tid >> 3, rq = (tid & 7) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) As[kr * LDA_S + rq + u] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + NTHREADS * u;
+            const int kr = e / BN, cc = e - kr * BN;
+            if (e < BK * BN) Bs[kr * ldbs + cc] = rb[u];
         }
         __syncthreads();
+        if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const double a = As[(kk * 4 + (lane >> 4)) * LDA_S + wave * 16 + (lane & 15)];
@@ -238,9 +261,9 @@ Plan make_plan(int M, int N, int K)
     p.gy = (N + 16 * p.nt - 1) / (16 * p.nt);
     p.gx = (M + BM - 1) / BM;
     const long tiles = (long)p.gx * p.gy;
-    // Aim at ~512 workgroups, each split no shorter than 4 LDS stages, and
-    // keep the partial sums below 4M doubles.
-    long s = (512 + tiles - 1) / tiles;
+    // Aim at ~384 workgroups (1.5 per CU), each split no shorter than 4 LDS
+    // stages, and keep the partial sums below 4M doubles.
+    long s = (384 + tiles - 1) / tiles;
     const long smax_k = (K + 4 * BK - 1) / (4 * BK);
     if (s > smax_k) s = smax_k;
     const long smax_mem = (4L << 20) / ((long)M * N > 0 ? (long)M * N : 1);
