@@ -198,6 +198,13 @@ int blws_timing_enable(blws_ctx ctx, int enable);
  * algorithmic flop and byte counts of those launches. Synchronises the device. */
 int blws_timing_get(blws_ctx ctx, const char* name, long long* launches, double* ms,
                     double* flops, double* bytes);
+/* Autotuning: force the split-K plans of the generic W-product GEMM kernels
+ * to aim at `target` workgroups (0 restores the tuned table the library was
+ * built with). Process-wide, for paper_1012_0365_amd/autotune.py; a plan
+ * change changes the order in which partial sums are added, so results then
+ * differ from the tuned ones in the last bits. Returns BLWS_EINVAL for
+ * target < 0 or > 65536. */
+int blws_set_plan_target(int target);
 /* Comma-separated names of the kernel families recorded since timing was
  * enabled, into buf (host, len bytes, NUL-terminated). */
 int blws_timing_list(blws_ctx ctx, char* buf, size_t len);

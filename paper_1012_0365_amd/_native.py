@@ -120,6 +120,7 @@ SIGNATURES = {
     "blws_server_wait": (_i, [_vp, _ll, ctypes.POINTER(SolveInfo)]),
     "blws_server_get_stats": (_i, [_vp, ctypes.POINTER(ServerStats)]),
     "blws_server_last_error": (ctypes.c_char_p, [_vp]),
+    "blws_set_plan_target": (_i, [_i]),
     "blws_timing_enable": (_i, [_vp, _i]),
     "blws_timing_list": (_i, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
     "blws_timing_get": (_i, [_vp, ctypes.c_char_p, ctypes.POINTER(_ll), ctypes.POINTER(_d),

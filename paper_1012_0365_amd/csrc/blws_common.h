@@ -60,6 +60,12 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
           TC* C, int ldc, double* partial, size_t partial_elems, hipStream_t s);
 size_t gemm_partial_elems(int M, int N, int K);
 
+// Workgroup target of the split-K plan of a generic GEMM (prec 0 FP64,
+// 1 FP32, 2 BF16) from the autotuned table (tuning.hip); `fallback` outside
+// the shapes it covers. set_plan_override(t > 0) forces t for tuning runs.
+int plan_target(int prec, int M, int N, int K, int fallback);
+void set_plan_override(int target);
+
 // One W-product C = op(A) B (op(A) = A^T if trans) for a grouped launch:
 // prec 0 = FP64 (A, B, C double, partial doubles), 1 = FP32 (float), 2 = BF16
 // (A holds BF16 bits, B and C float, partial floats). partial is the

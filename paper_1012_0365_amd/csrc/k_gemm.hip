@@ -261,9 +261,11 @@ Plan make_plan(int M, int N, int K)
     p.gy = (N + 16 * p.nt - 1) / (16 * p.nt);
     p.gx = (M + BM - 1) / BM;
     const long tiles = (long)p.gx * p.gy;
-    // Aim at ~384 workgroups (1.5 per CU), each split no shorter than 4 LDS
-    // stages, and keep the partial sums below 4M doubles.
-    long s = (384 + tiles - 1) / tiles;
+    // Aim at the tuned workgroup count (~384, 1.5 per CU, outside the tuned
+    // shapes), each split no shorter than 4 LDS stages, and keep the partial
+    // sums below 4M doubles.
+    const long target = plan_target(0, M, N, K, 384);
+    long s = (target + tiles - 1) / tiles;
     const long smax_k = (K + 4 * BK - 1) / (4 * BK);
     if (s > smax_k) s = smax_k;
     const long smax_mem = (4L << 20) / ((long)M * N > 0 ? (long)M * N : 1);

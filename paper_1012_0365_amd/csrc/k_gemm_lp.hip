@@ -63,14 +63,17 @@ __device__ __forceinline__ void gemm_f32_block(float* As, float* Bs, int ldbs, i
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = kb; k0 < ke; k0 += BK) {
+    // the next stage's tiles load into registers while the current one is used
+    constexpr int NB = (BK * 16 * NT + LNTHREADS - 1) / LNTHREADS;
+    float ra[8], rb[NB];
+    auto fetch = [&](int k0) {
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 8;
             const int gr = r0 + row;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gk = k0 + kq + u;
-                As[(kq + u) * LDA_S + row] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : 0.f;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : 0.f;
             }
         } else {
             const int kr = tid >> 3, rq = (tid & 7) * 8;
@@ -78,15 +81,36 @@ __device__ __forceinline__ void gemm_f32_block(float* As, float* Bs, int ldbs, i
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gr = r0 + rq + u;
-                As[kr * LDA_S + rq + u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : 0.f;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : 0.f;
             }
         }
-        for (int e = tid; e < BK * BN; e += LNTHREADS) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + LNTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[kr * ldbs + cc] = (gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
+            rb[u] = (e < BK * BN && gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
+        }
+    };
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            const int row = tid >> 2, kq = (tid & 3) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) As[(kq + u) * LDA_S + row] = ra[u];
+        } else {
+            const int kr = tid >> 3, rq = (tid & 7) * 8;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) As[kr * LDA_S + rq + u] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + LNTHREADS * u;
+            const int kr = e / BN, cc = e - kr * BN;
+            if (e < BK * BN) Bs[kr * ldbs + cc] = rb[u];
         }
         __syncthreads();
+        if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 4; ++kk) {
             const float a = As[(kk * 4 + (lane >> 4)) * LDA_S + wave * 16 + (lane & 15)];
@@ -154,15 +178,18 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
 #pragma unroll
     for (int j = 0; j < NT; ++j) acc[j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int k0 = kb; k0 < ke; k0 += BK) {
+    // the next stage's tiles load into registers while the current one is used
+    constexpr int NB = (BK * 16 * NT + LNTHREADS - 1) / LNTHREADS;
+    unsigned short ra[16];
+    unsigned short rb[NB];
+    auto fetch = [&](int k0) {
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 16;
             const int gr = r0 + row;
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gk = k0 + kq + u;
-                As[row * LDK + kq + u] =
-                    (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
             }
         } else {
             const int kr = tid >> 2, rq = (tid & 3) * 16;
@@ -170,17 +197,37 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gr = r0 + rq + u;
-                As[(rq + u) * LDK + kr] =
-                    (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
             }
         }
-        for (int e = tid; e < BK * BN; e += LNTHREADS) {
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + LNTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            Bs[cc * LDK + kr] =
-                (gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc]) : (unsigned short)0;
+            rb[u] = (e < BK * BN && gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc])
+                                                       : (unsigned short)0;
+        }
+    };
+    fetch(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+        if (!TRANS) {
+            const int row = tid >> 2, kq = (tid & 3) * 16;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) As[row * LDK + kq + u] = ra[u];
+        } else {
+            const int kr = tid >> 2, rq = (tid & 3) * 16;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) As[(rq + u) * LDK + kr] = ra[u];
+        }
+#pragma unroll
+        for (int u = 0; u < NB; ++u) {
+            const int e = tid + LNTHREADS * u;
+            const int kr = e / BN, cc = e - kr * BN;
+            if (e < BK * BN) Bs[cc * LDK + kr] = rb[u];
         }
         __syncthreads();
+        if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 32; ++kk) {
             const s8 a = *(const s8*)&As[(wave * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4)];
@@ -350,7 +397,8 @@ PlanLp make_plan_lp(int M, int N, int K, int BK)
     p.gy = (N + 16 * p.nt - 1) / (16 * p.nt);
     p.gx = (M + LBM - 1) / LBM;
     const long tiles = (long)p.gx * p.gy;
-    long s = (512 + tiles - 1) / tiles;
+    const long target = plan_target(BK == 64 ? 2 : 1, M, N, K, 512);
+    long s = (target + tiles - 1) / tiles;
     const long smax_k = (K + 4 * BK - 1) / (4 * BK);
     if (s > smax_k) s = smax_k;
     const long smax_mem = (8L << 20) / ((long)M * N > 0 ? (long)M * N : 1);
