@@ -226,7 +226,8 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
 // matrix by FP64 MFMA into LDS, the Cholesky inverse in registers (in place
 // in LDS), X <- X R^{-1} in place row by row. Columns found dependent in the
 // first pass are redrawn from the counter-based generator (stream ids sid0,
-// sid1) before the second; *nflag counts them.
+// sid1) before the second; *nflag counts them. When the first Gram matrix is
+// already the identity to 1e-8, the first pass is the only one.
 constexpr int CQ_LD = 129;
 
 __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, double* X0, double* X1,
@@ -237,6 +238,8 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
     __shared__ double G[128 * CQ_LD];
     __shared__ double scal[128], row[2 * 128], piv[128];
     __shared__ int flg[128];
+    __shared__ double dev_w[16];
+    __shared__ int one_pass;
     double* X = blockIdx.x == 0 ? X0 : X1;
     const uint64_t sid = blockIdx.x == 0 ? sid0 : sid1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -272,6 +275,25 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
             }
         }
         __syncthreads();
+        if (pass == 0) {
+            // Columns already orthonormal to 1e-8 (the usual case for inverse
+            // iteration vectors): one pass leaves them orthonormal to rounding
+            // (its error is of order u cond(G), cond(G) <= 1 + 2e-8), so the
+            // second is skipped.
+            double dv = 0.0;
+            for (int e = tid; e < c * c; e += 1024) {
+                const int i = e / c, j = e - i * c;
+                dv = fmax(dv, fabs(G[i * CQ_LD + j] - (i == j ? 1.0 : 0.0)));
+            }
+            for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
+            if (lane == 0) dev_w[wave] = dv;
+            __syncthreads();
+            if (tid == 0) {
+                double m = 0.0;
+                for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
+                one_pass = m <= 1e-8 ? 1 : 0;
+            }
+        }
         chol_inv_regs(c, G, CQ_LD, G, CQ_LD, eta, scal, row, piv, flg);
         // X <- X R^{-1} by MFMA: wavefront w owns row blocks w, w + 16, ... (16
         // rows each, all column tiles), so each row block is read completely
@@ -320,6 +342,7 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
             if (cnt) atomicAdd(nflag, cnt);
         }
         __syncthreads();
+        if (one_pass) break;  // uniform (set before the barriers of chol_inv_regs)
     }
 }
 
