@@ -921,20 +921,57 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
         xr[r] = (col < nv && i < N) ? UB[(size_t)i * ld + col] : 0.0;
         yr[r] = (col < nv && i < N) ? VB[(size_t)i * ld + col] : 0.0;
     }
-    for (int side = 0; side < 2; ++side) {
+    // The blocks of both sides as one sequence of steps (left side, last
+    // block first, then the right side); with MAXN <= 512 the next step's Y
+    // block is loaded into registers while the current one is applied.
+    const int nblkR = (N - 1 + WY_RB - 1) / WY_RB;
+    const int nsteps = nblkL + nblkR;
+    constexpr int PFN = MAXN <= 512 ? WY_RB * ((MAXN + 255) / 256) : 1;
+    double pf[PFN];
+    auto step_of = [&](int st, int& side, int& blk) {
+        side = st < nblkL ? 0 : 1;
+        blk = side == 0 ? nblkL - 1 - st : nblkR - 1 - (st - nblkL);
+    };
+    auto y_elem = [&](int side, int blk, int q, int i) -> double {
         const double* Vh = side == 0 ? VL : VR;
-        const int nref = side == 0 ? N : N - 1, off = side;
-        const int nblk = (nref + WY_RB - 1) / WY_RB;
-        for (int blk = nblk - 1; blk >= 0; --blk) {
-            const int k0 = blk * WY_RB;
-            const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
-            const int tb = side == 0 ? blk : nblkL + blk;
-            __syncthreads();
+        const int nref = side == 0 ? N : N - 1;
+        const int k0 = blk * WY_RB;
+        const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
+        return (q < cnt && i < N && i >= k0 + q + side) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+    };
+    auto prefetch = [&](int st) {
+        if constexpr (MAXN <= 512) {
+            int side, blk;
+            step_of(st, side, blk);
+#pragma unroll
             for (int q = 0; q < WY_RB; ++q)
-                for (int i = tid; i < N; i += 256)
-                    Y[q][i] = (q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
-            Tm[tid >> 4][tid & 15] = Tall[(size_t)tb * WY_RB * WY_RB + tid];
-            __syncthreads();
+#pragma unroll
+                for (int u = 0; u < PFN / WY_RB; ++u)
+                    pf[q * (PFN / WY_RB) + u] = y_elem(side, blk, q, tid + 256 * u);
+        }
+    };
+    prefetch(0);
+    for (int st = 0; st < nsteps; ++st) {
+        int side, blk;
+        step_of(st, side, blk);
+        const int tb = side == 0 ? blk : nblkL + blk;
+        __syncthreads();  // the previous step's reads of Y and Tm are done
+        if constexpr (MAXN <= 512) {
+#pragma unroll
+            for (int q = 0; q < WY_RB; ++q)
+#pragma unroll
+                for (int u = 0; u < PFN / WY_RB; ++u) {
+                    const int i = tid + 256 * u;
+                    if (i < MAXN) Y[q][i] = pf[q * (PFN / WY_RB) + u];
+                }
+        } else {
+            for (int q = 0; q < WY_RB; ++q)
+                for (int i = tid; i < N; i += 256) Y[q][i] = y_elem(side, blk, q, i);
+        }
+        Tm[tid >> 4][tid & 15] = Tall[(size_t)tb * WY_RB * WY_RB + tid];
+        __syncthreads();
+        if (st + 1 < nsteps) prefetch(st + 1);
+        {
             // x <- x - Y (T (Y^T x))
             double yx[WY_RB];
 #pragma unroll
