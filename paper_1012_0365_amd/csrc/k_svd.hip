@@ -119,6 +119,27 @@ __device__ __forceinline__ void house(double alpha, double s2, double& tau, doub
     }
 }
 
+// Sums over the 32 lanes of a half-wavefront of four values v[0..3] at once:
+// lane l (16-lane row position c = l % 16) ends with the sum of v[2 b3 + b2],
+// b3, b2 the bits 3 and 2 of c. Reduce-scatter over the first two levels
+// (DPP row rotation by 8 pairs c with c ^ 8, the half-row mirror pairs c with
+// 7 - c across bit 2; each lane keeps the half its bit selects and adds the
+// partner's copy of it), then sums within quads (xor 2, xor 1) and across the
+// two rows (permlane16 swap): about half the instructions of four full sums.
+__device__ __forceinline__ double quad_col_sum(const double (&v)[4])
+{
+    const int c = threadIdx.x & 15;
+    const bool b3 = (c & 8) != 0, b2 = (c & 4) != 0;
+    double k0 = b3 ? v[2] : v[0], k1 = b3 ? v[3] : v[1];
+    const double s0 = b3 ? v[0] : v[2], s1 = b3 ? v[1] : v[3];
+    k0 += dpp_move<0x128>(s0);  // row_ror:8
+    k1 += dpp_move<0x128>(s1);
+    double r = (b2 ? k1 : k0) + dpp_move<0x141>(b2 ? k0 : k1);  // row_half_mirror
+    r += dpp_move<0x4E>(r);                                    // quad_perm [2,3,0,1]
+    r += dpp_move<0xB1>(r);                                    // quad_perm [1,0,3,2]
+    return rows_pair_sum(r);
+}
+
 constexpr int GK_LD = GK_MAXN + 1;  // padded LDS row of the partial sums
 
 struct GkShared {
@@ -178,12 +199,22 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
             for (int a = KA; a < NPR; ++a)  // rows > k (xc is zero beyond N)
                 xa[a] = (tr > k - 32 * a) ? sh.xc[tr + 32 * a] : 0.0;
 #pragma unroll
-            for (int c = KC; c < NPC; ++c) {
-                double p = 0.0;
+            for (int g = KC; g < NPC; g += 4) {
+                // four columns at a time; lane 4 j of the first row then holds
+                // the sum of column g + j
+                double v[4];
 #pragma unroll
-                for (int a = KA; a < NPR; ++a) p += xa[a] * Br[a][c];
-                p = half_sum32(p);
-                if (tr == 0) sh.sq[tc * 16 + c] = p;
+                for (int u = 0; u < 4; ++u) {
+                    const int c = g + u < NPC ? g + u : NPC - 1;
+                    double p = 0.0;
+#pragma unroll
+                    for (int a = KA; a < NPR; ++a) p += xa[a] * Br[a][c];
+                    v[u] = g + u < NPC ? p : 0.0;
+                }
+                const double q4 = quad_col_sum(v);
+                const int l16 = tr & 15;
+                if (tr < 16 && (l16 & 3) == 0 && g + (l16 >> 2) < NPC)
+                    sh.sq[tc * 16 + g + (l16 >> 2)] = q4;
             }
             double tauLk, betaL, scaleL;
             house(alphaL, wave_sum64(s2a + s2b), tauLk, betaL, scaleL);
