@@ -89,22 +89,15 @@ __device__ __forceinline__ double wave_sum64(double x)
     return halves_sum(rows_pair_sum(row_sum16(x)));
 }
 
-// Broadcast within each half-wavefront: every lane of lanes 0-31 gets v of
-// lane src, every lane of lanes 32-63 gets v of lane src + 32 (src uniform).
-__device__ __forceinline__ double bcast_half(double v, int src)
-{
-    const unsigned long long u = __double_as_longlong(v);
-    const int lo = (int)(u & 0xffffffffu), hi = (int)(u >> 32);
-    const int lo0 = __builtin_amdgcn_readlane(lo, src), hi0 = __builtin_amdgcn_readlane(hi, src);
-    const int lo1 = __builtin_amdgcn_readlane(lo, src + 32);
-    const int hi1 = __builtin_amdgcn_readlane(hi, src + 32);
-    const bool upper = (threadIdx.x & 32) != 0;
-    const int rlo = upper ? lo1 : lo0, rhi = upper ? hi1 : hi0;
-    return __longlong_as_double(((unsigned long long)(unsigned)rhi << 32) | (unsigned)rlo);
-}
-
 // Householder reflector H = I - tau v v^T with v_0 = 1 mapping (alpha, x)
-// to (beta, 0): from alpha and s2 = |x|^2; v = (1, x * scale).
+// to (beta, 0): from alpha and s2 = |x|^2; v = (1, x * scale). With
+// nrm = sqrt(alpha^2 + s2) and beta = -sign(alpha) nrm:
+//   tau = (beta - alpha) / beta = 1 + |alpha| / nrm,
+//   scale = 1 / (alpha - beta) = sign(alpha) / (|alpha| + nrm),
+// from r = 1 / nrm (hardware estimate, two Newton steps r <- r (3 - a r^2) / 2)
+// and one reciprocal (estimate, two Newton steps): a shorter dependence chain
+// than a square root and two divisions. Every thread runs the same sequence,
+// so all of them hold the same bits.
 __device__ __forceinline__ void house(double alpha, double s2, double& tau, double& beta,
                                       double& scale)
 {
@@ -112,10 +105,20 @@ __device__ __forceinline__ void house(double alpha, double s2, double& tau, doub
     beta = alpha;
     scale = 0.0;
     if (s2 > 0.0) {
-        const double nrm = sqrt(alpha * alpha + s2);
+        const double a2 = fma(alpha, alpha, s2);
+        double r = __builtin_amdgcn_rsq(a2);
+        const double h = 0.5 * a2;
+        r = r * fma(-h * r, r, 1.5);
+        r = r * fma(-h * r, r, 1.5);
+        const double nrm = a2 * r;
+        const double aa = fabs(alpha);
         beta = alpha >= 0.0 ? -nrm : nrm;
-        tau = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
+        tau = fma(aa, r, 1.0);
+        const double den = aa + nrm;
+        double q = __builtin_amdgcn_rcp(den);
+        q = fma(q, fma(-den, q, 1.0), q);
+        q = fma(q, fma(-den, q, 1.0), q);
+        scale = alpha >= 0.0 ? q : -q;
     }
 }
 
@@ -148,6 +151,7 @@ struct GkShared {
     double cp[GK_MAXN];      // column k + 1 after the left reflection of step k
     double zs[GK_MAXN];      // B v of the right reflection (without tau), rows > k
     double sx[16 * 16];      // row k beyond k + 1, per half-wavefront: its own columns only
+    double srk[16 * 16];     // row k before the left reflection, per half-wavefront
     double sq[16 * 16];      // column sums of the left reflection, per half-wavefront
     double pn[8];            // per-wavefront partial sums of squares of row k
     double ax;               // B[k][k + 1] after the left reflection
@@ -194,6 +198,13 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
                 }
                 if (i < N) s2a += sh.xc[i] * sh.xc[i];
             }
+            // the owner of row k in each half-wavefront hands its entries to the
+            // other lanes through the half-wavefront's own LDS row (read back
+            // by the same wavefront, in order)
+            if (tr == (k & 31)) {
+#pragma unroll
+                for (int c = KC; c < NPC; ++c) sh.srk[tc * 16 + c] = Br[KA][c];
+            }
             double xa[NPR];
 #pragma unroll
             for (int a = KA; a < NPR; ++a)  // rows > k (xc is zero beyond N)
@@ -227,11 +238,10 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
             double va[NPR];
 #pragma unroll
             for (int a = KA; a < NPR; ++a) va[a] = (tr == k - 32 * a) ? 1.0 : xa[a] * scaleL;
-            const int kl = k & 31;
             double axv = 0.0;
 #pragma unroll
             for (int c = KC; c < NPC; ++c) {  // column j = tc + 16 c; zero beyond N
-                const double rk = bcast_half(Br[KA][c], kl);  // B[k][j]
+                const double rk = sh.srk[tc * 16 + c];  // B[k][j]
                 const double wj =
                     (tc > k - 16 * c) ? tauLk * (rk + scaleL * sh.sq[tc * 16 + c]) : 0.0;
 #pragma unroll
