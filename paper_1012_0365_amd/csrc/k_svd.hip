@@ -489,6 +489,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
     __shared__ double xcol[SVD_MAXN];  // column k, then the left vector
     __shared__ double zs[SVD_MAXN];    // z = B v of the right reflector
     __shared__ double red[16][33];
+    __shared__ double red0[16][33];
     __shared__ double wcol[32];
     __shared__ double rowk[32];
     __shared__ double sc[4];
@@ -508,49 +509,50 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
     __syncthreads();
 
     for (int k = 0; k < N; ++k) {
-        // ---- left reflector of column k (rows k..N-1), formed by every workgroup
-        if (wave == 0) {
+        // ---- left reflector of column k (rows k..N-1), formed by every
+        // wavefront of every workgroup from the published column (the same
+        // loads and the same order everywhere: the same bits). The column
+        // products are taken unscaled, sum_{i > k} x_i B[i][j] and row k's own
+        // entry apart, while the norm is formed:
+        //   w_j = tau (B[k][j] + scale sum_{i > k} x_i B[i][j]).
+        double tl, sl;
+        {
             const double alpha = xcol[k];
-            double s2 = 0.0;
-            for (int i = k + 1 + lane; i < N; i += 64) s2 += xcol[i] * xcol[i];
-            s2 = wave_sum64(s2);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (s2 > 0.0) {
-                const double nrm = sqrt(alpha * alpha + s2);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
+            double s2a = 0.0, s2b = 0.0;
+            {
+                int i = k + 1 + lane;
+                for (; i + 64 < N; i += 128) {
+                    const double u0 = xcol[i], u1 = xcol[i + 64];
+                    s2a += u0 * u0;
+                    s2b += u1 * u1;
+                }
+                if (i < N) s2a += xcol[i] * xcol[i];
             }
-            for (int i = k + 1 + lane; i < N; i += 64) {
-                const double v = xcol[i] * scale;
-                xcol[i] = v;
-                if (p == 0) VL[(size_t)k * N + i] = v;
+            double pw[4] = {0.0, 0.0, 0.0, 0.0}, p0 = 0.0;
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (16 * q + 15 < k) continue;  // uniform
+                const int i = g + 16 * q;
+                pw[q & 3] += (i > k && i < N) ? xcol[i] * a[q] : 0.0;
+                if (i == k) p0 = a[q];
             }
-            if (lane == 0) {
-                xcol[k] = 1.0;
-                sc[0] = tau;
-                if (p == 0) {
+            red[g][c] = (pw[0] + pw[1]) + (pw[2] + pw[3]);
+            red0[g][c] = p0;
+            double beta;
+            house(alpha, wave_sum64(s2a + s2b), tl, beta, sl);
+            if (p == 0) {
+                for (int i = k + 1 + tid; i < N; i += 512) VL[(size_t)k * N + i] = xcol[i] * sl;
+                if (tid == 0) {
                     VL[(size_t)k * N + k] = 1.0;
-                    tauL[k] = tau;
+                    tauL[k] = tl;
                     dout[k] = beta;
                 }
             }
         }
         __syncthreads();
-        const double tl = sc[0];
         if (tl != 0.0) {
-            // w_j = tau sum_{i >= k} u_i B[i][j] for own columns j > k
-            double pw[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (16 * q + 15 < k) continue;  // uniform
-                const int i = g + 16 * q;
-                pw[q & 3] += (i >= k && i < N) ? xcol[i] * a[q] : 0.0;
-            }
-            red[g][c] = (pw[0] + pw[1]) + (pw[2] + pw[3]);
-            __syncthreads();
             if (tid < 32) {
-                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0;
+                double w0 = 0.0, w1 = 0.0, w2 = 0.0, w3 = 0.0, r0 = 0.0;
 #pragma unroll
                 for (int gg = 0; gg < 16; gg += 4) {
                     w0 += red[gg][tid];
@@ -558,7 +560,9 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
                     w2 += red[gg + 2][tid];
                     w3 += red[gg + 3][tid];
                 }
-                wcol[tid] = tl * ((w0 + w1) + (w2 + w3));
+#pragma unroll
+                for (int gg = 0; gg < 16; ++gg) r0 += red0[gg][tid];  // one nonzero term
+                wcol[tid] = tl * fma(sl, (w0 + w1) + (w2 + w3), r0);
             }
             __syncthreads();
             const double wj = (jv && j > k) ? wcol[c] : 0.0;
@@ -566,7 +570,8 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
             for (int q = 0; q < NQ; ++q) {
                 if (16 * q + 15 < k) continue;
                 const int i = g + 16 * q;
-                if (i >= k && i < N) a[q] -= xcol[i] * wj;
+                const double vi = (i == k) ? 1.0 : xcol[i] * sl;
+                if (i >= k && i < N) a[q] -= vi * wj;
             }
         }
         if (k + 1 >= N) break;
@@ -622,13 +627,8 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
             const double alpha = ld_agent(cb.colpub + (size_t)slot * N + k);
             double s2 = 0.0;
             for (int q = 0; q < P; ++q) s2 += ld_agent(cb.nrm + slot * P + q);
-            double tau = 0.0, beta = alpha, scale = 0.0;
-            if (s2 > 0.0) {
-                const double nrm = sqrt(alpha * alpha + s2);
-                beta = alpha >= 0.0 ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scale = 1.0 / (alpha - beta);
-            }
+            double tau, beta, scale;
+            house(alpha, s2, tau, beta, scale);
             tq = tau;
             scl = scale;
             if (p == 0 && tid == 0) {
