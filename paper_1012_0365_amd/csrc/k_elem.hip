@@ -12,7 +12,7 @@ namespace blws {
 namespace {
 
 constexpr int TILE = 64;
-constexpr int EBK = 32;
+constexpr int EBK = 16;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
