@@ -673,6 +673,7 @@ __device__ int count_ge(int N, const double* f2, double x, double pivmin)
     double q = -x;
     if (fabs(q) < pivmin) q = -pivmin;
     neg += q < 0.0;
+#pragma unroll 8
     for (int j = 1; j < 2 * N; ++j) {
         double r = __builtin_amdgcn_rcp(q);
         r = fma(r, fma(-q, r, 1.0), r);
@@ -778,6 +779,7 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
         const double tiny = fm_s * 0x1.0p-52 + 1e-300;
         // LU of T - s I: carried (dd_j, du_j); dl_j, du_{j+1} come from f
         double ddj = -s, duj = n > 1 ? f[0] : 0.0;
+#pragma unroll 8
         for (int j = 0; j < n - 1; ++j) {
             const double dlj = f[j];
             const double dun = (j + 1 < n - 1) ? f[j + 1] : 0.0;
@@ -817,6 +819,7 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
         for (int it = 0; it < 2; ++it) {
             // forward: L^{-1} with the row interchanges, z_j carried
             double zj = z[0];
+#pragma unroll 8
             for (int j = 0; j < n - 1; ++j) {
                 const double zn = z[j + 1];
                 const double l = dl[j];
@@ -840,6 +843,7 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
                 z1 = z0;
                 mx = fmax(mx, fabs(z0));
             }
+#pragma unroll 8
             for (int j = n - 3; j >= 0; --j) {
                 const double z0 = fma(-bdu[j], z1, fma(-bdu2[j], z2, z[j] * rdd[j]));
                 z[j] = z0;
