@@ -9,6 +9,7 @@ TimedLaunch::TimedLaunch(Timer* timer, const char* family, hipStream_t s, double
     : t(timer && timer->on ? timer : nullptr), slot(-1), stream(s), fam(family)
 {
     if (!t) return;
+    std::lock_guard<std::mutex> g(t->mu);
     Timer::Family& f = t->fam[family];
     hipEvent_t a, b;
     HIP_TRY(hipEventCreate(&a));
@@ -25,6 +26,7 @@ TimedLaunch::TimedLaunch(Timer* timer, const char* family, hipStream_t s, double
 TimedLaunch::~TimedLaunch()
 {
     if (!t || slot < 0) return;
+    std::lock_guard<std::mutex> g(t->mu);
     (void)hipEventRecord(t->fam[fam].stop[slot], stream);
 }
 

@@ -37,6 +37,7 @@ inline void run_blocking(Job& job, Context& cx, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
     cx.fix_calls = 0;
+    cx.fix_calls_aux = 0;
     cx.ensure(job.workspace_bytes());
     job.start(cx, s);
     while (!job.done) {

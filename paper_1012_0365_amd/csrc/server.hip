@@ -380,6 +380,7 @@ struct blws_server_s {
                 try {
                     if (ready[i].second) {
                         sl->cx.fix_calls = 0;
+                        sl->cx.fix_calls_aux = 0;
                         sl->cx.ensure(sl->bytes);
                         sl->job->start(sl->cx, sl->stream);
                     } else {

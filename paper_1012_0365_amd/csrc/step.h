@@ -10,8 +10,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <exception>
+#include <functional>
 #include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -24,6 +30,7 @@ namespace blws {
 // ---------------------------------------------------------------------------
 struct Timer {
     bool on = false;
+    std::mutex mu;  // launches are recorded from two host threads
     struct Family {
         std::vector<hipEvent_t> start, stop;
         double flops = 0.0, bytes = 0.0;
@@ -65,6 +72,77 @@ struct Carver {
 
 struct Context;
 
+// A host thread that queues one task at a time (the second stream's half of
+// a step), so that the launches of both halves are issued concurrently.
+struct AuxWorker {
+    std::thread th;
+    std::mutex m;
+    std::condition_variable cv;
+    std::function<void()> task;
+    bool has = false, busy = false, stop = false;
+    std::exception_ptr err;
+
+    void start(int device)
+    {
+        th = std::thread([this, device] {
+            (void)hipSetDevice(device);
+            for (;;) {
+                std::function<void()> t;
+                {
+                    std::unique_lock<std::mutex> lk(m);
+                    cv.wait(lk, [&] { return has || stop; });
+                    if (!has) return;
+                    t = std::move(task);
+                    has = false;
+                }
+                std::exception_ptr e;
+                try {
+                    t();
+                } catch (...) {
+                    e = std::current_exception();
+                }
+                {
+                    std::lock_guard<std::mutex> g(m);
+                    err = e;
+                    busy = false;
+                }
+                cv.notify_all();
+            }
+        });
+    }
+    void run(std::function<void()> f)
+    {
+        {
+            std::lock_guard<std::mutex> g(m);
+            task = std::move(f);
+            has = true;
+            busy = true;
+            err = nullptr;
+        }
+        cv.notify_all();
+    }
+    // wait for the task; rethrow what it threw
+    void wait()
+    {
+        std::unique_lock<std::mutex> lk(m);
+        cv.wait(lk, [&] { return !busy; });
+        if (err) {
+            std::exception_ptr e = err;
+            err = nullptr;
+            std::rethrow_exception(e);
+        }
+    }
+    void shutdown()
+    {
+        {
+            std::lock_guard<std::mutex> g(m);
+            stop = true;
+        }
+        cv.notify_all();
+        if (th.joinable()) th.join();
+    }
+};
+
 // Rendezvous for the W-products of several solves stepping at the same time
 // (the request server): a solve hands over its products and returns once a
 // grouped launch holding them has been queued after the work already on the
@@ -82,11 +160,13 @@ struct Context {
     void* host_pinned = nullptr;  // small readback area
     std::string last_error;
     Timer timer;
-    uint64_t fix_calls = 0;  // stream ids for breakdown replacement draws
+    uint64_t fix_calls = 0;      // stream ids for breakdown replacement draws
+    uint64_t fix_calls_aux = 0;  // the same for the work on the second stream
     // second stream for independent halves of a step (default priority),
     // forked from and joined back into the caller's stream by events
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    std::unique_ptr<AuxWorker> worker;  // issues the second stream's launches
 
     void ensure_aux()
     {
@@ -94,9 +174,15 @@ struct Context {
         HIP_TRY(hipStreamCreateWithFlags(&aux, hipStreamNonBlocking));
         HIP_TRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
         HIP_TRY(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming));
+        worker.reset(new AuxWorker());
+        worker->start(device);
     }
     void release_aux()
     {
+        if (worker) {
+            worker->shutdown();
+            worker.reset();
+        }
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (aux) (void)hipStreamDestroy(aux);
@@ -273,7 +359,10 @@ void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx
         gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, cur, c, w.Ri, c, 0.0,
                            (const T*)nullptr, 0, dst, ldd, w.partial, w.partial_elems, s);
         if (pass == 0) {
-            fill_flagged<T>(rows, c, w.T2, c, w.flags, seed, (1ULL << 20) + (++cx.fix_calls), s);
+            // stream ids of the replacement draws: one sequence per stream
+            const uint64_t sid = s == cx.aux ? (1ULL << 21) + (++cx.fix_calls_aux)
+                                             : (1ULL << 20) + (++cx.fix_calls);
+            fill_flagged<T>(rows, c, w.T2, c, w.flags, seed, sid, s);
             if (nx > 0) {
                 project_out<T>(cx, w, s, rows, nx, X, ldx, bx, w.T2, c, w.T1, c);
                 cur = w.T1;
@@ -460,7 +549,8 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     // products with the start block: P = W V, Q = W^T U (the low-rank
     // coefficients of the matrix-completion operator have one buffer: there
     // Q waits for P)
-    if (cx.group && W.W) {
+    const bool grouped = cx.group && W.W;
+    if (grouped) {
         // the request server groups these with other solves' products
         const WProduct pr[2] = {dense_wproduct<T>(w, W, m, n, false, V, ldv, b, w.PH, b2),
                                 dense_wproduct<T>(wb, W, m, n, true, U, ldu, b, w.Qb, b)};
@@ -469,11 +559,30 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     } else {
         op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
         if (!W.W) cx.fork(s);
-        op_apply<T>(cx, wb, cx.aux, W, m, n, true, U, ldu, b, w.Qb, b);
     }
-    // new block: F = orth(P - U U^T P), G = orth(Q - V V^T Q)
-    orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
-    orth_against<T>(cx, wb, cx.aux, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
+    // new block: F = orth(P - U U^T P) on this thread and stream, Q = W^T U
+    // and G = orth(Q - V V^T Q) queued by the context's second host thread on
+    // the second stream, so that both streams are fed at once
+    {
+        struct Join {  // the task refers to this frame: wait for it on every path
+            AuxWorker* wk;
+            bool waited = false;
+            ~Join()
+            {
+                if (!waited) try {
+                        wk->wait();
+                    } catch (...) {
+                    }
+            }
+        } jn{cx.worker.get()};
+        cx.worker->run([&] {
+            if (!grouped) op_apply<T>(cx, wb, cx.aux, W, m, n, true, U, ldu, b, w.Qb, b);
+            orth_against<T>(cx, wb, cx.aux, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
+        });
+        orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
+        jn.waited = true;
+        cx.worker->wait();
+    }
     cx.join(s);
     // the last product of the pass: H = W G
     if (cx.group && W.W) {
