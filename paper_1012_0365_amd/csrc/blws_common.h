@@ -141,8 +141,12 @@ size_t small_svd_jacobi_scratch_elems(int N);
 // caller) is set if one of its barrier waits timed out.
 bool small_svd_gk_supported(int N);
 size_t small_svd_gk_scratch_elems(int N);
+// With a second stream s2 and two events, the blocked reflectors' T factors
+// are built on s2 (after the bidiagonalisation on s) while s finds the values
+// and vectors; s waits for them before the back-transformation.
 void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
-                  double* VB, double* scratch, int* err, hipStream_t s);
+                  double* VB, double* scratch, int* err, hipStream_t s, hipStream_t s2 = nullptr,
+                  hipEvent_t ev_a = nullptr, hipEvent_t ev_b = nullptr);
 
 // Copy a rows x cols block (types may differ).
 template <typename TS, typename TD>

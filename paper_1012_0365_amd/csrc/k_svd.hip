@@ -1109,7 +1109,8 @@ size_t small_svd_gk_scratch_elems(int N)
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
 void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB, double* S,
-                  double* VB, double* scratch, int* err, hipStream_t s)
+                  double* VB, double* scratch, int* err, hipStream_t s, hipStream_t s2,
+                  hipEvent_t ev_a, hipEvent_t ev_b)
 {
     BLWS_REQUIRE(small_svd_gk_supported(N) && nv >= 1 && nv <= N, BLWS_EUNSUPPORTED,
                  "small_svd_gk: size out of range");
@@ -1174,18 +1175,34 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         }
 #undef BLWS_GK_CASE
     }
+    // The T factors of the reflector blocks need only the reflectors: with a
+    // second stream they are built there while the values and vectors of the
+    // bidiagonal are found.
+    const int nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
+    double* Tall = VR + (size_t)N * N + 2 * (size_t)N + 2 * (size_t)((N + 31) / 32) +
+                   2 * (size_t)((N + 31) / 32) * N + 8;
+    const bool two = s2 != nullptr && ev_a != nullptr && ev_b != nullptr;
+    if (two) {
+        HIP_TRY(hipEventRecord(ev_a, s));
+        HIP_TRY(hipStreamWaitEvent(s2, ev_a, 0));
+        TimedLaunch tl(tm, "wy_t", s2, 0.0, 0.0);
+        hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s2, N, VL, tL, VR, tR, Tall);
+        HIP_TRY(hipEventRecord(ev_b, s2));
+    }
     {
         TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
         hipLaunchKernelGGL(tgk_bisect_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S);
         hipLaunchKernelGGL(tgk_invit_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S, UB, VB, N);
     }
+    if (two) {
+        HIP_TRY(hipStreamWaitEvent(s, ev_b, 0));
+    } else {
+        TimedLaunch tl(tm, "wy_t", s, 0.0, 0.0);
+        hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, N, VL, tL, VR, tR, Tall);
+    }
     {
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
-        const int nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
-        double* Tall = VR + (size_t)N * N + 2 * (size_t)N + 2 * (size_t)((N + 31) / 32) +
-                       2 * (size_t)((N + 31) / 32) * N + 8;
-        hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s, N, VL, tL, VR, tR, Tall);
         if (N <= 256)
             hipLaunchKernelGGL((backtransform_kernel<256, 4>), dim3(blocks), dim3(256), 0, s, N,
                                nv, VL, VR, Tall, UB, VB, N);

@@ -420,7 +420,9 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
 {
     TimedLaunch tl(&cx.timer, "small_svd", s, 0.0, 0.0);
     if (small_svd_gk_supported(N)) {
-        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s);
+        cx.ensure_aux();  // the reflector blocks' T factors go on the second stream
+        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s, cx.aux,
+                     cx.ev_fork, cx.ev_join);
         if (cholqr2_small_supported(N, nv)) {
             const uint64_t sid0 = (1ULL << 20) + (++cx.fix_calls);
             const uint64_t sid1 = (1ULL << 20) + (++cx.fix_calls);
