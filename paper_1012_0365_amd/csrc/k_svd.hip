@@ -659,78 +659,228 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
     }
 }
 
-// Number of singular values of the bidiagonal (d, e) that are >= x (x > 0),
-// from the Sturm count of the Golub-Kahan tridiagonal T (zero diagonal,
-// off-diagonals f2 squared): #{eig(T) < x} = N + #{sigma < x}. The LDL^T
-// recurrence q_j = -x - f_{j-1}^2 / q_{j-1} counts negative pivots.
-// The quotient f2 / q is taken as f2 r with r = 1 / q from the hardware
-// estimate (relative error ~5e-8) refined by one Newton step (~2e-15): the
-// count is then exact for T with its f_j^2 perturbed by a few units in the
-// 15th digit, far inside the accuracy the values are found to.
-__device__ int count_ge(int N, const double* f2, double x, double pivmin)
+// The recurrences below read their operands from LDS in blocks of eight,
+// alternating between two register sets: the loads of one block are issued
+// before the previous block is computed. A compiler barrier right after them
+// keeps them there (otherwise they are folded into loads at their use, each
+// waited on in turn).
+__device__ __forceinline__ void loads_issued() { asm volatile("" ::: "memory"); }
+
+// Number of singular values of the upper bidiagonal B = (d, e) below sqrt(tau),
+// by the differential stationary qd transform of B^T B - tau I = L D L^T
+// carried on the squared entries q_i = d_i^2, ee_i = e_i^2 (B^T B is never
+// formed): from s_0 = -tau,
+//   D_i = q_i + s_i,    s_{i+1} = ee_i s_i / D_i - tau,
+// and by Sylvester's law of inertia the number of negative D_i is the number
+// of eigenvalues of B^T B below tau. The transform is exact for entries
+// perturbed by a few units in the last place, so the count carries the
+// relative accuracy of the bidiagonal's values, at half the length of the
+// Sturm sequence of the Golub-Kahan tridiagonal. 1 / D is the hardware
+// estimate (relative error ~5e-8) refined by one Newton step (~2e-15), which
+// again perturbs ee_i in the 15th digit only.
+__device__ __forceinline__ void qd_block(const double2 (&c)[8], double& s, int& neg, double tau,
+                                         double pivmin)
 {
-    int neg = 0;
-    double q = -x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    neg += q < 0.0;
-#pragma unroll 8
-    for (int j = 1; j < 2 * N; ++j) {
-        double r = __builtin_amdgcn_rcp(q);
-        r = fma(r, fma(-q, r, 1.0), r);
-        q = fma(-f2[j - 1], r, -x);
-        if (fabs(q) < pivmin) q = -pivmin;
-        neg += q < 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        double D = c[u].x + s;
+        D = fabs(D) < pivmin ? -pivmin : D;
+        neg += D < 0.0;
+        double r = __builtin_amdgcn_rcp(D);
+        r = fma(r, fma(-D, r, 1.0), r);
+        s = fma(c[u].y * s, r, -tau);
     }
-    return 2 * N - neg;  // = N - #{sigma < x}
 }
 
-// One workgroup of BS_PTS threads per singular value: sigma_t, the t-th
-// largest, by multisection with BS_PTS Sturm counts per step.
-constexpr int BS_PTS = 256;
-__global__ __launch_bounds__(BS_PTS) void tgk_bisect_kernel(int N, const double* __restrict__ d,
-                                                            const double* __restrict__ e,
-                                                            double* __restrict__ sig)
+// qe holds (q_i, ee_i) for i < N with ee_{N-1} = 0, then at least 23 pad
+// pairs (4, 0) that are never counted (the entries are scaled below 1, so
+// tau < 1 and 4 - tau > 0).
+__device__ __forceinline__ int count_below(int N, const double2* __restrict__ qe, double tau,
+                                           double pivmin)
 {
-    __shared__ double f2[2 * SVD_MAXN];
-    __shared__ int cnt[BS_PTS];
-    __shared__ double bnd[2];
-    __shared__ int best_s;
-    const int t = blockIdx.x, lane = threadIdx.x;
-    for (int j = lane; j < 2 * N - 1; j += BS_PTS) {
-        const double f = (j & 1) ? e[j >> 1] : d[j >> 1];
-        f2[j] = f * f;
+    int neg = 0;
+    double s = -tau;
+    double2 a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] = qe[u];
+    for (int i0 = 0; i0 < N; i0 += 16) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = qe[i0 + 8 + u];
+        loads_issued();
+        qd_block(a, s, neg, tau, pivmin);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = qe[i0 + 16 + u];
+        loads_issued();
+        qd_block(b, s, neg, tau, pivmin);
     }
+    return neg;
+}
+
+// One inverse-iteration factor row: the multiplier of L, and U's row divided
+// by its diagonal.
+struct InvFac {
+    double dl, rdd, bdu, bdu2;
+};
+
+// One step of the LU factorisation with partial pivoting of the tridiagonal
+// T - s I (zero diagonal, off-diagonals f): rows j and j + 1 of the active
+// part are (.. ddj duj 0 ..) and (.. dlj -s dun ..). The pivot is the larger
+// of ddj, dlj; a pivot below `tiny` in magnitude is taken as +-tiny. A row
+// interchange gives U a second superdiagonal. The quotient uses the hardware
+// reciprocal refined by one Newton step; the stored 1 / u_jj by two.
+// Beyond the last row (dlj = dun = 0) a step stores 1 / u_jj of the last row
+// and zero multipliers, and leaves ddj = -s.
+__device__ __forceinline__ void lu_step(double& ddj, double& duj, double dlj, double dun,
+                                        double s, double tiny, InvFac& o, unsigned char& sw)
+{
+    const bool swp = fabs(ddj) < fabs(dlj);
+    const double piv = swp ? dlj : ddj;
+    const double oth = swp ? ddj : dlj;
+    const double pc = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+    double r = __builtin_amdgcn_rcp(pc);
+    r = fma(r, fma(-pc, r, 1.0), r);
+    const double fact = oth * r;
+    const double odu = swp ? -s : duj;
+    const double odu2 = swp ? dun : 0.0;
+    const double ndd = swp ? fma(fact, s, duj) : fma(-fact, duj, -s);
+    duj = swp ? -fact * dun : dun;
+    ddj = ndd;
+    const double rd = fma(r, fma(-pc, r, 1.0), r);
+    o.dl = fact;
+    o.rdd = rd;
+    o.bdu = odu * rd;
+    o.bdu2 = odu2 * rd;
+    sw = swp;
+}
+
+template <int B0>
+__device__ __forceinline__ void lu_block(double& ddj, double& duj, const double (&fw)[9], double s,
+                                         double tiny, InvFac* fac, unsigned char* swp)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u) lu_step(ddj, duj, fw[u], fw[u + 1], s, tiny, fac[B0 + u], swp[B0 + u]);
+}
+
+// Forward substitution with L (row interchanges as recorded), z_j carried;
+// zn holds z_{j+1} before it is overwritten, scaled by `inv` on use.
+__device__ __forceinline__ void fwd_block(double& zj, const double (&zn)[8], const double (&l)[8],
+                                          const unsigned char (&sw)[8], double inv, double* z)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double znx = zn[u] * inv;
+        const double out = sw[u] ? znx : zj;
+        const double oth = sw[u] ? zj : znx;
+        z[u] = out;
+        zj = fma(-l[u], out, oth);
+    }
+}
+
+// Back substitution, rows j, j - 1, ..., j - 7 with z_{j+1}, z_{j+2} carried:
+// z_j = z_j / u_jj - (u_j,j+1 / u_jj) z_{j+1} - (u_j,j+2 / u_jj) z_{j+2}.
+__device__ __forceinline__ void bwd_block(double& z1, double& z2, const InvFac (&c)[8],
+                                          const double (&zc)[8], double* z)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double z0 = fma(-c[u].bdu, z1, fma(-c[u].bdu2, z2, zc[u] * c[u].rdd));
+        z[-u] = z0;
+        z2 = z1;
+        z1 = z0;
+    }
+}
+
+// Singular value sigma_t (the t-th largest) of the bidiagonal (d, e) and its
+// left and right singular vectors, one workgroup per value.
+//  - Values: multisection on [0, Gershgorin bound] with BS_PTS Sturm counts
+//    per step (count_below), to relative precision 2u (absolute u ||B|| near
+//    zero). The entries are first scaled by a power of two to below 1.
+//  - Vectors: inverse iteration on the Golub-Kahan tridiagonal T (zero
+//    diagonal, off-diagonals (d_0, e_0, d_1, e_1, ...)) at +sigma_t: the LU
+//    factorisation of T - sigma I, then two solves from the counter-based
+//    start vector, rescaled to max |z| = 1 in between. The eigenvector
+//    z = (v_0, u_0, v_1, u_1, ...) splits into the right and left singular
+//    vectors, each normalised.
+// The factorisation and the solves are recurrences run by one thread in
+// blocks of eight steps. Blocks run past the ends of the n = 2N rows into
+// padding (zero off-diagonals above, an offset of TG_OFF rows below); n is
+// even, so the factorisation's blocks always include its step n - 1, which
+// stores the last 1 / u_jj.
+constexpr int BS_PTS = 256;
+constexpr int TG_PAD = 24;
+constexpr int TG_OFF = 24;
+struct TgkShared {
+    union {
+        double2 qe[SVD_MAXN + TG_PAD];                     // multisection
+        InvFac fac[TG_OFF + 2 * SVD_MAXN + TG_PAD];        // LU factors, row j at TG_OFF + j
+    };
+    double f[2 * SVD_MAXN + TG_PAD];                       // scaled off-diagonals, zero beyond
+    double z[TG_OFF + 2 * SVD_MAXN + TG_PAD];              // row j at TG_OFF + j
+    unsigned char swp[TG_OFF + 2 * SVD_MAXN + TG_PAD];
+    int cnt[BS_PTS];
+    double red[BS_PTS / 64];
+    int best;
+};
+
+__global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* __restrict__ d,
+                                                           const double* __restrict__ e,
+                                                           double* __restrict__ sig,
+                                                           double* __restrict__ ubd,
+                                                           double* __restrict__ vbd, int ldv)
+{
+    __shared__ TgkShared sh;
+    const int t = blockIdx.x, tid = threadIdx.x, lane = tid & 63;
+    const int n = 2 * N;
+    // Gershgorin bound of T: max_j |f_{j-1}| + |f_j|
+    double gb = 0.0;
+    for (int j = tid; j < n; j += BS_PTS) {
+        const double l = j > 0 ? fabs(((j - 1) & 1) ? e[(j - 1) >> 1] : d[(j - 1) >> 1]) : 0.0;
+        const double r = j < n - 1 ? fabs((j & 1) ? e[j >> 1] : d[j >> 1]) : 0.0;
+        gb = fmax(gb, l + r);
+    }
+    for (int off = 32; off > 0; off >>= 1) gb = fmax(gb, __shfl_xor(gb, off, 64));
+    if (lane == 0) sh.red[tid >> 6] = gb;
     __syncthreads();
-    if (lane == 0) {
-        double fmax2 = 0.0, bound = 0.0;
-        for (int j = 0; j < 2 * N - 1; ++j) fmax2 = fmax(fmax2, f2[j]);
-        // Gershgorin bound of T: max_j |f_{j-1}| + |f_j|
-        for (int j = 0; j < 2 * N; ++j) {
-            const double l = j > 0 ? sqrt(f2[j - 1]) : 0.0;
-            const double r = j < 2 * N - 1 ? sqrt(f2[j]) : 0.0;
-            bound = fmax(bound, l + r);
+    double bound = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS_PTS / 64; ++w) bound = fmax(bound, sh.red[w]);
+    if (!(bound > 0.0)) {  // B = 0: the value and the vectors are zero
+        if (tid == 0) sig[t] = 0.0;
+        for (int i = tid; i < N; i += BS_PTS) {
+            ubd[(size_t)i * ldv + t] = 0.0;
+            vbd[(size_t)i * ldv + t] = 0.0;
         }
-        bnd[0] = fmax2;
-        bnd[1] = bound;
+        return;
     }
+    int ex;
+    frexp(bound, &ex);
+    const double sc = ldexp(1.0, -ex);  // bound * sc in [0.5, 1)
+    const double bs = bound * sc;
+    for (int j = tid; j < N + TG_PAD; j += BS_PTS) {
+        double2 v = make_double2(4.0, 0.0);
+        if (j < N) {
+            const double dj = d[j] * sc, ej = j < N - 1 ? e[j] * sc : 0.0;
+            v = make_double2(dj * dj, ej * ej);
+        }
+        sh.qe[j] = v;
+    }
+    for (int j = tid; j < n + TG_PAD; j += BS_PTS)
+        sh.f[j] = j < n - 1 ? ((j & 1) ? e[j >> 1] : d[j >> 1]) * sc : 0.0;
     __syncthreads();
-    const double fmax2 = bnd[0], bound = bnd[1];
-    const double pivmin = 2.2250738585072014e-308 * fmax(1.0, fmax2);
-    double lo = 0.0, hi = bound * (1.0 + 4.0 * 0x1.0p-52) + pivmin;
+    constexpr double U = 0x1.0p-52;
+    constexpr double PIVMIN = 0x1.0p-1000;
+    double lo = 0.0, hi = bs * (1.0 + 4.0 * U) + 0x1.0p-1000;
     // invariant: #{sigma >= lo} >= t + 1 (lo = 0 counts every value), #{sigma >= hi} <= t
     for (int step = 0; step < 16; ++step) {
-        // relative precision 2u, or absolute u * ||T|| for values near zero
-        if (hi - lo <= 2.0 * 0x1.0p-52 * fmax(fabs(lo), fabs(hi)) + pivmin ||
-            hi - lo <= 0x1.0p-52 * bound)
-            break;
-        const double x = lo + (hi - lo) * (double)(lane + 1) / (double)(BS_PTS + 1);
-        cnt[lane] = count_ge(N, f2, x, pivmin);
-        if (lane == 0) best_s = -1;
+        if (hi - lo <= 2.0 * U * hi || hi - lo <= U * bs) break;
+        const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BS_PTS + 1);
+        sh.cnt[tid] = N - count_below(N, sh.qe, x * x, PIVMIN);
+        if (tid == 0) sh.best = -1;
         __syncthreads();
         // the last point still holding >= t + 1 values
-        if (cnt[lane] >= t + 1) atomicMax(&best_s, lane);
+        if (sh.cnt[tid] >= t + 1) atomicMax(&sh.best, tid);
         __syncthreads();
-        const int best = best_s;
+        const int best = sh.best;
         const double nlo = best >= 0 ? lo + (hi - lo) * (double)(best + 1) / (double)(BS_PTS + 1) : lo;
         const double nhi = best < BS_PTS - 1
                                ? lo + (hi - lo) * (double)(best + 2) / (double)(BS_PTS + 1)
@@ -740,125 +890,116 @@ __global__ __launch_bounds__(BS_PTS) void tgk_bisect_kernel(int N, const double*
         __syncthreads();
     }
     // a value the bracket cannot separate from zero is reported as zero
-    const bool zero = lo == 0.0 && hi <= 8.0 * 0x1.0p-52 * bound + 4.0 * pivmin;
-    if (lane == 0) sig[t] = zero ? 0.0 : 0.5 * (lo + hi);
-}
+    const bool zero = lo == 0.0 && hi <= 8.0 * U * bs;
+    const double ss = zero ? 0.0 : 0.5 * (lo + hi);  // sigma_t, scaled
+    if (tid == 0) sig[t] = ss / sc;
 
-// Inverse iteration for the eigenvector of T at +sigma_t: LU factorisation
-// with partial pivoting of the tridiagonal T - sigma I (row interchanges give
-// U a second superdiagonal), then two solves from the counter-based start
-// vector, normalising each time. The eigenvector z = (v0, u0, v1, u1, ...)
-// splits into the bidiagonal's right and left singular vectors. One wavefront
-// per value; the recurrences run on lane 0 with their carried values in
-// registers, the factors in LDS.
-__global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __restrict__ d,
-                                                       const double* __restrict__ e,
-                                                       const double* __restrict__ sig,
-                                                       double* __restrict__ ubd,
-                                                       double* __restrict__ vbd, int ldv)
-{
-    __shared__ double f[2 * SVD_MAXN];
-    __shared__ double z[2 * SVD_MAXN], dl[2 * SVD_MAXN], rdd[2 * SVD_MAXN], bdu[2 * SVD_MAXN],
-        bdu2[2 * SVD_MAXN];
-    __shared__ unsigned char swp[2 * SVD_MAXN];
-    __shared__ double fm_s;
-    const int t = blockIdx.x, lane = threadIdx.x;
-    const int n = 2 * N;
-    const double s = sig[t];
-    double fm = 0.0;
-    for (int j = lane; j < n - 1; j += 64) {
-        const double v = (j & 1) ? e[j >> 1] : d[j >> 1];
-        f[j] = v;
-        fm = fmax(fm, fabs(v));
-    }
-    for (int j = lane; j < n; j += 64) z[j] = start_pm1((uint64_t)t * 4096ULL + (uint64_t)j);
-    for (int off = 32; off > 0; off >>= 1) fm = fmax(fm, __shfl_xor(fm, off, 64));
-    if (lane == 0) fm_s = fmax(fm, fabs(s));
+    // ---- inverse iteration at +ss on the scaled T (qe is dead from here)
+    double* const z = sh.z + TG_OFF;
+    InvFac* const fac = sh.fac + TG_OFF;
+    unsigned char* const swp = sh.swp + TG_OFF;
+    for (int j = tid - TG_OFF; j < n + TG_PAD; j += BS_PTS)
+        z[j] = (j >= 0 && j < n) ? start_pm1((uint64_t)t * 4096ULL + (uint64_t)j) : 0.0;
     __syncthreads();
-    if (lane == 0) {
-        const double tiny = fm_s * 0x1.0p-52 + 1e-300;
-        // LU of T - s I: carried (dd_j, du_j); dl_j, du_{j+1} come from f
-        double ddj = -s, duj = n > 1 ? f[0] : 0.0;
-#pragma unroll 8
-        for (int j = 0; j < n - 1; ++j) {
-            const double dlj = f[j];
-            const double dun = (j + 1 < n - 1) ? f[j + 1] : 0.0;
-            double odd, odu, odu2 = 0.0, fact;
-            unsigned char osw;
-            if (fabs(ddj) >= fabs(dlj)) {
-                fact = ddj != 0.0 ? dlj / ddj : 0.0;
-                osw = 0;
-                odd = ddj;
-                odu = duj;
-                ddj = -s - fact * duj;
-                duj = dun;
-            } else {
-                fact = ddj / dlj;
-                osw = 1;
-                odd = dlj;
-                odu = -s;
-                ddj = duj + fact * s;
-                if (j < n - 2) {
-                    odu2 = dun;
-                    duj = -fact * dun;
-                } else {
-                    duj = dun;
-                }
-            }
-            // U's row j divided by its diagonal: the back substitution is then
-            // one multiply-add per element on its dependence chain
-            const double ddc = fabs(odd) < tiny ? (odd < 0.0 ? -tiny : tiny) : odd;
-            const double rd = 1.0 / ddc;
-            rdd[j] = rd;
-            bdu[j] = odu * rd;
-            bdu2[j] = odu2 * rd;
-            dl[j] = fact;
-            swp[j] = osw;
+    if (tid == 0) {
+        const double tiny = bs * U + 1e-300;
+        double ddj = -ss, duj = sh.f[0];
+        double fa[9], fb[9];
+#pragma unroll
+        for (int u = 0; u < 9; ++u) fa[u] = sh.f[u];
+        for (int j0 = 0; j0 < n - 1; j0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 9; ++u) fb[u] = sh.f[j0 + 8 + u];
+            loads_issued();
+            lu_block<0>(ddj, duj, fa, ss, tiny, fac + j0, swp + j0);
+#pragma unroll
+            for (int u = 0; u < 9; ++u) fa[u] = sh.f[j0 + 16 + u];
+            loads_issued();
+            lu_block<8>(ddj, duj, fb, ss, tiny, fac + j0, swp + j0);
         }
-        rdd[n - 1] = 1.0 / (fabs(ddj) < tiny ? (ddj < 0.0 ? -tiny : tiny) : ddj);
-        for (int it = 0; it < 2; ++it) {
-            // forward: L^{-1} with the row interchanges, z_j carried
-            double zj = z[0];
-#pragma unroll 8
-            for (int j = 0; j < n - 1; ++j) {
-                const double zn = z[j + 1];
-                const double l = dl[j];
-                if (!swp[j]) {
-                    z[j] = zj;
-                    zj = zn - l * zj;
-                } else {
-                    z[j] = zn;
-                    zj = zj - l * zn;
+    }
+    for (int it = 0; it < 2; ++it) {
+        __syncthreads();
+        double inv = 1.0;
+        if (it > 0) {  // the previous solve's scale, 1 / max |z|
+            double m = 0.0;
+            for (int j = tid; j < n; j += BS_PTS) m = fmax(m, fabs(z[j]));
+            for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+            if (lane == 0) sh.red[tid >> 6] = m;
+            __syncthreads();
+            m = 0.0;
+#pragma unroll
+            for (int w = 0; w < BS_PTS / 64; ++w) m = fmax(m, sh.red[w]);
+            inv = m > 0.0 ? 1.0 / m : 0.0;
+        }
+        if (tid == 0) {
+            // forward: z_j for j = 0 .. n - 2; the step at n - 1 (no
+            // interchange, zero multiplier) stores the carried value as z_{n-1}
+            double zj = z[0] * inv;
+            {
+                double za[8], la[8], zb[8], lb[8];
+                unsigned char sa[8], sb[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    za[u] = z[u + 1];
+                    la[u] = fac[u].dl;
+                    sa[u] = swp[u];
+                }
+                for (int j0 = 0; j0 < n - 1; j0 += 16) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        zb[u] = z[j0 + 9 + u];
+                        lb[u] = fac[j0 + 8 + u].dl;
+                        sb[u] = swp[j0 + 8 + u];
+                    }
+                    loads_issued();
+                    fwd_block(zj, za, la, sa, inv, z + j0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        za[u] = z[j0 + 17 + u];
+                        la[u] = fac[j0 + 16 + u].dl;
+                        sa[u] = swp[j0 + 16 + u];
+                    }
+                    loads_issued();
+                    fwd_block(zj, zb, lb, sb, inv, z + j0 + 8);
                 }
             }
-            // back substitution, z_{j+1}, z_{j+2} carried:
-            // z_j = z_j / u_jj - (u_j,j+1 / u_jj) z_{j+1} - (u_j,j+2 / u_jj) z_{j+2}
-            double z1 = zj * rdd[n - 1], z2 = 0.0;
+            // back substitution from row n - 1 down; rows below 0 land in the
+            // offset and are ignored
+            double z1 = z[n - 1] * fac[n - 1].rdd, z2 = 0.0;
             z[n - 1] = z1;
-            double mx = fabs(z1);
-            if (n >= 2) {
-                const double z0 = fma(-bdu[n - 2], z1, z[n - 2] * rdd[n - 2]);
-                z[n - 2] = z0;
-                z2 = z1;
-                z1 = z0;
-                mx = fmax(mx, fabs(z0));
+            {
+                InvFac ca[8], cb[8];
+                double ya[8], yb[8];
+                int k0 = n - 2;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    ca[u] = fac[k0 - u];
+                    ya[u] = z[k0 - u];
+                }
+                for (; k0 >= 0; k0 -= 16) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        cb[u] = fac[k0 - 8 - u];
+                        yb[u] = z[k0 - 8 - u];
+                    }
+                    loads_issued();
+                    bwd_block(z1, z2, ca, ya, z + k0);
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        ca[u] = fac[k0 - 16 - u];
+                        ya[u] = z[k0 - 16 - u];
+                    }
+                    loads_issued();
+                    bwd_block(z1, z2, cb, yb, z + k0 - 8);
+                }
             }
-#pragma unroll 8
-            for (int j = n - 3; j >= 0; --j) {
-                const double z0 = fma(-bdu[j], z1, fma(-bdu2[j], z2, z[j] * rdd[j]));
-                z[j] = z0;
-                z2 = z1;
-                z1 = z0;
-                mx = fmax(mx, fabs(z0));
-            }
-            const double inv = mx > 0.0 ? 1.0 / mx : 0.0;
-            for (int j = 0; j < n; ++j) z[j] *= inv;
         }
     }
     __syncthreads();
     // split and normalise each half to unit length
     double nu = 0.0, nv = 0.0;
-    for (int i = lane; i < N; i += 64) {
+    for (int i = tid; i < N; i += BS_PTS) {
         nv += z[2 * i] * z[2 * i];
         nu += z[2 * i + 1] * z[2 * i + 1];
     }
@@ -866,11 +1007,22 @@ __global__ __launch_bounds__(64) void tgk_invit_kernel(int N, const double* __re
         nu += __shfl_xor(nu, off, 64);
         nv += __shfl_xor(nv, off, 64);
     }
-    nu = nu > 0.0 ? 1.0 / sqrt(nu) : 0.0;
-    nv = nv > 0.0 ? 1.0 / sqrt(nv) : 0.0;
-    for (int i = lane; i < N; i += 64) {
-        vbd[(size_t)i * ldv + t] = z[2 * i] * nv;
-        ubd[(size_t)i * ldv + t] = z[2 * i + 1] * nu;
+    if (lane == 0) sh.red[tid >> 6] = nu;
+    __syncthreads();
+    double su = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS_PTS / 64; ++w) su += sh.red[w];
+    __syncthreads();
+    if (lane == 0) sh.red[tid >> 6] = nv;
+    __syncthreads();
+    double sv = 0.0;
+#pragma unroll
+    for (int w = 0; w < BS_PTS / 64; ++w) sv += sh.red[w];
+    const double ru = su > 0.0 ? 1.0 / sqrt(su) : 0.0;
+    const double rv = sv > 0.0 ? 1.0 / sqrt(sv) : 0.0;
+    for (int i = tid; i < N; i += BS_PTS) {
+        vbd[(size_t)i * ldv + t] = z[2 * i] * rv;
+        ubd[(size_t)i * ldv + t] = z[2 * i + 1] * ru;
     }
 }
 
@@ -1191,8 +1343,7 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     }
     {
         TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
-        hipLaunchKernelGGL(tgk_bisect_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S);
-        hipLaunchKernelGGL(tgk_invit_kernel, dim3(nv), dim3(64), 0, s, N, d, e, S, UB, VB, N);
+        hipLaunchKernelGGL(tgk_solve_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S, UB, VB, N);
     }
     if (two) {
         HIP_TRY(hipStreamWaitEvent(s, ev_b, 0));
