@@ -152,10 +152,24 @@ struct GkShared {
     double zs[GK_MAXN];      // B v of the right reflection (without tau), rows > k
     double sx[16 * 16];      // row k beyond k + 1, per half-wavefront: its own columns only
     double srk[16 * 16];     // row k before the left reflection, per half-wavefront
-    double sq[16 * 16];      // column sums of the left reflection, per half-wavefront
+    double sw[16 * 16];      // weights of the left update, per half-wavefront
     double pn[8];            // per-wavefront partial sums of squares of row k
     double ax;               // B[k][k + 1] after the left reflection
 };
+
+// Row stores of the reflectors go through buffer resources: the per-lane
+// part of the address is then a 32-bit offset, and no 64-bit per-lane pointer
+// is held in registers beside the matrix tile. Stores beyond n elements are
+// dropped by the hardware range check.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(double* p, int n)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(p, (short)0, n * 8, 0x00020000);
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int idx, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, idx * 8, 0, 0);
+}
 
 struct GkOut {
     int N;
@@ -184,8 +198,25 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
         constexpr int KA = KC / 2;
         const int N = o.N;
         const int tid = threadIdx.x, lane = tid & 63, tr = tid & 31, tc = tid >> 5;
+        const __amdgpu_buffer_rsrc_t rVL = buf_rsrc(o.VL, N * N), rVR = buf_rsrc(o.VR, N * N);
         const int kend = min(16 * KC + 16, N);
         for (int k = 16 * KC; k < kend; ++k) {
+            // Lane tests against step k. Here 16 KC <= k < 16 KC + 16, so
+            // only column groups KC, KC + 1 and row group KA can straddle the
+            // boundary; the tests are written so (once the loops over c and
+            // a are unrolled) the others fold to constants and no per-column
+            // index is kept in a register.
+            const int kr = k - 16 * KC;  // 0 .. 15
+            const int kq = k - 32 * KA;  // 0 .. 31
+            auto row_gt = [&](int a) { return a == KA ? tr > kq : true; };          // i > k
+            auto row_eq = [&](int a) { return a == KA && tr == kq; };              // i == k
+            auto col_gt = [&](int c) { return c == KC ? tc > kr : true; };         // j > k
+            auto col_ge2 = [&](int c) {                                           // j >= k + 2
+                return c == KC ? tc >= kr + 2 : (c == KC + 1 ? tc >= kr - 14 : true);
+            };
+            auto col_eq1 = [&](int c) {                                           // j == k + 1
+                return c == KC ? tc == kr + 1 : (c == KC + 1 && tc == kr - 15);
+            };
             // ---- left reflection of column k
             const double alphaL = sh.xc[k];
             double s2a = 0.0, s2b = 0.0;
@@ -198,9 +229,12 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
                 }
                 if (i < N) s2a += sh.xc[i] * sh.xc[i];
             }
+            // the reflector needs only column k
+            double tauLk, betaL, scaleL;
+            house(alphaL, wave_sum64(s2a + s2b), tauLk, betaL, scaleL);
             // the owner of row k in each half-wavefront hands its entries to the
-            // other lanes through the half-wavefront's own LDS row (read back
-            // by the same wavefront, in order)
+            // lanes that finish the column sums, through the half-wavefront's
+            // own LDS row (read back by the same wavefront, in order)
             if (tr == (k & 31)) {
 #pragma unroll
                 for (int c = KC; c < NPC; ++c) sh.srk[tc * 16 + c] = Br[KA][c];
@@ -208,11 +242,14 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
             double xa[NPR];
 #pragma unroll
             for (int a = KA; a < NPR; ++a)  // rows > k (xc is zero beyond N)
-                xa[a] = (tr > k - 32 * a) ? sh.xc[tr + 32 * a] : 0.0;
+                xa[a] = row_gt(a) ? sh.xc[tr + 32 * a] : 0.0;
+            // Column sums q_j = sum_{i > k} xc_i B_ij, four columns at a time;
+            // lane 4 u of the first row then holds q for column g + u and forms
+            // that column's weight w_j = tau (B_kj + scale q_j) of the left
+            // update (zero for j <= k), row k after the update (x_j, kept for
+            // j >= k + 2) and, for j = k + 1, the right reflector's alpha.
 #pragma unroll
             for (int g = KC; g < NPC; g += 4) {
-                // four columns at a time; lane 4 j of the first row then holds
-                // the sum of column g + j
                 double v[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -224,68 +261,64 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
                 }
                 const double q4 = quad_col_sum(v);
                 const int l16 = tr & 15;
-                if (tr < 16 && (l16 & 3) == 0 && g + (l16 >> 2) < NPC)
-                    sh.sq[tc * 16 + g + (l16 >> 2)] = q4;
+                const int c = g + (l16 >> 2);
+                if (tr < 16 && (l16 & 3) == 0 && c < NPC) {
+                    const double rk = sh.srk[tc * 16 + c];  // B[k][j]
+                    const double wj = col_gt(c) ? tauLk * (rk + scaleL * q4) : 0.0;
+                    const double xk = rk - wj;
+                    sh.sw[tc * 16 + c] = wj;
+                    sh.sx[tc * 16 + c] = col_ge2(c) ? xk : 0.0;
+                    if (col_eq1(c)) sh.ax = xk;
+                }
             }
-            double tauLk, betaL, scaleL;
-            house(alphaL, wave_sum64(s2a + s2b), tauLk, betaL, scaleL);
-            if (tid > k && tid < N) o.VL[(size_t)k * N + tid] = sh.xc[tid] * scaleL;
+            if (tid > k && tid < N) buf_st(rVL, k * N + tid, sh.xc[tid] * scaleL);
             if (tid == k) {
                 o.VL[(size_t)k * N + k] = 1.0;
                 o.tauL[k] = tauLk;
                 o.d[k] = betaL;
             }
-            double va[NPR];
+            // left update B <- B - v w^T over rows > k (row k: v = 1)
 #pragma unroll
-            for (int a = KA; a < NPR; ++a) va[a] = (tr == k - 32 * a) ? 1.0 : xa[a] * scaleL;
-            double axv = 0.0;
+            for (int a = KA; a < NPR; ++a) xa[a] = row_eq(a) ? 1.0 : xa[a] * scaleL;
 #pragma unroll
             for (int c = KC; c < NPC; ++c) {  // column j = tc + 16 c; zero beyond N
-                const double rk = sh.srk[tc * 16 + c];  // B[k][j]
-                const double wj =
-                    (tc > k - 16 * c) ? tauLk * (rk + scaleL * sh.sq[tc * 16 + c]) : 0.0;
+                const double wj = sh.sw[tc * 16 + c];
 #pragma unroll
-                for (int a = KA; a < NPR; ++a) Br[a][c] -= va[a] * wj;
-                const double xk = rk - wj;  // row k after the reflection
-                if (tr == 0) sh.sx[tc * 16 + c] = (tc >= k + 2 - 16 * c) ? xk : 0.0;
-                if (tc == k + 1 - 16 * c) axv = xk;
+                for (int a = KA; a < NPR; ++a) Br[a][c] -= xa[a] * wj;
             }
             if (k + 1 >= N) break;
             // ---- right reflection of row k: partial sums, column k + 1
             // (sx is private to the half-wavefront: written and read back by
             // the same wavefront, in order)
             {
-                double xr[NPC];
-#pragma unroll
-                for (int c = KC; c < NPC; ++c) xr[c] = sh.sx[tc * 16 + c];
-                double pa = 0.0, pb = 0.0;
-#pragma unroll
-                for (int c = KC; c < NPC; ++c) {
-                    if ((c - KC) & 1)
-                        pb += xr[c] * xr[c];
-                    else
-                        pa += xr[c] * xr[c];
-                }
-                const double pnh = halves_sum(pa + pb);
-                if (lane == 0) sh.pn[tid >> 6] = pnh;
                 if (tc == ((k + 1) & 15)) {
-                    if (tr == 0) sh.ax = axv;
                     const bool next = (k & 15) == 15;
 #pragma unroll
                     for (int a = KA; a < NPR; ++a) {
                         double v = Br[a][KC];
                         if constexpr (KC + 1 < NPC)
                             if (next) v = Br[a][KC + 1];
-                        if (tr > k - 32 * a) sh.cp[tr + 32 * a] = v;
+                        if (row_gt(a)) sh.cp[tr + 32 * a] = v;
                     }
                 }
+                // row k's entries are read as they are used (not held in
+                // registers beside the tile)
                 double acc[NPR];
 #pragma unroll
                 for (int a = KA; a < NPR; ++a) acc[a] = 0.0;
+                double pa = 0.0, pb = 0.0;
 #pragma unroll
-                for (int c = KC; c < NPC; ++c)
+                for (int c = KC; c < NPC; ++c) {
+                    const double x = sh.sx[tc * 16 + c];
+                    if ((c - KC) & 1)
+                        pb += x * x;
+                    else
+                        pa += x * x;
 #pragma unroll
-                    for (int a = KA; a < NPR; ++a) acc[a] += Br[a][c] * xr[c];
+                    for (int a = KA; a < NPR; ++a) acc[a] += Br[a][c] * x;
+                }
+                const double pnh = halves_sum(pa + pb);
+                if (lane == 0) sh.pn[tid >> 6] = pnh;
 #pragma unroll
                 for (int a = KA; a < NPR; ++a) {
                     const double t = halves_sum(acc[a]);
@@ -302,7 +335,7 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
             }
             if (tr < NPC - KC) {  // lane tr stores column tc + 16 (KC + tr) of row k
                 const int j = tc + 16 * (KC + tr);
-                if (j >= k + 2 && j < N) o.VR[(size_t)k * N + j] = sh.sx[tc * 16 + KC + tr] * scaleR;
+                if (j >= k + 2 && j < N) buf_st(rVR, k * N + j, sh.sx[tc * 16 + KC + tr] * scaleR);
             }
             if (tid == 0) {
                 o.VR[(size_t)k * N + k + 1] = 1.0;
@@ -327,11 +360,11 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
                 double zr[NPR];
 #pragma unroll
                 for (int a = KA; a < NPR; ++a)  // zs is zero beyond N
-                    zr[a] = (tr > k - 32 * a) ? tauRk * sh.zs[tr + 32 * a] : 0.0;
+                    zr[a] = row_gt(a) ? tauRk * sh.zs[tr + 32 * a] : 0.0;
 #pragma unroll
                 for (int c = KC; c < NPC; ++c) {
                     const double vj =
-                        (tc == k + 1 - 16 * c) ? 1.0 : sh.sx[tc * 16 + c] * scaleR;
+                        col_eq1(c) ? 1.0 : sh.sx[tc * 16 + c] * scaleR;
 #pragma unroll
                     for (int a = KA; a < NPR; ++a) Br[a][c] -= zr[a] * vj;
                 }
