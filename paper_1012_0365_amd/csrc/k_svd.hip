@@ -711,13 +711,18 @@ __device__ __forceinline__ void loads_issued() { asm volatile("" ::: "memory"); 
 // Sturm sequence of the Golub-Kahan tridiagonal. 1 / D is the hardware
 // estimate (relative error ~5e-8) refined by one Newton step (~2e-15), which
 // again perturbs ee_i in the 15th digit only.
+// Without GUARD a pivot D = 0 (or one whose quotient overflows) turns s into
+// a NaN or an infinity that reaches the end of the chain; the caller then
+// counts again with GUARD, which replaces |D| < pivmin by -pivmin. (The
+// recurrence is a chain of dependent operations; the guard would lengthen it.)
+template <bool GUARD>
 __device__ __forceinline__ void qd_block(const double2 (&c)[8], double& s, int& neg, double tau,
                                          double pivmin)
 {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
         double D = c[u].x + s;
-        D = fabs(D) < pivmin ? -pivmin : D;
+        if (GUARD) D = fabs(D) < pivmin ? -pivmin : D;
         neg += D < 0.0;
         double r = __builtin_amdgcn_rcp(D);
         r = fma(r, fma(-D, r, 1.0), r);
@@ -727,9 +732,11 @@ __device__ __forceinline__ void qd_block(const double2 (&c)[8], double& s, int& 
 
 // qe holds (q_i, ee_i) for i < N with ee_{N-1} = 0, then at least 23 pad
 // pairs (4, 0) that are never counted (the entries are scaled below 1, so
-// tau < 1 and 4 - tau > 0).
+// tau < 1 and 4 - tau > 0). The chain ends with s = -tau unless a pivot
+// broke it.
+template <bool GUARD>
 __device__ __forceinline__ int count_below(int N, const double2* __restrict__ qe, double tau,
-                                           double pivmin)
+                                           double pivmin, double& s_end)
 {
     int neg = 0;
     double s = -tau;
@@ -740,12 +747,13 @@ __device__ __forceinline__ int count_below(int N, const double2* __restrict__ qe
 #pragma unroll
         for (int u = 0; u < 8; ++u) b[u] = qe[i0 + 8 + u];
         loads_issued();
-        qd_block(a, s, neg, tau, pivmin);
+        qd_block<GUARD>(a, s, neg, tau, pivmin);
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = qe[i0 + 16 + u];
         loads_issued();
-        qd_block(b, s, neg, tau, pivmin);
+        qd_block<GUARD>(b, s, neg, tau, pivmin);
     }
+    s_end = s;
     return neg;
 }
 
@@ -784,6 +792,39 @@ __device__ __forceinline__ void lu_step(double& ddj, double& duj, double dlj, do
     o.bdu = odu * rd;
     o.bdu2 = odu2 * rd;
     sw = swp;
+}
+
+// The factorisation's dependence chain alone: the multiplier is formed both
+// ways, dlj / ddj from a reciprocal of ddj on the chain and ddj / dlj from
+// the reciprocal rl of dlj taken beforehand, and the pivot test only selects
+// between them. The step stores the multiplier and the incoming (ddj, duj);
+// U's row divided by its (guarded) diagonal is formed afterwards for all rows
+// at once (tgk_solve_kernel). For nonzero pivots this gives lu_step's factors
+// except that a pivot below `tiny` is used as it is in the multiplier.
+__device__ __forceinline__ void lu_chain_step(double& ddj, double& duj, double dlj, double rl,
+                                              double dun, double s, InvFac& o, unsigned char& sw)
+{
+    const bool swp = fabs(ddj) < fabs(dlj);
+    double r = __builtin_amdgcn_rcp(ddj);
+    r = fma(r, fma(-ddj, r, 1.0), r);
+    const double fact = swp ? ddj * rl : dlj * r;
+    o.dl = fact;
+    o.rdd = ddj;  // replaced by 1 / u_jj
+    o.bdu = duj;  // replaced by u_j,j+1 / u_jj
+    sw = swp;
+    const double ndd = swp ? fma(fact, s, duj) : fma(-fact, duj, -s);
+    duj = swp ? -fact * dun : dun;
+    ddj = ndd;
+}
+
+template <int B0>
+__device__ __forceinline__ void lu_chain_block(double& ddj, double& duj, const double (&fw)[9],
+                                               const double (&rl)[8], double s, InvFac* fac,
+                                               unsigned char* swp)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        lu_chain_step(ddj, duj, fw[u], rl[u], fw[u + 1], s, fac[B0 + u], swp[B0 + u]);
 }
 
 template <int B0>
@@ -848,6 +889,7 @@ struct TgkShared {
         InvFac fac[TG_OFF + 2 * SVD_MAXN + TG_PAD];        // LU factors, row j at TG_OFF + j
     };
     double f[2 * SVD_MAXN + TG_PAD];                       // scaled off-diagonals, zero beyond
+    double rl[2 * SVD_MAXN + TG_PAD];                      // their reciprocals
     double z[TG_OFF + 2 * SVD_MAXN + TG_PAD];              // row j at TG_OFF + j
     unsigned char swp[TG_OFF + 2 * SVD_MAXN + TG_PAD];
     int cnt[BS_PTS];
@@ -907,7 +949,11 @@ __global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* 
     for (int step = 0; step < 16; ++step) {
         if (hi - lo <= 2.0 * U * hi || hi - lo <= U * bs) break;
         const double x = lo + (hi - lo) * (double)(tid + 1) / (double)(BS_PTS + 1);
-        sh.cnt[tid] = N - count_below(N, sh.qe, x * x, PIVMIN);
+        double s_end;
+        int neg = count_below<false>(N, sh.qe, x * x, PIVMIN, s_end);
+        if (!(fabs(s_end) <= 4.0))  // a zero pivot broke the chain
+            neg = count_below<true>(N, sh.qe, x * x, PIVMIN, s_end);
+        sh.cnt[tid] = N - neg;
         if (tid == 0) sh.best = -1;
         __syncthreads();
         // the last point still holding >= t + 1 values
@@ -934,21 +980,61 @@ __global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* 
     for (int j = tid - TG_OFF; j < n + TG_PAD; j += BS_PTS)
         z[j] = (j >= 0 && j < n) ? start_pm1((uint64_t)t * 4096ULL + (uint64_t)j) : 0.0;
     __syncthreads();
+    for (int j = tid; j < n + TG_PAD; j += BS_PTS) {  // 1 / f_j (infinite for f_j = 0, then unused)
+        const double fj = sh.f[j];
+        double r = __builtin_amdgcn_rcp(fj);
+        r = fma(r, fma(-fj, r, 1.0), r);
+        sh.rl[j] = fma(r, fma(-fj, r, 1.0), r);
+    }
+    __syncthreads();
+    const double tiny = bs * U + 1e-300;
     if (tid == 0) {
-        const double tiny = bs * U + 1e-300;
         double ddj = -ss, duj = sh.f[0];
-        double fa[9], fb[9];
+        double fa[9], fb[9], ra[8], rb[8];
 #pragma unroll
         for (int u = 0; u < 9; ++u) fa[u] = sh.f[u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ra[u] = sh.rl[u];
         for (int j0 = 0; j0 < n - 1; j0 += 16) {
 #pragma unroll
             for (int u = 0; u < 9; ++u) fb[u] = sh.f[j0 + 8 + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) rb[u] = sh.rl[j0 + 8 + u];
             loads_issued();
-            lu_block<0>(ddj, duj, fa, ss, tiny, fac + j0, swp + j0);
+            lu_chain_block<0>(ddj, duj, fa, ra, ss, fac + j0, swp + j0);
 #pragma unroll
             for (int u = 0; u < 9; ++u) fa[u] = sh.f[j0 + 16 + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ra[u] = sh.rl[j0 + 16 + u];
             loads_issued();
-            lu_block<8>(ddj, duj, fb, ss, tiny, fac + j0, swp + j0);
+            lu_chain_block<8>(ddj, duj, fb, rb, ss, fac + j0, swp + j0);
+        }
+    }
+    __syncthreads();
+    // U's rows divided by the guarded diagonal; a multiplier that is not a
+    // number of magnitude <= 1 (a zero or underflowing pivot in a row below
+    // n - 1) sends the factorisation to the guarded form
+    int bad = 0;
+    for (int j = tid; j < n; j += BS_PTS) {
+        const InvFac o = fac[j];
+        const bool sw = swp[j];
+        const double piv = sw ? sh.f[j] : o.rdd;
+        const double pc = fabs(piv) < tiny ? (piv < 0.0 ? -tiny : tiny) : piv;
+        const double rd = 1.0 / pc;
+        const double odu = sw ? -ss : o.bdu;
+        const double odu2 = sw ? sh.f[j + 1] : 0.0;
+        fac[j].rdd = rd;
+        fac[j].bdu = odu * rd;
+        fac[j].bdu2 = odu2 * rd;
+        if (j < n - 1 && !(fabs(o.dl) <= 1.0000001)) bad = 1;
+    }
+    if (__syncthreads_or(bad) && tid == 0) {
+        double ddj = -ss, duj = sh.f[0];
+        for (int j0 = 0; j0 < n - 1; j0 += 8) {
+            double fw[9];
+#pragma unroll
+            for (int u = 0; u < 9; ++u) fw[u] = sh.f[j0 + u];
+            lu_block<0>(ddj, duj, fw, ss, tiny, fac + j0, swp + j0);
         }
     }
     for (int it = 0; it < 2; ++it) {
