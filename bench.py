@@ -160,7 +160,33 @@ def bench_rpca(args):
         log(f"[bench] warmup {i}: {info['iters']} iters, {info['seconds']:.3f}s")
     torch.cuda.synchronize()
 
+    # Per-family breakdown: one more solve with every launch timed (two event
+    # records per launch), before and outside the timed region.
     ctx.timing(True)
+    ctx.rpca_solve(D, A=A, E=E, bf16=bf16)
+    torch.cuda.synchronize()
+    fams = {}
+    for name in ctx.timing_families():
+        rec = ctx.timing_get(name)
+        if rec["launches"]:
+            fams[name] = rec
+    ctx.timing(False)
+    leaves = {k: v for k, v in fams.items() if k not in COMPOSITE}
+    kernel_ms = sum(r["ms"] for r in leaves.values())
+    dominant = max(leaves, key=lambda k: leaves[k]["ms"])
+    kernels = {}
+    for name, rec in sorted(fams.items(), key=lambda kv: -kv[1]["ms"]):
+        e = roofline_entry(name, rec, args.prec)
+        kernels[name] = {"ms_per_step": rec["ms"],
+                         "share": (rec["ms"] / kernel_ms if kernel_ms and name not in COMPOSITE
+                                   else None),
+                         "launches_per_step": rec["launches"],
+                         "avg_us": e["avg_us"], "achieved": e["achieved"], "unit": e["unit"],
+                         "frac": e["frac"], "bound": e["bound"],
+                         "composite": name in COMPOSITE}
+
+    # Timed region: only the dominant family's launches carry HIP events.
+    ctx.timing(True, only=[dominant])
     lat, iters = [], []
     torch.cuda.synchronize()
     t_start = time.perf_counter()
@@ -173,29 +199,11 @@ def bench_rpca(args):
         log(f"[bench] step {k}: {info['iters']} iters, {lat[-1]:.3f}s, rank {info['rank']}")
     torch.cuda.synchronize()
     total = time.perf_counter() - t_start
-
-    fams = {}
-    for name in ctx.timing_families():
-        rec = ctx.timing_get(name)
-        if rec["launches"]:
-            fams[name] = rec
+    dom = ctx.timing_get(dominant)
     ctx.timing(False)
-    leaves = {k: v for k, v in fams.items() if k not in COMPOSITE}
-    kernel_ms = sum(r["ms"] for r in leaves.values())
-    dominant = max(leaves, key=lambda k: leaves[k]["ms"])
-    roof = roofline_entry(dominant, leaves[dominant], args.prec)
+    roof = roofline_entry(dominant, dom, args.prec)
     roof["kernel"] = dominant
-    roof["launches_per_step"] = leaves[dominant]["launches"] / args.steps
-    kernels = {}
-    for name, rec in sorted(fams.items(), key=lambda kv: -kv[1]["ms"]):
-        e = roofline_entry(name, rec, args.prec)
-        kernels[name] = {"ms_per_step": rec["ms"] / args.steps,
-                         "share": (rec["ms"] / kernel_ms if kernel_ms and name not in COMPOSITE
-                                   else None),
-                         "launches_per_step": rec["launches"] / args.steps,
-                         "avg_us": e["avg_us"], "achieved": e["achieved"], "unit": e["unit"],
-                         "frac": e["frac"], "bound": e["bound"],
-                         "composite": name in COMPOSITE}
+    roof["launches_per_step"] = dom["launches"] / args.steps
 
     # accuracy of the last solve
     Ad = A.double()
@@ -233,9 +241,10 @@ def bench_rpca(args):
         "svt_calls_per_s": sum(iters) / total,
         "rel_err_vs_A0": rel_A0,
         "rel_err_vs_oracle_samples": rel_oracle,
-        "kernel_ms_per_step": kernel_ms / args.steps,
+        "kernel_ms_per_step": kernel_ms,
         "roofline": roof,
         "kernels": kernels,
+        "kernels_from": "one extra solve before the timed region, every launch timed",
     }
 
     if not args.no_plain:

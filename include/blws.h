@@ -208,6 +208,12 @@ int blws_set_plan_target(int target);
 /* Comma-separated names of the kernel families recorded since timing was
  * enabled, into buf (host, len bytes, NUL-terminated). */
 int blws_timing_list(blws_ctx ctx, char* buf, size_t len);
+/* Restrict timing to the comma-separated kernel families in `families` (host
+ * string; NULL or "" records every family). Recording a family costs two
+ * event records per launch; restricting it keeps that cost off the other
+ * launches. Takes effect for launches after the call; synchronises the
+ * device. */
+int blws_timing_only(blws_ctx ctx, const char* families);
 
 /* ------------------------------------------------------------------------
  * Request server (serving many solves on one GPU).

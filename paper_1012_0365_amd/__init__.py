@@ -231,7 +231,12 @@ class Context:
                                               U.data_ptr(), b, V.data_ptr(), b))
         return U, V
 
-    def timing(self, enable: bool):
+    def timing(self, enable: bool, only=None):
+        """Start (clearing the totals) or stop per-kernel timing; `only` names
+        the families to record (default: all)."""
+        if enable:
+            names = ",".join(only) if only else ""
+            self._check(self._lib.blws_timing_only(self.handle, names.encode()))
         self._check(self._lib.blws_timing_enable(self.handle, int(enable)))
 
     def timing_families(self) -> list:

@@ -123,6 +123,7 @@ SIGNATURES = {
     "blws_set_plan_target": (_i, [_i]),
     "blws_timing_enable": (_i, [_vp, _i]),
     "blws_timing_list": (_i, [_vp, ctypes.c_char_p, ctypes.c_size_t]),
+    "blws_timing_only": (_i, [_vp, ctypes.c_char_p]),
     "blws_timing_get": (_i, [_vp, ctypes.c_char_p, ctypes.POINTER(_ll), ctypes.POINTER(_d),
                              ctypes.POINTER(_d), ctypes.POINTER(_d)]),
 }

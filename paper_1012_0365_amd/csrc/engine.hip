@@ -10,10 +10,12 @@ TimedLaunch::TimedLaunch(Timer* timer, const char* family, hipStream_t s, double
 {
     if (!t) return;
     std::lock_guard<std::mutex> g(t->mu);
+    if (!t->wants(family)) {
+        t = nullptr;
+        return;
+    }
     Timer::Family& f = t->fam[family];
-    hipEvent_t a, b;
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
+    hipEvent_t a = t->take(), b = t->take();
     HIP_TRY(hipEventRecord(a, s));
     f.start.push_back(a);
     f.stop.push_back(b);
@@ -91,7 +93,7 @@ int blws_destroy(blws_ctx ctx)
     if (!ctx) return BLWS_EINVAL;
     (void)hipSetDevice(ctx->cx.device);
     (void)hipDeviceSynchronize();
-    ctx->cx.timer.clear();
+    ctx->cx.timer.release();
     ctx->cx.release_aux();
     if (ctx->cx.ws) (void)hipFree(ctx->cx.ws);
     if (ctx->cx.host_pinned) (void)hipHostFree(ctx->cx.host_pinned);
@@ -342,6 +344,27 @@ int blws_timing_enable(blws_ctx ctx, int enable)
     HIP_TRY(hipDeviceSynchronize());
     if (enable) cx.timer.clear();
     cx.timer.on = enable != 0;
+    return BLWS_OK;
+    ABI_END
+}
+
+int blws_timing_only(blws_ctx ctx, const char* families)
+{
+    ABI_BEGIN(ctx)
+    HIP_TRY(hipDeviceSynchronize());
+    cx.timer.only.clear();
+    if (families) {
+        std::string cur;
+        for (const char* c = families;; ++c) {
+            if (*c == ',' || *c == '\0') {
+                if (!cur.empty()) cx.timer.only.insert(cur);
+                cur.clear();
+                if (*c == '\0') break;
+            } else {
+                cur += *c;
+            }
+        }
+    }
     return BLWS_OK;
     ABI_END
 }

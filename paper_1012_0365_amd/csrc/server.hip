@@ -553,7 +553,7 @@ int blws_server_destroy(blws_server srv)
         (void)hipStreamSynchronize(sl->stream);
         (void)hipEventDestroy(sl->ev);
         (void)hipStreamDestroy(sl->stream);
-        sl->cx.timer.clear();
+        sl->cx.timer.release();
         sl->cx.release_aux();
         if (sl->cx.ws) (void)hipFree(sl->cx.ws);
         if (sl->cx.host_pinned) (void)hipHostFree(sl->cx.host_pinned);

@@ -14,6 +14,7 @@
 #include <exception>
 #include <functional>
 #include <map>
+#include <set>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -37,13 +38,33 @@ struct Timer {
         long long launches = 0;
     };
     std::map<std::string, Family> fam;
+    std::set<std::string> only;    // families to record (empty: all)
+    std::vector<hipEvent_t> pool;  // events of earlier recordings, reused
+    bool wants(const char* family) const { return only.empty() || only.count(family) != 0; }
+    hipEvent_t take()
+    {
+        if (pool.empty()) {
+            hipEvent_t e;
+            HIP_TRY(hipEventCreate(&e));
+            return e;
+        }
+        hipEvent_t e = pool.back();
+        pool.pop_back();
+        return e;
+    }
     void clear()
     {
         for (auto& kv : fam) {
-            for (auto e : kv.second.start) (void)hipEventDestroy(e);
-            for (auto e : kv.second.stop) (void)hipEventDestroy(e);
+            pool.insert(pool.end(), kv.second.start.begin(), kv.second.start.end());
+            pool.insert(pool.end(), kv.second.stop.begin(), kv.second.stop.end());
         }
         fam.clear();
+    }
+    void release()
+    {
+        clear();
+        for (auto e : pool) (void)hipEventDestroy(e);
+        pool.clear();
     }
 };
 
