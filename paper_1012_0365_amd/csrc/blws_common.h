@@ -186,6 +186,8 @@ void svt_reconstruct(Timer* tm, int m, int n, int b, const T* U, int ldu, const 
 
 // out[0] = sum of partials[0..count) in a fixed order.
 void sum_partials(int count, const double* partials, double* out, hipStream_t s);
+void iter_readback(int count, const double* partials, const int* rank, const int* err, double* zz,
+                   int* rank_out, int* err_out, hipStream_t s);
 
 // Count nonzeros of an m x n matrix into out (long long), deterministic.
 template <typename T>

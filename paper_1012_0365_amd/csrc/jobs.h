@@ -33,6 +33,18 @@ struct Job {
     blws_solve_info info{};
 };
 
+// Wait for the work queued on s by polling it: a blocking wait can add a
+// thread wake-up to every tick of a solve.
+inline void poll_stream(hipStream_t s)
+{
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e == hipSuccess) return;
+        if (e != hipErrorNotReady) HIP_TRY(e);
+        std::this_thread::yield();
+    }
+}
+
 inline void run_blocking(Job& job, Context& cx, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
@@ -41,7 +53,7 @@ inline void run_blocking(Job& job, Context& cx, hipStream_t s)
     cx.ensure(job.workspace_bytes());
     job.start(cx, s);
     while (!job.done) {
-        HIP_TRY(hipStreamSynchronize(s));
+        poll_stream(s);
         job.advance(cx, s);
     }
     HIP_TRY(hipStreamSynchronize(s));
@@ -147,10 +159,7 @@ struct RpcaJob : Job {
 
     void queue_readback(Context& cx, hipStream_t s)
     {
-        sum_partials(np, part, &rb->zz, s);
-        HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(&rb->svd_err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToDevice,
-                               s));
+        iter_readback(np, part, rank_dev, w.nflag + 1, &rb->zz, &rb->rank, &rb->svd_err, s);
         HIP_TRY(hipMemcpyAsync(cx.host_pinned, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
     }
 
@@ -402,10 +411,7 @@ struct McJob : Job {
         mu_next = next_mu(o, mu, mu_bar);
         mc_update<T>(&cx.timer, m, nnz, row_ptr, col_idx, d, y, sv, U, bmax, V, bmax, S, eps,
                      rank_dev, b, mu, mu_next, part, s);
-        sum_partials(npart, part, &rb->zz, s);
-        HIP_TRY(hipMemcpyAsync(&rb->rank, rank_dev, sizeof(int), hipMemcpyDeviceToDevice, s));
-        HIP_TRY(hipMemcpyAsync(&rb->svd_err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToDevice,
-                               s));
+        iter_readback(npart, part, rank_dev, w.nflag + 1, &rb->zz, &rb->rank, &rb->svd_err, s);
         HIP_TRY(hipMemcpyAsync(cx.host_pinned, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
     }
 

@@ -291,6 +291,28 @@ void svt_reconstruct(Timer* tm, int m, int n, int b, const T* U, int ldu, const 
                        (T*)nullptr, (unsigned short*)nullptr, A, lda, (double*)nullptr);
 }
 
+// The per-iteration readback gathered by one kernel: the summed partials, and
+// two device counters copied beside them (rank may be null: then 0).
+__global__ void iter_readback_kernel(int count, const double* p, const int* rank, const int* err,
+                                     double* zz, int* rank_out, int* err_out)
+{
+    double s = 0.0;
+    for (int i = threadIdx.x; i < count; i += 64) s += p[i];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (threadIdx.x == 0) {
+        zz[0] = s;
+        rank_out[0] = rank ? rank[0] : 0;
+        err_out[0] = err[0];
+    }
+}
+
+void iter_readback(int count, const double* partials, const int* rank, const int* err, double* zz,
+                   int* rank_out, int* err_out, hipStream_t s)
+{
+    hipLaunchKernelGGL(iter_readback_kernel, dim3(1), dim3(64), 0, s, count, partials, rank, err,
+                       zz, rank_out, err_out);
+}
+
 void sum_partials(int count, const double* partials, double* out, hipStream_t s)
 {
     hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(64), 0, s, count, partials, out);

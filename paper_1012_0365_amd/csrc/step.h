@@ -6,6 +6,7 @@
 #pragma once
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -95,12 +96,20 @@ struct Context;
 
 // A host thread that queues one task at a time (the second stream's half of
 // a step), so that the launches of both halves are issued concurrently.
+// Second host thread of a context: it queues the second stream's half of a
+// step. A posted task is picked up by polling while tasks keep coming (for
+// up to IDLE_SPIN after the last one; the tasks of a solve come an ALM
+// iteration apart) and through the condition variable after that, so that
+// the hand-over costs no thread wake-up in the middle of a solve. wait()
+// polls likewise for up to WAIT_SPIN.
 struct AuxWorker {
+    static constexpr std::chrono::microseconds IDLE_SPIN{5000}, WAIT_SPIN{5000};
     std::thread th;
     std::mutex m;
     std::condition_variable cv;
     std::function<void()> task;
-    bool has = false, busy = false, stop = false;
+    std::atomic<int> state{0};  // 0 idle, 1 posted, 2 running
+    bool stop = false;
     std::exception_ptr err;
 
     void start(int device)
@@ -108,13 +117,17 @@ struct AuxWorker {
         th = std::thread([this, device] {
             (void)hipSetDevice(device);
             for (;;) {
+                const auto t0 = std::chrono::steady_clock::now();
+                while (state.load(std::memory_order_acquire) != 1 &&
+                       std::chrono::steady_clock::now() - t0 < IDLE_SPIN)
+                    std::this_thread::yield();
                 std::function<void()> t;
                 {
                     std::unique_lock<std::mutex> lk(m);
-                    cv.wait(lk, [&] { return has || stop; });
-                    if (!has) return;
+                    cv.wait(lk, [&] { return state.load(std::memory_order_acquire) == 1 || stop; });
+                    if (state.load(std::memory_order_acquire) != 1) return;
                     t = std::move(task);
-                    has = false;
+                    state.store(2, std::memory_order_release);
                 }
                 std::exception_ptr e;
                 try {
@@ -125,7 +138,7 @@ struct AuxWorker {
                 {
                     std::lock_guard<std::mutex> g(m);
                     err = e;
-                    busy = false;
+                    state.store(0, std::memory_order_release);
                 }
                 cv.notify_all();
             }
@@ -136,17 +149,20 @@ struct AuxWorker {
         {
             std::lock_guard<std::mutex> g(m);
             task = std::move(f);
-            has = true;
-            busy = true;
             err = nullptr;
+            state.store(1, std::memory_order_release);
         }
         cv.notify_all();
     }
     // wait for the task; rethrow what it threw
     void wait()
     {
+        const auto t0 = std::chrono::steady_clock::now();
+        while (state.load(std::memory_order_acquire) != 0 &&
+               std::chrono::steady_clock::now() - t0 < WAIT_SPIN)
+            std::this_thread::yield();
         std::unique_lock<std::mutex> lk(m);
-        cv.wait(lk, [&] { return !busy; });
+        cv.wait(lk, [&] { return state.load(std::memory_order_acquire) == 0; });
         if (err) {
             std::exception_ptr e = err;
             err = nullptr;
