@@ -1220,6 +1220,10 @@ __global__ __launch_bounds__(256) void wy_t_kernel(int N, const double* __restri
     }
 }
 
+// grid (ceil(nv / 4), 2): blockIdx.y = 0 applies the left blocks to UB,
+// 1 the right blocks to VB (the two sides are independent); one wavefront
+// per column, the Y block of each step shared in LDS. The next step's Y block
+// and T factor are loaded into registers while the current one is applied.
 template <int MAXN, int R>
 __global__ __launch_bounds__(256) void backtransform_kernel(
     int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
@@ -1229,48 +1233,42 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
     __shared__ double Tm[WY_RB][WY_RB];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int col = blockIdx.x * 4 + wave;
+    const int side = blockIdx.y;
+    const double* Vh = side == 0 ? VL : VR;
+    double* X = side == 0 ? UB : VB;
+    const int nref = side == 0 ? N : N - 1;
     const int nblkL = (N + WY_RB - 1) / WY_RB;
-    double xr[R], yr[R];
+    const int nsteps = (nref + WY_RB - 1) / WY_RB;
+    double xr[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int i = lane + 64 * r;
-        xr[r] = (col < nv && i < N) ? UB[(size_t)i * ld + col] : 0.0;
-        yr[r] = (col < nv && i < N) ? VB[(size_t)i * ld + col] : 0.0;
+        xr[r] = (col < nv && i < N) ? X[(size_t)i * ld + col] : 0.0;
     }
-    // The blocks of both sides as one sequence of steps (left side, last
-    // block first, then the right side); with MAXN <= 512 the next step's Y
-    // block is loaded into registers while the current one is applied.
-    const int nblkR = (N - 1 + WY_RB - 1) / WY_RB;
-    const int nsteps = nblkL + nblkR;
+    // steps: this side's blocks, last block first
     constexpr int PFN = MAXN <= 512 ? WY_RB * ((MAXN + 255) / 256) : 1;
     double pf[PFN];
-    auto step_of = [&](int st, int& side, int& blk) {
-        side = st < nblkL ? 0 : 1;
-        blk = side == 0 ? nblkL - 1 - st : nblkR - 1 - (st - nblkL);
-    };
-    auto y_elem = [&](int side, int blk, int q, int i) -> double {
-        const double* Vh = side == 0 ? VL : VR;
-        const int nref = side == 0 ? N : N - 1;
+    double tpf = 0.0;
+    auto y_elem = [&](int blk, int q, int i) -> double {
         const int k0 = blk * WY_RB;
         const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
         return (q < cnt && i < N && i >= k0 + q + side) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
     };
+    auto t_index = [&](int blk) { return side == 0 ? blk : nblkL + blk; };
     auto prefetch = [&](int st) {
+        const int blk = nsteps - 1 - st;
         if constexpr (MAXN <= 512) {
-            int side, blk;
-            step_of(st, side, blk);
 #pragma unroll
             for (int q = 0; q < WY_RB; ++q)
 #pragma unroll
                 for (int u = 0; u < PFN / WY_RB; ++u)
-                    pf[q * (PFN / WY_RB) + u] = y_elem(side, blk, q, tid + 256 * u);
+                    pf[q * (PFN / WY_RB) + u] = y_elem(blk, q, tid + 256 * u);
         }
+        tpf = Tall[(size_t)t_index(blk) * WY_RB * WY_RB + tid];
     };
     prefetch(0);
     for (int st = 0; st < nsteps; ++st) {
-        int side, blk;
-        step_of(st, side, blk);
-        const int tb = side == 0 ? blk : nblkL + blk;
+        const int blk = nsteps - 1 - st;
         __syncthreads();  // the previous step's reads of Y and Tm are done
         if constexpr (MAXN <= 512) {
 #pragma unroll
@@ -1282,84 +1280,87 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
                 }
         } else {
             for (int q = 0; q < WY_RB; ++q)
-                for (int i = tid; i < N; i += 256) Y[q][i] = y_elem(side, blk, q, i);
+                for (int i = tid; i < N; i += 256) Y[q][i] = y_elem(blk, q, i);
         }
-        Tm[tid >> 4][tid & 15] = Tall[(size_t)tb * WY_RB * WY_RB + tid];
+        Tm[tid >> 4][tid & 15] = tpf;
         __syncthreads();
         if (st + 1 < nsteps) prefetch(st + 1);
-        {
-            // x <- x - Y (T (Y^T x))
-            double yx[WY_RB];
+        // x <- x - Y (T (Y^T x))
+        double yx[WY_RB];
 #pragma unroll
-            for (int q = 0; q < WY_RB; ++q) {
-                double s = 0.0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int i = lane + 64 * r;
-                    if (i < N) s += Y[q][i] * (side == 0 ? xr[r] : yr[r]);
-                }
-                yx[q] = s;
-            }
-#pragma unroll
-            for (int q = 0; q < WY_RB; ++q) yx[q] = wave_sum64(yx[q]);
-            double wv[WY_RB];
-#pragma unroll
-            for (int p = 0; p < WY_RB; ++p) {
-                double s = 0.0;
-#pragma unroll
-                for (int q = 0; q < WY_RB; ++q)
-                    if (q >= p) s += Tm[p][q] * yx[q];
-                wv[p] = s;
-            }
+        for (int q = 0; q < WY_RB; ++q) {
+            double sm = 0.0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int i = lane + 64 * r;
-                if (i < N) {
-                    double s = 0.0;
+                if (i < N) sm += Y[q][i] * xr[r];
+            }
+            yx[q] = sm;
+        }
 #pragma unroll
-                    for (int p = 0; p < WY_RB; ++p) s += Y[p][i] * wv[p];
-                    if (side == 0)
-                        xr[r] -= s;
-                    else
-                        yr[r] -= s;
-                }
+        for (int q = 0; q < WY_RB; ++q) yx[q] = wave_sum64(yx[q]);
+        double wv[WY_RB];
+#pragma unroll
+        for (int p = 0; p < WY_RB; ++p) {
+            double sm = 0.0;
+#pragma unroll
+            for (int q = 0; q < WY_RB; ++q)
+                if (q >= p) sm += Tm[p][q] * yx[q];
+            wv[p] = sm;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            if (i < N) {
+                double sm = 0.0;
+#pragma unroll
+                for (int p = 0; p < WY_RB; ++p) sm += Y[p][i] * wv[p];
+                xr[r] -= sm;
             }
         }
     }
-    // sign convention: the first largest-magnitude entry of the left vector positive
-    double vmax = -1.0;
-    int imax = 0;
+    if (col < nv) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int i = lane + 64 * r;
-        const double a = fabs(xr[r]);
-        if (i < N && a > vmax) {
-            vmax = a;
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            if (i < N) X[(size_t)i * ld + col] = xr[r];
+        }
+    }
+}
+
+// Sign convention of the singular pairs: the first largest-magnitude entry of
+// the left vector positive (u and v of a pair flip together). One wavefront
+// per column.
+__global__ __launch_bounds__(256) void sign_fix_kernel(int N, int nv, double* __restrict__ UB,
+                                                       double* __restrict__ VB, int ld)
+{
+    const int lane = threadIdx.x & 63;
+    const int col = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (col >= nv) return;  // uniform per wavefront
+    double vmax = -1.0, xv = 0.0;
+    int imax = 0;
+    for (int i = lane; i < N; i += 64) {
+        const double x = UB[(size_t)i * ld + col];
+        if (fabs(x) > vmax) {
+            vmax = fabs(x);
             imax = i;
+            xv = x;
         }
     }
     for (int o = 32; o > 0; o >>= 1) {
         const double ov = __shfl_xor(vmax, o, 64);
         const int oi = __shfl_xor(imax, o, 64);
+        const double ox = __shfl_xor(xv, o, 64);
         if (ov > vmax || (ov == vmax && oi < imax)) {
             vmax = ov;
             imax = oi;
+            xv = ox;
         }
     }
-    double xv = 0.0;
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-        if (lane + 64 * r == imax) xv = xr[r];
-    xv = wave_sum64(xv);
-    const double sg = xv < 0.0 ? -1.0 : 1.0;
-    if (col < nv) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = lane + 64 * r;
-            if (i < N) {
-                UB[(size_t)i * ld + col] = sg * xr[r];
-                VB[(size_t)i * ld + col] = sg * yr[r];
-            }
+    if (xv < 0.0) {
+        for (int i = lane; i < N; i += 64) {
+            UB[(size_t)i * ld + col] = -UB[(size_t)i * ld + col];
+            VB[(size_t)i * ld + col] = -VB[(size_t)i * ld + col];
         }
     }
 }
@@ -1474,14 +1475,15 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
         if (N <= 256)
-            hipLaunchKernelGGL((backtransform_kernel<256, 4>), dim3(blocks), dim3(256), 0, s, N,
+            hipLaunchKernelGGL((backtransform_kernel<256, 4>), dim3(blocks, 2), dim3(256), 0, s, N,
                                nv, VL, VR, Tall, UB, VB, N);
         else if (N <= 512)
-            hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks), dim3(256), 0, s, N,
+            hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s, N,
                                nv, VL, VR, Tall, UB, VB, N);
         else
-            hipLaunchKernelGGL((backtransform_kernel<SVD_MAXN, 16>), dim3(blocks), dim3(256), 0, s,
-                               N, nv, VL, VR, Tall, UB, VB, N);
+            hipLaunchKernelGGL((backtransform_kernel<SVD_MAXN, 16>), dim3(blocks, 2), dim3(256), 0,
+                               s, N, nv, VL, VR, Tall, UB, VB, N);
+        hipLaunchKernelGGL(sign_fix_kernel, dim3(blocks), dim3(256), 0, s, N, nv, UB, VB, N);
     }
 }
 
