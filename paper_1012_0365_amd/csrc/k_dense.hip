@@ -227,7 +227,8 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
 // in LDS), X <- X R^{-1} in place row by row. Columns found dependent in the
 // first pass are redrawn from the counter-based generator (stream ids sid0,
 // sid1) before the second; *nflag counts them. When the first Gram matrix is
-// already the identity to 1e-8, the first pass is the only one.
+// already the identity to 1e-8, one pass of X <- X (3 I - G) / 2 replaces
+// both.
 constexpr int CQ_LD = 129;
 
 __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, double* X0, double* X1,
@@ -293,8 +294,22 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
                 for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
                 one_pass = m <= 1e-8 ? 1 : 0;
             }
+            __syncthreads();
         }
-        chol_inv_regs(c, G, CQ_LD, G, CQ_LD, eta, scal, row, piv, flg);
+        if (pass == 0 && one_pass) {
+            // G = I + E with |E| <= 1e-8: X (3 I - G) / 2 is orthonormal to
+            // O(|E|^2) (its Gram matrix is I - 3 E^2 / 4 + O(E^3)), the
+            // symmetric orthonormalisation to first order, with no Cholesky
+            // factorisation; no column is dependent
+            for (int e = tid; e < c * c; e += 1024) {
+                const int i = e / c, j = e - i * c;
+                G[i * CQ_LD + j] = (i == j ? 1.5 : 0.0) - 0.5 * G[i * CQ_LD + j];
+            }
+            for (int j = tid; j < c; j += 1024) flg[j] = 0;
+            __syncthreads();
+        } else {
+            chol_inv_regs(c, G, CQ_LD, G, CQ_LD, eta, scal, row, piv, flg);
+        }
         // X <- X R^{-1} by MFMA: wavefront w owns row blocks w, w + 16, ... (16
         // rows each, all column tiles), so each row block is read completely
         // before it is overwritten
