@@ -212,9 +212,33 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
     __shared__ double row[2 * 128];
     __shared__ double piv[128];
     __shared__ int flg[128];
+    __shared__ double dev_w[16];
+    const int tid = threadIdx.x;
+    // Columns already orthonormal to 1e-8 (the second Cholesky-QR pass of a
+    // block): R^{-1} is replaced by (3 I - G) / 2, with which X R^{-1} is
+    // orthonormal to O(|G - I|^2), and no column is dependent.
+    double dv = 0.0;
+    for (int e = tid; e < n * n; e += 1024) {
+        const int i = e / n, j = e - i * n;
+        dv = fmax(dv, fabs(G[(size_t)i * ldg + j] - (i == j ? 1.0 : 0.0)));
+    }
+    for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
+    if ((tid & 63) == 0) dev_w[tid >> 6] = dv;
+    __syncthreads();
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
+    if (m <= 1e-8) {
+        for (int e = tid; e < n * n; e += 1024) {
+            const int i = e / n, j = e - i * n;
+            Rinv[(size_t)i * n + j] = (i == j ? 1.5 : 0.0) - 0.5 * G[(size_t)i * ldg + j];
+        }
+        for (int i = tid; i < n; i += 1024) flags[i] = 0;
+        return;
+    }
     chol_inv_regs(n, G, ldg, Rinv, n, eta, scal, row, piv, flg);
     int cnt = 0;
-    for (int i = threadIdx.x; i < n; i += 1024) {
+    for (int i = tid; i < n; i += 1024) {
         flags[i] = flg[i];
         cnt += flg[i];
     }
