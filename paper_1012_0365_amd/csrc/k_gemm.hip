@@ -312,10 +312,11 @@ void launch_nt(const Plan& p, int M, int N, int K, double alpha, const TA* A, in
 // workgroup and runs its K range in LDS stages: for the orthonormalisation
 // products (M ~ 2000, N ~ 112) that is ~32 workgroups on a 256-CU chip. Two
 // dedicated forms instead:
-//  - NN with K <= SK_MAXK: one workgroup per 16-row strip of C; the strip of
-//    A is staged once in LDS (transposed, so fragment reads are unit-stride),
-//    B fragments are read straight from L2 (every workgroup reads all of B),
-//    the four wavefronts take interleaved 16-column tiles;
+//  - NN with K <= SK_MAXK: one workgroup per 16-row strip of C (and group
+//    of column tiles, when C has few strips); the strip of A is staged once
+//    in LDS (transposed, so fragment reads are unit-stride), B fragments are
+//    read straight from L2, the four wavefronts take interleaved 16-column
+//    tiles;
 //  - TN with M, N <= TN_MAXMN and long K: a workgroup owns a 64 x 64 block of
 //    C and one K chunk (LDS stages of 32 rows); the chunks' partial blocks are
 //    summed in chunk order by the split-K reduction, so results do not depend
@@ -348,7 +349,7 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
 #pragma unroll
     for (int t = 0; t < NTW; ++t) {
         acc[t] = d4{0.0, 0.0, 0.0, 0.0};
-        col[t] = 16 * (wave + 4 * t) + cl;
+        col[t] = 16 * (4 * NTW * (int)blockIdx.y + wave + 4 * t) + cl;
     }
     // B fragments by groups of PF k-steps, the next group's loads in flight
     // while the current one feeds the matrix cores
@@ -492,8 +493,15 @@ template <typename TA, typename TB, typename TC>
 void launch_nn_sk(int M, int N, int K, double alpha, const TA* A, int lda, const TB* B, int ldb,
                   double beta, const TC* Cin, int ldcin, TC* C, int ldc, hipStream_t s)
 {
-    const int ntw = ((N + 15) / 16 + 3) / 4;
-    dim3 grid((M + 15) / 16), block(256);
+    // a workgroup per 16-row strip and group of 4 NTW column tiles; for a
+    // short C the column tiles are spread over more workgroups (one per wave)
+    const int ntiles = (N + 15) / 16, strips = (M + 15) / 16;
+    int ntw = (ntiles + 3) / 4, gy = 1;
+    if (strips < 192 && ntw > 1) {
+        ntw = 1;
+        gy = (ntiles + 3) / 4;
+    }
+    dim3 grid(strips, gy), block(256);
 #define BLWS_NNSK_CASE(V)                                                                       \
     case V:                                                                                     \
         hipLaunchKernelGGL((gemm_nn_sk_kernel<TA, TB, TC, V>), grid, block, 0, s, M, N, K, alpha, \
