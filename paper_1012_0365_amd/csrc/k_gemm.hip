@@ -325,6 +325,7 @@ void launch_nt(const Plan& p, int M, int N, int K, double alpha, const TA* A, in
 constexpr int SK_MAXK = 512;
 constexpr int TN_MAXMN = 512;
 constexpr int TN_BK = 32;
+constexpr int TN_TARGET_WG = 256;  // workgroups a long-K TN product aims at
 
 template <typename TA, typename TB, typename TC, int NTW>
 __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, double alpha,
@@ -462,7 +463,7 @@ struct TnPlan {
     int gx, gy, splits, kchunk;
 };
 
-// about 256 workgroups, chunks of at least one LDS stage, partials below
+// about TN_TARGET_WG workgroups, chunks of at least one LDS stage, partials below
 // min(4M, cap) doubles
 TnPlan make_tn_plan(int M, int N, int K, size_t cap = (size_t)4 << 20)
 {
@@ -470,7 +471,7 @@ TnPlan make_tn_plan(int M, int N, int K, size_t cap = (size_t)4 << 20)
     p.gx = (M + 63) / 64;
     p.gy = (N + 63) / 64;
     const long blocks = (long)p.gx * p.gy;
-    long s = (256 + blocks - 1) / blocks;
+    long s = (TN_TARGET_WG + blocks - 1) / blocks;
     const long smax_k = (K + TN_BK - 1) / TN_BK;
     if (s > smax_k) s = smax_k;
     const long smax_mem = (long)(std::min(cap, (size_t)4 << 20) / ((size_t)M * N));
