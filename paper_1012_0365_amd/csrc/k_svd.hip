@@ -864,6 +864,26 @@ __device__ __forceinline__ void bwd_block(double& z1, double& z2, const InvFac (
     }
 }
 
+// Eight steps of the factorisation T - ss I = L D L^T of a tridiagonal with
+// zero diagonal and off-diagonals g (top-down, or bottom-up on the reversed
+// off-diagonals): the pivot x_j is stored, m_j = g_j / x_j, and
+// x_{j+1} = -ss - m_j g_j. A pivot below pivmin in magnitude is taken as
+// -pivmin (IEEE arithmetic then carries the huge multiplier through).
+__device__ __forceinline__ void twist_block(double& x, const double (&g)[8], double ss,
+                                            double pivmin, double* X, double* M)
+{
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        X[u] = x;
+        const double xc = fabs(x) < pivmin ? -pivmin : x;
+        double r = __builtin_amdgcn_rcp(xc);
+        r = fma(r, fma(-xc, r, 1.0), r);
+        const double m = g[u] * r;
+        M[u] = m;
+        x = fma(-m, g[u], -ss);
+    }
+}
+
 // Singular value sigma_t (the t-th largest) of the bidiagonal (d, e) and its
 // left and right singular vectors, one workgroup per value.
 //  - Values: multisection on [0, Gershgorin bound] with BS_PTS Sturm counts
@@ -883,10 +903,15 @@ __device__ __forceinline__ void bwd_block(double& z1, double& z2, const InvFac (
 constexpr int BS_PTS = 256;
 constexpr int TG_PAD = 24;
 constexpr int TG_OFF = 24;
+constexpr int TG_TW = TG_OFF + 2 * SVD_MAXN + TG_PAD;
 struct TgkShared {
     union {
         double2 qe[SVD_MAXN + TG_PAD];                     // multisection
         InvFac fac[TG_OFF + 2 * SVD_MAXN + TG_PAD];        // LU factors, row j at TG_OFF + j
+        struct {                                           // twisted factorisation:
+            double X0[TG_TW], M0[TG_TW];                   //  top-down pivots, multipliers
+            double X1[TG_TW], M1[TG_TW];                   //  bottom-up, in reversed order
+        } tw;
     };
     double f[2 * SVD_MAXN + TG_PAD];                       // scaled off-diagonals, zero beyond
     double rl[2 * SVD_MAXN + TG_PAD];                      // their reciprocals
@@ -895,6 +920,8 @@ struct TgkShared {
     int cnt[BS_PTS];
     double red[BS_PTS / 64];
     int best;
+    int twr;      // twist index
+    double twg;   // |gamma| at the twist
 };
 
 __global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* __restrict__ d,
@@ -973,10 +1000,154 @@ __global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* 
     const double ss = zero ? 0.0 : 0.5 * (lo + hi);  // sigma_t, scaled
     if (tid == 0) sig[t] = ss / sc;
 
-    // ---- inverse iteration at +ss on the scaled T (qe is dead from here)
+    // ---- eigenvector of T at +ss (qe is read once more, by the isolation test)
     double* const z = sh.z + TG_OFF;
     InvFac* const fac = sh.fac + TG_OFF;
     unsigned char* const swp = sh.swp + TG_OFF;
+    // First by a twisted factorisation: T - ss I = L D L^T (top-down) and
+    // U P U^T (bottom-up), run at once by lanes 0 and 1; at the twist index r
+    // minimising |gamma_k| = |d_k + p_k + ss|, z_r = 1, z_k = -l_k z_{k+1}
+    // above and z_{k+1} = -u_k z_k below (again two lanes at once). Then
+    // (T - ss I) z = gamma_r e_r: the vector is accepted when |gamma_r| is
+    // within 64 n u ||T|| of ||z|| (and every entry finite); otherwise inverse
+    // iteration below computes it. The twisted form is used only for a value
+    // isolated to 1e-6 relative (one value in [ss (1 - 1e-6), ss (1 + 1e-6)]
+    // widened by 1e-12 ||T||, counted by lanes 0 and 1): the vectors of close
+    // or repeated values come from inverse iteration's distinct start vectors.
+    if (tid < 2) {
+        const double xb = tid == 0 ? ss * (1.0 - 1e-6) - 1e-12 * bs : ss * (1.0 + 1e-6) + 1e-12 * bs;
+        int ge = N;  // #{sigma >= xb}
+        if (xb > 0.0) {
+            double s_end;
+            int neg = count_below<false>(N, sh.qe, xb * xb, PIVMIN, s_end);
+            if (!(fabs(s_end) <= 4.0)) neg = count_below<true>(N, sh.qe, xb * xb, PIVMIN, s_end);
+            ge = N - neg;
+        }
+        sh.cnt[tid] = ge;
+    }
+    __syncthreads();
+    const bool isolated = ss > 0.0 && sh.cnt[0] - sh.cnt[1] == 1;
+    __syncthreads();  // cnt is reused
+    bool twisted_ok = false;
+    if (isolated) {  // uniform
+    for (int j = tid; j < n + TG_PAD; j += BS_PTS)  // rl holds f reversed for now
+        sh.rl[j] = j < n - 1 ? sh.f[n - 2 - j] : 0.0;
+    __syncthreads();
+    if (tid < 2) {
+        const double* g = tid == 0 ? sh.f : sh.rl;
+        double* X = tid == 0 ? sh.tw.X0 : sh.tw.X1;
+        double* M = tid == 0 ? sh.tw.M0 : sh.tw.M1;
+        double x = -ss;
+        double ga[8], gb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ga[u] = g[u];
+        for (int j0 = 0; j0 < n - 1; j0 += 16) {  // steps beyond n - 2 run on zeros
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gb[u] = g[j0 + 8 + u];
+            loads_issued();
+            twist_block(x, ga, ss, PIVMIN, X + j0, M + j0);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ga[u] = g[j0 + 16 + u];
+            loads_issued();
+            twist_block(x, gb, ss, PIVMIN, X + j0 + 8, M + j0 + 8);
+        }
+    }
+    __syncthreads();
+    {
+        double gm = INFINITY;
+        int gk = n;
+        for (int k = tid; k < n; k += BS_PTS) {
+            const double gv = fabs(sh.tw.X0[k] + sh.tw.X1[n - 1 - k] + ss);
+            if (gv < gm) {
+                gm = gv;
+                gk = k;
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const double og = __shfl_xor(gm, off, 64);
+            const int ok = __shfl_xor(gk, off, 64);
+            if (og < gm || (og == gm && ok < gk)) {
+                gm = og;
+                gk = ok;
+            }
+        }
+        if (lane == 0) {
+            sh.red[tid >> 6] = gm;
+            sh.cnt[tid >> 6] = gk;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            double bg = sh.red[0];
+            int bk = sh.cnt[0];
+            for (int w = 1; w < BS_PTS / 64; ++w)
+                if (sh.red[w] < bg || (sh.red[w] == bg && sh.cnt[w] < bk)) {
+                    bg = sh.red[w];
+                    bk = sh.cnt[w];
+                }
+            sh.twr = bk < n ? bk : 0;
+            sh.twg = bg;
+        }
+        __syncthreads();
+    }
+    const int r = sh.twr;
+    if (tid < 2) {
+        // lane 0: z_k = -l_k z_{k+1}, k = r - 1 .. 0; lane 1: z_{k+1} = -u_k z_k,
+        // k = r .. n - 2 (u_k is M1[n - 2 - k]); multipliers read eight ahead
+        const int len = tid == 0 ? r : n - 1 - r;
+        const int len_max = r > n - 1 - r ? r : n - 1 - r;
+        const double* src = tid == 0 ? sh.tw.M0 + (r - 1) : sh.tw.M1 + (n - 2 - r);
+        const int step = tid == 0 ? -1 : 1;
+        double* dst = z + r + step;
+        if (tid == 0) z[r] = 1.0;
+        double zp = 1.0;
+        auto mul_at = [&](int q) { return q < len ? src[-q] : 0.0; };
+        double ma[8], mb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ma[u] = mul_at(u);
+        for (int q0 = 0; q0 < len_max; q0 += 16) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) mb[u] = mul_at(q0 + 8 + u);
+            loads_issued();
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + u < len) {
+                    zp = -ma[u] * zp;
+                    dst[step * (q0 + u)] = zp;
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) ma[u] = mul_at(q0 + 16 + u);
+            loads_issued();
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (q0 + 8 + u < len) {
+                    zp = -mb[u] * zp;
+                    dst[step * (q0 + 8 + u)] = zp;
+                }
+        }
+    }
+    __syncthreads();
+    {
+        double zz = 0.0;
+        bool fin = true;
+        for (int k = tid; k < n; k += BS_PTS) {
+            const double v = z[k];
+            fin = fin && fabs(v) <= 1e150;
+            zz += v * v;
+        }
+        for (int off = 32; off > 0; off >>= 1) zz += __shfl_xor(zz, off, 64);
+        const int allfin = __syncthreads_and(fin ? 1 : 0);
+        if (lane == 0) sh.red[tid >> 6] = zz;
+        __syncthreads();
+        double tot = 0.0;
+#pragma unroll
+        for (int w = 0; w < BS_PTS / 64; ++w) tot += sh.red[w];
+        const double tol = 64.0 * n * U * bs;
+        twisted_ok = allfin && sh.twg <= tol * sqrt(tot);
+        __syncthreads();  // red is reused
+    }
+    }  // twisted factorisation
+    if (!twisted_ok) {
+    // ---- inverse iteration at +ss on the scaled T
     for (int j = tid - TG_OFF; j < n + TG_PAD; j += BS_PTS)
         z[j] = (j >= 0 && j < n) ? start_pm1((uint64_t)t * 4096ULL + (uint64_t)j) : 0.0;
     __syncthreads();
@@ -1115,6 +1286,7 @@ __global__ __launch_bounds__(BS_PTS) void tgk_solve_kernel(int N, const double* 
             }
         }
     }
+    }  // inverse iteration
     __syncthreads();
     // split and normalise each half to unit length
     double nu = 0.0, nv = 0.0;
