@@ -114,9 +114,12 @@ size_t chol_scratch_elems(int n);
 // Two Cholesky-QR passes on X0 and X1 (rows x c each, leading dimension ld,
 // rows <= 512, c <= 128) in place, one workgroup per matrix: dependent
 // columns of the first pass redrawn (stream ids sid0, sid1), counted in nflag.
+// G0, G1 (c x c each) receive the Gram matrices formed first; when a side's
+// is within 1e-8 of I, X (3I - G)/2 replaces the passes, over many workgroups.
 bool cholqr2_small_supported(int rows, int c);
 void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, int* nflag,
-                   double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, hipStream_t s);
+                   double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, double* G0, double* G1,
+                   hipStream_t s);
 
 // Fill flagged columns of X (rows x c, ldx) with the counter-based uniform draw.
 template <typename T>

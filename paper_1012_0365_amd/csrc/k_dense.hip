@@ -255,20 +255,101 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
 // both.
 constexpr int CQ_LD = 129;
 
+// Gram matrices G_s = X_s^T X_s (rows x c, c <= 128) of the two sides, one
+// wavefront per 16 x 16 tile (grid T*T x 2), two interleaved MFMA chains over
+// the rows; G_s is c x c, row-major.
+__global__ __launch_bounds__(64) void polish_gram_kernel(int rows, int c, const double* X0,
+                                                         const double* X1, int ld, double* G0,
+                                                         double* G1)
+{
+    const double* X = blockIdx.y == 0 ? X0 : X1;
+    double* G = blockIdx.y == 0 ? G0 : G1;
+    const int T = (c + 15) / 16;
+    const int ti = blockIdx.x / T, tj = blockIdx.x - ti * T;
+    const int lane = threadIdx.x;
+    const int ca = 16 * ti + (lane & 15), cb = 16 * tj + (lane & 15);
+    d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < rows; k0 += 8) {
+        const int k = k0 + (lane >> 4), k2 = k + 4;
+        const double a0 = (k < rows && ca < c) ? X[(size_t)k * ld + ca] : 0.0;
+        const double b0 = (k < rows && cb < c) ? X[(size_t)k * ld + cb] : 0.0;
+        const double a1 = (k2 < rows && ca < c) ? X[(size_t)k2 * ld + ca] : 0.0;
+        const double b1 = (k2 < rows && cb < c) ? X[(size_t)k2 * ld + cb] : 0.0;
+        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
+        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = 16 * ti + (lane >> 4) + 4 * i;
+        if (r < c && cb < c) G[(size_t)r * c + cb] = acc0[i] + acc1[i];
+    }
+}
+
 __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, double* X0, double* X1,
                                                              int ld, int* nflag, double eta,
                                                              uint64_t seed, uint64_t sid0,
-                                                             uint64_t sid1)
+                                                             uint64_t sid1, const double* G0pre,
+                                                             const double* G1pre)
 {
     __shared__ double G[128 * CQ_LD];
     __shared__ double scal[128], row[2 * 128], piv[128];
     __shared__ int flg[128];
     __shared__ double dev_w[16];
     __shared__ int one_pass;
+    __shared__ double Xs[16][128];
     double* X = blockIdx.x == 0 ? X0 : X1;
     const uint64_t sid = blockIdx.x == 0 ? sid0 : sid1;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int T = (c + 15) / 16;
+    {
+        // The side's Gram matrix, formed beforehand by polish_gram_kernel. Within
+        // 1e-8 of I (the usual case): workgroup (side, rb) replaces rows 16 rb ..
+        // 16 rb + 15 of X by X (3 I - G) / 2, a column tile per wavefront, and
+        // nothing else is done. Otherwise workgroup (side, 0) runs the two
+        // Cholesky-QR passes below and the others leave.
+        const double* Gp = blockIdx.x == 0 ? G0pre : G1pre;
+        double dv = 0.0;
+        for (int e = tid; e < c * c; e += 1024) {
+            const int i = e / c, j = e - i * c;
+            dv = fmax(dv, fabs(Gp[e] - (i == j ? 1.0 : 0.0)));
+        }
+        for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
+        if (lane == 0) dev_w[wave] = dv;
+        __syncthreads();
+        double m = 0.0;
+#pragma unroll
+        for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
+        if (m <= 1e-8) {
+            const int r0 = 16 * blockIdx.y;
+            for (int e = tid; e < c * c; e += 1024) {
+                const int i = e / c, j = e - i * c;
+                G[i * CQ_LD + j] = (i == j ? 1.5 : 0.0) - 0.5 * Gp[e];
+            }
+            for (int e = tid; e < 16 * c; e += 1024) {
+                const int i = e / c, j = e - i * c;
+                Xs[i][j] = r0 + i < rows ? X[(size_t)(r0 + i) * ld + j] : 0.0;
+            }
+            __syncthreads();
+            if (wave < T) {  // uniform per wavefront
+                const int cb = 16 * wave + (lane & 15);
+                d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+                for (int k0 = 0; k0 < c; k0 += 4) {
+                    const int k = k0 + (lane >> 4);
+                    const double a = k < c ? Xs[lane & 15][k] : 0.0;
+                    const double b = (k < c && cb < c) ? G[k * CQ_LD + cb] : 0.0;
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = r0 + (lane >> 4) + 4 * i;
+                    if (r < rows && cb < c) X[(size_t)r * ld + cb] = acc[i];
+                }
+            }
+            return;
+        }
+        if (blockIdx.y != 0) return;
+        __syncthreads();  // dev_w is reused
+    }
     for (int pass = 0; pass < 2; ++pass) {
         // Gram G = X^T X: 16 x 16 tiles, wavefront w takes tiles w + 16 u,
         // two at a time (independent MFMA chains)
@@ -643,13 +724,17 @@ void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* fla
 bool cholqr2_small_supported(int rows, int c) { return rows >= 1 && rows <= 512 && c >= 1 && c <= 128; }
 
 void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, int* nflag,
-                   double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, hipStream_t s)
+                   double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, double* G0, double* G1,
+                   hipStream_t s)
 {
     BLWS_REQUIRE(cholqr2_small_supported(rows, c), BLWS_EUNSUPPORTED, "cholqr2_small: size");
     TimedLaunch tl(tm, "svd_polish", s, 2.0 * 2.0 * (2.0 * rows * (double)c * c + c * (double)c * c / 3.0),
                    0.0);
-    hipLaunchKernelGGL(cholqr2_small_kernel, dim3(2), dim3(1024), 0, s, rows, c, X0, X1, ld, nflag,
-                       eta, seed, sid0, sid1);
+    const int T = (c + 15) / 16;
+    hipLaunchKernelGGL(polish_gram_kernel, dim3(T * T, 2), dim3(64), 0, s, rows, c, X0, X1, ld, G0,
+                       G1);
+    hipLaunchKernelGGL(cholqr2_small_kernel, dim3(2, (rows + 15) / 16), dim3(1024), 0, s, rows, c,
+                       X0, X1, ld, nflag, eta, seed, sid0, sid1, G0, G1);
 }
 
 size_t small_svd_jacobi_scratch_elems(int N) { return 2 * (size_t)N * N; }

@@ -463,7 +463,8 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
         if (cholqr2_small_supported(N, nv)) {
             const uint64_t sid0 = (1ULL << 20) + (++cx.fix_calls);
             const uint64_t sid1 = (1ULL << 20) + (++cx.fix_calls);
-            cholqr2_small(&cx.timer, N, nv, UB, VB, N, w.nflag, CHOL_ETA, seed, sid0, sid1, s);
+            cholqr2_small(&cx.timer, N, nv, UB, VB, N, w.nflag, CHOL_ETA, seed, sid0, sid1, w.Gr,
+                          w.Ri, s);
         } else {
             orth_against<double>(cx, w, s, N, 0, nullptr, 0, UB, N, nv, UB, N, seed);
             orth_against<double>(cx, w, s, N, 0, nullptr, 0, VB, N, nv, VB, N, seed);
