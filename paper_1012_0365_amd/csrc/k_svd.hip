@@ -1500,6 +1500,115 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
     }
 }
 
+// The same back-transformation with matrix cores for N <= BT_MAXN: grid
+// (ceil(nv / 16), 2), workgroup (c, side) holds columns 16 c .. 16 c + 15 of
+// UB (side 0) or VB (side 1) in LDS and applies that side's blocks, last
+// first: W = Y^T X by MFMA with the rows split over the four wavefronts (the
+// partial products summed in LDS in wavefront order), W <- T W, then
+// X <- X - Y W by MFMA over 16-row tiles. The next block's Y is loaded into
+// registers while the current one is applied.
+constexpr int BT_MAXN = 256;
+typedef double d4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void backtransform_mfma_kernel(
+    int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
+    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld)
+{
+    __shared__ double Xs[BT_MAXN][17];
+    __shared__ double Ys[BT_MAXN][17];
+    __shared__ double Wp[4][16][17];
+    __shared__ double Ws[16][17];
+    __shared__ double WT[16][17];
+    __shared__ double Tm[16][17];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int side = blockIdx.y, c0 = 16 * blockIdx.x;
+    const double* Vh = side == 0 ? VL : VR;
+    double* X = side == 0 ? UB : VB;
+    const int nref = side == 0 ? N : N - 1;
+    const int nblkL = (N + WY_RB - 1) / WY_RB;
+    const int nsteps = (nref + WY_RB - 1) / WY_RB;
+    for (int e = tid; e < N * 16; e += 256) {
+        const int i = e >> 4, q = e & 15;
+        Xs[i][q] = c0 + q < nv ? X[(size_t)i * ld + c0 + q] : 0.0;
+    }
+    // the Y block of a step as 16 x N (row q = reflector k0 + q), read along
+    // the reflector rows; at most BT_MAXN * 16 / 256 = 16 values per thread
+    constexpr int PY = BT_MAXN * 16 / 256;
+    double py[PY];
+    double pt = 0.0;
+    auto prefetch = [&](int st) {
+        const int blk = nsteps - 1 - st, k0 = blk * WY_RB;
+        const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
+#pragma unroll
+        for (int u = 0; u < PY; ++u) {
+            const int e = tid + 256 * u, q = e / N, i = e - q * N;
+            py[u] = (e < 16 * N && q < cnt && i >= k0 + q + side) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+        }
+        pt = Tall[(size_t)(side == 0 ? blk : nblkL + blk) * WY_RB * WY_RB + tid];
+    };
+    prefetch(0);
+    for (int st = 0; st < nsteps; ++st) {
+        const int k0 = (nsteps - 1 - st) * WY_RB;
+        __syncthreads();  // the previous step is done with Ys, Tm, WT and Xs
+#pragma unroll
+        for (int u = 0; u < PY; ++u) {
+            const int e = tid + 256 * u, q = e / N, i = e - q * N;
+            if (e < 16 * N) Ys[i][q] = py[u];
+        }
+        Tm[tid >> 4][tid & 15] = pt;
+        __syncthreads();
+        if (st + 1 < nsteps) prefetch(st + 1);
+        // W = Y^T X over rows >= k0, four rows per MFMA step, interleaved by wavefront
+        {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+            for (int kb = k0 + 4 * wave; kb < N; kb += 16) {
+                const int i = kb + (lane >> 4);
+                const double a = i < N ? Ys[i][lane & 15] : 0.0;
+                const double b = i < N ? Xs[i][lane & 15] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Wp[wave][(lane >> 4) + 4 * r][lane & 15] = acc[r];
+        }
+        __syncthreads();
+        {
+            const int q = tid >> 4, col = tid & 15;
+            Ws[q][col] = ((Wp[0][q][col] + Wp[1][q][col]) + Wp[2][q][col]) + Wp[3][q][col];
+        }
+        __syncthreads();
+        {
+            const int p = tid >> 4, col = tid & 15;
+            double sm = 0.0;
+#pragma unroll
+            for (int q = 0; q < WY_RB; ++q)
+                if (q >= p) sm += Tm[p][q] * Ws[q][col];
+            WT[p][col] = sm;
+        }
+        __syncthreads();
+        // X <- X - Y (T W) over 16-row tiles from k0 (rows above k0 + q + side
+        // have Y = 0)
+        for (int rt = k0 / 16 + wave; 16 * rt < N; rt += 4) {
+            d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int i = 16 * rt + (lane & 15);
+                const double a = i < N ? Ys[i][4 * kk + (lane >> 4)] : 0.0;
+                const double b = WT[4 * kk + (lane >> 4)][lane & 15];
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = 16 * rt + (lane >> 4) + 4 * r;
+                if (row < N) Xs[row][lane & 15] -= acc[r];
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < N * 16; e += 256) {
+        const int i = e >> 4, q = e & 15;
+        if (c0 + q < nv) X[(size_t)i * ld + c0 + q] = Xs[i][q];
+    }
+}
+
 // Sign convention of the singular pairs: the first largest-magnitude entry of
 // the left vector positive (u and v of a pair flip together). One wavefront
 // per column.
@@ -1646,9 +1755,9 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     {
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
-        if (N <= 256)
-            hipLaunchKernelGGL((backtransform_kernel<256, 4>), dim3(blocks, 2), dim3(256), 0, s, N,
-                               nv, VL, VR, Tall, UB, VB, N);
+        if (N <= BT_MAXN)
+            hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0, s,
+                               N, nv, VL, VR, Tall, UB, VB, N);
         else if (N <= 512)
             hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s, N,
                                nv, VL, VR, Tall, UB, VB, N);
