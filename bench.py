@@ -80,6 +80,8 @@ def parse():
                     help="copy: one device copy of 256 MiB (counter calibration)")
     ap.add_argument("--requests", type=int, default=64, help="serving: number of requests")
     ap.add_argument("--slots", type=int, default=8, help="serving: solves in flight")
+    ap.add_argument("--group-window", type=int, default=200,
+                    help="serving: microseconds a ready solve waits for others to group with")
     ap.add_argument("--no-group", action="store_true",
                     help="serving: one launch per W-product instead of grouped launches")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
@@ -334,7 +336,8 @@ def bench_serving(args):
                          torch.tensor(inst["values"], dtype=torch.float32, device="cuda")))
     torch.cuda.synchronize()
     mc_opts = blws.default_mc_opts()
-    srv = blws.Server(0, max_slots=args.slots, group_products=not args.no_group)
+    srv = blws.Server(0, max_slots=args.slots, group_products=not args.no_group,
+                      group_window_us=args.group_window)
     # warm-up: one request of each kind
     for item in data[:2]:
         t = (srv.submit_rpca(item[3]) if item[0] == "rpca"
@@ -396,7 +399,8 @@ def bench_serving(args):
         "data": "synthetic",
         "config": {"workload": "serving_mix_rpca70_mc30", "requests": len(reqs),
                    "m_range": [500, 3000], "arrivals": "poisson, mean gap 20 ms",
-                   "max_slots": args.slots, "grouped_products": not args.no_group},
+                   "max_slots": args.slots, "grouped_products": not args.no_group,
+                   "group_window_us": args.group_window},
         "sequential_fp64_solves_per_s": seq,
         "speedup_vs_sequential_fp64": (len(lat) / total) / seq if seq else None,
         "latency_s_p50": pct(lat, 50),
