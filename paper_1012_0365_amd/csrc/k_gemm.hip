@@ -224,6 +224,62 @@ __global__ void splitk_reduce_kernel(int M, int N, int S, double alpha, const do
     }
 }
 
+// The same sum for many splits (S >= RED_WIDE_MIN_S): a workgroup per 64
+// consecutive elements, wavefront w adding splits w q .. w q + q - 1 in order
+// (q = ceil(S / 4)) with sixteen loads in flight, and the four wavefront sums
+// added in wavefront order, so the result does not depend on scheduling.
+constexpr int RED_WIDE_MIN_S = 16;
+
+template <typename TC>
+__global__ __launch_bounds__(256) void splitk_reduce_wide_kernel(int M, int N, int S, double alpha,
+                                                                 const double* __restrict__ partial,
+                                                                 double beta, const TC* Cin,
+                                                                 int ldcin, TC* C, int ldc)
+{
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const size_t total = (size_t)M * N;
+    const size_t e = (size_t)blockIdx.x * 64 + lane;
+    const int q = (S + 3) / 4, s0 = wave * q, s1 = min(S, s0 + q);
+    double acc = 0.0;
+    if (e < total) {
+        for (int s = s0; s < s1; s += 16) {
+            double v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                v[u] = s + u < s1 ? partial[(size_t)(s + u) * total + e] : 0.0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) acc += v[u];
+        }
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && e < total) {
+        const double sum = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+        const int row = (int)(e / N), col = (int)(e - (size_t)row * N);
+        double out = alpha * sum;
+        if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col];
+        C[(size_t)row * ldc + col] = (TC)out;
+    }
+}
+
+// C = alpha * sum_s partial[s] + beta * Cin by whichever reduction suits S.
+template <typename TC>
+void splitk_reduce(int M, int N, int S, double alpha, const double* partial, double beta,
+                   const TC* Cin, int ldcin, TC* C, int ldc, hipStream_t s)
+{
+    const size_t total = (size_t)M * N;
+    if (S >= RED_WIDE_MIN_S) {
+        hipLaunchKernelGGL((splitk_reduce_wide_kernel<TC>), dim3((unsigned)((total + 63) / 64)),
+                           dim3(256), 0, s, M, N, S, alpha, partial, beta, Cin, ldcin, C, ldc);
+        return;
+    }
+    int blocks = (int)((total + 255) / 256);
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(blocks), dim3(256), 0, s, M, N, S, alpha,
+                       partial, beta, Cin, ldcin, C, ldc);
+}
+
 // The split-K sums of a grouped launch: problem q owns blocks start[q] ..
 // start[q + 1] - 1 (the same sums, in the same order, as alone).
 struct GroupRedF64 {
@@ -620,11 +676,7 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
                        8.0 * ((double)M * K + (double)K * N + (double)M * N));
         hipLaunchKernelGGL((gemm_tn_lk_kernel<TA, TB>), dim3(q.gx, q.gy, q.splits), dim3(256), 0,
                            s, M, N, K, q.kchunk, A, lda, B, ldb, partial);
-        const size_t total = (size_t)M * N;
-        int blocks = (int)((total + 255) / 256);
-        if (blocks > 2048) blocks = 2048;
-        hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(blocks), dim3(256), 0, s, M, N,
-                           q.splits, alpha, partial, beta, Cin, ldcin, C, ldc);
+        splitk_reduce<TC>(M, N, q.splits, alpha, partial, beta, Cin, ldcin, C, ldc, s);
         return;
     }
     Plan p = make_plan(M, N, K);
@@ -639,13 +691,7 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
     else
         launch_nt<TA, TB, TC, false>(p, M, N, K, alpha, A, lda, B, ldb, beta, Cin, ldcin, C, ldc,
                                       split ? partial : nullptr, s);
-    if (split) {
-        const size_t total = (size_t)M * N;
-        int blocks = (int)((total + 255) / 256);
-        if (blocks > 2048) blocks = 2048;
-        hipLaunchKernelGGL((splitk_reduce_kernel<TC>), dim3(blocks), dim3(256), 0, s, M, N,
-                           p.splits, alpha, partial, beta, Cin, ldcin, C, ldc);
-    }
+    if (split) splitk_reduce<TC>(M, N, p.splits, alpha, partial, beta, Cin, ldcin, C, ldc, s);
 }
 
 #define BLWS_GEMM_INST(TA, TB, TC)                                                           \
