@@ -217,11 +217,12 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
     // Columns already orthonormal to 1e-8 (the second Cholesky-QR pass of a
     // block): R^{-1} is replaced by (3 I - G) / 2, with which X R^{-1} is
     // orthonormal to O(|G - I|^2), and no column is dependent.
+    // thread (ty, tx) of an 8 x 128 grid visits rows ty, ty + 8, ... (n <= 128)
+    const int ty = tid >> 7, tx = tid & 127;
     double dv = 0.0;
-    for (int e = tid; e < n * n; e += 1024) {
-        const int i = e / n, j = e - i * n;
-        dv = fmax(dv, fabs(G[(size_t)i * ldg + j] - (i == j ? 1.0 : 0.0)));
-    }
+    if (tx < n)
+        for (int i = ty; i < n; i += 8)
+            dv = fmax(dv, fabs(G[(size_t)i * ldg + tx] - (i == tx ? 1.0 : 0.0)));
     for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
     if ((tid & 63) == 0) dev_w[tid >> 6] = dv;
     __syncthreads();
@@ -229,10 +230,9 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
 #pragma unroll
     for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
     if (m <= 1e-8) {
-        for (int e = tid; e < n * n; e += 1024) {
-            const int i = e / n, j = e - i * n;
-            Rinv[(size_t)i * n + j] = (i == j ? 1.5 : 0.0) - 0.5 * G[(size_t)i * ldg + j];
-        }
+        if (tx < n)
+            for (int i = ty; i < n; i += 8)
+                Rinv[(size_t)i * n + tx] = (i == tx ? 1.5 : 0.0) - 0.5 * G[(size_t)i * ldg + tx];
         for (int i = tid; i < n; i += 1024) flags[i] = 0;
         return;
     }

@@ -381,7 +381,10 @@ void launch_nt(const Plan& p, int M, int N, int K, double alpha, const TA* A, in
 constexpr int SK_MAXK = 512;
 constexpr int TN_MAXMN = 512;
 constexpr int TN_BK = 32;
-constexpr int TN_TARGET_WG = 256;  // workgroups a long-K TN product aims at
+#ifndef BLWS_TN_TARGET_WG
+#define BLWS_TN_TARGET_WG 256
+#endif
+constexpr int TN_TARGET_WG = BLWS_TN_TARGET_WG;  // workgroups a long-K TN product aims at
 
 template <typename TA, typename TB, typename TC, int NTW>
 __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, double alpha,
