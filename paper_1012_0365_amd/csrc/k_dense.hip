@@ -204,6 +204,34 @@ __device__ __forceinline__ void chol_inv_regs(int n, const double* G, int ldg, d
     __syncthreads();
 }
 
+// Thread (ty, tx) of an 8 x 128 grid (1024 threads) loads rows ty + 8 k,
+// k < 16, of column tx of the n x n matrix G (n <= 128, leading dimension
+// ldg) into g[k], every load issued before any is used, and returns the
+// largest |G - I| over the workgroup (dev_w: 16 doubles of LDS).
+__device__ __forceinline__ double load_dev_from_identity(int n, const double* G, int ldg,
+                                                         double (&g)[16], double* dev_w)
+{
+    const int tid = threadIdx.x, ty = tid >> 7, tx = tid & 127;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = ty + 8 * k;
+        g[k] = (i < n && tx < n) ? G[(size_t)i * ldg + tx] : 0.0;
+    }
+    double dv = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int i = ty + 8 * k;
+        if (i < n && tx < n) dv = fmax(dv, fabs(g[k] - (i == tx ? 1.0 : 0.0)));
+    }
+    for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
+    if ((tid & 63) == 0) dev_w[tid >> 6] = dv;
+    __syncthreads();
+    double m = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
+    return m;
+}
+
 __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double* __restrict__ G,
                                                             int ldg, double* __restrict__ Rinv,
                                                             int* flags, int* nflag, double eta)
@@ -217,22 +245,14 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
     // Columns already orthonormal to 1e-8 (the second Cholesky-QR pass of a
     // block): R^{-1} is replaced by (3 I - G) / 2, with which X R^{-1} is
     // orthonormal to O(|G - I|^2), and no column is dependent.
-    // thread (ty, tx) of an 8 x 128 grid visits rows ty, ty + 8, ... (n <= 128)
-    const int ty = tid >> 7, tx = tid & 127;
-    double dv = 0.0;
-    if (tx < n)
-        for (int i = ty; i < n; i += 8)
-            dv = fmax(dv, fabs(G[(size_t)i * ldg + tx] - (i == tx ? 1.0 : 0.0)));
-    for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
-    if ((tid & 63) == 0) dev_w[tid >> 6] = dv;
-    __syncthreads();
-    double m = 0.0;
+    double g[16];
+    if (load_dev_from_identity(n, G, ldg, g, dev_w) <= 1e-8) {
+        const int ty = tid >> 7, tx = tid & 127;
 #pragma unroll
-    for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
-    if (m <= 1e-8) {
-        if (tx < n)
-            for (int i = ty; i < n; i += 8)
-                Rinv[(size_t)i * n + tx] = (i == tx ? 1.5 : 0.0) - 0.5 * G[(size_t)i * ldg + tx];
+        for (int k = 0; k < 16; ++k) {
+            const int i = ty + 8 * k;
+            if (i < n && tx < n) Rinv[(size_t)i * n + tx] = (i == tx ? 1.5 : 0.0) - 0.5 * g[k];
+        }
         for (int i = tid; i < n; i += 1024) flags[i] = 0;
         return;
     }
@@ -308,27 +328,19 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
         // nothing else is done. Otherwise workgroup (side, 0) runs the two
         // Cholesky-QR passes below and the others leave.
         const double* Gp = blockIdx.x == 0 ? G0pre : G1pre;
-        double dv = 0.0;
-        for (int e = tid; e < c * c; e += 1024) {
-            const int i = e / c, j = e - i * c;
-            dv = fmax(dv, fabs(Gp[e] - (i == j ? 1.0 : 0.0)));
-        }
-        for (int off = 32; off > 0; off >>= 1) dv = fmax(dv, __shfl_xor(dv, off, 64));
-        if (lane == 0) dev_w[wave] = dv;
-        __syncthreads();
-        double m = 0.0;
-#pragma unroll
-        for (int w = 0; w < 16; ++w) m = fmax(m, dev_w[w]);
-        if (m <= 1e-8) {
+        double g[16];
+        if (load_dev_from_identity(c, Gp, c, g, dev_w) <= 1e-8) {
             const int r0 = 16 * blockIdx.y;
-            for (int e = tid; e < c * c; e += 1024) {
-                const int i = e / c, j = e - i * c;
-                G[i * CQ_LD + j] = (i == j ? 1.5 : 0.0) - 0.5 * Gp[e];
+            {
+                const int ty = tid >> 7, tx = tid & 127;
+#pragma unroll
+                for (int k = 0; k < 16; ++k) {
+                    const int i = ty + 8 * k;
+                    if (i < c && tx < c) G[i * CQ_LD + tx] = (i == tx ? 1.5 : 0.0) - 0.5 * g[k];
+                }
             }
-            for (int e = tid; e < 16 * c; e += 1024) {
-                const int i = e / c, j = e - i * c;
-                Xs[i][j] = r0 + i < rows ? X[(size_t)(r0 + i) * ld + j] : 0.0;
-            }
+            for (int j = lane; j < c; j += 64)  // row r0 + wave of the block
+                Xs[wave][j] = r0 + wave < rows ? X[(size_t)(r0 + wave) * ld + j] : 0.0;
             __syncthreads();
             if (wave < T) {  // uniform per wavefront
                 const int cb = 16 * wave + (lane & 15);
