@@ -397,10 +397,27 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = blockIdx.x * 16;
     const int K4 = (K + 3) & ~3;
-    for (int row = wave; row < 16; row += 4) {
-        const int gr = r0 + row;
-        for (int k = lane; k < K4; k += 64)
-            AsT[k][row] = (gr < M && k < K) ? ld_d(A + (size_t)gr * lda + k) : 0.0;
+    {
+        // wavefront w stages rows w, w + 4, w + 8, w + 12 of the strip, every
+        // load issued before the first LDS store
+        constexpr int KCH = SK_MAXK / 64;
+        double st[4][KCH];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int gr = r0 + wave + 4 * q;
+#pragma unroll
+            for (int u = 0; u < KCH; ++u) {
+                const int k = lane + 64 * u;
+                st[q][u] = (64 * u < K4 && gr < M && k < K) ? ld_d(A + (size_t)gr * lda + k) : 0.0;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int u = 0; u < KCH; ++u) {
+                const int k = lane + 64 * u;
+                if (k < K4) AsT[k][wave + 4 * q] = st[q][u];
+            }
     }
     __syncthreads();
     const int kq = lane >> 4, cl = lane & 15;
