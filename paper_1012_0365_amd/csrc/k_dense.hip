@@ -289,14 +289,44 @@ __global__ __launch_bounds__(64) void polish_gram_kernel(int rows, int c, const 
     const int lane = threadIdx.x;
     const int ca = 16 * ti + (lane & 15), cb = 16 * tj + (lane & 15);
     d4 acc0 = d4{0.0, 0.0, 0.0, 0.0}, acc1 = d4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < rows; k0 += 8) {
-        const int k = k0 + (lane >> 4), k2 = k + 4;
-        const double a0 = (k < rows && ca < c) ? X[(size_t)k * ld + ca] : 0.0;
-        const double b0 = (k < rows && cb < c) ? X[(size_t)k * ld + cb] : 0.0;
-        const double a1 = (k2 < rows && ca < c) ? X[(size_t)k2 * ld + ca] : 0.0;
-        const double b1 = (k2 < rows && cb < c) ? X[(size_t)k2 * ld + cb] : 0.0;
-        acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc0, 0, 0, 0);
-        acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc1, 0, 0, 0);
+    // batches of 16 rows (four k-steps), the next batch's loads in flight
+    // while the current one feeds the matrix cores; loads are unconditional,
+    // from clamped in-range addresses, and masked only when used, so that
+    // neither a branch nor a select waits on them early
+    double a0[4], b0[4], a1[4], b1[4];
+    const int cac = min(ca, c - 1), cbc = min(cb, c - 1);
+    auto fetch = [&](int k0, double (&av)[4], double (&bv)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * u + (lane >> 4);
+            const double* xr = X + (size_t)min(k, rows - 1) * ld;
+            av[u] = xr[cac];
+            bv[u] = xr[cbc];
+        }
+        // keeps the compiler from merging the two register sets' loads
+        asm volatile("" ::: "memory");
+    };
+    auto compute = [&](int k0, const double (&av)[4], const double (&bv)[4]) {
+#pragma unroll
+        for (int u = 0; u < 4; u += 2) {
+            const int k = k0 + 4 * u + (lane >> 4);
+            const bool i0 = k < rows, i1 = k + 4 < rows;
+            acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64((i0 && ca < c) ? av[u] : 0.0,
+                                                        (i0 && cb < c) ? bv[u] : 0.0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64((i1 && ca < c) ? av[u + 1] : 0.0,
+                                                        (i1 && cb < c) ? bv[u + 1] : 0.0, acc1, 0,
+                                                        0, 0);
+        }
+    };
+    // (the prefetches past the last row read clamped rows and go unused:
+    // unconditional, they leave no branch for the wait counts to merge over)
+    fetch(0, a0, b0);
+    for (int k0 = 0; k0 < rows; k0 += 32) {  // uniform trip count
+        fetch(k0 + 16, a1, b1);
+        compute(k0, a0, b0);
+        if (k0 + 16 >= rows) break;
+        fetch(k0 + 32, a0, b0);
+        compute(k0 + 16, a1, b1);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
