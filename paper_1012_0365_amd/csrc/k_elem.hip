@@ -47,7 +47,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 
 // MODE 0: ALM epilogue. MODE 1: reconstruction only (A_out).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void svt_tile_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void svt_tile_kernel(
     int m, int n, int b, const T* __restrict__ U, int ldu, const T* __restrict__ V, int ldv,
     const double* __restrict__ S, double eps, double lam, double mu, double mu_next,
     const T* __restrict__ D, int ldd, T* __restrict__ Y, T* __restrict__ E, int lde,
@@ -74,60 +74,104 @@ __global__ __launch_bounds__(256) void svt_tile_kernel(
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[j] = d4{0.0, 0.0, 0.0, 0.0};
 
-    for (int k0 = 0; k0 < rank; k0 += EBK) {
-        // 64 rows x 32 ranks of U (scaled by S_k - eps) and of V
-        for (int e = tid; e < TILE * EBK; e += 256) {
-            const int row = e / EBK, kk = e - row * EBK;
-            const int k = k0 + kk;
-            const int gu = r0 + row, gv = c0 + row;
-            double th = 0.0;
-            if (k < rank) th = S[k] - eps;
-            Us[kk][row] = (k < rank && gu < m) ? rd(U + (size_t)gu * ldu + k) * th : 0.0;
-            Vs[kk][row] = (k < rank && gv < n) ? rd(V + (size_t)gv * ldv + k) : 0.0;
-        }
-        __syncthreads();
+    // FP64 16x16 tile: register i of lane l holds row (l / 16) + 4 i, column l % 16
+    const int rbase = r0 + wave * 16 + (lane >> 4);
+    // 64 rows x EBK ranks of U (scaled by S_k - eps) and of V per chunk: thread
+    // (rr, kk) holds rows rr + 16 q, q < 4, of rank kk, the next chunk loaded
+    // into registers (clamped in range) while the current one is used
+    static_assert(TILE * EBK == 4 * 256, "four staged values per thread and matrix");
+    const int kk = tid % EBK, rr = tid / EBK;
+    double ur[4], vr[4], sk = 0.0;
+    auto fetch = [&](int k0) {
+        const int k = min(k0 + kk, rank - 1);
+        sk = S[k];
 #pragma unroll
-        for (int kk = 0; kk < EBK / 4; ++kk) {
-            const double a = Us[kk * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
+        for (int q = 0; q < 4; ++q) {
+            ur[q] = rd(U + (size_t)min(r0 + rr + 16 * q, m - 1) * ldu + k);
+            vr[q] = rd(V + (size_t)min(c0 + rr + 16 * q, n - 1) * ldv + k);
+        }
+    };
+    auto stage = [&](int ch) {
+        const bool kin = ch * EBK + kk < rank;
+        const double th = kin ? sk - eps : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int row = rr + 16 * q;
+            Us[kk][row] = (kin && r0 + row < m) ? ur[q] * th : 0.0;
+            Vs[kk][row] = (kin && c0 + row < n) ? vr[q] : 0.0;
+        }
+    };
+    auto products = [&]() {
+#pragma unroll
+        for (int k4 = 0; k4 < EBK / 4; ++k4) {
+            const double a = Us[k4 * 4 + (lane >> 4)][wave * 16 + (lane & 15)];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const double bv = Vs[kk * 4 + (lane >> 4)][j * 16 + (lane & 15)];
+                const double bv = Vs[k4 * 4 + (lane >> 4)][j * 16 + (lane & 15)];
                 acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc[j], 0, 0, 0);
             }
         }
+    };
+    const int nch = (rank + EBK - 1) / EBK;
+    if (nch > 0) fetch(0);
+    for (int ch = 0; ch + 1 < nch; ++ch) {
+        stage(ch);
+        __syncthreads();
+        fetch((ch + 1) * EBK);
+        products();
         __syncthreads();
     }
-
+    if (nch > 0) {
+        stage(nch - 1);
+        __syncthreads();
+        products();
+    }
     double zz = 0.0;
     const double thr = lam / mu;
-    // FP64 16x16 tile: register i of lane l holds row (l / 16) + 4 i, column l % 16
-    const int rbase = r0 + wave * 16 + (lane >> 4);
+    // the lane's 16 elements in two halves of eight; each half's D and Y are
+    // loaded together (from clamped in-range addresses) before any is used
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int col = c0 + j * 16 + (lane & 15);
+    for (int h = 0; h < 2; ++h) {
+        double dv[2][4], yv[2][4];
+        if (MODE == 0) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int row = rbase + 4 * i;
-            if (row >= m || col >= n) continue;
-            const double a = acc[j][i];
-            if (MODE == 1) {
-                A_out[(size_t)row * lda + col] = (T)a;
-                continue;
+            for (int jj = 0; jj < 2; ++jj)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = min(rbase + 4 * i, m - 1);
+                    const int col = min(c0 + (2 * h + jj) * 16 + (lane & 15), n - 1);
+                    dv[jj][i] = rd(D + (size_t)row * ldd + col);
+                    yv[jj][i] = rd(Y + (size_t)row * n + col);
+                }
+        }
+#pragma unroll
+        for (int jj = 0; jj < 2; ++jj) {
+            const int j = 2 * h + jj;
+            const int col = c0 + j * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = rbase + 4 * i;
+                if (row >= m || col >= n) continue;
+                const double a = acc[j][i];
+                if (MODE == 1) {
+                    A_out[(size_t)row * lda + col] = (T)a;
+                    continue;
+                }
+                const double d = dv[jj][i];
+                const size_t ye = (size_t)row * n + col;
+                const double y = yv[jj][i];
+                const double t = d - a + y / mu;
+                const double e = t > thr ? t - thr : (t < -thr ? t + thr : 0.0);
+                const double z = d - a - e;
+                const double y2 = y + mu * z;
+                E[(size_t)row * lde + col] = (T)e;
+                Y[ye] = (T)y2;
+                const T wn = (T)(d - e + y2 / mu_next);
+                W[ye] = wn;
+                if (Wh) Wh[ye] = bf16_rne((float)wn);
+                if (A_out) A_out[(size_t)row * lda + col] = (T)a;
+                zz += z * z;
             }
-            const double d = rd(D + (size_t)row * ldd + col);
-            const size_t ye = (size_t)row * n + col;
-            const double y = rd(Y + ye);
-            const double t = d - a + y / mu;
-            const double e = t > thr ? t - thr : (t < -thr ? t + thr : 0.0);
-            const double z = d - a - e;
-            const double y2 = y + mu * z;
-            E[(size_t)row * lde + col] = (T)e;
-            Y[ye] = (T)y2;
-            const T wn = (T)(d - e + y2 / mu_next);
-            W[ye] = wn;
-            if (Wh) Wh[ye] = bf16_rne((float)wn);
-            if (A_out) A_out[(size_t)row * lda + col] = (T)a;
-            zz += z * z;
         }
     }
     if (MODE == 0) {
