@@ -55,8 +55,11 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
     // one feeds the matrix cores: A 8 values per thread (NN: 4 threads read 32
     // consecutive k of one row; TN: 8 threads read 64 consecutive columns of
     // one row), B 2 NT values (element e = tid + 256 u of the BK x BN tile).
+    // (held in the storage types and widened when stored to LDS, so that no
+    // conversion waits on a load in flight)
     constexpr int NB = (BK * 16 * NT + NTHREADS - 1) / NTHREADS;
-    double ra[8], rb[NB];
+    TA ra[8];
+    TB rb[NB];
     auto fetch = [&](int k0) {
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 8;
@@ -64,7 +67,7 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gk = k0 + kq + u;
-                ra[u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gr * lda + gk) : 0.0;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : TA(0);
             }
         } else {
             const int kr = tid >> 3, rq = (tid & 7) * 8;
@@ -72,7 +75,7 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 const int gr = r0 + rq + u;
-                ra[u] = (gr < M && gk < ke) ? ld_d(A + (size_t)gk * lda + gr) : 0.0;
+                ra[u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : TA(0);
             }
         }
 #pragma unroll
@@ -80,7 +83,7 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
             const int e = tid + NTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            rb[u] = (e < BK * BN && gk < ke && gc < N) ? ld_d(B + (size_t)gk * ldb + gc) : 0.0;
+            rb[u] = (e < BK * BN && gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : TB(0);
         }
     };
     fetch(kb);
@@ -88,17 +91,17 @@ __device__ __forceinline__ void gemm_f64_block(double* As, double* Bs, int ldbs,
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 8;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) As[(kq + u) * LDA_S + row] = ra[u];
+            for (int u = 0; u < 8; ++u) As[(kq + u) * LDA_S + row] = (double)ra[u];
         } else {
             const int kr = tid >> 3, rq = (tid & 7) * 8;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) As[kr * LDA_S + rq + u] = ra[u];
+            for (int u = 0; u < 8; ++u) As[kr * LDA_S + rq + u] = (double)ra[u];
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int e = tid + NTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
-            if (e < BK * BN) Bs[kr * ldbs + cc] = rb[u];
+            if (e < BK * BN) Bs[kr * ldbs + cc] = (double)rb[u];
         }
         __syncthreads();
         if (k0 + BK < ke) fetch(k0 + BK);
@@ -401,14 +404,14 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
         // wavefront w stages rows w, w + 4, w + 8, w + 12 of the strip, every
         // load issued before the first LDS store
         constexpr int KCH = SK_MAXK / 64;
-        double st[4][KCH];
+        TA st[4][KCH];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const int gr = r0 + wave + 4 * q;
 #pragma unroll
             for (int u = 0; u < KCH; ++u) {
                 const int k = lane + 64 * u;
-                st[q][u] = (64 * u < K4 && gr < M && k < K) ? ld_d(A + (size_t)gr * lda + k) : 0.0;
+                st[q][u] = (64 * u < K4 && gr < M && k < K) ? A[(size_t)gr * lda + k] : TA(0);
             }
         }
 #pragma unroll
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
 #pragma unroll
             for (int u = 0; u < KCH; ++u) {
                 const int k = lane + 64 * u;
-                if (k < K4) AsT[k][wave + 4 * q] = st[q][u];
+                if (k < K4) AsT[k][wave + 4 * q] = (double)st[q][u];
             }
     }
     __syncthreads();
@@ -432,24 +435,24 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
     // while the current one feeds the matrix cores
     constexpr int PF = NTW >= 8 ? 2 : (NTW >= 4 ? 4 : (NTW >= 2 ? 8 : 16));
     const int nst = K4 / 4, ng = (nst + PF - 1) / PF;
-    double b0[PF][NTW], b1[PF][NTW];
-    auto load = [&](int g, double (&bq)[PF][NTW]) {
+    TB b0[PF][NTW], b1[PF][NTW];  // storage type, widened at use
+    auto load = [&](int g, TB (&bq)[PF][NTW]) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             const int k = 4 * (g * PF + u) + kq;
 #pragma unroll
             for (int t = 0; t < NTW; ++t)
-                bq[u][t] = (k < K && col[t] < N) ? ld_d(B + (size_t)k * ldb + col[t]) : 0.0;
+                bq[u][t] = (k < K && col[t] < N) ? B[(size_t)k * ldb + col[t]] : TB(0);
         }
     };
-    auto compute = [&](int g, const double (&bq)[PF][NTW]) {
+    auto compute = [&](int g, const TB (&bq)[PF][NTW]) {
 #pragma unroll
         for (int u = 0; u < PF; ++u) {
             if (g * PF + u >= nst) break;  // uniform
             const double a = AsT[4 * (g * PF + u) + kq][cl];
 #pragma unroll
             for (int t = 0; t < NTW; ++t)
-                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bq[u][t], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, (double)bq[u][t], acc[t], 0, 0, 0);
         }
     };
     load(0, b0);
@@ -492,22 +495,23 @@ __global__ __launch_bounds__(256) void gemm_tn_lk_kernel(int M, int N, int K, in
     // 4 rows of 64 per pass of the 256 threads, coalesced along M / N; the
     // next stage is loaded into registers while the current one is used
     constexpr int NU = TN_BK / 4;
-    double ra[NU], rb[NU];
+    TA ra[NU];  // storage types, widened when stored to LDS
+    TB rb[NU];
     const int gm = m0 + lane, gn = n0 + lane;
     auto fetch = [&](int k0) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
             const int gk = k0 + 4 * u + wave;
-            ra[u] = (gk < ke && gm < M) ? ld_d(A + (size_t)gk * lda + gm) : 0.0;
-            rb[u] = (gk < ke && gn < N) ? ld_d(B + (size_t)gk * ldb + gn) : 0.0;
+            ra[u] = (gk < ke && gm < M) ? A[(size_t)gk * lda + gm] : TA(0);
+            rb[u] = (gk < ke && gn < N) ? B[(size_t)gk * ldb + gn] : TB(0);
         }
     };
     fetch(kb);
     for (int k0 = kb; k0 < ke; k0 += TN_BK) {
 #pragma unroll
         for (int u = 0; u < NU; ++u) {
-            As[4 * u + wave][lane] = ra[u];
-            Bs[4 * u + wave][lane] = rb[u];
+            As[4 * u + wave][lane] = (double)ra[u];
+            Bs[4 * u + wave][lane] = (double)rb[u];
         }
         __syncthreads();
         if (k0 + TN_BK < ke) fetch(k0 + TN_BK);
