@@ -107,8 +107,10 @@ void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s);
 // writes Rinv (n x n, ld n) such that X * Rinv has orthonormal columns when
 // G = X^T X; columns whose scaled pivot is <= eta are flagged (flags[j] = 1)
 // and get a zero column in Rinv. nflag (device int) += number of flags.
+// When n <= 128 and every entry of G - I is within ni_tol, Rinv = (3 I - G) / 2
+// instead (X Rinv orthonormal to O(ni_tol^2)) and no column is flagged.
 void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* flags,
-              int* nflag, double eta, double* scratch, hipStream_t s);
+              int* nflag, double eta, double ni_tol, double* scratch, hipStream_t s);
 size_t chol_scratch_elems(int n);
 
 // Two Cholesky-QR passes on X0 and X1 (rows x c each, leading dimension ld,

@@ -234,7 +234,8 @@ __device__ __forceinline__ double load_dev_from_identity(int n, const double* G,
 
 __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double* __restrict__ G,
                                                             int ldg, double* __restrict__ Rinv,
-                                                            int* flags, int* nflag, double eta)
+                                                            int* flags, int* nflag, double eta,
+                                                            double ni_tol)
 {
     __shared__ double scal[128];
     __shared__ double row[2 * 128];
@@ -242,11 +243,11 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
     __shared__ int flg[128];
     __shared__ double dev_w[16];
     const int tid = threadIdx.x;
-    // Columns already orthonormal to 1e-8 (the second Cholesky-QR pass of a
+    // Columns already orthonormal to ni_tol (the second Cholesky-QR pass of a
     // block): R^{-1} is replaced by (3 I - G) / 2, with which X R^{-1} is
     // orthonormal to O(|G - I|^2), and no column is dependent.
     double g[16];
-    if (load_dev_from_identity(n, G, ldg, g, dev_w) <= 1e-8) {
+    if (load_dev_from_identity(n, G, ldg, g, dev_w) <= ni_tol) {
         const int ty = tid >> 7, tx = tid & 127;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -748,13 +749,13 @@ int grid_for(size_t total)
 size_t chol_scratch_elems(int n) { return n > CHOL_LDS_MAX ? (size_t)n * n : 0; }
 
 void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* flags, int* nflag,
-              double eta, double* scratch, hipStream_t s)
+              double eta, double ni_tol, double* scratch, hipStream_t s)
 {
     BLWS_REQUIRE(n >= 1 && n <= 512, BLWS_EUNSUPPORTED, "chol_inv: block width above 512");
     TimedLaunch tl(tm, "chol", s, (double)n * n * n / 3.0, 16.0 * n * n);
     if (n <= 128)
         hipLaunchKernelGGL(chol_inv_reg_kernel, dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv, flags,
-                           nflag, eta);
+                           nflag, eta, ni_tol);
     else if (n <= CHOL_LDS_MAX)
         hipLaunchKernelGGL((chol_inv_kernel<true>), dim3(1), dim3(1024), 0, s, n, G, ldg, Rinv,
                            flags, nflag, eta, (double*)nullptr);

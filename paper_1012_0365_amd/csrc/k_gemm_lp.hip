@@ -181,7 +181,7 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
     // the next stage's tiles load into registers while the current one is used
     constexpr int NB = (BK * 16 * NT + LNTHREADS - 1) / LNTHREADS;
     unsigned short ra[16];
-    unsigned short rb[NB];
+    float rb[NB];  // rounded to BF16 when stored to LDS, not as it arrives
     auto fetch = [&](int k0) {
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 16;
@@ -205,8 +205,7 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
             const int e = tid + LNTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
             const int gk = k0 + kr, gc = c0 + cc;
-            rb[u] = (e < BK * BN && gk < ke && gc < N) ? f2bf(B[(size_t)gk * ldb + gc])
-                                                       : (unsigned short)0;
+            rb[u] = (e < BK * BN && gk < ke && gc < N) ? B[(size_t)gk * ldb + gc] : 0.f;
         }
     };
     fetch(kb);
@@ -224,7 +223,7 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
         for (int u = 0; u < NB; ++u) {
             const int e = tid + LNTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
-            if (e < BK * BN) Bs[cc * LDK + kr] = rb[u];
+            if (e < BK * BN) Bs[cc * LDK + kr] = f2bf(rb[u]);
         }
         __syncthreads();
         if (k0 + BK < ke) fetch(k0 + BK);

@@ -73,6 +73,16 @@ namespace {
 
 constexpr double CHOL_ETA = 1e-13;  // scaled pivot below which a column is dependent
 
+// Largest |G - I| for which the Cholesky inverse is replaced by (3 I - G) / 2,
+// whose orthonormality error 3 |G - I|^2 / 4 stays below the storage
+// precision's rounding: 1e-8 in FP64, 1e-4 in FP32 (columns stored in FP32
+// are orthonormal to about 1e-7 at best, so a tighter test would never pass).
+template <typename T>
+constexpr double chol_ni_tol()
+{
+    return std::is_same<T, double>::value ? 1e-8 : 1e-4;
+}
+
 // ---------------------------------------------------------------------------
 // Workspace: one device allocation per context, carved into sub-buffers.
 // ---------------------------------------------------------------------------
@@ -390,7 +400,7 @@ void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx
     for (int pass = 0; pass < 2; ++pass) {
         gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, cur, c, cur, c, 0.0,
                            (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
-        chol_inv(tm, c, w.Gr, c, w.Ri, w.flags, w.nflag, CHOL_ETA, w.chol, s);
+        chol_inv(tm, c, w.Gr, c, w.Ri, w.flags, w.nflag, CHOL_ETA, chol_ni_tol<T>(), w.chol, s);
         T* dst = (pass == 0) ? w.T2 : Out;
         const int ldd = (pass == 0) ? c : ldout;
         gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, cur, c, w.Ri, c, 0.0,
