@@ -48,7 +48,11 @@ def test_counter_generator_is_bit_exact(torch, ctx):
                                    # tall-skinny forms: NN with K <= 512, TN with M, N <= 512
                                    (2000, 112, 112), (1999, 511, 512), (33, 300, 3),
                                    (5000, 256, 224), (112, 112, 2000), (448, 448, 2001),
-                                   (512, 512, 4096), (100, 37, 130)])
+                                   (512, 512, 4096), (100, 37, 130),
+                                   # TN split-K sums over 16 or more splits: 128 splits
+                                   # and 3700 outputs (not a multiple of 64), 32 splits
+                                   # and 1500 outputs, 17 splits (quarters of 5, 5, 5, 2)
+                                   (100, 37, 4096), (50, 30, 1000), (112, 112, 540)])
 def test_gemm_matches_numpy(torch, ctx, trans, M, N, K):
     g = np.random.default_rng(M * 7 + N * 3 + K)
     A = g.standard_normal((K, M) if trans else (M, K))
