@@ -10,6 +10,17 @@
 
 namespace blws {
 
+// Counter-based uniform draw: the (counter + 1)-th output of SplitMix64
+// (Steele, Lea & Flood 2014) seeded with `seed`, mapped to [-1, 1).
+__device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t counter)
+{
+    uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    z ^= z >> 31;
+    return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+}
+
 // ---------------------------------------------------------------------------
 // Error plumbing: every HIP call in host code goes through HIP_TRY, which turns
 // a failure into a BlwsError carrying BLWS_EDEVICE and the HIP message.
@@ -90,6 +101,14 @@ struct WProduct {
 bool wproduct_groupable(const WProduct& w);
 bool wproduct_lp_groupable(const WProduct& w);
 // n <= GEMM_GROUP_MAX groupable problems of one precision, on stream s.
+// C = X R (X M x N, R N x N FP64, N <= 512) with the columns j where
+// flags[j] != 0 replaced by the counter-based draws uniform_pm1(seed,
+// (sid << 40) + 4096 i + j): the apply step of a Cholesky-QR pass whose
+// dependent columns are redrawn.
+template <typename T>
+void gemm_apply_flagged(Timer* tm, int M, int N, const T* X, int ldx, const double* R, int ldr,
+                        T* C, int ldc, const int* flags, uint64_t seed, uint64_t sid,
+                        hipStream_t s);
 void gemm_f64_grouped(const WProduct* ps, int n, hipStream_t s);
 void gemm_lp_grouped(const WProduct* ps, int n, hipStream_t s);
 
@@ -122,11 +141,6 @@ bool cholqr2_small_supported(int rows, int c);
 void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, int* nflag,
                    double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, double* G0, double* G1,
                    hipStream_t s);
-
-// Fill flagged columns of X (rows x c, ldx) with the counter-based uniform draw.
-template <typename T>
-void fill_flagged(int rows, int c, T* X, int ldx, const int* flags, uint64_t seed,
-                  uint64_t stream_id, hipStream_t s);
 
 // X[i][j] = u(seed, stream_id * 2^40 + i * 4096 + j) for i < rows, j < cols.
 template <typename T>

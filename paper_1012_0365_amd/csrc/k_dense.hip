@@ -12,17 +12,6 @@ constexpr int CHOL_LDS_MAX = 128;  // Gram matrices up to 128 x 128 live in LDS
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Counter-based uniform draw: the (counter + 1)-th output of SplitMix64
-// (Steele, Lea & Flood 2014) seeded with `seed`, mapped to [-1, 1).
-__device__ __forceinline__ double uniform_pm1(uint64_t seed, uint64_t counter)
-{
-    uint64_t z = seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
-    z ^= z >> 31;
-    return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
-}
-
 // Scaled LDL^T elimination of the Gram matrix G = X^T X, tracking L^{-1} in the
 // strictly lower triangle of the same array (the trailing matrix lives in the
 // upper triangle). With d the pivots and s_i = G_ii^{-1/2}:
@@ -687,20 +676,6 @@ __global__ __launch_bounds__(1024) void jacobi_svd_kernel(int N, const double* _
 }
 
 template <typename T>
-__global__ void fill_flagged_kernel(int rows, int c, T* X, int ldx, const int* flags,
-                                    uint64_t seed, uint64_t stream_id)
-{
-    const size_t total = (size_t)rows * c;
-    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
-         e += (size_t)gridDim.x * blockDim.x) {
-        const int i = (int)(e / c), j = (int)(e - (size_t)i * c);
-        if (flags[j])
-            X[(size_t)i * ldx + j] =
-                (T)uniform_pm1(seed, (stream_id << 40) + (uint64_t)i * 4096ULL + (uint64_t)j);
-    }
-}
-
-template <typename T>
 __global__ void fill_uniform_kernel(int rows, int cols, T* X, int ldx, uint64_t seed,
                                     uint64_t stream_id)
 {
@@ -793,14 +768,6 @@ void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, do
 }
 
 template <typename T>
-void fill_flagged(int rows, int c, T* X, int ldx, const int* flags, uint64_t seed,
-                  uint64_t stream_id, hipStream_t s)
-{
-    hipLaunchKernelGGL((fill_flagged_kernel<T>), dim3(grid_for((size_t)rows * c)), dim3(256), 0, s,
-                       rows, c, X, ldx, flags, seed, stream_id);
-}
-
-template <typename T>
 void fill_uniform(int rows, int cols, T* X, int ldx, uint64_t seed, uint64_t stream_id,
                   hipStream_t s)
 {
@@ -821,10 +788,6 @@ void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t 
     hipLaunchKernelGGL(count_above_kernel, dim3(1), dim3(256), 0, s, b, S, eps, rank_out);
 }
 
-template void fill_flagged<double>(int, int, double*, int, const int*, uint64_t, uint64_t,
-                                   hipStream_t);
-template void fill_flagged<float>(int, int, float*, int, const int*, uint64_t, uint64_t,
-                                  hipStream_t);
 template void fill_uniform<double>(int, int, double*, int, uint64_t, uint64_t, hipStream_t);
 template void fill_uniform<float>(int, int, float*, int, uint64_t, uint64_t, hipStream_t);
 template void copy2d<double, double>(int, int, const double*, int, double*, int, hipStream_t);

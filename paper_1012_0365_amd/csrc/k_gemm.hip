@@ -394,7 +394,8 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
                                                          const TA* __restrict__ A, int lda,
                                                          const TB* __restrict__ B, int ldb,
                                                          double beta, const TC* Cin, int ldcin,
-                                                         TC* C, int ldc)
+                                                         TC* C, int ldc, const int* flags,
+                                                         uint64_t seed, uint64_t sid)
 {
     __shared__ double AsT[SK_MAXK][16];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -472,6 +473,9 @@ __global__ __launch_bounds__(256) void gemm_nn_sk_kernel(int M, int N, int K, do
             if (row >= M) continue;
             double out = alpha * acc[t][i];
             if (beta != 0.0) out += beta * (double)Cin[(size_t)row * ldcin + col[t]];
+            // a column flagged dependent is replaced by counter-based draws
+            if (flags && flags[col[t]])
+                out = uniform_pm1(seed, (sid << 40) + (uint64_t)row * 4096ULL + (uint64_t)col[t]);
             C[(size_t)row * ldc + col[t]] = (TC)out;
         }
     }
@@ -572,7 +576,8 @@ bool use_tn_lk(bool trans_a, int M, int N, int K)
 
 template <typename TA, typename TB, typename TC>
 void launch_nn_sk(int M, int N, int K, double alpha, const TA* A, int lda, const TB* B, int ldb,
-                  double beta, const TC* Cin, int ldcin, TC* C, int ldc, hipStream_t s)
+                  double beta, const TC* Cin, int ldcin, TC* C, int ldc, hipStream_t s,
+                  const int* flags = nullptr, uint64_t seed = 0, uint64_t sid = 0)
 {
     // a workgroup per 16-row strip and group of 4 NTW column tiles; for a
     // short C the column tiles are spread over more workgroups (one per wave)
@@ -586,7 +591,7 @@ void launch_nn_sk(int M, int N, int K, double alpha, const TA* A, int lda, const
 #define BLWS_NNSK_CASE(V)                                                                       \
     case V:                                                                                     \
         hipLaunchKernelGGL((gemm_nn_sk_kernel<TA, TB, TC, V>), grid, block, 0, s, M, N, K, alpha, \
-                           A, lda, B, ldb, beta, Cin, ldcin, C, ldc);                           \
+                           A, lda, B, ldb, beta, Cin, ldcin, C, ldc, flags, seed, sid);         \
         break;
     switch (ntw) {
         BLWS_NNSK_CASE(1)
@@ -717,6 +722,23 @@ void gemm(Timer* tm, const char* family, bool trans_a, int M, int N, int K, doub
                                       split ? partial : nullptr, s);
     if (split) splitk_reduce<TC>(M, N, p.splits, alpha, partial, beta, Cin, ldcin, C, ldc, s);
 }
+
+template <typename T>
+void gemm_apply_flagged(Timer* tm, int M, int N, const T* X, int ldx, const double* R, int ldr,
+                        T* C, int ldc, const int* flags, uint64_t seed, uint64_t sid,
+                        hipStream_t s)
+{
+    if (M <= 0 || N <= 0) return;
+    BLWS_REQUIRE(use_nn_sk(false, N, N), BLWS_EUNSUPPORTED, "gemm_apply_flagged: width");
+    TimedLaunch tl(tm, "gemm_ts", s, 2.0 * M * N * (double)N,
+                   8.0 * ((double)M * N + (double)N * N + (double)M * N));
+    launch_nn_sk<T, double, T>(M, N, N, 1.0, X, ldx, R, ldr, 0.0, (const T*)nullptr, 0, C, ldc, s,
+                               flags, seed, sid);
+}
+template void gemm_apply_flagged<double>(Timer*, int, int, const double*, int, const double*, int,
+                                         double*, int, const int*, uint64_t, uint64_t, hipStream_t);
+template void gemm_apply_flagged<float>(Timer*, int, int, const float*, int, const double*, int,
+                                        float*, int, const int*, uint64_t, uint64_t, hipStream_t);
 
 #define BLWS_GEMM_INST(TA, TB, TC)                                                           \
     template void gemm<TA, TB, TC>(Timer*, const char*, bool, int, int, int, double, const TA*, \

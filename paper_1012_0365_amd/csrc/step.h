@@ -401,15 +401,15 @@ void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx
         gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, cur, c, cur, c, 0.0,
                            (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
         chol_inv(tm, c, w.Gr, c, w.Ri, w.flags, w.nflag, CHOL_ETA, chol_ni_tol<T>(), w.chol, s);
-        T* dst = (pass == 0) ? w.T2 : Out;
-        const int ldd = (pass == 0) ? c : ldout;
-        gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, cur, c, w.Ri, c, 0.0,
-                           (const T*)nullptr, 0, dst, ldd, w.partial, w.partial_elems, s);
-        if (pass == 0) {
+        if (pass == 1) {
+            gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, cur, c, w.Ri, c, 0.0,
+                               (const T*)nullptr, 0, Out, ldout, w.partial, w.partial_elems, s);
+        } else {
+            // T2 = cur R^{-1}, its dependent columns redrawn in the same launch;
             // stream ids of the replacement draws: one sequence per stream
             const uint64_t sid = s == cx.aux ? (1ULL << 21) + (++cx.fix_calls_aux)
                                              : (1ULL << 20) + (++cx.fix_calls);
-            fill_flagged<T>(rows, c, w.T2, c, w.flags, seed, sid, s);
+            gemm_apply_flagged<T>(tm, rows, c, cur, c, w.Ri, c, w.T2, c, w.flags, seed, sid, s);
             if (nx > 0) {
                 project_out<T>(cx, w, s, rows, nx, X, ldx, bx, w.T2, c, w.T1, c);
                 cur = w.T1;
