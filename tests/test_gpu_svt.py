@@ -116,6 +116,27 @@ def test_svt_warm_matches_oracle(torch, ctx, m, n, b, eps, kind):
     compare(gpu, ref, eps)
 
 
+@pytest.mark.parametrize("m,n,b,eps,kind", CASES[:5])
+def test_svt_fp32_warm_matches_oracle(torch, ctx, m, n, b, eps, kind):
+    """FP32 path (W, U, V stored in FP32; Gram matrices, Cholesky and the small
+    SVD in FP64): its second Cholesky-QR pass takes the near-identity form at
+    |G - I| <= 1e-4, which must leave the blocks orthonormal to FP32 rounding.
+    Bars scaled to FP32: Ritz values to 1e-5 of the largest, A to 1e-4."""
+    W = make_w(m, n, kind, seed=m + n)
+    U, V = warm_block(W, b, 1e-2, seed=1)
+    Uo, Vo, So, Ao, ro = oracle.blws_step(W, eps, U, V)
+    Ug, Vg, Sg, Ag, rg = run_gpu(torch, ctx, W, eps, U, V, dtype=torch.float32)
+    assert np.abs(Ug.T @ Ug - np.eye(b)).max() < 2e-5
+    assert np.abs(Vg.T @ Vg - np.eye(b)).max() < 2e-5
+    assert np.abs(Sg - So).max() <= 1e-5 * So[0], np.abs(Sg - So).max() / So[0]
+    na = np.linalg.norm(Ao)
+    if na > 0:
+        assert np.linalg.norm(Ag - Ao) <= 1e-4 * na, np.linalg.norm(Ag - Ao) / na
+    # the rank can differ only where a Ritz value sits within FP32 error of eps
+    if rg != ro:
+        assert np.min(np.abs(So - eps)) <= 1e-5 * So[0]
+
+
 @pytest.mark.parametrize("m,n,b,eps,kind", CASES[:4])
 def test_svt_cold_matches_oracle(torch, ctx, m, n, b, eps, kind):
     W = make_w(m, n, kind, seed=m + 2 * n)
