@@ -590,12 +590,15 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
 {
     Timer* tm = &cx.timer;
     const int b2 = 2 * b;
-    copy2d<T, T>(m, b, U, ldu, w.UF, b2, s);
-    copy2d<T, T>(n, b, V, ldv, w.VG, b2, s);
     // The left (U, P, F) and right (V, Q, G) halves until H are independent:
     // the right half runs on the second stream with its own scratch.
     StepWs<T> wb = w.aux_view();
     cx.fork(s);
+    // U and V into the left halves of [U, F] and [V, G], on this stream after
+    // the fork: the second stream's chain is the longer one and needs neither
+    // (it reads U and V and writes only the right half of [V, G])
+    copy2d<T, T>(m, b, U, ldu, w.UF, b2, s);
+    copy2d<T, T>(n, b, V, ldv, w.VG, b2, s);
     // products with the start block: P = W V, Q = W^T U (the low-rank
     // coefficients of the matrix-completion operator have one buffer: there
     // Q waits for P)
