@@ -8,12 +8,15 @@
 //    device-wide barrier per column. Each step is a left and a right
 //    Householder reflection; their vectors are written to global memory for
 //    the back-transformation.
-// 2. Singular values of Bd by multisection on the Golub-Kahan tridiagonal
-//    T = tridiag(0; d0, e0, d1, e1, ..., d_{N-1}) of size 2N, whose eigenvalues
-//    are +-sigma (Theorem 1 applied to the bidiagonal): one wavefront per value,
-//    64 Sturm counts per step.
-// 3. Singular vectors by inverse iteration on T - sigma I: the eigenvector is
-//    (v0, u0, v1, u1, ...), so u and v come out paired.
+// 2. Singular values of Bd by multisection with Sturm counts of B^T B - x^2 I,
+//    taken by the differential stationary qd transform on the squared
+//    bidiagonal entries (exact for entries perturbed in their last places):
+//    one workgroup per value, 256 counts per multisection step.
+// 3. Singular vectors from the Golub-Kahan tridiagonal T (size 2N, eigenvector
+//    (v0, u0, v1, u1, ...), so u and v come out paired): a twisted
+//    factorisation of T - sigma I for a value isolated to 1e-6 relative,
+//    inverse iteration otherwise (close, repeated or zero values), in the
+//    same workgroup that found the value.
 // 4. Back-transformation through the stored reflectors (one workgroup per
 //    column block).
 #include "blws_common.h"
