@@ -44,8 +44,6 @@ class AlmOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("norm_steps", ctypes.c_int),
         ("norm_rtol", ctypes.c_double),
-        ("b_max", ctypes.c_int),
-        ("b_soft", ctypes.c_int),
     ]
 
 
@@ -75,6 +73,15 @@ def lib():
         L = ctypes.CDLL(_SO)
         d = ctypes.POINTER(ctypes.c_double)
         i = ctypes.POINTER(ctypes.c_int)
+        L.orc_splitmix64.restype = ctypes.c_uint64
+        L.orc_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_predict_rank.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int]
+        L.orc_block_width.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_resize_block.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, d,
+                                       ctypes.c_uint64, ctypes.c_uint64, d]
+        L.orc_rpca_snapshot.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_double,
+                                        ctypes.POINTER(AlmOpts), ctypes.c_int, d, d, d,
+                                        ctypes.c_int, i, d]
         L.orc_uniform.restype = ctypes.c_double
         L.orc_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.orc_fill_uniform.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
@@ -120,6 +127,49 @@ def default_opts(**kw) -> AlmOpts:
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    """The (counter + 1)-th 64-bit output of SplitMix64 seeded with `seed`."""
+    return int(lib().orc_splitmix64(seed, counter))
+
+
+def predict_rank(svp: int, sv: int, step_frac: float, p: int) -> int:
+    return int(lib().orc_predict_rank(svp, sv, step_frac, p))
+
+
+def block_width(sv: int, b_round: int, p: int) -> int:
+    return int(lib().orc_block_width(sv, b_round, p))
+
+
+def resize_block(X, b_new: int, seed: int, stream: int) -> np.ndarray:
+    X = _f64(X)
+    rows, b_old = X.shape
+    Y = np.empty((rows, b_new))
+    rc = lib().orc_resize_block(rows, b_old, b_new, _dp(X), seed, stream, _dp(Y))
+    if rc < 0:
+        raise RuntimeError(f"orc_resize_block failed: {rc}")
+    return Y
+
+
+def rpca_snapshot(D, it: int, lam: float | None = None, b_cap: int = 1024, **opts):
+    """State at the start of BLWS-mode RPCA iteration `it` (1-based): returns
+    (W, U, V, eps) with U, V the warm block of that iteration."""
+    D = _f64(D)
+    m, n = D.shape
+    o = default_opts(**opts)
+    W = np.empty((m, n))
+    U = np.empty(m * b_cap)
+    V = np.empty(n * b_cap)
+    b = ctypes.c_int(0)
+    eps = ctypes.c_double(0.0)
+    rc = lib().orc_rpca_snapshot(m, n, _dp(D), -1.0 if lam is None else float(lam),
+                                 ctypes.byref(o), it, _dp(W), _dp(U), _dp(V), b_cap,
+                                 ctypes.byref(b), ctypes.byref(eps))
+    if rc < 0:
+        raise RuntimeError(f"orc_rpca_snapshot failed: {rc}")
+    bb = b.value
+    return W, U[: m * bb].reshape(m, bb).copy(), V[: n * bb].reshape(n, bb).copy(), eps.value
 
 
 def uniform(seed: int, counter: int) -> float:
@@ -189,7 +239,7 @@ def cold_block(W, b: int, pow_steps: int, seed: int, stream_v: int = 1):
 
 
 def spectral_norm_blws(W, bs: int = 16, pow_steps: int = 2, seed: int = 20101202,
-                       rtol: float = 1e-13, max_steps: int = 60):
+                       rtol: float = 1e-13, max_steps: int = 5000):
     W = _f64(W)
     m, n = W.shape
     steps = ctypes.c_int(0)

@@ -38,9 +38,14 @@ static uint64_t splitmix64_mix(uint64_t z)
     return z ^ (z >> 31);
 }
 
+uint64_t orc_splitmix64(uint64_t seed, uint64_t counter)
+{
+    return splitmix64_mix(seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL);
+}
+
 double orc_uniform(uint64_t seed, uint64_t counter)
 {
-    uint64_t z = splitmix64_mix(seed + (counter + 1ULL) * 0x9E3779B97F4A7C15ULL);
+    uint64_t z = orc_splitmix64(seed, counter);
     return (double)(z >> 11) * 0x1.0p-53 * 2.0 - 1.0;
 }
 
@@ -652,29 +657,27 @@ void orc_default_opts(orc_alm_opts* o)
     o->b_round = 16;
     o->pow_steps = 2;
     o->seed = 20101202ULL;
-    o->norm_steps = 8;
+    o->norm_steps = 5000; /* a safety bound only: the steps stop on norm_rtol */
     o->norm_rtol = 1e-13;
-    o->b_max = 512;
-    o->b_soft = 112;
 }
 
-/* Block width for a predicted rank sv: rounded up, at most floor(p / 2) and
- * at most b_max. Beyond b_soft the block grows only as far as the count of
- * values above the threshold in the previous iteration (svp) requires, without
- * the prediction's extra margin. */
-static int block_width(int sv, int svp, const orc_alm_opts* o, int p)
+/* Block width for a predicted rank sv (Sec. 4.2: the Ritz output follows the
+ * predicted rank): sv rounded up to a multiple of b_round, at most floor(p / 2)
+ * (the projected matrix of one step is 2b x 2b and must fit in min(m, n)). */
+static int block_width(int sv, const orc_alm_opts* o, int p)
 {
     int b = ((sv + o->b_round - 1) / o->b_round) * o->b_round;
-    if (b > o->b_soft) {
-        int need = ((svp + 1 + o->b_round - 1) / o->b_round) * o->b_round;
-        b = need > o->b_soft ? need : o->b_soft;
-        if (b > ((sv + o->b_round - 1) / o->b_round) * o->b_round)
-            b = ((sv + o->b_round - 1) / o->b_round) * o->b_round;
-    }
     if (b > p / 2) b = p / 2;
-    if (b > o->b_max) b = o->b_max;
     if (b < 1) b = 1;
     return b;
+}
+
+int orc_block_width(int sv, int b_round, int p)
+{
+    orc_alm_opts o;
+    orc_default_opts(&o);
+    o.b_round = b_round;
+    return block_width(sv, &o, p);
 }
 
 /* Rank prediction (Sec. 4.2 leaves the rule to the host algorithm): grow by one
@@ -685,6 +688,11 @@ static int predict_rank(int svp, int sv, double step_frac, int p)
     if (svp < sv) return (svp + 1 < p) ? svp + 1 : p;
     int s = svp + (int)lround(step_frac * p);
     return s < p ? s : p;
+}
+
+int orc_predict_rank(int svp, int sv, double step_frac, int p)
+{
+    return predict_rank(svp, sv, step_frac, p);
 }
 
 /* Resize the warm block from width b_old to b_new (row-major, ld = width).
@@ -714,6 +722,19 @@ static void resize_block(int rows, int b_old, int b_new, double** X, uint64_t se
     *X = Y;
 }
 
+int orc_resize_block(int rows, int b_old, int b_new, const double* X, uint64_t seed,
+                     uint64_t stream, double* Y)
+{
+    if (rows < 1 || b_old < 1 || b_new < 1 || b_new > rows || !X || !Y) return -1;
+    double* T = (double*)malloc(sizeof(double) * (size_t)rows * b_old);
+    if (!T) return -2;
+    memcpy(T, X, sizeof(double) * (size_t)rows * b_old);
+    resize_block(rows, b_old, b_new, &T, seed, stream);
+    memcpy(Y, T, sizeof(double) * (size_t)rows * b_new);
+    free(T);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Inexact ALM for RPCA (the "ADM" host of the experiments, Sec. 5):        */
 /*   W = D - E + Y/mu;  A = T_{1/mu}(W);  E = S_{lambda/mu}(D - A + Y/mu);    */
@@ -721,10 +742,47 @@ static void resize_block(int rows, int b_old, int b_new, double** X, uint64_t se
 /* stop when ||Z||_F / ||D||_F < tol. Y_0 = D / max(||D||_2, ||D||_inf/lambda),*/
 /* E_0 = 0, mu_0 = mu0_scale / ||D||_2.                                       */
 /* ------------------------------------------------------------------------ */
+/* State handed out at the start of one iteration of the BLWS-mode loop. */
+typedef struct {
+    int it;          /* 1-based iteration to stop at (0: run to the end) */
+    int b_cap;
+    double *W, *U, *V;
+    int* b;
+    double* eps;
+} rpca_snap;
+
+static int rpca_core(int m, int n, const double* D, double lambda, const orc_alm_opts* opts_in,
+                     int mode, double* A, double* E, double* Yout, int* svp_trace, orc_info* info,
+                     const rpca_snap* snap);
+
 int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* opts_in,
              int mode, double* A, double* E, double* Yout, int* svp_trace, orc_info* info)
 {
     if (m < 2 || n < 2 || !D || !A || !E) return -1;
+    return rpca_core(m, n, D, lambda, opts_in, mode, A, E, Yout, svp_trace, info, NULL);
+}
+
+int orc_rpca_snapshot(int m, int n, const double* D, double lambda, const orc_alm_opts* opts,
+                      int it, double* W, double* U, double* V, int b_cap, int* b, double* eps)
+{
+    if (m < 2 || n < 2 || !D || it < 1 || !W || !U || !V || b_cap < 1 || !b || !eps) return -1;
+    const size_t mn = (size_t)m * n;
+    double* A = (double*)malloc(sizeof(double) * mn);
+    double* E = (double*)malloc(sizeof(double) * mn);
+    if (!A || !E) return -2;
+    const rpca_snap sn = {it, b_cap, W, U, V, b, eps};
+    *b = 0;
+    int rc = rpca_core(m, n, D, lambda, opts, 1, A, E, NULL, NULL, NULL, &sn);
+    free(A);
+    free(E);
+    if (rc == 0 && *b == 0) return -3; /* converged before iteration `it` */
+    return rc;
+}
+
+static int rpca_core(int m, int n, const double* D, double lambda, const orc_alm_opts* opts_in,
+                     int mode, double* A, double* E, double* Yout, int* svp_trace, orc_info* info,
+                     const rpca_snap* snap)
+{
     orc_alm_opts o;
     if (opts_in) o = *opts_in; else orc_default_opts(&o);
     const int p = m < n ? m : n;
@@ -756,7 +814,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
         E[e] = 0.0;
     }
     double mu = o.mu0_scale / s1, mu_bar = mu * o.mu_max_factor;
-    int sv = o.sv0, b = 0, svp = 0, svp_prev = 0, it = 0;
+    int sv = o.sv0, b = 0, svp = 0, it = 0;
     double rel = INFINITY;
     double *U = NULL, *V = NULL, *S = NULL;
     for (it = 1; it <= o.max_iter; ++it) {
@@ -765,7 +823,7 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
         if (mode == 0) {
             orc_svt_exact(m, n, W, eps, A, NULL, &svp);
         } else {
-            int bn = block_width(sv, svp_prev, &o, p);
+            int bn = block_width(sv, &o, p);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);
@@ -775,11 +833,23 @@ int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* o
                 resize_block(n, b, bn, &V, o.seed, 1000 + 2 * (uint64_t)it + 1);
             }
             b = bn;
+            if (snap && it == snap->it) {
+                if (b > snap->b_cap) {
+                    free(Y); free(W); free(U); free(V); free(S);
+                    return -3;
+                }
+                memcpy(snap->W, W, sizeof(double) * mn);
+                memcpy(snap->U, U, sizeof(double) * (size_t)m * b);
+                memcpy(snap->V, V, sizeof(double) * (size_t)n * b);
+                *snap->b = b;
+                *snap->eps = eps;
+                free(Y); free(W); free(U); free(V); free(S);
+                return 0;
+            }
             free(S);
             S = (double*)malloc(sizeof(double) * (size_t)b);
             orc_blws_step(m, n, W, eps, b, U, V, S, A, &svp);
             sv = predict_rank(svp, sv, o.sv_step_frac, p);
-            svp_prev = svp;
         }
         if (svp_trace) svp_trace[it - 1] = svp;
         /* E = S_{lambda/mu}(D - A + Y/mu); Z = D - A - E; Y += mu Z */
@@ -860,7 +930,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
         s1 = spectral_norm_op(&op, 16, o.pow_steps, o.seed, o.norm_rtol, o.norm_steps, NULL);
     }
     double mu = o.mu0_scale / s1, mu_bar = mu * o.mu_max_factor;
-    int sv = o.sv0, b = 0, r = 0, it = 0, svp_prev = 0;
+    int sv = o.sv0, b = 0, r = 0, it = 0;
     double rel = INFINITY;
     double *U = NULL, *V = NULL, *S = NULL, *th = NULL;
     double *Ua = NULL, *Va = NULL; /* factors of the current A (width r) */
@@ -887,7 +957,7 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
             w.Ul = Ua;
             w.Vl = Va;
             w.th = th;
-            int bn = block_width(sv, svp_prev, &o, p);
+            int bn = block_width(sv, &o, p);
             if (b == 0) {
                 U = (double*)malloc(sizeof(double) * (size_t)m * bn);
                 V = (double*)malloc(sizeof(double) * (size_t)n * bn);
@@ -902,7 +972,6 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
             int svp = 0;
             blws_step_op(&w, eps, b, U, V, S, &svp);
             sv = predict_rank(svp, sv, o.sv_step_frac, p);
-            svp_prev = svp;
             /* new A = U_r diag(S_r - eps) V_r^T, kept as factors */
             r = svp;
             free(Ua); free(Va); free(th);

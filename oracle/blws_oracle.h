@@ -17,6 +17,9 @@
 extern "C" {
 #endif
 
+/* The (counter + 1)-th 64-bit output of SplitMix64 seeded with `seed`. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t counter);
+
 /* The (counter + 1)-th output of SplitMix64 seeded with `seed`, mapped to
  * [-1, 1) as ((z >> 11) * 2^-53) * 2 - 1. Exact in binary64. */
 double orc_uniform(uint64_t seed, uint64_t counter);
@@ -61,10 +64,8 @@ typedef struct {
     int b_round;           /* Lanczos block width = sv rounded up to this          */
     int pow_steps;         /* power half-step pairs in the cold start               */
     uint64_t seed;
-    int norm_steps;        /* max BLWS steps for the ||D||_2 estimate               */
-    double norm_rtol;
-    int b_max;             /* upper bound on the Lanczos block width                */
-    int b_soft;            /* beyond this width the block follows svp, not sv      */
+    int norm_steps;        /* safety bound on the BLWS steps of the ||D||_2 estimate */
+    double norm_rtol;      /* those steps stop once the top value changes less      */
 } orc_alm_opts;
 
 typedef struct {
@@ -79,12 +80,32 @@ typedef struct {
 
 void orc_default_opts(orc_alm_opts* o);
 
+/* Rank prediction: svp + 1 if svp < sv, else min(svp + round(step_frac p), p). */
+int orc_predict_rank(int svp, int sv, double step_frac, int p);
+
+/* Block width for a predicted rank: sv rounded up to b_round, at most p / 2. */
+int orc_block_width(int sv, int b_round, int p);
+
+/* The warm block X (rows x b_old) resized to Y (rows x b_new): truncation keeps
+ * the leading columns; growth keeps X and appends the columns of
+ * orc_fill_uniform(rows, b_new - b_old, seed, stream) orthonormalised against X
+ * (Householder QR of [X, R], second block). */
+int orc_resize_block(int rows, int b_old, int b_new, const double* X, uint64_t seed,
+                     uint64_t stream, double* Y);
+
 /* mode: 0 = exact SVT (full Jacobi SVD each iteration, the plain form),
  *       1 = BLWS SVT.
  * Y (m x n, may be NULL) receives the final multiplier. sv_trace (may be NULL,
  * length max_iter) receives the per-iteration svp. */
 int orc_rpca(int m, int n, const double* D, double lambda, const orc_alm_opts* opts,
              int mode, double* A, double* E, double* Y, int* svp_trace, orc_info* info);
+
+/* The BLWS-mode RPCA loop of orc_rpca stopped at the start of iteration `it`
+ * (1-based): W (m x n) receives that iteration's W = D - E + Y/mu, U (m x b)
+ * and V (n x b) its warm block, *b its width (<= b_cap) and *eps = 1/mu.
+ * Returns -3 if the loop converges first or the width exceeds b_cap. */
+int orc_rpca_snapshot(int m, int n, const double* D, double lambda, const orc_alm_opts* opts,
+                      int it, double* W, double* U, double* V, int b_cap, int* b, double* eps);
 
 /* Matrix completion by inexact ALM: min ||A||_* s.t. P_Omega(A) = P_Omega(M).
  * Omega as CSR (row_ptr m+1, col_idx nnz). mode as for orc_rpca; the exact mode

@@ -126,8 +126,9 @@ void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s);
 // writes Rinv (n x n, ld n) such that X * Rinv has orthonormal columns when
 // G = X^T X; columns whose scaled pivot is <= eta are flagged (flags[j] = 1)
 // and get a zero column in Rinv. nflag (device int) += number of flags.
-// When n <= 128 and every entry of G - I is within ni_tol, Rinv = (3 I - G) / 2
-// instead (X Rinv orthonormal to O(ni_tol^2)) and no column is flagged.
+// When n <= 128 and n max|G_ij - I_ij| (a bound on ||G - I||_2) is within
+// ni_tol, Rinv = (3 I - G) / 2 instead (X Rinv orthonormal to 3 ni_tol^2 / 4)
+// and no column is flagged.
 void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* flags,
               int* nflag, double eta, double ni_tol, double* scratch, hipStream_t s);
 size_t chol_scratch_elems(int n);
@@ -136,7 +137,8 @@ size_t chol_scratch_elems(int n);
 // rows <= 512, c <= 128) in place, one workgroup per matrix: dependent
 // columns of the first pass redrawn (stream ids sid0, sid1), counted in nflag.
 // G0, G1 (c x c each) receive the Gram matrices formed first; when a side's
-// is within 1e-8 of I, X (3I - G)/2 replaces the passes, over many workgroups.
+// is within 1e-8 of I in the bound c max|G_ij - I_ij| on ||G - I||_2,
+// X (3I - G)/2 replaces the passes, over many workgroups.
 bool cholqr2_small_supported(int rows, int c);
 void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, int* nflag,
                    double eta, uint64_t seed, uint64_t sid0, uint64_t sid1, double* G0, double* G1,
@@ -147,10 +149,8 @@ template <typename T>
 void fill_uniform(int rows, int cols, T* X, int ldx, uint64_t seed, uint64_t stream_id,
                   hipStream_t s);
 
-// One-sided Jacobi SVD of the N x N matrix B (ldb): UB, VB (N x N, ld N), S (N).
-void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, double* S,
-                      double* VB, double* scratch, hipStream_t s);
-size_t small_svd_jacobi_scratch_elems(int N);
+// SVD of a 1 x 1 matrix B: UB = 1, S = |B|, VB = sign(B).
+void small_svd_1x1(const double* B, double* UB, double* S, double* VB, hipStream_t s);
 
 // Golub-Kahan bidiagonalisation + bisection / inverse iteration on the
 // Golub-Kahan tridiagonal (N <= 512): the top nv singular values S[0..nv) and

@@ -267,8 +267,7 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
                  "blws_small_svd_f64: bad arguments");
     double* svd = nullptr;
     auto layout = [&](Carver& c, blws::OrthWs<double>& w) {
-        size_t e1 = blws::small_svd_jacobi_scratch_elems(N), e2 = blws::small_svd_gk_scratch_elems(N);
-        svd = c.take<double>(e1 > e2 ? e1 : e2);
+        svd = c.take<double>(blws::small_svd_gk_scratch_elems(N));
         w.T1 = c.take<double>((size_t)N * N);
         w.T2 = c.take<double>((size_t)N * N);
         w.Cp = c.take<double>((size_t)N * N);

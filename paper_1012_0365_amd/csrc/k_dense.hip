@@ -232,11 +232,12 @@ __global__ __launch_bounds__(1024) void chol_inv_reg_kernel(int n, const double*
     __shared__ int flg[128];
     __shared__ double dev_w[16];
     const int tid = threadIdx.x;
-    // Columns already orthonormal to ni_tol (the second Cholesky-QR pass of a
-    // block): R^{-1} is replaced by (3 I - G) / 2, with which X R^{-1} is
-    // orthonormal to O(|G - I|^2), and no column is dependent.
+    // Columns already orthonormal (the second Cholesky-QR pass of a block):
+    // with E = G - I and ||E||_2 <= n max|E_ij| <= ni_tol, R^{-1} is replaced
+    // by (3 I - G) / 2, with which X R^{-1} has the Gram matrix
+    // I - 3 E^2 / 4 + O(E^3), and no column is dependent.
     double g[16];
-    if (load_dev_from_identity(n, G, ldg, g, dev_w) <= ni_tol) {
+    if ((double)n * load_dev_from_identity(n, G, ldg, g, dev_w) <= ni_tol) {
         const int ty = tid >> 7, tx = tid & 127;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
@@ -342,14 +343,15 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int T = (c + 15) / 16;
     {
-        // The side's Gram matrix, formed beforehand by polish_gram_kernel. Within
-        // 1e-8 of I (the usual case): workgroup (side, rb) replaces rows 16 rb ..
+        // The side's Gram matrix, formed beforehand by polish_gram_kernel. When
+        // ||G - I||_2 <= c max|G_ij - I_ij| <= 1e-8 (the usual case), X (3 I - G) / 2
+        // is orthonormal to 3 ||G - I||^2 / 4 <= 1e-16: workgroup (side, rb) replaces rows 16 rb ..
         // 16 rb + 15 of X by X (3 I - G) / 2, a column tile per wavefront, and
         // nothing else is done. Otherwise workgroup (side, 0) runs the two
         // Cholesky-QR passes below and the others leave.
         const double* Gp = blockIdx.x == 0 ? G0pre : G1pre;
         double g[16];
-        if (load_dev_from_identity(c, Gp, c, g, dev_w) <= 1e-8) {
+        if ((double)c * load_dev_from_identity(c, Gp, c, g, dev_w) <= 1e-8) {
             const int r0 = 16 * blockIdx.y;
             {
                 const int ty = tid >> 7, tx = tid & 127;
@@ -498,181 +500,14 @@ __global__ __launch_bounds__(1024) void cholqr2_small_kernel(int rows, int c, do
     }
 }
 
-// One-sided (Hestenes) Jacobi SVD of the N x N matrix B in one workgroup.
-// Columns live column-major in global scratch (Ac, Vc). Each round of the
-// round-robin ordering pairs all columns disjointly; a group of G lanes owns
-// one pair, computes the three inner products with a shuffle reduction and
-// applies the rotation to the pair's columns of B and V.
-constexpr int SVD_MAXN = 512;
-
-__global__ __launch_bounds__(1024) void jacobi_svd_kernel(int N, const double* __restrict__ B,
-                                                          int ldb, double* __restrict__ UB,
-                                                          double* __restrict__ S,
-                                                          double* __restrict__ VB, double* Ac,
-                                                          double* Vc, double tol, int max_sweeps)
+// SVD of a 1 x 1 matrix: the left vector +1 (the sign convention), the
+// value |b|, the right vector sign(b) (+1 for b = 0).
+__global__ void svd1_kernel(const double* B, double* UB, double* S, double* VB)
 {
-    __shared__ int rot_count;
-    __shared__ double sig[SVD_MAXN];
-    __shared__ int perm[SVD_MAXN];
-    __shared__ int ok[SVD_MAXN];
-    __shared__ double vtmp[SVD_MAXN];
-    __shared__ double dots[SVD_MAXN];
-    __shared__ double red;
-    const int tid = threadIdx.x, nth = blockDim.x;
-    for (int e = tid; e < N * N; e += nth) {
-        const int j = e / N, i = e - j * N;
-        Ac[e] = B[(size_t)i * ldb + j];
-        Vc[e] = (i == j) ? 1.0 : 0.0;
-    }
-    __syncthreads();
-    const int Ne = N + (N & 1);
-    const int npairs = Ne / 2;
-    int G = 64;
-    while (G > 1 && G * npairs > nth) G >>= 1;
-    const int grp = tid / G, gl = tid % G;
-    for (int sweep = 0; sweep < max_sweeps && N > 1; ++sweep) {
-        if (tid == 0) rot_count = 0;
-        __syncthreads();
-        for (int round = 0; round < Ne - 1; ++round) {
-            if (grp < npairs) {
-                int p, q;
-                if (grp == 0) {
-                    p = round;
-                    q = Ne - 1;
-                } else {
-                    p = (round + grp) % (Ne - 1);
-                    q = (round - grp + (Ne - 1)) % (Ne - 1);
-                }
-                if (p > q) {
-                    const int t = p;
-                    p = q;
-                    q = t;
-                }
-                if (q < N) {
-                    double* ap = Ac + (size_t)p * N;
-                    double* aq = Ac + (size_t)q * N;
-                    double al = 0.0, be = 0.0, ga = 0.0;
-                    for (int i = gl; i < N; i += G) {
-                        const double x = ap[i], y = aq[i];
-                        al += x * x;
-                        be += y * y;
-                        ga += x * y;
-                    }
-                    for (int off = G >> 1; off > 0; off >>= 1) {
-                        al += __shfl_xor(al, off, G);
-                        be += __shfl_xor(be, off, G);
-                        ga += __shfl_xor(ga, off, G);
-                    }
-                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double t =
-                            (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double c = 1.0 / sqrt(1.0 + t * t);
-                        const double s = c * t;
-                        for (int i = gl; i < N; i += G) {
-                            const double x = ap[i], y = aq[i];
-                            ap[i] = c * x - s * y;
-                            aq[i] = s * x + c * y;
-                        }
-                        double* vp = Vc + (size_t)p * N;
-                        double* vq = Vc + (size_t)q * N;
-                        for (int i = gl; i < N; i += G) {
-                            const double x = vp[i], y = vq[i];
-                            vp[i] = c * x - s * y;
-                            vq[i] = s * x + c * y;
-                        }
-                        if (gl == 0) atomicAdd(&rot_count, 1);
-                    }
-                }
-            }
-            __syncthreads();
-        }
-        const int rc = rot_count;
-        __syncthreads();
-        if (rc == 0) break;
-    }
-    // singular values = column norms; left vectors = normalised columns
-    for (int j = tid; j < N; j += nth) {
-        const double* a = Ac + (size_t)j * N;
-        double s2 = 0.0;
-        for (int i = 0; i < N; ++i) s2 += a[i] * a[i];
-        sig[j] = sqrt(s2);
-        ok[j] = sig[j] > 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < N * N; e += nth) {
-        const int j = e / N;
-        if (ok[j]) Ac[e] /= sig[j];
-    }
-    __syncthreads();
-    // complete exactly-zero columns with unit vectors orthogonalised (twice)
-    // against the accepted columns
-    int cand = 0;
-    for (int zc = 0; zc < N; ++zc) {
-        if (ok[zc]) continue;  // uniform: ok[] is shared
-        for (; cand < N; ++cand) {
-            for (int i = tid; i < N; i += nth) vtmp[i] = (i == cand) ? 1.0 : 0.0;
-            __syncthreads();
-            for (int pass = 0; pass < 2; ++pass) {
-                for (int j = tid; j < N; j += nth) {
-                    double d = 0.0;
-                    if (ok[j])
-                        for (int i = 0; i < N; ++i) d += Ac[(size_t)j * N + i] * vtmp[i];
-                    dots[j] = d;
-                }
-                __syncthreads();
-                for (int i = tid; i < N; i += nth) {
-                    double v = vtmp[i];
-                    for (int j = 0; j < N; ++j)
-                        if (ok[j]) v -= dots[j] * Ac[(size_t)j * N + i];
-                    vtmp[i] = v;
-                }
-                __syncthreads();
-            }
-            if (tid == 0) {
-                double s2 = 0.0;
-                for (int i = 0; i < N; ++i) s2 += vtmp[i] * vtmp[i];
-                red = sqrt(s2);
-            }
-            __syncthreads();
-            const double nv = red;
-            if (nv > 0.5) {
-                for (int i = tid; i < N; i += nth) Ac[(size_t)zc * N + i] = vtmp[i] / nv;
-                __syncthreads();
-                if (tid == 0) ok[zc] = 1;
-                __syncthreads();
-                ++cand;
-                break;
-            }
-            __syncthreads();
-        }
-    }
-    // decreasing order, ties by column index. The key maps NaN to -inf so the
-    // order is total and perm is a permutation whatever the data hold.
-    for (int j = tid; j < N; j += nth) {
-        const double kj = isnan(sig[j]) ? -INFINITY : sig[j];
-        int pos = 0;
-        for (int k = 0; k < N; ++k) {
-            const double kk = isnan(sig[k]) ? -INFINITY : sig[k];
-            pos += (kk > kj) || (kk == kj && k < j);
-        }
-        perm[pos] = j;
-    }
-    __syncthreads();
-    for (int t = tid; t < N; t += nth) {
-        int j = perm[t];
-        if (j < 0 || j >= N) j = t;  // unreachable when perm is a permutation
-        const double* u = Ac + (size_t)j * N;
-        int imax = 0;
-        for (int i = 1; i < N; ++i)
-            if (fabs(u[i]) > fabs(u[imax])) imax = i;
-        const double sg = u[imax] < 0.0 ? -1.0 : 1.0;
-        S[t] = sig[j];
-        for (int i = 0; i < N; ++i) {
-            UB[(size_t)i * N + t] = sg * u[i];
-            VB[(size_t)i * N + t] = sg * Vc[(size_t)j * N + i];
-        }
-    }
+    const double v = B[0];
+    UB[0] = 1.0;
+    S[0] = fabs(v);
+    VB[0] = v < 0.0 ? -1.0 : 1.0;
 }
 
 template <typename T>
@@ -755,16 +590,9 @@ void cholqr2_small(Timer* tm, int rows, int c, double* X0, double* X1, int ld, i
                        X0, X1, ld, nflag, eta, seed, sid0, sid1, G0, G1);
 }
 
-size_t small_svd_jacobi_scratch_elems(int N) { return 2 * (size_t)N * N; }
-
-void small_svd_jacobi(Timer* tm, int N, const double* B, int ldb, double* UB, double* S,
-                      double* VB, double* scratch, hipStream_t s)
+void small_svd_1x1(const double* B, double* UB, double* S, double* VB, hipStream_t s)
 {
-    BLWS_REQUIRE(N >= 1 && N <= SVD_MAXN, BLWS_EUNSUPPORTED, "small_svd: size above 512");
-    TimedLaunch tl(tm, "jacobi_svd", s, 10.0 * (double)N * N * N, 32.0 * N * N);
-    const double tol = sqrt((double)N) * 0x1.0p-53;
-    hipLaunchKernelGGL(jacobi_svd_kernel, dim3(1), dim3(1024), 0, s, N, B, ldb, UB, S, VB, scratch,
-                       scratch + (size_t)N * N, tol, 60);
+    hipLaunchKernelGGL(svd1_kernel, dim3(1), dim3(1), 0, s, B, UB, S, VB);
 }
 
 template <typename T>

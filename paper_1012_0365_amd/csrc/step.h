@@ -73,14 +73,15 @@ namespace {
 
 constexpr double CHOL_ETA = 1e-13;  // scaled pivot below which a column is dependent
 
-// Largest |G - I| for which the Cholesky inverse is replaced by (3 I - G) / 2,
-// whose orthonormality error 3 |G - I|^2 / 4 stays below the storage
-// precision's rounding: 1e-8 in FP64, 1e-4 in FP32 (columns stored in FP32
-// are orthonormal to about 1e-7 at best, so a tighter test would never pass).
+// Bound on ||G - I||_2 (taken as n max|G_ij - I_ij|) below which the Cholesky
+// inverse is replaced by (3 I - G) / 2, whose orthonormality error
+// 3 ||G - I||^2 / 4 then stays below the storage precision's rounding: 1e-8 in
+// FP64, 2.5e-4 in FP32 (4.7e-8; columns stored in FP32 are orthonormal to
+// about 1e-7 at best, so an FP64-sized test would never pass there).
 template <typename T>
 constexpr double chol_ni_tol()
 {
-    return std::is_same<T, double>::value ? 1e-8 : 1e-4;
+    return std::is_same<T, double>::value ? 1e-8 : 2.5e-4;
 }
 
 // ---------------------------------------------------------------------------
@@ -299,10 +300,7 @@ struct StepWs {
         UB = c.take<double>((size_t)b2 * b2);
         VB = c.take<double>((size_t)b2 * b2);
         Sall = c.take<double>((size_t)b2);
-        {
-            size_t e1 = small_svd_jacobi_scratch_elems(b2), e2 = small_svd_gk_scratch_elems(b2);
-            svd = c.take<double>(e1 > e2 ? e1 : e2);
-        }
+        svd = c.take<double>(small_svd_gk_scratch_elems(b2));
         D1 = c.take<double>((size_t)b2 * b);
         D2 = c.take<double>((size_t)b2 * b);
         chol = c.take<double>(chol_scratch_elems(b) + 1);
@@ -457,9 +455,9 @@ void orth_against(Context& cx, StepWs<T>& sw, hipStream_t s, int rows, int b0, c
 }
 
 // SVD of the small projected matrix: the top nv values and vectors, by the
-// Golub-Kahan path (N <= 1024), whose leading vectors are then polished to
-// orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
-// values only nearly orthogonal). The one-sided Jacobi kernel serves larger N.
+// Golub-Kahan path (2 <= N <= 1024), whose leading vectors are then polished
+// to orthonormal by Cholesky-QR (inverse iteration leaves the vectors of close
+// values only nearly orthogonal).
 // nflag[1] is set if the cooperative bidiagonalisation timed out.
 void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double* B, int ldb,
                         double* UB, double* S, double* VB, double* svd_scratch,
@@ -480,7 +478,8 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
             orth_against<double>(cx, w, s, N, 0, nullptr, 0, VB, N, nv, VB, N, seed);
         }
     } else {
-        small_svd_jacobi(&cx.timer, N, B, ldb, UB, S, VB, svd_scratch, s);
+        BLWS_REQUIRE(N == 1, BLWS_EUNSUPPORTED, "small SVD: size above 1024");
+        small_svd_1x1(B, UB, S, VB, s);
     }
 }
 

@@ -42,7 +42,7 @@ MC_CASES = {
     # matrix completion: n = 5000, L, R 5000 x 50 N(0, 1), 10% of entries sampled,
     # stop at relative residual on Omega < 1e-6
     "mc_n5000_s0": dict(m=5000, n=5000, r=50, frac=0.10, seed=0, tol=1e-6, rho=1.1,
-                        mu0_scale=1.0, b_max=256),
+                        mu0_scale=1.0),
 }
 
 SAMPLES = 4096
@@ -89,8 +89,7 @@ def make_mc(name: str) -> dict:
     inst = synth.mc_instance(c["m"], c["n"], c["r"], c["frac"], c["seed"])
     t0 = time.time()
     out = oracle.mc(c["m"], c["n"], inst["row_ptr"], inst["col_idx"], inst["values"],
-                    mode="blws", r_cap=256, tol=c["tol"], rho=c["rho"], mu0_scale=c["mu0_scale"],
-                    b_max=c.get("b_max", 256))
+                    mode="blws", r_cap=256, tol=c["tol"], rho=c["rho"], mu0_scale=c["mu0_scale"])
     secs = time.time() - t0
     U, S, V = out["U"], out["S"], out["V"]
     pos = synth.sample_positions(c["m"], c["n"], SAMPLES, SAMPLE_SEED)

@@ -93,6 +93,42 @@ def test_small_svd_matches_oracle_jacobi(torch, ctx, N):
     assert np.linalg.norm(UB * S @ VB.T - B) <= 1e-13 * np.linalg.norm(B)
 
 
+@pytest.mark.parametrize("N", [224, 512])
+@pytest.mark.parametrize("kind", ["repeated", "clustered"])
+def test_small_svd_multiple_and_clustered_values(torch, ctx, N, kind):
+    """B = Q1 diag(sigma) Q2^T with nonzero values repeated (groups of 4 equal
+    values) or clustered (groups of 4 within 1e-12 relative): the inverse
+    iteration branch. Values to 1e-13 against the oracle's Jacobi and against
+    the prescribed sigma; vectors through orthonormality, the reconstruction
+    and the spectral projectors of whole groups (the vectors inside a group are
+    not unique)."""
+    g = np.random.default_rng(N + len(kind))
+    base = np.geomspace(100.0, 1e-3, N // 4)
+    if kind == "repeated":
+        sigma = np.repeat(base, 4)
+    else:
+        sigma = (base[:, None] * (1.0 + 1e-12 * np.arange(4))[None, :]).reshape(-1)
+    sigma = np.sort(sigma)[::-1]
+    B, q1, q2 = synth.prescribed_spectrum(N, N, sigma, seed=N)
+    UB, S, VB = ctx.small_svd_f64(dev(torch, B))
+    torch.cuda.synchronize()
+    UB, S, VB = host(UB), host(S), host(VB)
+    _, So, _ = oracle.jacobi_svd(B)
+    assert np.all(np.abs(S - So) <= 1e-13 * So[0] + 1e-12 * So)
+    assert np.all(np.abs(S - sigma) <= 1e-13 * sigma[0] + 1e-12 * sigma)
+    assert np.abs(UB.T @ UB - np.eye(N)).max() < 1e-13
+    assert np.abs(VB.T @ VB - np.eye(N)).max() < 1e-13
+    assert np.linalg.norm(UB * S @ VB.T - B) <= 1e-13 * np.linalg.norm(B)
+    nb = np.linalg.norm(B)
+    for k in range(0, N, 4):
+        Pg = UB[:, k:k + 4] @ UB[:, k:k + 4].T
+        Pq = q1[:, k:k + 4] @ q1[:, k:k + 4].T
+        # group gap over the group scale bounds the projector error (Davis-Kahan)
+        gap = min(abs(sigma[k - 1] - sigma[k]) if k else np.inf,
+                  abs(sigma[k + 3] - sigma[k + 4]) if k + 4 < N else np.inf)
+        assert np.abs(Pg - Pq).max() <= 1e-13 * nb / gap + 1e-12
+
+
 def test_small_svd_rank_deficient(torch, ctx):
     g = np.random.default_rng(3)
     B = g.standard_normal((40, 3)) @ g.standard_normal((3, 40))

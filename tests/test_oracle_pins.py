@@ -33,6 +33,21 @@ def test_uniform_generator_range_and_moments():
     assert np.all(np.mod(X * 2.0**52, 1.0) == 0.0)
 
 
+def test_splitmix64_published_outputs():
+    """SplitMix64 (Steele, Lea & Flood 2014) reference outputs: the first three
+    64-bit values of the generators seeded with 0 and with 1234567."""
+    assert [oracle.splitmix64(0, k) for k in range(3)] == [
+        16294208416658607535, 7960286522194355700, 487617019471545679]
+    assert [oracle.splitmix64(1234567, k) for k in range(3)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423]
+
+
+def test_uniform_is_the_top_53_bits_mapped_to_pm1():
+    for seed, k in [(0, 0), (0, 2), (1234567, 1)]:
+        z = oracle.splitmix64(seed, k)
+        assert oracle.uniform(seed, k) == (z >> 11) * 2.0**-52 - 1.0
+
+
 # --------------------------------------------------------------------------
 # one-sided Jacobi SVD
 # --------------------------------------------------------------------------
@@ -254,6 +269,100 @@ def test_spectral_norm_by_blws():
     assert np.abs(V.T @ V - np.eye(8)).max() < 1e-13
 
 
+def _projector(X):
+    Q = np.linalg.qr(X)[0]
+    return Q @ Q.T
+
+
+def test_cold_block_without_power_steps_spans_the_drawn_blocks():
+    """pow_steps = 0: V spans the generator's block of stream s, U that of
+    stream s + 1 (both orthonormal)."""
+    W = synth.gaussian((70, 50), seed=4)
+    U, V = oracle.cold_block(W, 6, 0, seed=99, stream_v=5)
+    Rv = oracle.fill_uniform(50, 6, seed=99, stream=5)
+    Ru = oracle.fill_uniform(70, 6, seed=99, stream=6)
+    assert np.abs(V.T @ V - np.eye(6)).max() < 1e-14
+    assert np.abs(U.T @ U - np.eye(6)).max() < 1e-14
+    assert np.abs(_projector(V) - _projector(Rv)).max() < 1e-13
+    assert np.abs(_projector(U) - _projector(Ru)).max() < 1e-13
+
+
+def test_cold_block_power_steps_contract_like_subspace_iteration():
+    """Each power half-step pair V <- orth(W^T orth(W V)) is one step of subspace
+    iteration on W^T W: with the top b singular values equal (8) and one value
+    (4) below them, the tangent of the largest principal angle between span(V)
+    and the top right singular subspace shrinks by exactly (4/8)^2 per step once
+    the much smaller rest of the spectrum has died out. U stays the independent
+    draw of stream s + 1 whatever the number of steps."""
+    b, m, n = 6, 150, 120
+    sigma = np.r_[np.full(b, 8.0), 4.0, np.geomspace(0.05, 0.01, n - b - 1)]
+    W, q1, q2 = synth.prescribed_spectrum(m, n, sigma, seed=17)
+    top = q2[:, :b]
+    tans = []
+    for t in range(4):
+        U, V = oracle.cold_block(W, b, t, seed=3, stream_v=1)
+        cos = np.linalg.svd(top.T @ V, compute_uv=False).min()
+        tans.append(np.sqrt(1.0 - cos * cos) / cos)
+        assert np.abs(_projector(U) - _projector(oracle.fill_uniform(m, b, 3, 2))).max() < 1e-13
+    ratios = [tans[t] / tans[t - 1] for t in range(1, 4)]
+    assert ratios[0] < 0.2501, ratios
+    assert all(abs(r - 0.25) < 1e-3 for r in ratios[1:]), ratios
+
+
+def test_predict_rank_hand_worked():
+    """Rank rule of the host solver: one more than the count above the threshold
+    when it fell short of the prediction, else that count plus 5% of min(m, n),
+    never beyond min(m, n)."""
+    assert oracle.predict_rank(50, 60, 0.05, 2000) == 51
+    assert oracle.predict_rank(0, 10, 0.05, 2000) == 1
+    assert oracle.predict_rank(101, 101, 0.05, 2000) == 201
+    assert oracle.predict_rank(10, 10, 0.05, 200) == 20
+    assert oracle.predict_rank(1990, 1000, 0.05, 2000) == 2000
+    assert oracle.predict_rank(1999, 2000, 0.05, 2000) == 2000
+
+
+def test_block_width_hand_worked():
+    """b = the predicted rank rounded up to a multiple of 16, at most p / 2."""
+    assert oracle.block_width(101, 16, 2000) == 112
+    assert oracle.block_width(112, 16, 2000) == 112
+    assert oracle.block_width(113, 16, 2000) == 128
+    assert oracle.block_width(1, 16, 2000) == 16
+    assert oracle.block_width(201, 16, 2000) == 208
+    assert oracle.block_width(1500, 16, 2000) == 1000
+    assert oracle.block_width(5, 16, 20) == 10
+    assert oracle.block_width(5, 4, 20) == 8
+
+
+def test_resize_block_truncates_or_extends_the_span():
+    g = np.random.default_rng(2)
+    X = np.linalg.qr(g.standard_normal((40, 7)))[0]
+    Y = oracle.resize_block(X, 4, seed=5, stream=11)
+    assert np.array_equal(Y, X[:, :4])
+    Y = oracle.resize_block(X, 12, seed=5, stream=11)
+    R = oracle.fill_uniform(40, 5, seed=5, stream=11)
+    assert np.array_equal(Y[:, :7], X)
+    assert np.abs(Y.T @ Y - np.eye(12)).max() < 1e-14
+    assert np.abs(_projector(Y) - _projector(np.hstack([X, R]))).max() < 1e-13
+
+
+def test_rpca_snapshot_first_iteration_closed_form():
+    """Iteration 1 of the RPCA loop: W = D + Y0/mu0 with Y0 = D / max(||D||_2,
+    ||D||_inf / lambda), mu0 = 1.25 / ||D||_2 and eps = 1/mu0, ||D||_2 exact;
+    the first block is 16 wide (predicted rank 10) and orthonormal."""
+    inst = synth.rpca_instance(120, 90, 6, 0.05, 50.0, 1)
+    D = inst["D"]
+    W, U, V, eps = oracle.rpca_snapshot(D, 1)
+    s1 = np.linalg.norm(D, 2)
+    lam = 1.0 / np.sqrt(120)
+    J = max(s1, np.abs(D).max() / lam)
+    mu0 = 1.25 / s1
+    assert eps == pytest.approx(1.0 / mu0, rel=1e-12)
+    assert np.abs(W - (D + D / J / mu0)).max() <= 1e-12 * np.abs(D).max()
+    assert U.shape == (120, 16) and V.shape == (90, 16)
+    assert np.abs(U.T @ U - np.eye(16)).max() < 1e-13
+    assert np.abs(V.T @ V - np.eye(16)).max() < 1e-13
+
+
 # --------------------------------------------------------------------------
 # inexact ALM for RPCA
 # --------------------------------------------------------------------------
@@ -267,6 +376,8 @@ def test_rpca_exact_recovery_small(seed):
         info = out["info"]
         assert info["status"] == 0 and info["rel_residual"] < 1e-7
         assert info["rank"] == 10
+        # ||D||_2 (it sets Y0 and mu0) to rounding in both modes
+        assert info["norm2_D"] == pytest.approx(np.linalg.norm(inst["D"], 2), rel=1e-11)
         assert np.linalg.norm(out["A"] - inst["A0"]) / nA0 < 2e-6
         assert abs(info["nnz_E"] - inst["nnz"]) <= 10
         lam = 1.0 / np.sqrt(200)
