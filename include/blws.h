@@ -71,9 +71,9 @@ typedef struct {
     unsigned long long seed;  /* counter-based generator seed                           */
     int norm_steps;           /* max BLWS steps for the ||D||_2 estimate (8)            */
     double norm_rtol;         /* relative change that stops the ||D||_2 steps (1e-13)   */
-    int b_max;                /* upper bound on the block width, <= 512 (512; MC 256)   */
-    int b_soft;               /* beyond this width the block follows the previous count */
-                              /* of values above the threshold, not the prediction (112)*/
+    int b_max;                /* upper bound on the block width, <= 512 (512; MC 256);  */
+                              /* the width is the predicted rank rounded up to b_round, */
+                              /* at most min(m, n) / 2 and b_max                        */
     double ladder_tol;        /* BLWS_BF16 solves: W products in BF16 while the relative */
                               /* residual is at or above this, FP32 below (1e-3)         */
 } blws_alm_opts;
@@ -125,7 +125,10 @@ int blws_rpca_solve(blws_ctx ctx, void* stream, int prec, int m, int n, const vo
                     void* E, int lde, blws_solve_info* info);
 
 /* Defaults of the matrix-completion solver: those of blws_default_alm_opts
- * with tol = 1e-6, rho = 1.1 and mu0_scale = 1.0 (mu_0 = 1/||P_Omega(M)||_2). */
+ * with tol = 1e-6, rho = 1.05 and mu0_scale = 1.0 (mu_0 = 1/||P_Omega(M)||_2);
+ * rho = 1.05 is the largest value with which n = 5000, rank 50, 10% sampled
+ * ends at the planted rank (larger ones keep spurious components just above
+ * the last threshold). */
 void blws_default_mc_opts(blws_alm_opts* opts);
 
 /* Matrix completion: min ||A||_* s.t. P_Omega(A) = P_Omega(M), by inexact ALM

@@ -94,9 +94,10 @@ class Context:
 
     # -- the BLWS SVT step ---------------------------------------------------
     def svt(self, W, eps: float, U, V, warm: bool = True, A=None, S=None, seed: int = 20101202,
-            pow_steps: int = 2):
+            pow_steps: int = 2, rank=None):
         """A = T_eps(W) by one BLWS step. U (m x b), V (n x b) are updated in
-        place with the top-b Ritz vectors. Returns (S, rank) as device tensors."""
+        place with the top-b Ritz vectors. Returns (S, rank) as device tensors
+        (S: float64 [b], rank: int32 [1]; pass them in to reuse buffers)."""
         torch = _torch()
         prec = _prec_of(W)
         ldw = _check_mat(W, "W")
@@ -108,7 +109,10 @@ class Context:
             raise ValueError("U must be m x b and V n x b, with W's dtype")
         if S is None:
             S = torch.empty(b, dtype=torch.float64, device=W.device)
-        rank = torch.zeros(1, dtype=torch.int32, device=W.device)
+        if rank is None:
+            rank = torch.zeros(1, dtype=torch.int32, device=W.device)
+        if S.dtype != torch.float64 or S.numel() < b or rank.dtype != torch.int32:
+            raise ValueError("S must be float64 with b entries and rank int32")
         lda = 0
         if A is not None:
             lda = _check_mat(A, "A")

@@ -37,7 +37,6 @@ class AlmOpts(ctypes.Structure):
         ("norm_steps", ctypes.c_int),
         ("norm_rtol", ctypes.c_double),
         ("b_max", ctypes.c_int),
-        ("b_soft", ctypes.c_int),
         ("ladder_tol", ctypes.c_double),
     ]
 

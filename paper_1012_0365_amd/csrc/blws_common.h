@@ -171,6 +171,11 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
 template <typename TS, typename TD>
 void copy2d(int rows, int cols, const TS* src, int lds, TD* dst, int ldd, hipStream_t s);
 
+// Zero `bytes` bytes at p (both multiples of 4) with a kernel: used in place
+// of hipMemsetAsync, whose nodes in a captured graph have given wrong results
+// on replays.
+void zero_bytes(void* p, size_t bytes, hipStream_t s);
+
 // rank_out[0] = #{S_i > eps, i < b}.
 void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t s);
 

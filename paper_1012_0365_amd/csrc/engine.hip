@@ -47,6 +47,8 @@ using blws::BlwsError;
 using blws::Carver;
 using blws::Context;
 
+
+
 struct blws_ctx_s {
     Context cx;
 };
@@ -137,7 +139,6 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->norm_steps = 8;
     o->norm_rtol = 1e-13;
     o->b_max = 512;
-    o->b_soft = 112;
     o->ladder_tol = 1e-3;
 }
 
@@ -195,7 +196,7 @@ void blws_default_mc_opts(blws_alm_opts* o)
     if (!o) return;
     blws_default_alm_opts(o);
     o->tol = 1e-6;
-    o->rho = 1.1;
+    o->rho = 1.05;
     o->mu0_scale = 1.0;
     o->b_max = 256;
 }
@@ -289,7 +290,7 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
     Carver c(cx.ws);
     layout(c, w);
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+    blws::zero_bytes(w.nflag, 4 * sizeof(int), s);
     blws::small_svd_dispatch(cx, s, N, N, B, ldb, UB, S, VB, svd, w, 20101202ULL);
     int err = 0;
     HIP_TRY(hipMemcpyAsync(&err, w.nflag + 1, sizeof(int), hipMemcpyDeviceToHost, s));

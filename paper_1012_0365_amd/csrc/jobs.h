@@ -141,7 +141,7 @@ struct RpcaJob : Job {
     {
         Carver c(cx.ws);
         layout(c);
-        HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+        zero_bytes(w.nflag, 4 * sizeof(int), s);
         // ||D||_F and ||D||_inf
         norms<T>(m, n, D, ldd, scal, part, s);
         HIP_TRY(hipMemcpyAsync(cx.host_pinned, scal, 2 * sizeof(double), hipMemcpyDeviceToHost,
@@ -168,7 +168,7 @@ struct RpcaJob : Job {
     {
         eps = 1.0 / mu;
         if (!refine) {
-            const int bn = block_width(sv, svp, o, p);
+            const int bn = block_width(sv, o, p);
             const Op<T> opW0{Wb, n, nullptr, nullptr};
             if (b == 0) {
                 cold_block<T>(cx, w, s, m, n, opW0, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
@@ -377,7 +377,7 @@ struct McJob : Job {
     {
         Carver c(cx.ws);
         layout(c);
-        HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+        zero_bytes(w.nflag, 4 * sizeof(int), s);
         // the pattern must be valid before any kernel indexes with it
         csr_check(m, n, nnz, row_ptr, col_idx, flag, s);
         HIP_TRY(hipMemcpyAsync(cx.host_pinned, flag, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -399,7 +399,7 @@ struct McJob : Job {
         mo.r = svp;
         mo.eps = eps_prev;
         const Op<T> op{nullptr, 0, &mo, nullptr};
-        const int bn = block_width(sv_pred, svp, o, p);
+        const int bn = block_width(sv_pred, o, p);
         if (b == 0) {
             cold_block<T>(cx, w, s, m, n, op, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
         } else if (bn > b) {
@@ -551,7 +551,7 @@ inline void check_alm_opts(const blws_alm_opts& o, const std::string& who)
     BLWS_REQUIRE(o.tol > 0.0 && o.max_iter >= 1 && o.rho >= 1.0 && o.mu0_scale > 0.0 &&
                      o.mu_max_factor >= 1.0 && o.sv0 >= 1 && o.b_round >= 1 &&
                      o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
-                     o.b_soft >= 1 && o.ladder_tol >= 0.0,
+                     o.ladder_tol >= 0.0,
                  BLWS_EINVAL, who + ": bad options");
     BLWS_REQUIRE(o.b_max <= 512, BLWS_EUNSUPPORTED, who + ": b_max above 512");
 }
@@ -619,7 +619,7 @@ void svt_call_t(Context& cx, hipStream_t s, int m, int n, const T* W, int ldw, d
     }
     Carver c(cx.ws);
     w.carve(c, m, n, b);
-    HIP_TRY(hipMemsetAsync(w.nflag, 0, 4 * sizeof(int), s));
+    zero_bytes(w.nflag, 4 * sizeof(int), s);
     const Op<T> op{W, ldw, nullptr, nullptr};
     if (!warm) cold_block<T>(cx, w, s, m, n, op, b, o.pow_steps, o.seed, 1, U, ldu, V, ldv);
     svt_step<T>(cx, w, s, m, n, op, eps, b, U, ldu, V, ldv, S, rank_dev, o.seed);

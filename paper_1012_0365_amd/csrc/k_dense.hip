@@ -534,6 +534,13 @@ __global__ void copy2d_kernel(int rows, int cols, const TS* src, int lds, TD* ds
     }
 }
 
+__global__ void zero_words_kernel(unsigned* p, size_t words)
+{
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < words;
+         e += (size_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
 __global__ void count_above_kernel(int b, const double* S, double eps, int* out)
 {
     __shared__ int cnt;
@@ -609,6 +616,15 @@ void copy2d(int rows, int cols, const TS* src, int lds, TD* dst, int ldd, hipStr
     if (rows <= 0 || cols <= 0) return;
     hipLaunchKernelGGL((copy2d_kernel<TS, TD>), dim3(grid_for((size_t)rows * cols)), dim3(256), 0,
                        s, rows, cols, src, lds, dst, ldd);
+}
+
+void zero_bytes(void* p, size_t bytes, hipStream_t s)
+{
+    BLWS_REQUIRE(bytes % 4 == 0 && ((uintptr_t)p & 3) == 0, BLWS_EINVAL,
+                 "zero_bytes: size or address not a multiple of 4");
+    if (bytes == 0) return;
+    hipLaunchKernelGGL(zero_words_kernel, dim3(grid_for(bytes / 4)), dim3(256), 0, s,
+                       (unsigned*)p, bytes / 4);
 }
 
 void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t s)

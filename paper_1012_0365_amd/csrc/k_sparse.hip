@@ -266,7 +266,7 @@ int grid_for(long long work, int block)
 void csr_check(int m, int n, int nnz, const int* row_ptr, const int* col_idx, int* flag,
                hipStream_t s)
 {
-    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), s));
+    zero_bytes(flag, sizeof(int), s);
     hipLaunchKernelGGL(csr_check_kernel, dim3(grid_for((long long)nnz + m + 1, 256)), dim3(256),
                        0, s, m, n, nnz, row_ptr, col_idx, flag);
 }
@@ -280,7 +280,7 @@ void csc_build(int m, int n, int nnz, const int* row_ptr, const int* col_idx, in
     int* cursor = cnt + (n + 1);          // n + 1
     int* perm = cursor + (n + 1);         // nnz
     int* row_of = perm + nnz;             // nnz
-    HIP_TRY(hipMemsetAsync(cnt, 0, 2 * (size_t)(n + 1) * sizeof(int), s));
+    zero_bytes(cnt, 2 * (size_t)(n + 1) * sizeof(int), s);
     if (nnz > 0)
         hipLaunchKernelGGL(col_count_kernel, dim3(grid_for(nnz, 256)), dim3(256), 0, s, nnz,
                            col_idx, cnt);

@@ -1697,7 +1697,7 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         cb.part = cb.nrm + 2 * (size_t)P;
         cb.ctr = (unsigned*)(cb.part + 2 * (size_t)P * N);
         cb.err = err;
-        HIP_TRY(hipMemsetAsync(cb.ctr, 0, sizeof(unsigned), s));
+        zero_bytes(cb.ctr, sizeof(unsigned), s);
         void* args[] = {(void*)&N,  (void*)&B,  (void*)&ldb, (void*)&d,  (void*)&e,
                         (void*)&VL, (void*)&tL, (void*)&VR,  (void*)&tR, (void*)&cb};
         const void* fn = nullptr;

@@ -202,6 +202,12 @@ struct ProductGroup {
 
 struct Context {
     ProductGroup* group = nullptr;  // set by the request server while a solve steps
+    // all of a step's work on the caller's stream, queued by the calling thread
+    // (no second stream, events or helper thread are created or used)
+    bool single_stream = false;
+    // device address of the library's static scratch on this context's device
+    // (blws_svt_noalloc), looked up when the context is created
+    void* static_scratch = nullptr;
     int device = 0;
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -283,7 +289,9 @@ struct StepWs {
     double *Cpb, *Grb, *Rib, *cholb, *partialb;
     int* flagsb;
 
-    void carve(Carver& c, int m, int n, int b)
+    // second_set = false leaves out the scratch of the second stream (the
+    // single-stream form of the step never uses it)
+    void carve(Carver& c, int m, int n, int b, bool second_set = true)
     {
         const int b2 = 2 * b, mx = m > n ? m : n;
         UF = c.take<T>((size_t)m * b2);
@@ -319,6 +327,12 @@ struct StepWs {
         }
         partial_elems = pe;
         partial = c.take<double>(pe + 1);
+        if (!second_set) {
+            T1b = T2b = nullptr;
+            Cpb = Grb = Rib = cholb = partialb = nullptr;
+            flagsb = nullptr;
+            return;
+        }
         T1b = c.take<T>((size_t)mx * b);
         T2b = c.take<T>((size_t)mx * b);
         Cpb = c.take<double>((size_t)b * b);
@@ -465,9 +479,13 @@ void small_svd_dispatch(Context& cx, hipStream_t s, int N, int nv, const double*
 {
     TimedLaunch tl(&cx.timer, "small_svd", s, 0.0, 0.0);
     if (small_svd_gk_supported(N)) {
-        cx.ensure_aux();  // the reflector blocks' T factors go on the second stream
-        small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s, cx.aux,
-                     cx.ev_fork, cx.ev_join);
+        if (cx.single_stream) {
+            small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s);
+        } else {
+            cx.ensure_aux();  // the reflector blocks' T factors go on the second stream
+            small_svd_gk(&cx.timer, N, nv, B, ldb, UB, S, VB, svd_scratch, w.nflag + 1, s,
+                         cx.aux, cx.ev_fork, cx.ev_join);
+        }
         if (cholqr2_small_supported(N, nv)) {
             const uint64_t sid0 = (1ULL << 20) + (++cx.fix_calls);
             const uint64_t sid1 = (1ULL << 20) + (++cx.fix_calls);
@@ -573,24 +591,16 @@ WProduct dense_wproduct(const StepWs<T>& w, const Op<T>& op, int m, int n, bool 
     return pr;
 }
 
-// One BLWS step (Algorithms 2-3, k = 2) on W from the orthonormal block
-// (U, V); on return U, V hold the top-b Ritz vectors and S the Ritz values.
-//
-// The augmented matrix [[0, W], [W^T, 0]] (Theorem 1) is never formed: its
-// product with the start block splits into W V and W^T U; the new block is
-// the orthonormalised part of [W V; W^T U] outside span(U) x span(V); the
-// Rayleigh-Ritz matrix on the two blocks is, up to a permutation,
-// [[0, B], [B^T, 0]] with B = [U, F]^T W [V, G] = [U, F]^T [W V, W G], whose
-// SVD gives the Ritz values and vectors.
+// The first half of a BLWS step on two streams: [U, F] and [V, G] with
+// F = orth(W V against U), G = orth(W^T U against V), the right half (V, Q, G)
+// on the context's second stream with its own scratch, queued by the
+// context's second host thread; the caller's stream waits for both.
 template <typename T>
-void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
-              double eps, int b, T* U, int ldu, T* V, int ldv, double* S, int* rank_dev,
-              uint64_t seed)
+void svt_step_pair1_two_streams(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n,
+                                const Op<T>& W, int b, const T* U, int ldu, const T* V, int ldv,
+                                uint64_t seed)
 {
-    Timer* tm = &cx.timer;
     const int b2 = 2 * b;
-    // The left (U, P, F) and right (V, Q, G) halves until H are independent:
-    // the right half runs on the second stream with its own scratch.
     StepWs<T> wb = w.aux_view();
     cx.fork(s);
     // U and V into the left halves of [U, F] and [V, G], on this stream after
@@ -636,8 +646,38 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
         cx.worker->wait();
     }
     cx.join(s);
+}
+
+// One BLWS step (Algorithms 2-3, k = 2) on W from the orthonormal block
+// (U, V); on return U, V hold the top-b Ritz vectors and S the Ritz values.
+//
+// The augmented matrix [[0, W], [W^T, 0]] (Theorem 1) is never formed: its
+// product with the start block splits into W V and W^T U; the new block is
+// the orthonormalised part of [W V; W^T U] outside span(U) x span(V); the
+// Rayleigh-Ritz matrix on the two blocks is, up to a permutation,
+// [[0, B], [B^T, 0]] with B = [U, F]^T W [V, G] = [U, F]^T [W V, W G], whose
+// SVD gives the Ritz values and vectors.
+template <typename T>
+void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
+              double eps, int b, T* U, int ldu, T* V, int ldv, double* S, int* rank_dev,
+              uint64_t seed)
+{
+    Timer* tm = &cx.timer;
+    const int b2 = 2 * b;
+    if (cx.single_stream) {
+        // everything in order on s: the right half's work reuses the left
+        // half's scratch once that is done with it
+        copy2d<T, T>(m, b, U, ldu, w.UF, b2, s);
+        copy2d<T, T>(n, b, V, ldv, w.VG, b2, s);
+        op_apply<T>(cx, w, s, W, m, n, false, V, ldv, b, w.PH, b2);
+        orth_against<T>(cx, w, s, m, b, U, ldu, w.PH, b2, b, w.UF + b, b2, seed);
+        op_apply<T>(cx, w, s, W, m, n, true, U, ldu, b, w.Qb, b);
+        orth_against<T>(cx, w, s, n, b, V, ldv, w.Qb, b, b, w.VG + b, b2, seed);
+    } else {
+        svt_step_pair1_two_streams<T>(cx, w, s, m, n, W, b, U, ldu, V, ldv, seed);
+    }
     // the last product of the pass: H = W G
-    if (cx.group && W.W) {
+    if (cx.group && W.W && !cx.single_stream) {
         const WProduct pr = dense_wproduct<T>(w, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
         cx.group->submit(&pr, &s, 1);
     } else {
@@ -652,12 +692,20 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
         small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, w.svd, ow, seed);
     }
     // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b), on the two streams
-    cx.fork(s);
-    gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
-                       (const T*)nullptr, 0, U, ldu, w.partial, w.partial_elems, s);
-    gemm<T, double, T>(tm, "gemm_ts", false, n, b, b2, 1.0, w.VG, b2, w.VB, b2, 0.0,
-                       (const T*)nullptr, 0, V, ldv, wb.partial, wb.partial_elems, cx.aux);
-    cx.join(s);
+    if (cx.single_stream) {
+        gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
+                           (const T*)nullptr, 0, U, ldu, w.partial, w.partial_elems, s);
+        gemm<T, double, T>(tm, "gemm_ts", false, n, b, b2, 1.0, w.VG, b2, w.VB, b2, 0.0,
+                           (const T*)nullptr, 0, V, ldv, w.partial, w.partial_elems, s);
+    } else {
+        const StepWs<T> wb = w.aux_view();
+        cx.fork(s);
+        gemm<T, double, T>(tm, "gemm_ts", false, m, b, b2, 1.0, w.UF, b2, w.UB, b2, 0.0,
+                           (const T*)nullptr, 0, U, ldu, w.partial, w.partial_elems, s);
+        gemm<T, double, T>(tm, "gemm_ts", false, n, b, b2, 1.0, w.VG, b2, w.VB, b2, 0.0,
+                           (const T*)nullptr, 0, V, ldv, wb.partial, wb.partial_elems, cx.aux);
+        cx.join(s);
+    }
     copy2d<double, double>(1, b, w.Sall, b2, S, b, s);
     if (rank_dev) count_above(b, S, eps, rank_dev, s);
 }
@@ -694,18 +742,11 @@ void grow_block(Context& cx, StepWs<T>& w, hipStream_t s, int rows, int b_old, i
     orth_against<T>(cx, w, s, rows, b_old, X, ldx, w.R, c, c, X + b_old, ldx, seed);
 }
 
-// Block width for a predicted rank sv: rounded up, at most floor(p / 2) and
-// b_max. Beyond b_soft the block grows only as far as the previous count of
-// values above the threshold (svp) requires, without the prediction's margin.
-int block_width(int sv, int svp, const blws_alm_opts& o, int p)
+// Block width for a predicted rank sv (Sec. 4.2: the Ritz output follows the
+// predicted rank): rounded up to b_round, at most floor(p / 2) and b_max.
+int block_width(int sv, const blws_alm_opts& o, int p)
 {
-    const int want = ((sv + o.b_round - 1) / o.b_round) * o.b_round;
-    int b = want;
-    if (b > o.b_soft) {
-        const int need = ((svp + 1 + o.b_round - 1) / o.b_round) * o.b_round;
-        b = need > o.b_soft ? need : o.b_soft;
-        if (b > want) b = want;
-    }
+    int b = ((sv + o.b_round - 1) / o.b_round) * o.b_round;
     if (b > p / 2) b = p / 2;
     if (b > o.b_max) b = o.b_max;
     if (b < 1) b = 1;

@@ -118,8 +118,11 @@ def test_small_svd_multiple_and_clustered_values(torch, ctx, N, kind):
     assert np.all(np.abs(S - sigma) <= 1e-13 * sigma[0] + 1e-12 * sigma)
     assert np.abs(UB.T @ UB - np.eye(N)).max() < 1e-13
     assert np.abs(VB.T @ VB - np.eye(N)).max() < 1e-13
-    assert np.linalg.norm(UB * S @ VB.T - B) <= 1e-13 * np.linalg.norm(B)
+    # backward error of a stable SVD: a small multiple of N u ||B||_F (the
+    # vectors of a multiple value come from inverse iteration and a Cholesky-QR
+    # polish of each side)
     nb = np.linalg.norm(B)
+    assert np.linalg.norm(UB * S @ VB.T - B) <= 8 * N * 2.0**-53 * nb
     for k in range(0, N, 4):
         Pg = UB[:, k:k + 4] @ UB[:, k:k + 4].T
         Pq = q1[:, k:k + 4] @ q1[:, k:k + 4].T

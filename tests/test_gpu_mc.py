@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 OPTS = dict(rho=1.1, tol=1e-8, mu0_scale=1.0)
+GPU_NORM_STEPS = 8  # the library's default norm_steps
 
 
 @pytest.fixture(scope="module")
@@ -62,8 +63,10 @@ CASES = [(200, 150, 5, 0.3, 0), (300, 250, 8, 0.25, 1)]
 def case(request):
     m, n, r, frac, seed = request.param
     inst = synth.mc_instance(m, n, r, frac, seed)
+    # the oracle's BLWS form with the GPU's reading of the ||D||_2 estimate (at
+    # most 8 BLWS steps), so that both follow the same iterates
     bl = oracle.mc(m, n, inst["row_ptr"], inst["col_idx"], inst["values"], mode="blws",
-                   r_cap=64, **OPTS)
+                   r_cap=64, norm_steps=GPU_NORM_STEPS, **OPTS)
     return inst, bl
 
 
@@ -196,14 +199,16 @@ def test_mc_n5000_fp32_matches_stored_oracle(torch, blws, ctx):
     m_ref = np.array(g["M_samples"])
     err = np.linalg.norm(a_s - a_ref) / np.linalg.norm(a_ref)
     rec = np.linalg.norm(a_s - m_ref) / np.linalg.norm(m_ref)
-    # the planted rank-50 part; the ALM iterate also carries ~200 components just
-    # above the threshold, whose count may differ by a few between FP32 and FP64
     r = p["r"]
     s_ref = np.array(g["sigma_A"])
     s_err = np.max(np.abs(S.cpu().numpy()[:r] - s_ref[:r]) / s_ref[:r])
     print(f"mc n5000 fp32: iters={info['iters']} (oracle {g['iters']}) rank={info['rank']} "
           f"(oracle {g['rank']}) sampled rel err vs oracle {err:.3e}, vs planted {rec:.3e}, "
           f"top-{r} sigma {s_err:.3e}, {info['seconds']:.3f}s")
-    assert info["status"] == 0 and abs(info["rank"] - g["rank"]) <= 4
-    assert abs(info["iters"] - g["iters"]) <= 2
-    assert err < 1e-5 and s_err < 1e-5 and rec < 1e-5
+    # the planted rank; the iteration counts differ by the GPU's 8-step
+    # ||D||_2 estimate (it sets mu_0), which moves the iterates, not the optimum
+    assert info["status"] == 0 and info["rank"] == g["rank"] == r
+    assert abs(info["iters"] - g["iters"]) <= 8
+    assert err < 1e-6 and s_err < 1e-6
+    # recovery of the planted matrix at the level the tolerance allows
+    assert rec < 1e-5
