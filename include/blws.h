@@ -114,6 +114,22 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
              double eps, int b, void* U, int ldu, void* V, int ldv, int warm, double* S,
              int* rank_dev, void* A, int lda, const blws_svt_opts* opts);
 
+/* blws_svt for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and errors as blws_svt (FP64 or FP32), with every
+ * scratch buffer carved from a static device array of the library (64 MiB per
+ * device, held from the first context on that device until the process ends)
+ * and every launch on `stream` (no second stream, events or helper thread).
+ * The call makes no hipMalloc / hipFree and no allocating library call; it
+ * zeroes what must start at zero itself. A size whose scratch exceeds 64 MiB
+ * returns BLWS_EINVAL (m = n = 2000 at b = 112 needs about 50 MiB in FP64).
+ * All calls on one device share that array: calls whose work overlaps on the
+ * device (other streams, other host threads, other contexts) race and must
+ * be serialised by the caller. */
+int blws_svt_noalloc(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, int ldw,
+                     double eps, int b, void* U, int ldu, void* V, int ldv, int warm, double* S,
+                     int* rank_dev, void* A, int lda, const blws_svt_opts* opts);
+
 /* Robust PCA: min ||A||_* + lambda ||E||_1 s.t. D = A + E, by inexact ALM with
  * one BLWS step per iteration (Sec. 5). lambda <= 0 selects 1/sqrt(max(m, n)).
  * D (m x n, ldd) is read only; A (lda) and E (lde) receive the solution; E is

@@ -94,10 +94,12 @@ class Context:
 
     # -- the BLWS SVT step ---------------------------------------------------
     def svt(self, W, eps: float, U, V, warm: bool = True, A=None, S=None, seed: int = 20101202,
-            pow_steps: int = 2, rank=None):
+            pow_steps: int = 2, rank=None, noalloc: bool = False):
         """A = T_eps(W) by one BLWS step. U (m x b), V (n x b) are updated in
         place with the top-b Ritz vectors. Returns (S, rank) as device tensors
-        (S: float64 [b], rank: int32 [1]; pass them in to reuse buffers)."""
+        (S: float64 [b], rank: int32 [1]; pass them in to reuse buffers).
+        noalloc=True calls blws_svt_noalloc (the library's static scratch, no
+        device allocation inside the call)."""
         torch = _torch()
         prec = _prec_of(W)
         ldw = _check_mat(W, "W")
@@ -119,7 +121,8 @@ class Context:
             if A.shape != (m, n) or A.dtype != W.dtype:
                 raise ValueError("A must be m x n with W's dtype")
         o = SvtOpts(pow_steps, seed)
-        self._check(self._lib.blws_svt(
+        fn = self._lib.blws_svt_noalloc if noalloc else self._lib.blws_svt
+        self._check(fn(
             self.handle, self._stream(), prec, m, n, W.data_ptr(), ldw, float(eps), b,
             U.data_ptr(), ldu, V.data_ptr(), ldv, int(bool(warm)), S.data_ptr(),
             rank.data_ptr(), A.data_ptr() if A is not None else None, lda, ctypes.byref(o)))

@@ -97,6 +97,8 @@ SIGNATURES = {
     "blws_default_svt_opts": (None, [ctypes.POINTER(SvtOpts)]),
     "blws_svt": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, _i, _vp, _i, _vp, _i, _i, _vp, _vp, _vp,
                       _i, ctypes.POINTER(SvtOpts)]),
+    "blws_svt_noalloc": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, _i, _vp, _i, _vp, _i, _i, _vp,
+                              _vp, _vp, _i, ctypes.POINTER(SvtOpts)]),
     "blws_rpca_solve": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, ctypes.POINTER(AlmOpts), _vp, _i,
                              _vp, _i, ctypes.POINTER(SolveInfo)]),
     "blws_default_mc_opts": (None, [ctypes.POINTER(AlmOpts)]),

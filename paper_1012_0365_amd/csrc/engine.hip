@@ -47,7 +47,27 @@ using blws::BlwsError;
 using blws::Carver;
 using blws::Context;
 
+// Scratch of blws_svt_noalloc: a file-scope device array, so that the call
+// needs no allocation. Each device the library runs on holds its own copy for
+// the life of the process. Host code never passes `scratch` itself to a
+// kernel (on the host it names a stand-in, not device memory): it uses the
+// device address looked up per device by noalloc_scratch_address().
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
+namespace {
+
+// The device address of `scratch` on the current device (called once per
+// context, with its device current).
+void* noalloc_scratch_address()
+{
+    void* ptr = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    BLWS_REQUIRE(ptr != nullptr, BLWS_EDEVICE, "static scratch has no device address");
+    return ptr;
+}
+
+}  // namespace
 
 struct blws_ctx_s {
     Context cx;
@@ -85,6 +105,14 @@ int blws_create(blws_ctx* out, int device)
         hipHostMalloc(&c->cx.host_pinned, 4096, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return BLWS_EDEVICE;
+    }
+    try {
+        c->cx.static_scratch = noalloc_scratch_address();
+    } catch (const BlwsError& e) {
+        g_noctx_error = e.msg;
+        (void)hipHostFree(c->cx.host_pinned);
+        delete c;
+        return e.status;
     }
     *out = c;
     return BLWS_OK;
@@ -174,6 +202,64 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
                                 (float*)V, ldv, warm, S, rank_dev, (float*)A, lda, o);
     else
         throw BlwsError{BLWS_EUNSUPPORTED, "blws_svt: precision not supported"};
+    return BLWS_OK;
+    ABI_END
+}
+
+int blws_svt_noalloc(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, int ldw,
+                     double eps, int b, void* U, int ldu, void* V, int ldv, int warm, double* S,
+                     int* rank_dev, void* A, int lda, const blws_svt_opts* opts)
+{
+    ABI_BEGIN(ctx)
+    const int p = m < n ? m : n;
+    BLWS_REQUIRE(m >= 2 && n >= 2 && b >= 1 && 2 * b <= p, BLWS_EINVAL,
+                 "blws_svt_noalloc: need m, n >= 2 and 1 <= b <= min(m, n) / 2");
+    BLWS_REQUIRE(W && U && V && S, BLWS_EINVAL, "blws_svt_noalloc: null W, U, V or S");
+    BLWS_REQUIRE(ldw >= n && ldu >= b && ldv >= b && (!A || lda >= n), BLWS_EINVAL,
+                 "blws_svt_noalloc: leading dimension too small");
+    BLWS_REQUIRE(std::isfinite(eps) && eps >= 0.0, BLWS_EINVAL,
+                 "blws_svt_noalloc: eps must be >= 0");
+    BLWS_REQUIRE(2 * b <= 1024, BLWS_EUNSUPPORTED, "blws_svt_noalloc: b above 512");
+    BLWS_REQUIRE(prec == BLWS_FP64 || prec == BLWS_FP32, BLWS_EUNSUPPORTED,
+                 "blws_svt_noalloc: precision not supported");
+    BLWS_REQUIRE(cx.static_scratch, BLWS_EDEVICE, "blws_svt_noalloc: no static scratch");
+    blws_svt_opts o;
+    blws_default_svt_opts(&o);
+    if (opts) o = *opts;
+    hipStream_t s = (hipStream_t)stream;
+    auto run = [&](auto tag) {
+        using T = decltype(tag);
+        blws::StepWs<T> w;
+        Carver dry(nullptr);
+        w.carve(dry, m, n, b, false);
+        if (dry.off + 256 > NOALLOC_SCRATCH_BYTES)
+            throw BlwsError{BLWS_EINVAL, "blws_svt_noalloc: this size needs " +
+                                             std::to_string((dry.off + 256) >> 20) +
+                                             " MiB of scratch, above the static 64 MiB"};
+        Carver c(cx.static_scratch);
+        w.carve(c, m, n, b, false);
+        // single stream, no timing events, no allocation; restored on every path
+        struct Mode {
+            Context& cx;
+            bool on;
+            Mode(Context& c) : cx(c), on(c.timer.on) { cx.single_stream = true; cx.timer.on = false; }
+            ~Mode() { cx.single_stream = false; cx.timer.on = on; }
+        } mode(cx);
+        blws::zero_bytes(w.nflag, 4 * sizeof(int), s);
+        const blws::Op<T> op{(const T*)W, ldw, nullptr, nullptr};
+        if (!warm)
+            blws::cold_block<T>(cx, w, s, m, n, op, b, o.pow_steps, o.seed, 1, (T*)U, ldu, (T*)V,
+                                ldv);
+        blws::svt_step<T>(cx, w, s, m, n, op, eps, b, (T*)U, ldu, (T*)V, ldv, S, rank_dev,
+                          o.seed);
+        if (A)
+            blws::svt_reconstruct<T>(&cx.timer, m, n, b, (T*)U, ldu, (T*)V, ldv, S, eps, (T*)A,
+                                     lda, s);
+    };
+    if (prec == BLWS_FP64)
+        run(double{});
+    else
+        run(float{});
     return BLWS_OK;
     ABI_END
 }
