@@ -1402,7 +1402,8 @@ __global__ __launch_bounds__(256) void wy_t_kernel(int N, const double* __restri
 template <int MAXN, int R>
 __global__ __launch_bounds__(256) void backtransform_kernel(
     int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
-    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld)
+    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld,
+    int roff)
 {
     __shared__ double Y[WY_RB][MAXN];
     __shared__ double Tm[WY_RB][WY_RB];
@@ -1411,7 +1412,8 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
     const int side = blockIdx.y;
     const double* Vh = side == 0 ? VL : VR;
     double* X = side == 0 ? UB : VB;
-    const int nref = side == 0 ? N : N - 1;
+    const int off = side == 0 ? 0 : roff;  // right reflector k starts at column k + roff
+    const int nref = N - off;
     const int nblkL = (N + WY_RB - 1) / WY_RB;
     const int nsteps = (nref + WY_RB - 1) / WY_RB;
     double xr[R];
@@ -1427,7 +1429,7 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
     auto y_elem = [&](int blk, int q, int i) -> double {
         const int k0 = blk * WY_RB;
         const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
-        return (q < cnt && i < N && i >= k0 + q + side) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+        return (q < cnt && i < N && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
     };
     auto t_index = [&](int blk) { return side == 0 ? blk : nblkL + blk; };
     auto prefetch = [&](int st) {
@@ -1514,7 +1516,8 @@ constexpr int BT_MAXN = 256;
 typedef double d4 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
     int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
-    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld)
+    const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld,
+    int roff)
 {
     __shared__ double Xs[BT_MAXN][17];
     __shared__ double Ys[BT_MAXN][17];
@@ -1526,7 +1529,8 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
     const int side = blockIdx.y, c0 = 16 * blockIdx.x;
     const double* Vh = side == 0 ? VL : VR;
     double* X = side == 0 ? UB : VB;
-    const int nref = side == 0 ? N : N - 1;
+    const int off = side == 0 ? 0 : roff;  // right reflector k starts at column k + roff
+    const int nref = N - off;
     const int nblkL = (N + WY_RB - 1) / WY_RB;
     const int nsteps = (nref + WY_RB - 1) / WY_RB;
     for (int e = tid; e < N * 16; e += 256) {
@@ -1544,7 +1548,7 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
 #pragma unroll
         for (int u = 0; u < PY; ++u) {
             const int e = tid + 256 * u, q = e / N, i = e - q * N;
-            py[u] = (e < 16 * N && q < cnt && i >= k0 + q + side) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+            py[u] = (e < 16 * N && q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
         }
         pt = Tall[(size_t)(side == 0 ? blk : nblkL + blk) * WY_RB * WY_RB + tid];
     };
@@ -1587,7 +1591,7 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
             WT[p][col] = sm;
         }
         __syncthreads();
-        // X <- X - Y (T W) over 16-row tiles from k0 (rows above k0 + q + side
+        // X <- X - Y (T W) over 16-row tiles from k0 (rows above k0 + q + off
         // have Y = 0)
         for (int rt = k0 / 16 + wave; 16 * rt < N; rt += 4) {
             d4 acc = d4{0.0, 0.0, 0.0, 0.0};
@@ -1649,9 +1653,415 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(int N, int nv, double* __
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-stage bidiagonalisation for GK_MAXN < N <= TS_MAXN, N a multiple of 16.
+//
+// Stage 1 reduces B to upper band form (band width 16) by blocked Householder
+// transformations: for each 16-column panel k0, a QR of the column panel
+// B[k0:, k0:k0+16] whose block reflector I - Y T Y^T is applied to the columns
+// right of it, then an LQ of the row panel B[k0:k0+16, k0+16:] applied to the
+// rows below it. One launch per panel side: every workgroup factorizes the
+// panel itself (one wavefront, the panel in registers; all workgroups form the
+// same bits) and applies the block reflector to its own 16-column (or, on the
+// row side, 16-row) tile with FP64 matrix cores; workgroup 0 stores the
+// reflectors (left: row k of VL from column k; right: row k of VR from column
+// k + 16), their T factors and the triangular factor, which goes to the band.
+// The row side is the column side on the transposed matrix, so one kernel
+// serves both.
+// Stage 2 reduces the band to bidiagonal form by bulge chasing in one
+// workgroup, the band in LDS: sweep i annihilates row i beyond the
+// superdiagonal with a right reflector on columns i+1..i+16, removes the
+// fill below the diagonal with a left reflector, and chases the bulge down
+// 16 rows at a time; task j of sweep i runs in slot 2i + j, so the tasks of
+// one slot touch disjoint rows and columns and run on different wavefronts.
+// The reflectors are recorded for the back-transformation.
+// ---------------------------------------------------------------------------
+constexpr int TS_NB = 16;
+constexpr int TS_MAXN = 416;
+constexpr int TS_BW = 47, TS_BOFF = 15;  // band row r holds columns r - 15 .. r + 31
+constexpr int TS_REC = 34;               // per task: v[16], tau_v, u[16], tau_u
+
+__device__ __forceinline__ double readlane_f64(double x, int l)
+{
+    const unsigned long long u = __double_as_longlong(x);
+    return join_words((unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), l),
+                      (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l));
+}
+
+// QR of an H x 16 panel held by ONE wavefront: lane l owns rows l + 64 r
+// (r < R). On return P holds the reflector vectors below the diagonal
+// (column q, rows > q), the triangular factor on and above it, tau[q] the
+// reflector scalars (the same bits in every lane).
+template <int R>
+__device__ __forceinline__ void panel_qr_wave(int H, double (&P)[R][TS_NB], double (&tau)[TS_NB])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < TS_NB; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            s += (i > q && i < H) ? P[r][q] * P[r][q] : 0.0;
+        }
+        const double s2 = wave_sum64(s);
+        const double alpha = readlane_f64(P[0][q], q);
+        double tq, bq, sc;
+        house(alpha, s2, tq, bq, sc);
+        double y[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            y[r] = (i == q) ? 1.0 : ((i > q && i < H) ? P[r][q] * sc : 0.0);
+        }
+        double w[TS_NB];
+#pragma unroll
+        for (int c = q + 1; c < TS_NB; ++c) {
+            double p = 0.0;
+#pragma unroll
+            for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
+            w[c] = p;
+        }
+#pragma unroll
+        for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * wave_sum64(w[c]);
+#pragma unroll
+        for (int c = q + 1; c < TS_NB; ++c)
+#pragma unroll
+            for (int r = 0; r < R; ++r) P[r][c] -= y[r] * w[c];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int i = lane + 64 * r;
+            if (i >= q) P[r][q] = (i == q) ? bq : y[r];
+        }
+        tau[q] = tq;
+    }
+}
+
+// One panel side of stage 1 (see above). grid.x = max(1, ntiles) workgroups
+// of 256 threads; workgroup t < ntiles updates trailing tile t.
+//   TRANS = false: panel (i, q) = A[k0 + i][k0 + q], i < H = N - k0;
+//                  tile t (i, q) = A[k0 + i][k0 + 16 + 16 t + q].
+//   TRANS = true:  panel (i, q) = A[k0 + q][k0 + 16 + i], i < H = N - k0 - 16;
+//                  tile t (i, q) = A[k0 + 16 + 16 t + q][k0 + 16 + i].
+template <int R, bool TRANS>
+__global__ __launch_bounds__(256) void ts_stage1_kernel(int N, int k0, int ntiles,
+                                                        double* __restrict__ A,
+                                                        double* __restrict__ V,
+                                                        double* __restrict__ tauo,
+                                                        double* __restrict__ band,
+                                                        double* __restrict__ Tblk)
+{
+    __shared__ double Ys[TS_MAXN][17];
+    __shared__ double Xs[TS_MAXN][17];
+    __shared__ double Wp[4][16][17], Gp[4][16][17];
+    __shared__ double Ws[16][17], Gs[16][17], Tm[16][17], WT[16][17];
+    __shared__ double taus[TS_NB];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int H = TRANS ? N - k0 - TS_NB : N - k0;
+    const int t = blockIdx.x;
+    const bool has_tile = t < ntiles;
+    auto pidx = [&](int i, int q) -> size_t {
+        return TRANS ? (size_t)(k0 + q) * N + (k0 + TS_NB + i) : (size_t)(k0 + i) * N + (k0 + q);
+    };
+    auto tidx = [&](int i, int q) -> size_t {
+        return TRANS ? (size_t)(k0 + TS_NB + TS_NB * t + q) * N + (k0 + TS_NB + i)
+                     : (size_t)(k0 + i) * N + (k0 + TS_NB + TS_NB * t + q);
+    };
+    // panel into Ys and the tile into Xs by all four wavefronts (row-major
+    // panel: 16 consecutive doubles per row; transposed: along the rows)
+    for (int e = tid; e < H * TS_NB; e += 256) {
+        const int i = TRANS ? e % H : e >> 4, q = TRANS ? e / H : e & 15;
+        Ys[i][q] = A[pidx(i, q)];
+        if (has_tile) Xs[i][q] = A[tidx(i, q)];
+    }
+    __syncthreads();
+    if (wave == 0) {
+        double P[R][TS_NB];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < TS_NB; ++q) {
+                const int i = lane + 64 * r;
+                P[r][q] = i < H ? Ys[i][q] : 0.0;
+            }
+        double tau[TS_NB];
+        panel_qr_wave<R>(H, P, tau);
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < TS_NB; ++q) {
+                const int i = lane + 64 * r;
+                if (i < H) Ys[i][q] = i < q ? 0.0 : (i == q ? 1.0 : P[r][q]);
+            }
+        if (lane == 0)
+#pragma unroll
+            for (int q = 0; q < TS_NB; ++q) taus[q] = tau[q];
+        if (blockIdx.x == 0) {
+            const int off = TRANS ? k0 + TS_NB : k0;
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int q = 0; q < TS_NB; ++q) {
+                    const int i = lane + 64 * r;
+                    if (i >= q && i < H)
+                        V[(size_t)(k0 + q) * N + off + i] = i == q ? 1.0 : P[r][q];
+                    // triangular factor (rows i <= q) into the band: the
+                    // upper triangle of the diagonal block, or (row side) the
+                    // lower triangle of the block right of it
+                    if (i <= q) {
+                        if (TRANS)
+                            band[(size_t)(k0 + q) * TS_BW + (TS_NB + i - q + TS_BOFF)] = P[r][q];
+                        else
+                            band[(size_t)(k0 + i) * TS_BW + (q - i + TS_BOFF)] = P[r][q];
+                    }
+                }
+            if (lane == 0)
+#pragma unroll
+                for (int q = 0; q < TS_NB; ++q) tauo[k0 + q] = tau[q];
+        }
+    }
+    __syncthreads();
+    // G = Y^T Y and W = Y^T X, the rows split over the four wavefronts
+    {
+        d4 ag = d4{0.0, 0.0, 0.0, 0.0}, aw = d4{0.0, 0.0, 0.0, 0.0};
+        for (int kb = 4 * wave; kb < H; kb += 16) {
+            const int i = kb + (lane >> 4);
+            const double a = i < H ? Ys[i][lane & 15] : 0.0;
+            const double b = (i < H && has_tile) ? Xs[i][lane & 15] : 0.0;
+            ag = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, ag, 0, 0, 0);
+            aw = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, aw, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Gp[wave][(lane >> 4) + 4 * r][lane & 15] = ag[r];
+            Wp[wave][(lane >> 4) + 4 * r][lane & 15] = aw[r];
+        }
+    }
+    __syncthreads();
+    {
+        const int p = tid >> 4, c = tid & 15;
+        Gs[p][c] = ((Gp[0][p][c] + Gp[1][p][c]) + Gp[2][p][c]) + Gp[3][p][c];
+        Ws[p][c] = ((Wp[0][p][c] + Wp[1][p][c]) + Wp[2][p][c]) + Wp[3][p][c];
+    }
+    __syncthreads();
+    // T (forward, columnwise): T[q][q] = tau_q, T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q]
+    if (wave == 0) {
+        for (int q = 0; q < TS_NB; ++q) {
+            const double tq = taus[q];
+            double v = 0.0;
+            if (lane < q) {
+                for (int r = lane; r < q; ++r) v += Tm[lane][r] * Gs[r][q];
+                v *= -tq;
+            }
+            if (lane < TS_NB) Tm[lane][q] = lane < q ? v : (lane == q ? tq : 0.0);
+            __builtin_amdgcn_s_waitcnt(0);
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (blockIdx.x == 0)
+            for (int e = lane; e < TS_NB * TS_NB; e += 64) Tblk[e] = Tm[e >> 4][e & 15];
+    }
+    __syncthreads();
+    if (!has_tile) return;  // uniform per workgroup
+    // WT = T^T W
+    {
+        const int p = tid >> 4, c = tid & 15;
+        double sm = 0.0;
+#pragma unroll
+        for (int q = 0; q < TS_NB; ++q)
+            if (q <= p) sm += Tm[q][p] * Ws[q][c];
+        WT[p][c] = sm;
+    }
+    __syncthreads();
+    // X <- X - Y WT over 16-row tiles
+    for (int rt = wave; 16 * rt < H; rt += 4) {
+        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+            const int i = 16 * rt + (lane & 15);
+            const double a = i < H ? Ys[i][4 * kk + (lane >> 4)] : 0.0;
+            const double b = WT[4 * kk + (lane >> 4)][lane & 15];
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * rt + (lane >> 4) + 4 * r;
+            if (row < H) Xs[row][lane & 15] -= acc[r];
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < H * TS_NB; e += 256) {
+        const int i = e >> 4, q = e & 15;
+        A[tidx(i, q)] = Xs[i][q];
+    }
+}
+
+// Workgroup barrier that waits only for this wavefront's LDS operations (not
+// for its global stores, which nothing in the workgroup reads back).
+__device__ __forceinline__ void lds_barrier()
+{
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+__device__ __forceinline__ int ts_jmax(int N) { return (N - 2) / TS_NB + 1; }
+__device__ __forceinline__ int ts_nsteps(int N, int i) { return (N - 2 - i) / TS_NB + 1; }
+
+// Stage 2: band (global, rows of TS_BW) -> bidiagonal d, e; reflectors of
+// task (i, j) at rec[(i * jmax + j) * TS_REC]. One workgroup of 1024 threads;
+// in slot t the wavefront i % 16 runs task (i, t - 2 i).
+__global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __restrict__ band,
+                                                         double* __restrict__ dout,
+                                                         double* __restrict__ eout,
+                                                         double* __restrict__ rec)
+{
+    __shared__ double bd[TS_MAXN * TS_BW];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, l = lane & 15;
+    for (int e = tid; e < N * TS_BW; e += 1024) bd[e] = band[e];
+    __syncthreads();
+    auto B = [&](int r, int c) -> double& { return bd[r * TS_BW + (c - r + TS_BOFF)]; };
+    const int jmax = ts_jmax(N);
+    const int nslot = max(2 * (N - 2), jmax - 1) + 1;
+    for (int t = 0; t < nslot; ++t) {
+        // the sweep of this wavefront in slot t: i = wave (mod 16) with
+        // 0 <= t - 2 i < nsteps(i)
+        const int hi = min(t >> 1, N - 2);
+        const int i = hi - ((hi - wave) & 15);
+        const int j = t - 2 * i;
+        const bool has = i >= 0 && j < ts_nsteps(N, i);  // uniform per wavefront
+        if (has) {
+            const int r0 = j == 0 ? i : i + 1 + TS_NB * (j - 1);
+            const int c0 = i + 1 + TS_NB * j;
+            const int c1 = min(c0 + TS_NB - 1, N - 1);
+            const int L = c1 - c0 + 1;
+            double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
+            // right reflector on columns c0..c1 for row r0, rows r0..c1
+            {
+                const double x = l < L ? B(r0, c0 + l) : 0.0;
+                const double s2 = row_sum16(l >= 1 ? x * x : 0.0);
+                double tv, bv, sc;
+                house(readlane_f64(x, 0), s2, tv, bv, sc);
+                const double v = l == 0 ? 1.0 : (l < L ? x * sc : 0.0);
+                const int nr = c1 - r0 + 1;
+                double a[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    a[s] = (g + 4 * s < nr && l < L) ? B(r0 + g + 4 * s, c0 + l) : 0.0;
+                double dt[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s) dt[s] = tv * row_sum16(a[s] * v);
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int row = r0 + g + 4 * s;
+                    if (g + 4 * s < nr && l < L)
+                        B(row, c0 + l) = row == r0 ? (l == 0 ? bv : 0.0) : a[s] - dt[s] * v;
+                }
+                if (g == 0) rc[l] = v;
+                if (lane == 0) rc[16] = tv;
+            }
+        }
+        // the right reflectors of a slot before its left reflectors: task (i, j)
+        // ends its row r0 in column c0, which the left reflector of task
+        // (i + 1, j - 2) in the same slot then updates
+        lds_barrier();
+        if (has) {
+            const int c0 = i + 1 + TS_NB * j;
+            const int c1 = min(c0 + TS_NB - 1, N - 1);
+            const int L = c1 - c0 + 1;
+            double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
+            // left reflector on rows c0..c1 for column c0, columns c0..c0 + 31
+            {
+                const double x = l < L ? B(c0 + l, c0) : 0.0;
+                const double s2 = row_sum16(l >= 1 ? x * x : 0.0);
+                double tu, bu, sc;
+                house(readlane_f64(x, 0), s2, tu, bu, sc);
+                const double u = l == 0 ? 1.0 : (l < L ? x * sc : 0.0);
+                const int nc = min(c1 + TS_NB, N - 1) - c0 + 1;
+                double a[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s)
+                    a[s] = (g + 4 * s < nc && l < L) ? B(c0 + l, c0 + g + 4 * s) : 0.0;
+                double dt[8];
+#pragma unroll
+                for (int s = 0; s < 8; ++s) dt[s] = tu * row_sum16(a[s] * u);
+#pragma unroll
+                for (int s = 0; s < 8; ++s) {
+                    const int col = c0 + g + 4 * s;
+                    if (g + 4 * s < nc && l < L)
+                        B(c0 + l, col) = col == c0 ? (l == 0 ? bu : 0.0) : a[s] - dt[s] * u;
+                }
+                if (g == 0) rc[17 + l] = u;
+                if (lane == 0) rc[33] = tu;
+            }
+        }
+        lds_barrier();
+    }
+    for (int i = tid; i < N; i += 1024) {
+        dout[i] = B(i, i);
+        if (i + 1 < N) eout[i] = B(i, i + 1);
+    }
+}
+
+// Back-transformation through the stage-2 reflectors: X <- H_1 ... H_T X for
+// the first nv columns of UB (left reflectors u, side 0) or VB (right
+// reflectors v, side 1), the last slot first; grid (ceil(nv / 4), 2), one
+// wavefront per column (kept in LDS), its four 16-lane groups applying the
+// tasks of one slot (disjoint rows) four at a time. The reflectors of
+// TS_BCH slots at a time are staged in LDS by the whole workgroup (slot t's
+// task i at [t - t0][i - lo(t)]).
+constexpr int TS_BCH = 32;
+__global__ __launch_bounds__(256) void ts_back2_kernel(int N, int nv, const double* __restrict__ rec,
+                                                       double* __restrict__ UB,
+                                                       double* __restrict__ VB, int ld)
+{
+    __shared__ double xs[4][TS_MAXN];
+    __shared__ double hs[TS_BCH][TS_NB][TS_NB + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, l = lane & 15;
+    const int side = blockIdx.y, col = blockIdx.x * 4 + wave;
+    double* X = side == 0 ? UB : VB;
+    const int hoff = side == 0 ? 17 : 0;
+    const bool act = col < nv;  // uniform per wavefront
+    if (act)
+        for (int i = lane; i < N; i += 64) xs[wave][i] = X[(size_t)i * ld + col];
+    const int jmax = ts_jmax(N);
+    const int nslot = max(2 * (N - 2), jmax - 1) + 1;
+    auto lo_of = [&](int t) { return max(0, (t - jmax + 2) >> 1); };
+    for (int t1 = nslot - 1; t1 >= 0; t1 -= TS_BCH) {
+        const int t0 = max(0, t1 - TS_BCH + 1);
+        __syncthreads();  // the previous chunk's reflectors are no longer read
+        for (int e = tid; e < (t1 - t0 + 1) * TS_NB * (TS_NB + 1); e += 256) {
+            const int ts = e / (TS_NB * (TS_NB + 1)), rem = e - ts * (TS_NB * (TS_NB + 1));
+            const int k = rem / (TS_NB + 1), c = rem - k * (TS_NB + 1);
+            const int t = t0 + ts, i = lo_of(t) + k, j = t - 2 * i;
+            const bool ok = i <= min(t >> 1, N - 2) && j >= 0 && j < ts_nsteps(N, i);
+            hs[ts][k][c] = ok ? rec[((size_t)i * jmax + j) * TS_REC + hoff + c] : 0.0;
+        }
+        __syncthreads();
+        if (!act) continue;
+        for (int t = t1; t >= t0; --t) {
+            const int hi = min(t >> 1, N - 2), lo = lo_of(t);
+            for (int i = hi - g; i >= lo; i -= 4) {  // uniform per 16-lane group
+                const int j = t - 2 * i;
+                if (j >= ts_nsteps(N, i)) continue;
+                const int c0 = i + 1 + TS_NB * j;
+                const int L = min(TS_NB, N - c0);
+                const double* hr = hs[t - t0][i - lo];
+                const double h = hr[l], tau = hr[TS_NB];
+                const double xv = l < L ? xs[wave][c0 + l] : 0.0;
+                const double dt = tau * row_sum16(h * xv);
+                if (l < L) xs[wave][c0 + l] = xv - dt * h;
+            }
+        }
+    }
+    if (act)
+        for (int i = lane; i < N; i += 64) X[(size_t)i * ld + col] = xs[wave][i];
+}
+
 }  // namespace
 
 bool small_svd_gk_supported(int N) { return N >= 2 && N <= SVD_MAXN; }
+
+static bool two_stage(int N) { return N > GK_MAXN && N <= TS_MAXN && N % TS_NB == 0; }
 
 size_t small_svd_gk_scratch_elems(int N)
 {
@@ -1659,8 +2069,14 @@ size_t small_svd_gk_scratch_elems(int N)
     // bidiagonalisation the published column, partials and barrier counter
     const size_t P = (N + 31) / 32;
     const size_t nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
-    return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
-           nblk * WY_RB * WY_RB;
+    const size_t one = 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
+                       nblk * WY_RB * WY_RB;
+    // two-stage: d, e, tauL, tauR, VL, VR, the working matrix, the band, the
+    // stage-2 reflectors and the T factors
+    const size_t jm = (size_t)((N - 2) / TS_NB + 1);
+    const size_t two = 4 * (size_t)N + 3 * (size_t)N * N + (size_t)N * TS_BW +
+                       (size_t)(N > 1 ? N - 1 : 1) * jm * TS_REC + nblk * WY_RB * WY_RB;
+    return two_stage(N) && two > one ? two : one;
 }
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
@@ -1685,6 +2101,58 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
                                            "gk_bidiag_p7"};
     // bidiagonalisation flops: 4 N^3 - 4 N^3 / 3 (Householder, both sides)
     const double bd_flops = 8.0 / 3.0 * N * (double)N * N;
+    if (two_stage(N)) {
+        const int nblkL = N / TS_NB;
+        double* Aw = VR + (size_t)N * N;
+        double* band = Aw + (size_t)N * N;
+        const int jm = (N - 2) / TS_NB + 1;
+        double* rec = band + (size_t)N * TS_BW;
+        double* Tall = rec + (size_t)(N - 1) * jm * TS_REC;
+        {
+            TimedLaunch tl(tm, "ts_band", s, bd_flops, 16.0 * N * N);
+            copy2d<double, double>(N, N, B, ldb, Aw, N, s);
+            zero_bytes(band, sizeof(double) * (size_t)N * TS_BW, s);
+            for (int p = 0; p < nblkL; ++p) {
+                const int k0 = TS_NB * p;
+                const int nt = (N - k0 - TS_NB) / TS_NB;
+                if (N <= 256) {
+                    hipLaunchKernelGGL((ts_stage1_kernel<4, false>), dim3(nt > 0 ? nt : 1), dim3(256), 0, s,
+                                       N, k0, nt, Aw, VL, tL, band, Tall + (size_t)p * 256);
+                    if (nt > 0)
+                        hipLaunchKernelGGL((ts_stage1_kernel<4, true>), dim3(nt), dim3(256), 0, s, N, k0,
+                                           nt, Aw, VR, tR, band, Tall + (size_t)(nblkL + p) * 256);
+                } else {
+                    hipLaunchKernelGGL((ts_stage1_kernel<7, false>), dim3(nt > 0 ? nt : 1), dim3(256), 0, s,
+                                       N, k0, nt, Aw, VL, tL, band, Tall + (size_t)p * 256);
+                    if (nt > 0)
+                        hipLaunchKernelGGL((ts_stage1_kernel<7, true>), dim3(nt), dim3(256), 0, s, N, k0,
+                                           nt, Aw, VR, tR, band, Tall + (size_t)(nblkL + p) * 256);
+                }
+            }
+        }
+        {
+            TimedLaunch tl(tm, "ts_bulge", s, 0.0, 0.0);
+            hipLaunchKernelGGL(ts_stage2_kernel, dim3(1), dim3(1024), 0, s, N, band, d, e, rec);
+        }
+        {
+            TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
+            hipLaunchKernelGGL(tgk_solve_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S, UB, VB, N);
+        }
+        {
+            TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
+            const int blocks = (nv + 3) / 4;
+            hipLaunchKernelGGL(ts_back2_kernel, dim3(blocks, 2), dim3(256), 0, s, N, nv, rec, UB, VB,
+                               N);
+            if (N <= BT_MAXN)
+                hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0,
+                                   s, N, nv, VL, VR, Tall, UB, VB, N, TS_NB);
+            else
+                hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s,
+                                   N, nv, VL, VR, Tall, UB, VB, N, TS_NB);
+            hipLaunchKernelGGL(sign_fix_kernel, dim3(blocks), dim3(256), 0, s, N, nv, UB, VB, N);
+        }
+        return;
+    }
     if (N > GK_MAXN) {
         const int NQc = (N + 15) / 16;
         const int qi = NQc <= 20 ? 0 : NQc <= 24 ? 1 : NQc <= 28 ? 2 : NQc <= 32 ? 3
@@ -1760,13 +2228,13 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         const int blocks = (nv + 3) / 4;
         if (N <= BT_MAXN)
             hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0, s,
-                               N, nv, VL, VR, Tall, UB, VB, N);
+                               N, nv, VL, VR, Tall, UB, VB, N, 1);
         else if (N <= 512)
             hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s, N,
-                               nv, VL, VR, Tall, UB, VB, N);
+                               nv, VL, VR, Tall, UB, VB, N, 1);
         else
             hipLaunchKernelGGL((backtransform_kernel<SVD_MAXN, 16>), dim3(blocks, 2), dim3(256), 0,
-                               s, N, nv, VL, VR, Tall, UB, VB, N);
+                               s, N, nv, VL, VR, Tall, UB, VB, N, 1);
         hipLaunchKernelGGL(sign_fix_kernel, dim3(blocks), dim3(256), 0, s, N, nv, UB, VB, N);
     }
 }
