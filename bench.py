@@ -88,6 +88,11 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the full-SVD comparator")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="CPU baseline: repeat oracle solves until this much time has passed")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="rpca: skip the extra measurements (FP32 / BF16 solves, the SVT "
+                         "snapshot, n = 4000, matrix completion, the serving mix)")
+    ap.add_argument("--leg-requests", type=int, default=24,
+                    help="rpca legs: requests in the serving-mix leg")
     return ap.parse_args()
 
 
@@ -253,6 +258,10 @@ def bench_rpca(args):
         "kernels_from": "one extra solve before the timed region, every launch timed",
     }
 
+    if not args.no_legs:
+        out["legs"] = rpca_legs(args, ctx, D if args.prec == "f64" else D.double(),
+                                total / args.steps)
+
     if not args.no_plain:
         # Plain comparator: the same ALM with a full SVD per iteration on the same
         # GPU (torch.linalg.svd). Bounded sample: the best of two full SVDs of a
@@ -294,6 +303,231 @@ def bench_rpca(args):
                        f"n=2000 solve(s) of {n_it} iterations in {tc:.1f}s"),
         }
     return out
+
+
+def golden_error(name, A, E=None, planted=False):
+    """Sampled relative error of A (and E) against the stored oracle values."""
+    import numpy as np
+    import torch
+
+    with open(os.path.join(ROOT, "tests", "golden", name + ".json")) as f:
+        g = json.load(f)
+    pos = torch.tensor(g["sample_pos"], device=A.device)
+    As = A.double().reshape(-1)[pos].cpu().numpy()
+    ref = np.array(g["A_samples"])
+    out = {"A": float(np.linalg.norm(As - ref) / np.linalg.norm(ref))}
+    if E is not None:
+        Es = E.double().reshape(-1)[pos].cpu().numpy()
+        refe = np.array(g["E_samples"])
+        out["E"] = float(np.linalg.norm(Es - refe) / np.linalg.norm(refe))
+    return out, g
+
+
+def timed_solves(ctx, D, reps, **kw):
+    import torch
+
+    ts, info = [], None
+    A = torch.empty_like(D)
+    E = torch.empty_like(D)
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        _, _, info = ctx.rpca_solve(D, A=A, E=E, **kw)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t1)
+    return sorted(ts)[len(ts) // 2], info, A, E
+
+
+def svt_snapshot_leg(ctx, D):
+    """SVT calls/s on the state of the n = 2000 solve at iteration 15 (b = 112):
+    14 ALM iterations driven from here (blws_svt plus the elementwise updates
+    in torch, outside any timed region) give W, eps and the warm block; then
+    back-to-back blws_svt calls on that W, each fed the previous call's Ritz
+    vectors as its warm block."""
+    import torch
+
+    m, n = D.shape
+    lam = 1.0 / math.sqrt(max(m, n))
+    dn = float(torch.linalg.norm(D))
+    s1 = float(torch.linalg.matrix_norm(D, 2))
+    J = max(s1, float(D.abs().max()) / lam)
+    Y = D / J
+    E = torch.zeros_like(D)
+    mu, rho = 1.25 / s1, 1.5
+    sv, b = 10, 0
+    U = V = None
+    for it in range(1, 15):
+        W = D - E + Y / mu
+        bn = min(((sv + 15) // 16) * 16, min(m, n) // 2)
+        cold = b == 0 or bn != b
+        if cold:
+            # a cold block of the new width (this leg measures the steady
+            # state, not the block-resize rule)
+            U = torch.empty(m, bn, dtype=D.dtype, device=D.device)
+            V = torch.empty(n, bn, dtype=D.dtype, device=D.device)
+        b = bn
+        A = torch.empty_like(D)
+        S, rank = ctx.svt(W, 1.0 / mu, U, V, warm=not cold, A=A)
+        svp = int(rank.item())
+        sv = svp + 1 if svp < sv else min(svp + round(0.05 * min(m, n)), min(m, n))
+        T = D - A + Y / mu
+        E = torch.sign(T) * torch.clamp(T.abs() - lam / mu, min=0.0)
+        Y = Y + mu * (D - A - E)
+        mu = min(rho * mu, 1.25e7 / s1)
+    W = (D - E + Y / mu).contiguous()
+    eps = 1.0 / mu
+    bn = min(((sv + 15) // 16) * 16, min(m, n) // 2)
+    S = torch.empty(bn, dtype=torch.float64, device=D.device)
+    rank = torch.zeros(1, dtype=torch.int32, device=D.device)
+    A = torch.empty_like(W)
+    if bn != b:
+        U = torch.empty(m, bn, dtype=D.dtype, device=D.device)
+        V = torch.empty(n, bn, dtype=D.dtype, device=D.device)
+        ctx.svt(W, eps, U, V, warm=False, A=A, S=S, rank=rank)
+    b = bn
+    for _ in range(5):  # settle the warm block on this W
+        ctx.svt(W, eps, U, V, A=A, S=S, rank=rank)
+    torch.cuda.synchronize()
+    calls = 40
+    t1 = time.perf_counter()
+    for _ in range(calls):
+        ctx.svt(W, eps, U, V, A=A, S=S, rank=rank)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    r = int(rank.item())
+    flops = 6.0 * m * n * b + 2.0 * m * n * r
+    return {"calls_per_s": calls / el, "us_per_call": 1e6 * el / calls, "b": b, "rank": r,
+            "gflop_per_s": flops * calls / el / 1e9,
+            "flops_per_call": flops, "note": "W and the warm block of iteration 15"}
+
+
+def plain_alm_leg(D, iters_total, iters_timed=3):
+    """The plain form on the same GPU: the same inexact ALM with the SVT from a
+    full SVD (torch.linalg.svd), timed over its first iterations and scaled
+    to the BLWS solve's iteration count."""
+    import torch
+
+    m, n = D.shape
+    lam = 1.0 / math.sqrt(max(m, n))
+    s1 = float(torch.linalg.matrix_norm(D, 2))
+    J = max(s1, float(D.abs().max()) / lam)
+    Y = D / J
+    E = torch.zeros_like(D)
+    mu = 1.25 / s1
+    torch.linalg.svd(D[:64, :64])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(iters_timed):
+        W = D - E + Y / mu
+        Uf, Sf, Vh = torch.linalg.svd(W, full_matrices=False)
+        Sf = torch.clamp(Sf - 1.0 / mu, min=0.0)
+        A = (Uf * Sf) @ Vh
+        T = D - A + Y / mu
+        E = torch.sign(T) * torch.clamp(T.abs() - lam / mu, min=0.0)
+        Y = Y + mu * (D - A - E)
+        mu = 1.5 * mu
+    torch.cuda.synchronize()
+    per_it = (time.perf_counter() - t1) / iters_timed
+    return {"solve_s_est": per_it * iters_total, "s_per_iteration": per_it,
+            "sample": f"{iters_timed} ALM iterations with torch.linalg.svd ({D.dtype}), "
+                      f"x {iters_total} iterations"}
+
+
+def rpca_legs(args, ctx, D64, fp64_s):
+    """Extra measurements beside the headline FP64 line (each bounded)."""
+    import torch
+
+    import paper_1012_0365_amd as blws
+    import synth
+
+    legs = {}
+
+    def leg(name, fn):
+        t1 = time.time()
+        try:
+            legs[name] = fn()
+        except Exception as e:  # a failed leg is reported, the headline line stands
+            legs[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"[bench] leg {name}: {time.time() - t1:.1f}s")
+
+    def low_prec():
+        out = {}
+        D32 = D64.float()
+        for prec in ("f32", "bf16"):
+            timed_solves(ctx, D32, 1, bf16=prec == "bf16")
+            t, info, A, E = timed_solves(ctx, D32, 3, bf16=prec == "bf16")
+            err, _ = golden_error("rpca_n2000_s0", A, E)
+            out[prec] = {"solve_s": t, "solves_per_s": 1.0 / t, "iters": info["iters"],
+                         "iters_bf16": info["iters_bf16"], "status": info["status"],
+                         "rel_err_vs_oracle_samples": err, "vs_f64_speed": fp64_s / t}
+        return out
+
+    leg("n2000_low_precision", low_prec)
+    leg("svt_snapshot_n2000_f64", lambda: svt_snapshot_leg(ctx, D64))
+
+    def n4000():
+        inst = synth.rpca_instance(4000, 4000, 200, 0.10, AMP, 0)
+        out = {"config": "m = n = 4000, rank 200, 10% U[-500, 500], rho 1.2, tol 1e-7"}
+        opts = blws.default_alm_opts(rho=1.2)
+        for prec in ("f64", "f32", "bf16"):
+            D = torch.tensor(inst["D"], dtype=torch.float64 if prec == "f64" else torch.float32,
+                             device="cuda")
+            timed_solves(ctx, D, 1, opts=opts, bf16=prec == "bf16")
+            t, info, A, E = timed_solves(ctx, D, 1, opts=opts, bf16=prec == "bf16")
+            err, g = golden_error("rpca_n4000_s0", A, E)
+            sv = torch.linalg.svdvals(A.double())[:200].cpu()
+            import numpy as np
+
+            sref = np.array(g["sigma_A"][:200])
+            out[prec] = {"solve_s": t, "iters": info["iters"], "rank": info["rank"],
+                         "iters_bf16": info["iters_bf16"],
+                         "rel_err_vs_oracle_samples": err,
+                         "sigma_rel_err_top200": float(np.max(np.abs(sv.numpy() - sref) / sref))}
+            del D, A, E
+        return out
+
+    leg("rpca_n4000", n4000)
+
+    def mc5000():
+        import numpy as np
+
+        inst = synth.mc_instance(5000, 5000, 50, 0.10, 0)
+        rp = torch.tensor(inst["row_ptr"], dtype=torch.int32, device="cuda")
+        ci = torch.tensor(inst["col_idx"], dtype=torch.int32, device="cuda")
+        vals = torch.tensor(inst["values"], dtype=torch.float32, device="cuda")
+        opts = blws.default_mc_opts()
+        ctx.mc_solve(5000, 5000, rp, ci, vals, opts=opts, r_cap=256)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        U, S, V, info = ctx.mc_solve(5000, 5000, rp, ci, vals, opts=opts, r_cap=256)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t1
+        with open(os.path.join(ROOT, "tests", "golden", "mc_n5000_s0.json")) as f:
+            g = json.load(f)
+        pos = np.array(g["sample_pos"])
+        rows = torch.tensor(pos // 5000, device="cuda")
+        cols = torch.tensor(pos % 5000, device="cuda")
+        a_s = ((U.double()[rows] * S) * V.double()[cols]).sum(1).cpu().numpy()
+        ref = np.array(g["A_samples"])
+        msm = np.array(g["M_samples"])
+        return {"config": "m = n = 5000, rank 50, 10% sampled, FP32, rho 1.05, tol 1e-6",
+                "solve_s": t, "iters": info["iters"], "rank": info["rank"],
+                "rel_err_vs_oracle_samples": float(np.linalg.norm(a_s - ref) / np.linalg.norm(ref)),
+                "rel_err_vs_planted_samples": float(np.linalg.norm(a_s - msm) / np.linalg.norm(msm))}
+
+    leg("mc_n5000_f32", mc5000)
+    if not args.no_plain:
+        leg("plain_alm_n2000_f64", lambda: plain_alm_leg(D64, 23))
+
+    def serving():
+        sa = argparse.Namespace(requests=args.leg_requests, slots=8, group_window=200,
+                                no_group=False, no_plain=False)
+        r = bench_serving(sa)
+        return {k: r[k] for k in ("value", "unit", "latency_s_p50", "latency_s_p99",
+                                  "sequential_fp64_solves_per_s", "speedup_vs_sequential_fp64",
+                                  "failed", "config")}
+
+    leg("serving_mix", serving)
+    return legs
 
 
 def serving_mix(nreq, seed=2024):
