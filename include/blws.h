@@ -169,6 +169,41 @@ int blws_mc_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
                   const blws_alm_opts* opts, int r_cap, void* U, int ldu, double* S, void* V,
                   int ldv, blws_solve_info* info);
 
+/* Options of the SVT matrix-completion solver (defaults from
+ * blws_default_svt_mc_opts). */
+typedef struct {
+    double tau;               /* threshold; <= 0 selects 5 sqrt(m n)                    */
+    double delta;             /* step size; <= 0 selects 1.2 m n / nnz                  */
+    double tol;               /* stop at ||P_Omega(M - X)||_F / ||P_Omega(M)||_F <= tol */
+                              /* (1e-4)                                                 */
+    int max_iter;             /* 500                                                    */
+    int rank_step;            /* values added to a request that fell short (5)          */
+    int b_round;              /* block width = requested count rounded up to this (16)  */
+    int b_max;                /* upper bound on the block width, <= 512 (512)           */
+    int pow_steps;            /* power half-step pairs of the first (cold) block (2)    */
+    unsigned long long seed;  /* counter-based generator seed                           */
+    int norm_steps;           /* max BLWS steps for the ||P_Omega(M)||_2 estimate (8)   */
+    double norm_rtol;         /* relative change that stops those steps (1e-13)         */
+} blws_svt_mc_opts;
+
+void blws_default_svt_mc_opts(blws_svt_mc_opts* opts);
+
+/* Matrix completion by the singular value thresholding algorithm, the MC
+ * host of the experiments of Sec. 5 (its Table 2), with each thresholding
+ * X_k = T_tau(Y_{k-1}) computed by BLWS on the purely sparse W = Y_{k-1}:
+ *   Y_0 = k0 delta P_Omega(M), k0 = ceil(tau / (delta ||P_Omega(M)||_2));
+ *   Y_k = Y_{k-1} + delta P_Omega(M - X_k) until
+ *   ||P_Omega(M - X_k)||_F / ||P_Omega(M)||_F <= tol.
+ * Each thresholding asks for r_{k-1} + 1 values and, while all of them
+ * exceed tau, for rank_step more (BLWS steps warm-started from the block
+ * just computed). Arguments, pattern checks and outputs as blws_mc_solve
+ * (the factors of the last X_k); opts may be NULL. Blocks until done.
+ * Returns BLWS_OK, BLWS_NOT_CONVERGED, or an error. */
+int blws_mc_svt_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
+                      const int* row_ptr, const int* col_idx, const void* values,
+                      const blws_svt_mc_opts* opts, int r_cap, void* U, int ldu, double* S,
+                      void* V, int ldv, blws_solve_info* info);
+
 /* ---------------------------------------------------------------------- */
 /* Diagnostics (used by the parity tests and the bench).                   */
 /* ---------------------------------------------------------------------- */

@@ -47,6 +47,21 @@ class AlmOpts(ctypes.Structure):
     ]
 
 
+class SvtMcOpts(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("rank_step", ctypes.c_int),
+        ("b_round", ctypes.c_int),
+        ("pow_steps", ctypes.c_int),
+        ("seed", ctypes.c_uint64),
+        ("norm_steps", ctypes.c_int),
+        ("norm_rtol", ctypes.c_double),
+    ]
+
+
 class Info(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int),
@@ -103,6 +118,10 @@ def lib():
         L.orc_mc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i, i, d,
                              ctypes.POINTER(AlmOpts), ctypes.c_int, ctypes.c_int, d, d, d, i,
                              ctypes.POINTER(Info)]
+        L.orc_default_svt_mc_opts.argtypes = [ctypes.POINTER(SvtMcOpts)]
+        L.orc_mc_svt.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, i, i, d,
+                                 ctypes.POINTER(SvtMcOpts), ctypes.c_int, ctypes.c_int, d, d, d,
+                                 i, ctypes.POINTER(Info)]
         _lib = L
     return _lib
 
@@ -286,6 +305,39 @@ def mc(m: int, n: int, row_ptr, col_idx, values, mode: str = "blws", r_cap: int 
                       _dp(V), ctypes.byref(rank), ctypes.byref(info))
     if rc < 0:
         raise RuntimeError(f"orc_mc failed: {rc}")
+    r = min(rank.value, r_cap)
+    return {"U": U[:, :r], "S": S[:r], "V": V[:, :r], "rank": rank.value,
+            "info": info.as_dict()}
+
+
+def default_svt_mc_opts(**kw) -> SvtMcOpts:
+    o = SvtMcOpts()
+    lib().orc_default_svt_mc_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def mc_svt(m: int, n: int, row_ptr, col_idx, values, mode: str = "blws", r_cap: int = 256,
+           **opts):
+    """The SVT algorithm for matrix completion (exact or BLWS thresholding);
+    returns factors (U, S, V) of the completed matrix."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int32)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    values = _f64(values)
+    o = default_svt_mc_opts(**opts)
+    U = np.zeros((m, r_cap))
+    V = np.zeros((n, r_cap))
+    S = np.zeros(r_cap)
+    rank = ctypes.c_int(0)
+    info = Info()
+    rc = lib().orc_mc_svt(m, n, values.size, _ip(row_ptr), _ip(col_idx), _dp(values),
+                          ctypes.byref(o), {"exact": 0, "blws": 1}[mode], r_cap, _dp(U), _dp(S),
+                          _dp(V), ctypes.byref(rank), ctypes.byref(info))
+    if rc < 0:
+        raise RuntimeError(f"orc_mc_svt failed: {rc}")
     r = min(rank.value, r_cap)
     return {"U": U[:, :r], "S": S[:r], "V": V[:, :r], "rank": rank.value,
             "info": info.as_dict()}

@@ -1035,3 +1035,166 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
     free(Wd); free(Aden); free(Sfull);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* The SVT algorithm for matrix completion (the MC host of the experiments, */
+/* Sec. 5, from its cited source): with Y_0 = k0 delta P_Omega(M),          */
+/* k0 = ceil(tau / (delta ||P_Omega(M)||_2)), each iteration takes          */
+/*   X_k = T_tau(Y_{k-1}),  Y_k = Y_{k-1} + delta P_Omega(M - X_k),          */
+/* stopping when ||P_Omega(X_k - M)||_F / ||P_Omega(M)||_F <= tol. Y stays  */
+/* supported on Omega, so W = Y_{k-1} is purely sparse. The partial SVD asks */
+/* for s = r_{k-1} + 1 values and, while all s of them exceed tau, for      */
+/* rank_step more (repeated within the iteration); with BLWS each request   */
+/* is a step warm-started from the block just computed, widened when s      */
+/* outgrows it.                                                             */
+/* ------------------------------------------------------------------------ */
+void orc_default_svt_mc_opts(orc_svt_mc_opts* o)
+{
+    o->tau = 0.0;       /* <= 0: 5 sqrt(m n) */
+    o->delta = 0.0;     /* <= 0: 1.2 m n / nnz */
+    o->tol = 1e-4;
+    o->max_iter = 500;
+    o->rank_step = 5;
+    o->b_round = 16;
+    o->pow_steps = 2;
+    o->seed = 20101202ULL;
+    o->norm_steps = 5000;
+    o->norm_rtol = 1e-13;
+}
+
+int orc_mc_svt(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
+               const double* values, const orc_svt_mc_opts* opts_in, int mode, int r_cap,
+               double* Uout, double* Sout, double* Vout, int* rank_out, orc_info* info)
+{
+    if (m < 2 || n < 2 || nnz < 1 || !row_ptr || !col_idx || !values) return -1;
+    orc_svt_mc_opts o;
+    if (opts_in) o = *opts_in; else orc_default_svt_mc_opts(&o);
+    const int p = m < n ? m : n;
+    const double tau = o.tau > 0.0 ? o.tau : 5.0 * sqrt((double)m * (double)n);
+    const double delta = o.delta > 0.0 ? o.delta : 1.2 * (double)m * (double)n / (double)nnz;
+    double dnorm = 0.0;
+    for (int e = 0; e < nnz; ++e) dnorm += values[e] * values[e];
+    dnorm = sqrt(dnorm);
+    orc_op op = {0};
+    op.m = m;
+    op.n = n;
+    op.nnz = nnz;
+    op.row_ptr = row_ptr;
+    op.col_idx = col_idx;
+    op.sval = values;
+    double s1;
+    double* Wd = NULL;
+    if (mode == 0) {
+        Wd = (double*)calloc((size_t)m * n, sizeof(double));
+        for (int i = 0; i < m; ++i)
+            for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) Wd[(size_t)i * n + col_idx[e]] = values[e];
+        double* Sx = (double*)malloc(sizeof(double) * (size_t)p);
+        int rk;
+        orc_svt_exact(m, n, Wd, INFINITY, NULL, Sx, &rk);
+        s1 = Sx[0];
+        free(Sx);
+    } else {
+        s1 = spectral_norm_op(&op, 16, o.pow_steps, o.seed, o.norm_rtol, o.norm_steps, NULL);
+    }
+    const double k0 = ceil(tau / (delta * s1));
+    double* y = (double*)malloc(sizeof(double) * (size_t)nnz);
+    double* x = (double*)calloc((size_t)nnz, sizeof(double)); /* X on Omega */
+    for (int e = 0; e < nnz; ++e) y[e] = k0 * delta * values[e];
+    orc_alm_opts bo; /* block width rule */
+    orc_default_opts(&bo);
+    bo.b_round = o.b_round;
+    int b = 0, r = 0, it = 0;
+    double rel = INFINITY;
+    double *U = NULL, *V = NULL, *S = NULL, *Ua = NULL, *Va = NULL, *th = NULL;
+    double* Aden = (mode == 0) ? (double*)malloc(sizeof(double) * (size_t)m * n) : NULL;
+    double* Sfull = (mode == 0) ? (double*)malloc(sizeof(double) * (size_t)p) : NULL;
+    for (it = 1; it <= o.max_iter; ++it) {
+        if (mode == 0) {
+            for (size_t e = 0; e < (size_t)m * n; ++e) Wd[e] = 0.0;
+            for (int i = 0; i < m; ++i)
+                for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) Wd[(size_t)i * n + col_idx[e]] = y[e];
+            orc_svt_exact(m, n, Wd, tau, Aden, Sfull, &r);
+            for (int i = 0; i < m; ++i)
+                for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) x[e] = Aden[(size_t)i * n + col_idx[e]];
+        } else {
+            orc_op w = op;
+            w.sval = y; /* W = Y_{k-1}, supported on Omega */
+            int s = r + 1;
+            for (;;) {
+                int bn = block_width(s, &bo, p);
+                if (b == 0) {
+                    U = (double*)malloc(sizeof(double) * (size_t)m * bn);
+                    V = (double*)malloc(sizeof(double) * (size_t)n * bn);
+                    cold_block_op(&w, bn, o.pow_steps, o.seed, 1, U, V);
+                } else if (bn != b) {
+                    resize_block(m, b, bn, &U, o.seed, 1000 + 2 * (uint64_t)it);
+                    resize_block(n, b, bn, &V, o.seed, 1000 + 2 * (uint64_t)it + 1);
+                }
+                b = bn;
+                free(S);
+                S = (double*)malloc(sizeof(double) * (size_t)b);
+                int svp = 0;
+                blws_step_op(&w, tau, b, U, V, S, &svp);
+                r = svp;
+                /* all s requested values above tau: ask for rank_step more */
+                if (svp < s || s >= p || b >= p / 2) break;
+                s += o.rank_step;
+            }
+            free(Ua); free(Va); free(th);
+            Ua = (double*)malloc(sizeof(double) * (size_t)m * (r > 0 ? r : 1));
+            Va = (double*)malloc(sizeof(double) * (size_t)n * (r > 0 ? r : 1));
+            th = (double*)malloc(sizeof(double) * (size_t)(r > 0 ? r : 1));
+            take_cols(m, b, 0, r, U, Ua);
+            take_cols(n, b, 0, r, V, Va);
+            for (int k = 0; k < r; ++k) th[k] = S[k] - tau;
+#pragma omp parallel for schedule(static)
+            for (int i = 0; i < m; ++i)
+                for (int e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    double v = 0.0;
+                    for (int k = 0; k < r; ++k)
+                        v += Ua[(size_t)i * r + k] * th[k] * Va[(size_t)col_idx[e] * r + k];
+                    x[e] = v;
+                }
+        }
+        double zz = 0.0;
+        for (int e = 0; e < nnz; ++e) {
+            const double z = values[e] - x[e];
+            zz += z * z;
+            y[e] += delta * z;
+        }
+        rel = sqrt(zz) / dnorm;
+        if (rel <= o.tol) break;
+    }
+    int rc = r < r_cap ? r : r_cap;
+    if (mode == 0) {
+        double* Uf = (double*)malloc(sizeof(double) * (size_t)m * p);
+        double* Vf = (double*)malloc(sizeof(double) * (size_t)n * p);
+        orc_jacobi_svd(m, n, Aden, Uf, Sfull, Vf);
+        for (int i = 0; Uout && i < m; ++i)
+            memcpy(Uout + (size_t)i * r_cap, Uf + (size_t)i * p, sizeof(double) * (size_t)rc);
+        for (int i = 0; Vout && i < n; ++i)
+            memcpy(Vout + (size_t)i * r_cap, Vf + (size_t)i * p, sizeof(double) * (size_t)rc);
+        if (Sout) memcpy(Sout, Sfull, sizeof(double) * (size_t)rc);
+        free(Uf);
+        free(Vf);
+    } else {
+        for (int i = 0; Uout && i < m; ++i)
+            memcpy(Uout + (size_t)i * r_cap, Ua + (size_t)i * r, sizeof(double) * (size_t)rc);
+        for (int i = 0; Vout && i < n; ++i)
+            memcpy(Vout + (size_t)i * r_cap, Va + (size_t)i * r, sizeof(double) * (size_t)rc);
+        if (Sout) memcpy(Sout, th, sizeof(double) * (size_t)rc);
+    }
+    if (rank_out) *rank_out = r;
+    if (info) {
+        info->iters = it > o.max_iter ? o.max_iter : it;
+        info->rank = r;
+        info->b_final = b;
+        info->nnz_E = 0;
+        info->rel_residual = rel;
+        info->norm2_D = s1;
+        info->status = (rel <= o.tol) ? 0 : 1;
+    }
+    free(y); free(x); free(U); free(V); free(S); free(Ua); free(Va); free(th);
+    free(Wd); free(Aden); free(Sfull);
+    return 0;
+}

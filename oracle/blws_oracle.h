@@ -115,6 +115,28 @@ int orc_mc(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
            const double* values, const orc_alm_opts* opts, int mode, int r_cap,
            double* U, double* S, double* V, int* rank, orc_info* info);
 
+/* Options of the SVT algorithm for matrix completion. */
+typedef struct {
+    double tau;        /* threshold; <= 0 selects 5 sqrt(m n)                    */
+    double delta;      /* step; <= 0 selects 1.2 m n / nnz                       */
+    double tol;        /* stop at ||P_Omega(X - M)||_F / ||P_Omega(M)||_F <= tol */
+    int max_iter;
+    int rank_step;     /* values added to a partial-SVD request that fell short  */
+    int b_round;       /* BLWS block width = requested count rounded up to this  */
+    int pow_steps;
+    uint64_t seed;
+    int norm_steps;    /* safety bound on the BLWS steps of ||P_Omega(M)||_2     */
+    double norm_rtol;
+} orc_svt_mc_opts;
+
+void orc_default_svt_mc_opts(orc_svt_mc_opts* o);
+
+/* The SVT algorithm for matrix completion with exact (mode 0, dense Jacobi)
+ * or BLWS (mode 1) singular value thresholding; outputs as orc_mc. */
+int orc_mc_svt(int m, int n, int nnz, const int* row_ptr, const int* col_idx,
+               const double* values, const orc_svt_mc_opts* opts, int mode, int r_cap,
+               double* U, double* S, double* V, int* rank, orc_info* info);
+
 #ifdef __cplusplus
 }
 #endif

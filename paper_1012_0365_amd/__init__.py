@@ -16,10 +16,11 @@ from __future__ import annotations
 import ctypes
 
 from . import _native
-from ._native import AlmOpts, BlwsError, ServerOpts, ServerStats, SolveInfo, SvtOpts
+from ._native import (AlmOpts, BlwsError, ServerOpts, ServerStats, SolveInfo, SvtMcOpts,
+                      SvtOpts)
 
-__all__ = ["Context", "Server", "BlwsError", "AlmOpts", "SvtOpts", "SolveInfo",
-           "default_alm_opts", "default_mc_opts"]
+__all__ = ["Context", "Server", "BlwsError", "AlmOpts", "SvtOpts", "SvtMcOpts", "SolveInfo",
+           "default_alm_opts", "default_mc_opts", "default_svt_mc_opts"]
 
 
 def _torch():
@@ -48,6 +49,16 @@ def _check_mat(t, name: str):
 def default_alm_opts(**kw) -> AlmOpts:
     o = AlmOpts()
     _native.lib().blws_default_alm_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def default_svt_mc_opts(**kw) -> SvtMcOpts:
+    o = SvtMcOpts()
+    _native.lib().blws_default_svt_mc_opts(ctypes.byref(o))
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
@@ -163,6 +174,15 @@ class Context:
         """min ||A||_* s.t. A agrees with the samples on Omega (CSR: row_ptr int32[m+1],
         col_idx int32[nnz], values float64/float32[nnz], all device tensors), by
         inexact ALM with BLWS. Returns (U, S, V, info) with A = U diag(S) V^T."""
+        return self._mc(self._lib.blws_mc_solve, m, n, row_ptr, col_idx, values, opts, r_cap)
+
+    def mc_svt_solve(self, m: int, n: int, row_ptr, col_idx, values,
+                     opts: SvtMcOpts | None = None, r_cap: int = 256):
+        """Matrix completion by the SVT algorithm (Y_k = Y_{k-1} + delta P_Omega(M - X_k),
+        X_k = T_tau(Y_{k-1}) by BLWS). Arguments and results as mc_solve."""
+        return self._mc(self._lib.blws_mc_svt_solve, m, n, row_ptr, col_idx, values, opts, r_cap)
+
+    def _mc(self, fn, m, n, row_ptr, col_idx, values, opts, r_cap):
         torch = _torch()
         prec = _prec_of(values)
         for t, name in ((row_ptr, "row_ptr"), (col_idx, "col_idx"), (values, "values")):
@@ -177,7 +197,7 @@ class Context:
         V = torch.zeros(n, r_cap, dtype=values.dtype, device=values.device)
         S = torch.zeros(r_cap, dtype=torch.float64, device=values.device)
         info = SolveInfo()
-        st = self._lib.blws_mc_solve(
+        st = fn(
             self.handle, self._stream(), prec, m, n, nnz, row_ptr.data_ptr(), col_idx.data_ptr(),
             values.data_ptr(), ctypes.byref(opts) if opts is not None else None, r_cap,
             U.data_ptr(), r_cap, S.data_ptr(), V.data_ptr(), r_cap, ctypes.byref(info))

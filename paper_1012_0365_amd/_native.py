@@ -41,6 +41,22 @@ class AlmOpts(ctypes.Structure):
     ]
 
 
+class SvtMcOpts(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double),
+        ("delta", ctypes.c_double),
+        ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int),
+        ("rank_step", ctypes.c_int),
+        ("b_round", ctypes.c_int),
+        ("b_max", ctypes.c_int),
+        ("pow_steps", ctypes.c_int),
+        ("seed", ctypes.c_ulonglong),
+        ("norm_steps", ctypes.c_int),
+        ("norm_rtol", ctypes.c_double),
+    ]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("status", ctypes.c_int),
@@ -104,6 +120,9 @@ SIGNATURES = {
     "blws_default_mc_opts": (None, [ctypes.POINTER(AlmOpts)]),
     "blws_mc_solve": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp, ctypes.POINTER(AlmOpts), _i,
                            _vp, _i, _vp, _vp, _i, ctypes.POINTER(SolveInfo)]),
+    "blws_default_svt_mc_opts": (None, [ctypes.POINTER(SvtMcOpts)]),
+    "blws_mc_svt_solve": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _vp, ctypes.POINTER(SvtMcOpts),
+                               _i, _vp, _i, _vp, _vp, _i, ctypes.POINTER(SolveInfo)]),
     "blws_fill_uniform": (_i, [_vp, _vp, _i, _i, _vp, _i, _ull, _ull]),
     "blws_gemm_f64": (_i, [_vp, _vp, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i]),
     "blws_gemm_lp": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i]),

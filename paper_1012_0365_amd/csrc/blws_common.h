@@ -239,14 +239,21 @@ void spmm(Timer* tm, const char* family, int rows, int c, const int* ptr, const 
           hipStream_t s);
 // Row k of C (r x c) times S[k] - eps.
 void lr_scale(int r, int c, const double* S, double eps, double* C, int ldc, hipStream_t s);
-// Fused update over Omega (A_Omega from the factors, multiplier, residual,
-// next sparse part); partials has mc_partials(m) entries.
+// Fused update over Omega: A_Omega from the factors (the first min(rank_dev,
+// rmax) columns, coefficients S - eps), y += mu (d - A_Omega), the next sparse
+// part sv = d + y / mu_next - A_Omega (skipped when sv is null), per-row-block
+// partial sums of (d - A_Omega)^2; partials has mc_partials(m) entries. When
+// rank_dev >= need nothing is written but zero partials (the caller repeats
+// the thresholding with a larger request first).
 size_t mc_partials(int m);
 template <typename T>
 void mc_update(Timer* tm, int m, long long nnz, const int* row_ptr, const int* col_idx,
                const T* d, T* y, T* sv, const T* U, int ldu, const T* V, int ldv, const double* S,
-               double eps, const int* rank_dev, int rmax, double mu, double mu_next,
+               double eps, const int* rank_dev, int rmax, double mu, double mu_next, int need,
                double* partials, hipStream_t s);
+// y[e] = alpha d[e] for e < nnz.
+template <typename T>
+void scale_copy(long long nnz, double alpha, const T* d, T* y, hipStream_t s);
 template <typename T>
 void mc_init(long long nnz, const T* d, T* y, T* sv, hipStream_t s);
 void theta_out(int r, const double* S, double eps, double* Sout, hipStream_t s);

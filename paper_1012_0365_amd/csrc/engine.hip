@@ -301,6 +301,36 @@ int blws_mc_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
     ABI_END
 }
 
+void blws_default_svt_mc_opts(blws_svt_mc_opts* o)
+{
+    if (!o) return;
+    o->tau = 0.0;
+    o->delta = 0.0;
+    o->tol = 1e-4;
+    o->max_iter = 500;
+    o->rank_step = 5;
+    o->b_round = 16;
+    o->b_max = 512;
+    o->pow_steps = 2;
+    o->seed = 20101202ULL;
+    o->norm_steps = 8;
+    o->norm_rtol = 1e-13;
+}
+
+int blws_mc_svt_solve(blws_ctx ctx, void* stream, int prec, int m, int n, int nnz,
+                      const int* row_ptr, const int* col_idx, const void* values,
+                      const blws_svt_mc_opts* opts, int r_cap, void* U, int ldu, double* S,
+                      void* V, int ldv, blws_solve_info* info)
+{
+    ABI_BEGIN(ctx)
+    auto job = blws::make_mc_svt_job(prec, m, n, nnz, row_ptr, col_idx, values, opts, r_cap, U,
+                                     ldu, S, V, ldv, "blws_mc_svt_solve");
+    blws::run_blocking(*job, cx, (hipStream_t)stream);
+    if (info) *info = job->info;
+    return job->status;
+    ABI_END
+}
+
 int blws_fill_uniform(blws_ctx ctx, void* stream, int rows, int cols, double* X, int ldx,
                       unsigned long long seed, unsigned long long stream_id)
 {

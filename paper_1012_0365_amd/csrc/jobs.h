@@ -11,6 +11,7 @@
 // result does not depend on how it was scheduled.
 #pragma once
 
+#include <climits>
 #include <memory>
 #include <string>
 
@@ -410,7 +411,7 @@ struct McJob : Job {
         svt_step<T>(cx, w, s, m, n, op, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         mu_next = next_mu(o, mu, mu_bar);
         mc_update<T>(&cx.timer, m, nnz, row_ptr, col_idx, d, y, sv, U, bmax, V, bmax, S, eps,
-                     rank_dev, b, mu, mu_next, part, s);
+                     rank_dev, b, mu, mu_next, INT_MAX, part, s);
         iter_readback(npart, part, rank_dev, w.nflag + 1, &rb->zz, &rb->rank, &rb->svd_err, s);
         HIP_TRY(hipMemcpyAsync(cx.host_pinned, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
     }
@@ -543,6 +544,248 @@ struct McJob : Job {
 };
 
 // ---------------------------------------------------------------------------
+// Matrix completion by the SVT algorithm (the MC host of the experiments):
+// Y_0 = k0 delta P_Omega(M), k0 = ceil(tau / (delta ||P_Omega(M)||_2)); each
+// iteration X_k = T_tau(Y_{k-1}) by BLWS on the purely sparse W = Y_{k-1},
+// then Y_k = Y_{k-1} + delta P_Omega(M - X_k), until ||P_Omega(M - X_k)||_F /
+// ||P_Omega(M)||_F <= tol. The thresholding asks for s = r_{k-1} + 1 values;
+// while all s Ritz values exceed tau it asks for rank_step more, each time a
+// BLWS step warm-started from the block just computed (widened when s
+// outgrows it). The update kernel skips its writes when the step is to be
+// repeated, so one readback per step decides both.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct McSvtJob : Job {
+    int m, n, nnz, r_cap, ldu, ldv;
+    const int *row_ptr, *col_idx;
+    const T* d;
+    T *Uout, *Vout;
+    double* Sout;
+    blws_svt_mc_opts o;
+    double tau = 0.0, delta = 0.0;
+    int p, bmax;
+    StepWs<T> w;
+    T *U = nullptr, *V = nullptr, *y = nullptr;
+    double *S = nullptr, *coef = nullptr, *part = nullptr, *scal = nullptr;
+    int *col_ptr = nullptr, *csc_row = nullptr, *csc_perm = nullptr, *csc_scr = nullptr;
+    int *flag = nullptr, *rank_dev = nullptr;
+    Readback* rb = nullptr;
+    McOp<T> mo;
+    enum Phase { CHECK, NORMS, SPEC, STEP, FINISH } phase = CHECK;
+    double dnorm = 0.0, s1 = 0.0, prev = 0.0, rel = INFINITY;
+    int t = 0, sreq = 1, b = 0, r = 0, it = 0, npart = 0, steps = 0;
+
+    McSvtJob(int m_, int n_, int nnz_, const int* rp, const int* ci, const T* d_,
+             const blws_svt_mc_opts& o_, int r_cap_, T* U_, int ldu_, double* S_, T* V_, int ldv_)
+        : m(m_), n(n_), nnz(nnz_), r_cap(r_cap_), ldu(ldu_), ldv(ldv_), row_ptr(rp), col_idx(ci),
+          d(d_), Uout(U_), Vout(V_), Sout(S_), o(o_)
+    {
+        p = m < n ? m : n;
+        bmax = (p / 2 < o.b_max) ? p / 2 : o.b_max;
+        tau = o.tau > 0.0 ? o.tau : 5.0 * std::sqrt((double)m * (double)n);
+        delta = o.delta > 0.0 ? o.delta : 1.2 * (double)m * (double)n / (nnz > 0 ? nnz : 1);
+        npart = (int)mc_partials(m);
+    }
+
+    void layout(Carver& c)
+    {
+        const size_t np = std::max(mc_partials(m), norms_scratch_elems());
+        w.carve(c, m, n, bmax);
+        U = c.take<T>((size_t)m * bmax);
+        V = c.take<T>((size_t)n * bmax);
+        S = c.take<double>(bmax);
+        y = c.take<T>((size_t)nnz + 1);
+        coef = c.take<double>((size_t)bmax * bmax);
+        part = c.take<double>(np);
+        scal = c.take<double>(16);
+        col_ptr = c.take<int>((size_t)n + 1);
+        csc_row = c.take<int>((size_t)nnz + 1);
+        csc_perm = c.take<int>((size_t)nnz + 1);
+        csc_scr = c.take<int>(csc_scratch_ints(n, nnz));
+        flag = c.take<int>(4);
+        rank_dev = c.take<int>(4);
+        rb = c.take<Readback>(1);
+    }
+
+    size_t workspace_bytes() override
+    {
+        Carver dry(nullptr);
+        layout(dry);
+        return dry.off + 256;
+    }
+
+    void start(Context& cx, hipStream_t s) override
+    {
+        Carver c(cx.ws);
+        layout(c);
+        zero_bytes(w.nflag, 4 * sizeof(int), s);
+        csr_check(m, n, nnz, row_ptr, col_idx, flag, s);
+        HIP_TRY(hipMemcpyAsync(cx.host_pinned, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        phase = CHECK;
+    }
+
+    void spec_step(Context& cx, hipStream_t s)
+    {
+        const int bs = bmax < 16 ? bmax : 16;
+        const Op<T> op{nullptr, 0, &mo, nullptr};
+        svt_step<T>(cx, w, s, m, n, op, 0.0, bs, U, bs, V, bs, S, nullptr, o.seed);
+        HIP_TRY(hipMemcpyAsync(cx.host_pinned, S, sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+
+    // one thresholding of W = Y at the request sreq, and the update (skipped
+    // on the device when all sreq values exceed tau and sreq can still grow)
+    void queue_step(Context& cx, hipStream_t s)
+    {
+        const Op<T> op{nullptr, 0, &mo, nullptr};
+        int bn = ((sreq + o.b_round - 1) / o.b_round) * o.b_round;
+        bn = std::max(1, std::min(bn, bmax));
+        if (b == 0) {
+            cold_block<T>(cx, w, s, m, n, op, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
+        } else if (bn > b) {
+            grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)steps);
+            grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)steps + 1);
+        }
+        b = bn;
+        ++steps;
+        svt_step<T>(cx, w, s, m, n, op, tau, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        // the request can still grow unless it reached min(m, n) or the block its cap
+        const int need = (sreq >= p || b >= bmax) ? INT_MAX : sreq;
+        mc_update<T>(&cx.timer, m, nnz, row_ptr, col_idx, d, y, (T*)nullptr, U, bmax, V, bmax, S,
+                     tau, rank_dev, b, delta, delta, need, part, s);
+        iter_readback(npart, part, rank_dev, w.nflag + 1, &rb->zz, &rb->rank, &rb->svd_err, s);
+        HIP_TRY(hipMemcpyAsync(cx.host_pinned, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
+        last_need = need;
+    }
+    int last_need = INT_MAX;
+
+    void queue_finish(Context& cx, hipStream_t s)
+    {
+        const int rc = r < r_cap ? r : r_cap;
+        if (rc > 0) {
+            copy2d<T, T>(m, rc, U, bmax, Uout, ldu, s);
+            copy2d<T, T>(n, rc, V, bmax, Vout, ldv, s);
+            theta_out(rc, S, tau, Sout, s);
+        }
+        HIP_TRY(hipMemcpyAsync(&rb->nflag, w.nflag, sizeof(int), hipMemcpyDeviceToDevice, s));
+        HIP_TRY(hipMemcpyAsync(cx.host_pinned, rb, sizeof(Readback), hipMemcpyDeviceToHost, s));
+        phase = FINISH;
+    }
+
+    void advance(Context& cx, hipStream_t s) override
+    {
+        const Readback* hrb = (const Readback*)cx.host_pinned;
+        switch (phase) {
+            case CHECK: {
+                const int bad = *(const int*)hrb;
+                BLWS_REQUIRE(bad == 0, BLWS_EINVAL,
+                             (bad & 1) ? "mc_svt_solve: row_ptr is not nondecreasing from 0 to nnz"
+                                       : "mc_svt_solve: a column index lies outside [0, n)");
+                csc_build(m, n, nnz, row_ptr, col_idx, col_ptr, csc_row, csc_perm, flag + 1,
+                          csc_scr, s);
+                if (nnz == 0) {
+                    std::memset(&info, 0, sizeof(info));
+                    done = true;
+                    return;
+                }
+                norms<T>(1, nnz, d, nnz, scal, part, s);
+                HIP_TRY(hipMemcpyAsync(cx.host_pinned, scal, 2 * sizeof(double),
+                                       hipMemcpyDeviceToHost, s));
+                phase = NORMS;
+                return;
+            }
+            case NORMS: {
+                dnorm = std::sqrt(((const double*)hrb)[0]);
+                BLWS_REQUIRE(std::isfinite(dnorm), BLWS_ENUMERIC,
+                             "mc_svt_solve: values hold NaN or Inf");
+                if (dnorm == 0.0) {
+                    std::memset(&info, 0, sizeof(info));
+                    done = true;
+                    return;
+                }
+                mo.nnz = nnz;
+                mo.row_ptr = row_ptr;
+                mo.col_idx = col_idx;
+                mo.col_ptr = col_ptr;
+                mo.csc_row = csc_row;
+                mo.csc_perm = csc_perm;
+                mo.Ul = U;
+                mo.Vl = V;
+                mo.ldl = bmax;
+                mo.S = S;
+                mo.coef = coef;
+                mo.r = 0;  // W = Y is purely sparse
+                mo.sval = d;
+                const int bs = bmax < 16 ? bmax : 16;
+                const Op<T> op{nullptr, 0, &mo, nullptr};
+                cold_block<T>(cx, w, s, m, n, op, bs, o.pow_steps, o.seed, 3, U, bs, V, bs);
+                prev = 0.0;
+                t = 0;
+                spec_step(cx, s);
+                phase = SPEC;
+                return;
+            }
+            case SPEC: {
+                s1 = ((const double*)hrb)[0];
+                BLWS_REQUIRE(std::isfinite(s1) && s1 > 0.0, BLWS_ENUMERIC,
+                             "mc_svt_solve: ||P_Omega(M)||_2 is not finite");
+                const bool conv = t > 0 && std::fabs(s1 - prev) <= o.norm_rtol * s1;
+                prev = s1;
+                ++t;
+                if (!conv && t < o.norm_steps) {
+                    spec_step(cx, s);
+                    return;
+                }
+                const double k0 = std::ceil(tau / (delta * s1));
+                scale_copy<T>(nnz, k0 * delta, d, y, s);
+                mo.sval = y;
+                it = 1;
+                sreq = 1;
+                queue_step(cx, s);
+                phase = STEP;
+                return;
+            }
+            case STEP: {
+                BLWS_REQUIRE(hrb->svd_err == 0, BLWS_EDEVICE,
+                             "small SVD: a device-wide barrier wait timed out");
+                const int svp = hrb->rank;
+                if (svp >= last_need) {  // every requested value above tau: ask for more
+                    sreq += o.rank_step;
+                    queue_step(cx, s);
+                    return;
+                }
+                BLWS_REQUIRE(std::isfinite(hrb->zz), BLWS_ENUMERIC,
+                             "mc_svt_solve: residual is not finite");
+                r = svp;
+                rel = std::sqrt(hrb->zz) / dnorm;
+                if (rel <= o.tol || it >= o.max_iter) {
+                    queue_finish(cx, s);
+                    return;
+                }
+                ++it;
+                sreq = r + 1;
+                queue_step(cx, s);
+                return;
+            }
+            case FINISH: {
+                info.status = rel <= o.tol ? BLWS_OK : BLWS_NOT_CONVERGED;
+                info.iters = it;
+                info.rank = r;
+                info.b_final = b;
+                info.fallbacks = hrb->nflag;
+                info.nnz_E = 0;
+                info.iters_bf16 = 0;
+                info.refined = 0;
+                info.rel_residual = rel;
+                info.norm2_D = s1;
+                status = info.status;
+                done = true;
+                return;
+            }
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
 // Argument checks and job construction, shared by the blocking solvers and the
 // request server (errors are thrown as BlwsError before any work is queued).
 // ---------------------------------------------------------------------------
@@ -601,6 +844,36 @@ inline std::unique_ptr<Job> make_mc_job(int prec, int m, int n, int nnz, const i
         return std::unique_ptr<Job>(new McJob<float>(m, n, nnz, row_ptr, col_idx,
                                                      (const float*)values, o, r_cap, (float*)U,
                                                      ldu, S, (float*)V, ldv));
+    throw BlwsError{BLWS_EUNSUPPORTED, who + ": precision not supported"};
+}
+
+inline std::unique_ptr<Job> make_mc_svt_job(int prec, int m, int n, int nnz, const int* row_ptr,
+                                            const int* col_idx, const void* values,
+                                            const blws_svt_mc_opts* opts, int r_cap, void* U,
+                                            int ldu, double* S, void* V, int ldv,
+                                            const std::string& who)
+{
+    BLWS_REQUIRE(m >= 2 && n >= 2 && nnz >= 0, BLWS_EINVAL, who + ": need m, n >= 2");
+    BLWS_REQUIRE(row_ptr && U && S && V && (nnz == 0 || (col_idx && values)), BLWS_EINVAL,
+                 who + ": null pointer argument");
+    BLWS_REQUIRE(r_cap >= 1 && ldu >= r_cap && ldv >= r_cap, BLWS_EINVAL,
+                 who + ": need r_cap >= 1 and ldu, ldv >= r_cap");
+    blws_svt_mc_opts o;
+    blws_default_svt_mc_opts(&o);
+    if (opts) o = *opts;
+    BLWS_REQUIRE(std::isfinite(o.tau) && std::isfinite(o.delta) && o.tol > 0.0 &&
+                     o.max_iter >= 1 && o.rank_step >= 1 && o.b_round >= 1 && o.b_max >= 1 &&
+                     o.pow_steps >= 0 && o.norm_steps >= 1,
+                 BLWS_EINVAL, who + ": bad options");
+    BLWS_REQUIRE(o.b_max <= 512, BLWS_EUNSUPPORTED, who + ": b_max above 512");
+    if (prec == BLWS_FP64)
+        return std::unique_ptr<Job>(new McSvtJob<double>(m, n, nnz, row_ptr, col_idx,
+                                                         (const double*)values, o, r_cap,
+                                                         (double*)U, ldu, S, (double*)V, ldv));
+    if (prec == BLWS_FP32)
+        return std::unique_ptr<Job>(new McSvtJob<float>(m, n, nnz, row_ptr, col_idx,
+                                                        (const float*)values, o, r_cap, (float*)U,
+                                                        ldu, S, (float*)V, ldv));
     throw BlwsError{BLWS_EUNSUPPORTED, who + ": precision not supported"};
 }
 

@@ -205,12 +205,16 @@ template <typename T>
 __global__ __launch_bounds__(256) void mc_update_kernel(
     int m, const int* row_ptr, const int* col_idx, const T* d, T* y, T* sv, const T* U, int ldu,
     const T* V, int ldv, const double* S, double eps, const int* rank_dev, int rmax, double mu,
-    double mu_next, double* part)
+    double mu_next, int need, double* part)
 {
     __shared__ double coef[4][512];
     __shared__ double red[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + wave;
+    if (rank_dev[0] >= need) {  // the host repeats the thresholding first
+        if (threadIdx.x == 0) part[blockIdx.x] = 0.0;
+        return;
+    }
     int r = rank_dev[0];
     if (r > rmax) r = rmax;
     if (r < 0) r = 0;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(256) void mc_update_kernel(
             const double zv = dd - s;
             const T yn = (T)((double)y[e] + mu * zv);
             y[e] = yn;
-            sv[e] = (T)(dd + (double)yn / mu_next - s);
+            if (sv) sv[e] = (T)(dd + (double)yn / mu_next - s);
             zz += zv * zv;
         }
     }
@@ -236,6 +240,13 @@ __global__ __launch_bounds__(256) void mc_update_kernel(
     if (lane == 0) red[wave] = zz;
     __syncthreads();
     if (threadIdx.x == 0) part[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+template <typename T>
+__global__ void scale_copy_kernel(int nnz, double alpha, const T* d, T* y)
+{
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nnz; e += gridDim.x * blockDim.x)
+        y[e] = (T)(alpha * (double)d[e]);
 }
 
 template <typename T>
@@ -320,7 +331,7 @@ size_t mc_partials(int m) { return (size_t)(m + 3) / 4; }
 template <typename T>
 void mc_update(Timer* tm, int m, long long nnz, const int* row_ptr, const int* col_idx,
                const T* d, T* y, T* sv, const T* U, int ldu, const T* V, int ldv, const double* S,
-               double eps, const int* rank_dev, int rmax, double mu, double mu_next,
+               double eps, const int* rank_dev, int rmax, double mu, double mu_next, int need,
                double* partials, hipStream_t s)
 {
     BLWS_REQUIRE(rmax <= 512, BLWS_EUNSUPPORTED, "mc_update: rank above 512");
@@ -328,7 +339,15 @@ void mc_update(Timer* tm, int m, long long nnz, const int* row_ptr, const int* c
                    (double)nnz * (sizeof(int) + 5.0 * sizeof(T)));
     hipLaunchKernelGGL((mc_update_kernel<T>), dim3((m + 3) / 4), dim3(256), 0, s, m, row_ptr,
                        col_idx, d, y, sv, U, ldu, V, ldv, S, eps, rank_dev, rmax, mu, mu_next,
-                       partials);
+                       need, partials);
+}
+
+template <typename T>
+void scale_copy(long long nnz, double alpha, const T* d, T* y, hipStream_t s)
+{
+    if (nnz <= 0) return;
+    hipLaunchKernelGGL((scale_copy_kernel<T>), dim3(grid_for(nnz, 256)), dim3(256), 0, s,
+                       (int)nnz, alpha, d, y);
 }
 
 template <typename T>
@@ -350,8 +369,9 @@ void theta_out(int r, const double* S, double eps, double* Sout, hipStream_t s)
                           const T*, const T*, int, T*, int, long long, hipStream_t);           \
     template void mc_update<T>(Timer*, int, long long, const int*, const int*, const T*, T*,   \
                                T*, const T*, int, const T*, int, const double*, double,         \
-                               const int*, int, double, double, double*, hipStream_t);          \
-    template void mc_init<T>(long long, const T*, T*, T*, hipStream_t);
+                               const int*, int, double, double, int, double*, hipStream_t);     \
+    template void mc_init<T>(long long, const T*, T*, T*, hipStream_t);                        \
+    template void scale_copy<T>(long long, double, const T*, T*, hipStream_t);
 BLWS_INST_SPARSE(double)
 BLWS_INST_SPARSE(float)
 

@@ -421,3 +421,58 @@ def test_mc_recovers_planted_low_rank():
         assert np.linalg.norm(A - M) / np.linalg.norm(M) < 1e-6
         res[mode] = A
     assert np.linalg.norm(res["exact"] - res["blws"]) / np.linalg.norm(M) < 1e-6
+
+
+# --------------------------------------------------------------------------
+# the SVT algorithm for matrix completion (Table 2's host)
+# --------------------------------------------------------------------------
+def _planted_error(out, inst):
+    """||U S V^T - L R^T||_F / ||L R^T||_F from the factors (no dense product)."""
+    U, S, V, L, R = out["U"], out["S"], out["V"], inst["L"], inst["R"]
+    nA2 = float(np.sum(S ** 2))
+    nM2 = float(np.sum((L.T @ L) * (R.T @ R)))
+    ip = float(np.sum(((U * S).T @ L) * (V.T @ R)))
+    return np.sqrt(max(nA2 + nM2 - 2.0 * ip, 0.0)) / np.sqrt(nM2)
+
+
+def _table2_instance(m, r, ratio, seed=0):
+    s = ratio * r * (2 * m - r)  # s / d_r with d_r = r (2 m - r)
+    return synth.mc_instance(m, m, r, s / float(m * m), seed)
+
+
+def test_mc_svt_exact_and_blws_thresholding_agree():
+    """Same host, exact (Jacobi) or BLWS thresholding: the same iterations and
+    rank and the same completed matrix; recovery at the tolerance's scale."""
+    inst = _table2_instance(200, 5, 6)
+    ex = oracle.mc_svt(200, 200, inst["row_ptr"], inst["col_idx"], inst["values"], mode="exact",
+                       r_cap=32)
+    bl = oracle.mc_svt(200, 200, inst["row_ptr"], inst["col_idx"], inst["values"], mode="blws",
+                       r_cap=32)
+    assert ex["info"]["status"] == bl["info"]["status"] == 0
+    assert ex["info"]["iters"] == bl["info"]["iters"]
+    assert ex["rank"] == bl["rank"] == 5
+    Ae = ex["U"] * ex["S"] @ ex["V"].T
+    Ab = bl["U"] * bl["S"] @ bl["V"].T
+    assert np.linalg.norm(Ae - Ab) <= 1e-6 * np.linalg.norm(Ae)
+    assert _planted_error(bl, inst) < 5e-4
+
+
+@pytest.mark.parametrize("m,r,ratio,iters,err", [
+    (5000, 10, 6, 123, 1.74e-4),
+    (10000, 10, 6, 123, 1.70e-4),
+    (5000, 50, 5, 108, 1.55e-4),
+])
+def test_mc_svt_table2_rows(m, r, ratio, iters, err):
+    """Table 2, BLWS-SVT rows: m x m, rank r, s/d_r samples; the paper prints the
+    iteration count and the relative error of the recovered matrix. The host's
+    constants (tau = 5 m, delta = 1.2 m^2 / s, tol 1e-4, rank step 5) are those
+    of the SVT algorithm's source; the draws are ours, so the counts match to a
+    few iterations and the errors to a few percent."""
+    inst = _table2_instance(m, r, ratio)
+    out = oracle.mc_svt(m, m, inst["row_ptr"], inst["col_idx"], inst["values"], mode="blws",
+                        r_cap=128)
+    info = out["info"]
+    assert info["status"] == 0 and out["rank"] == r
+    assert abs(info["iters"] - iters) <= 6, info["iters"]
+    e = _planted_error(out, inst)
+    assert err / 1.25 <= e <= err * 1.25, e
