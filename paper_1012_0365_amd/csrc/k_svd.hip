@@ -1908,17 +1908,30 @@ __device__ __forceinline__ int ts_nsteps(int N, int i) { return (N - 2 - i) / TS
 // Stage 2: band (global, rows of TS_BW) -> bidiagonal d, e; reflectors of
 // task (i, j) at rec[(i * jmax + j) * TS_REC]. One workgroup of 1024 threads;
 // in slot t the wavefront i % 16 runs task (i, t - 2 i).
+//
+// A task's 16 x 32 block is held one row (right reflector: rows r0 .. r0 + 31,
+// columns c0 .. c0 + 15) or one column (left reflector: columns c0 .. c0 + 31,
+// rows c0 .. c0 + 15) per 32-lane half-wavefront position, each half owning
+// eight of the 16 reflector entries: the dot products are eight in-lane
+// products plus one cross-half sum, and the reflector itself is read by every
+// lane from LDS (a broadcast). Positions outside the block (past N - 1, or past
+// the task's last row or column) still read inside the array, which has 16
+// spare rows, and drop the value; their stores go to one spare word.
+constexpr int TS_S2_WORDS = (TS_MAXN + TS_NB) * TS_BW + 1;
+constexpr int TS_TRASH = TS_S2_WORDS - 1;
+__device__ __forceinline__ int ts_idx(int r, int c) { return r * (TS_BW - 1) + c + TS_BOFF; }
+
 __global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __restrict__ band,
                                                          double* __restrict__ dout,
                                                          double* __restrict__ eout,
                                                          double* __restrict__ rec)
 {
-    __shared__ double bd[TS_MAXN * TS_BW];
+    __shared__ double bd[TS_S2_WORDS];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, l = lane & 15;
+    const int h = lane >> 5, q = lane & 31;
     for (int e = tid; e < N * TS_BW; e += 1024) bd[e] = band[e];
+    for (int e = N * TS_BW + tid; e < TS_S2_WORDS; e += 1024) bd[e] = 0.0;
     __syncthreads();
-    auto B = [&](int r, int c) -> double& { return bd[r * TS_BW + (c - r + TS_BOFF)]; };
     const int jmax = ts_jmax(N);
     const int nslot = max(2 * (N - 2), jmax - 1) + 1;
     for (int t = 0; t < nslot; ++t) {
@@ -1928,35 +1941,50 @@ __global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __
         const int i = hi - ((hi - wave) & 15);
         const int j = t - 2 * i;
         const bool has = i >= 0 && j < ts_nsteps(N, i);  // uniform per wavefront
+        const int c0 = i + 1 + TS_NB * j;
+        const int c1 = min(c0 + TS_NB - 1, N - 1);
+        const int L = c1 - c0 + 1;
         if (has) {
-            const int r0 = j == 0 ? i : i + 1 + TS_NB * (j - 1);
-            const int c0 = i + 1 + TS_NB * j;
-            const int c1 = min(c0 + TS_NB - 1, N - 1);
-            const int L = c1 - c0 + 1;
             double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
-            // right reflector on columns c0..c1 for row r0, rows r0..c1
-            {
-                const double x = l < L ? B(r0, c0 + l) : 0.0;
-                const double s2 = row_sum16(l >= 1 ? x * x : 0.0);
-                double tv, bv, sc;
-                house(readlane_f64(x, 0), s2, tv, bv, sc);
-                const double v = l == 0 ? 1.0 : (l < L ? x * sc : 0.0);
-                const int nr = c1 - r0 + 1;
-                double a[8];
+            // right reflector on columns c0..c1 of row r0, applied to rows
+            // r0..c1; lane (h, q) holds row r0 + q, columns c0 + 8 h + k
+            const int r0 = j == 0 ? i : i + 1 + TS_NB * (j - 1);
+            const int nr = c1 - r0 + 1;
+            const double alpha = bd[ts_idx(r0, c0)];
+            const double* xr = bd + ts_idx(r0, c0 + 8 * h);
+            const double* ar = bd + ts_idx(r0 + q, c0 + 8 * h);
+            double x[8], a[8];
 #pragma unroll
-                for (int s = 0; s < 8; ++s)
-                    a[s] = (g + 4 * s < nr && l < L) ? B(r0 + g + 4 * s, c0 + l) : 0.0;
-                double dt[8];
+            for (int k = 0; k < 8; ++k) {
+                const double xv = xr[k], av = ar[k];
+                const bool in = 8 * h + k < L;
+                x[k] = (in & ((h | k) != 0)) ? xv : 0.0;
+                a[k] = (in & (q < nr)) ? av : 0.0;
+            }
+            double s2 = 0.0;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) dt[s] = tv * row_sum16(a[s] * v);
+            for (int k = 0; k < 8; ++k) s2 = fma(x[k], x[k], s2);
+            s2 = halves_sum(s2);
+            double tv, bv, sc;
+            house(alpha, s2, tv, bv, sc);
+            double v[8], d = 0.0;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int row = r0 + g + 4 * s;
-                    if (g + 4 * s < nr && l < L)
-                        B(row, c0 + l) = row == r0 ? (l == 0 ? bv : 0.0) : a[s] - dt[s] * v;
-                }
-                if (g == 0) rc[l] = v;
-                if (lane == 0) rc[16] = tv;
+            for (int k = 0; k < 8; ++k) {
+                v[k] = (h | k) ? x[k] * sc : 1.0;
+                d = fma(a[k], v[k], d);
+            }
+            const double dt = tv * halves_sum(d);
+            double* wr = bd + ts_idx(r0 + q, c0 + 8 * h);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool in = (8 * h + k < L) & (q < nr);
+                const double nv = q == 0 ? ((h | k) ? 0.0 : bv) : fma(-dt, v[k], a[k]);
+                *(in ? wr + k : bd + TS_TRASH) = nv;
+            }
+            if (q == 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) rc[8 * h + k] = v[k];
+                if (h == 0) rc[16] = tv;
             }
         }
         // the right reflectors of a slot before its left reflectors: task (i, j)
@@ -1964,40 +1992,52 @@ __global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __
         // (i + 1, j - 2) in the same slot then updates
         lds_barrier();
         if (has) {
-            const int c0 = i + 1 + TS_NB * j;
-            const int c1 = min(c0 + TS_NB - 1, N - 1);
-            const int L = c1 - c0 + 1;
             double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
-            // left reflector on rows c0..c1 for column c0, columns c0..c0 + 31
-            {
-                const double x = l < L ? B(c0 + l, c0) : 0.0;
-                const double s2 = row_sum16(l >= 1 ? x * x : 0.0);
-                double tu, bu, sc;
-                house(readlane_f64(x, 0), s2, tu, bu, sc);
-                const double u = l == 0 ? 1.0 : (l < L ? x * sc : 0.0);
-                const int nc = min(c1 + TS_NB, N - 1) - c0 + 1;
-                double a[8];
+            // left reflector on rows c0..c1 of column c0, applied to columns
+            // c0..c0 + nc - 1; lane (h, q) holds column c0 + q, rows c0 + 8 h + k
+            const int nc = min(c1 + TS_NB, N - 1) - c0 + 1;
+            const double alpha = bd[ts_idx(c0, c0)];
+            const double* xr = bd + ts_idx(c0 + 8 * h, c0);
+            const double* ar = bd + ts_idx(c0 + 8 * h, c0 + q);
+            double x[8], a[8];
 #pragma unroll
-                for (int s = 0; s < 8; ++s)
-                    a[s] = (g + 4 * s < nc && l < L) ? B(c0 + l, c0 + g + 4 * s) : 0.0;
-                double dt[8];
+            for (int k = 0; k < 8; ++k) {
+                const double xv = xr[k * (TS_BW - 1)], av = ar[k * (TS_BW - 1)];
+                const bool in = 8 * h + k < L;
+                x[k] = (in & ((h | k) != 0)) ? xv : 0.0;
+                a[k] = (in & (q < nc)) ? av : 0.0;
+            }
+            double s2 = 0.0;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) dt[s] = tu * row_sum16(a[s] * u);
+            for (int k = 0; k < 8; ++k) s2 = fma(x[k], x[k], s2);
+            s2 = halves_sum(s2);
+            double tu, bu, sc;
+            house(alpha, s2, tu, bu, sc);
+            double u[8], d = 0.0;
 #pragma unroll
-                for (int s = 0; s < 8; ++s) {
-                    const int col = c0 + g + 4 * s;
-                    if (g + 4 * s < nc && l < L)
-                        B(c0 + l, col) = col == c0 ? (l == 0 ? bu : 0.0) : a[s] - dt[s] * u;
-                }
-                if (g == 0) rc[17 + l] = u;
-                if (lane == 0) rc[33] = tu;
+            for (int k = 0; k < 8; ++k) {
+                u[k] = (h | k) ? x[k] * sc : 1.0;
+                d = fma(a[k], u[k], d);
+            }
+            const double dt = tu * halves_sum(d);
+            double* wr = bd + ts_idx(c0 + 8 * h, c0 + q);
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool in = (8 * h + k < L) & (q < nc);
+                const double nv = q == 0 ? ((h | k) ? 0.0 : bu) : fma(-dt, u[k], a[k]);
+                *(in ? wr + k * (TS_BW - 1) : bd + TS_TRASH) = nv;
+            }
+            if (q == 0) {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) rc[17 + 8 * h + k] = u[k];
+                if (h == 0) rc[33] = tu;
             }
         }
         lds_barrier();
     }
-    for (int i = tid; i < N; i += 1024) {
-        dout[i] = B(i, i);
-        if (i + 1 < N) eout[i] = B(i, i + 1);
+    for (int r = tid; r < N; r += 1024) {
+        dout[r] = bd[ts_idx(r, r)];
+        if (r + 1 < N) eout[r] = bd[ts_idx(r, r + 1)];
     }
 }
 
