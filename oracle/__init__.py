@@ -44,7 +44,14 @@ class AlmOpts(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("norm_steps", ctypes.c_int),
         ("norm_rtol", ctypes.c_double),
+        ("svt_start", ctypes.c_int),
+        ("k_blocks", ctypes.c_int),
     ]
+
+
+# start blocks of the literal block Lanczos on [[0, W], [W^T, 0]] (Sec. 4.1)
+START_SPLIT, START_AUG, START_LEFT, START_RIGHT = 0, 1, 2, 3
+STARTS = {"split": START_SPLIT, "aug": START_AUG, "left": START_LEFT, "right": START_RIGHT}
 
 
 class SvtMcOpts(ctypes.Structure):
@@ -105,6 +112,8 @@ def lib():
         L.orc_svt_exact.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_double, d, d, i]
         L.orc_blws_step.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_double,
                                     ctypes.c_int, d, d, d, d, i]
+        L.orc_lanczos_svt.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, d, d, i]
         L.orc_cold_block.argtypes = [ctypes.c_int, ctypes.c_int, d, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, d, d]
         L.orc_spectral_norm_blws.restype = ctypes.c_double
@@ -243,6 +252,25 @@ def blws_step(W, eps: float, U, V, want_A: bool = True):
                              _dp(A) if want_A else None, ctypes.byref(r))
     if rc < 0:
         raise RuntimeError(f"orc_blws_step failed: {rc}")
+    return U, V, S, A, r.value
+
+
+def lanczos_svt(W, eps: float, U, V, start: str = "aug", k: int = 2, want_A: bool = True):
+    """Algorithms 2-3 taken literally on the augmented matrix from the start
+    block `start` ("split", "aug", "left", "right") built from (U, V), with k
+    blocks; returns (U_new, V_new, S, A or None, rank) as blws_step does."""
+    W = _f64(W)
+    m, n = W.shape
+    U = np.array(U, dtype=np.float64, order="C", copy=True)
+    V = np.array(V, dtype=np.float64, order="C", copy=True)
+    b = U.shape[1]
+    S = np.empty(b)
+    A = np.empty((m, n)) if want_A else None
+    r = ctypes.c_int(0)
+    rc = lib().orc_lanczos_svt(m, n, _dp(W), eps, b, STARTS[start], k, _dp(U), _dp(V), _dp(S),
+                               _dp(A) if want_A else None, ctypes.byref(r))
+    if rc != 0:
+        raise RuntimeError(f"orc_lanczos_svt failed: {rc}")
     return U, V, S, A, r.value
 
 

@@ -659,6 +659,8 @@ void orc_default_opts(orc_alm_opts* o)
     o->seed = 20101202ULL;
     o->norm_steps = 5000; /* a safety bound only: the steps stop on norm_rtol */
     o->norm_rtol = 1e-13;
+    o->svt_start = ORC_START_SPLIT;
+    o->k_blocks = 2;
 }
 
 /* Block width for a predicted rank sv (Sec. 4.2: the Ritz output follows the
@@ -733,6 +735,200 @@ int orc_resize_block(int rows, int b_old, int b_new, const double* X, uint64_t s
     memcpy(Y, T, sizeof(double) * (size_t)rows * b_new);
     free(T);
     return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ablations of Sec. 4.1: Algorithms 2 and 3 taken literally on the          */
+/* augmented matrix W~ = [[0, W], [W^T, 0]] (Theorem 1), formed explicitly,  */
+/* from one of four start blocks and with k blocks:                          */
+/*   ORC_START_SPLIT  X_1 = blockdiag(U, V)       (2b columns; the reading   */
+/*                    of the default step, which skips the zero blocks)      */
+/*   ORC_START_AUG    X_1 = (U; V) / sqrt(2)      (b columns; the start the  */
+/*                    paper writes for BLWS in Sec. 4.1)                     */
+/*   ORC_START_LEFT   X_1 = (U; 0)                (b columns; the standard   */
+/*   ORC_START_RIGHT  X_1 = (0; V)                 half-information starts)  */
+/* The start block is orthonormalised (Algorithm 2 takes an orthogonal X_1;  */
+/* a no-op on the span when U and V are orthonormal). Each new block is kept */
+/* orthogonal to all earlier ones (block reorthogonalisation: the QR step    */
+/* runs on [X_1 .. X_l, R_l]), which changes nothing in exact arithmetic.    */
+/* Algorithm 3: EVD of the block tridiagonal T_k by cyclic Jacobi, values in */
+/* decreasing order; the top b Ritz vectors Y = Q_k Z(:, 1:b) give           */
+/* U = sqrt(2) Y_top, V = sqrt(2) Y_bottom (Theorem 1: an eigenvector of W~  */
+/* for sigma > 0 is (u; v) / sqrt(2)) and S the top b Ritz values.           */
+/* ------------------------------------------------------------------------ */
+
+/* Symmetric eigenvalue decomposition by the cyclic Jacobi method (textbook,
+ * e.g. Golub & Van Loan): rotations in the (p, q) planes, row by row, until a
+ * sweep finds every off-diagonal entry negligible against its diagonal pair.
+ * A (N x N, row-major) is destroyed; lam receives the eigenvalues in
+ * decreasing order and Z (N x N, row-major) the eigenvectors as columns. */
+static int jacobi_eig(int N, double* A, double* lam, double* Z)
+{
+    double* Zt = (double*)malloc(sizeof(double) * (size_t)N * N); /* row j = vector j */
+    int* idx = (int*)malloc(sizeof(int) * (size_t)N);
+    if (!Zt || !idx) return -2;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j) Zt[(size_t)i * N + j] = (i == j) ? 1.0 : 0.0;
+    double fro = 0.0;
+    for (size_t e = 0; e < (size_t)N * N; ++e) fro += A[e] * A[e];
+    fro = sqrt(fro);
+    int sweep = 0;
+    for (; sweep < 100; ++sweep) {
+        long long rot = 0;
+        for (int p = 0; p < N - 1; ++p)
+            for (int q = p + 1; q < N; ++q) {
+                const double apq = A[(size_t)p * N + q];
+                const double app = A[(size_t)p * N + p], aqq = A[(size_t)q * N + q];
+                /* negligible against its diagonal pair, or against the whole
+                 * matrix (zero diagonals: the half-information starts) */
+                if (fabs(apq) <= EPS64 * sqrt(fabs(app * aqq)) ||
+                    fabs(apq) <= 1e-4 * EPS64 * fro) {
+                    A[(size_t)p * N + q] = A[(size_t)q * N + p] = 0.0;
+                    continue;
+                }
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                /* A <- J^T A J with J the rotation in the (p, q) plane */
+                for (int r = 0; r < N; ++r) {
+                    const double arp = A[(size_t)r * N + p], arq = A[(size_t)r * N + q];
+                    A[(size_t)r * N + p] = c * arp - s * arq;
+                    A[(size_t)r * N + q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < N; ++r) {
+                    const double apr = A[(size_t)p * N + r], aqr = A[(size_t)q * N + r];
+                    A[(size_t)p * N + r] = c * apr - s * aqr;
+                    A[(size_t)q * N + r] = s * apr + c * aqr;
+                }
+                A[(size_t)p * N + q] = A[(size_t)q * N + p] = 0.0;
+                for (int r = 0; r < N; ++r) {
+                    const double zp = Zt[(size_t)p * N + r], zq = Zt[(size_t)q * N + r];
+                    Zt[(size_t)p * N + r] = c * zp - s * zq;
+                    Zt[(size_t)q * N + r] = s * zp + c * zq;
+                }
+                ++rot;
+            }
+        if (rot == 0) break;
+    }
+    /* decreasing order (selection sort on the diagonal) */
+    for (int i = 0; i < N; ++i) idx[i] = i;
+    for (int i = 0; i < N; ++i) {
+        int best = i;
+        for (int j = i + 1; j < N; ++j)
+            if (A[(size_t)idx[j] * N + idx[j]] > A[(size_t)idx[best] * N + idx[best]]) best = j;
+        int t = idx[i]; idx[i] = idx[best]; idx[best] = t;
+    }
+    for (int i = 0; i < N; ++i) {
+        lam[i] = A[(size_t)idx[i] * N + idx[i]];
+        for (int r = 0; r < N; ++r) Z[(size_t)r * N + i] = Zt[(size_t)idx[i] * N + r];
+    }
+    free(Zt);
+    free(idx);
+    return sweep >= 100 ? 1 : 0;
+}
+
+int orc_lanczos_svt(int m, int n, const double* W, double eps, int b, int start, int k,
+                    double* U, double* V, double* S, double* A, int* rank)
+{
+    if (m < 1 || n < 1 || !W || b < 1 || k < 1 || !U || !V || !S) return -1;
+    if (start < ORC_START_SPLIT || start > ORC_START_RIGHT) return -1;
+    const int N = m + n, c = start == ORC_START_SPLIT ? 2 * b : b, K = k * c;
+    if (K > N) return -1;
+    double* Wt = (double*)calloc((size_t)N * N, sizeof(double));
+    double* Q = (double*)calloc((size_t)N * K, sizeof(double)); /* [X_1 .. X_k] */
+    double* X = (double*)malloc(sizeof(double) * (size_t)N * c);
+    double* X0 = (double*)malloc(sizeof(double) * (size_t)N * c);
+    double* WX = (double*)malloc(sizeof(double) * (size_t)N * c);
+    double* R = (double*)malloc(sizeof(double) * (size_t)N * c);
+    double* Tm = (double*)malloc(sizeof(double) * (size_t)N * c);
+    double* Mb = (double*)malloc(sizeof(double) * (size_t)c * c);
+    double* Bb = (double*)calloc((size_t)c * c, sizeof(double)); /* B_{l-1}; B_0 = 0 */
+    double* Qp = (double*)malloc(sizeof(double) * (size_t)N * K);
+    double* T = (double*)calloc((size_t)K * K, sizeof(double));
+    double* Z = (double*)malloc(sizeof(double) * (size_t)K * K);
+    double* lam = (double*)malloc(sizeof(double) * (size_t)K);
+    double* Zb = (double*)malloc(sizeof(double) * (size_t)K * b);
+    double* Y = (double*)malloc(sizeof(double) * (size_t)N * b);
+    if (!Wt || !Q || !X || !X0 || !WX || !R || !Tm || !Mb || !Bb || !Qp || !T || !Z || !lam ||
+        !Zb || !Y)
+        return -2;
+    /* W~ */
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < n; ++j) {
+            Wt[(size_t)i * N + m + j] = W[(size_t)i * n + j];
+            Wt[(size_t)(m + j) * N + i] = W[(size_t)i * n + j];
+        }
+    /* start block */
+    memset(X0, 0, sizeof(double) * (size_t)N * c);
+    const double h = 1.0 / sqrt(2.0);
+    for (int j = 0; j < b; ++j) {
+        if (start == ORC_START_SPLIT) {
+            for (int i = 0; i < m; ++i) X0[(size_t)i * c + j] = U[(size_t)i * b + j];
+            for (int i = 0; i < n; ++i) X0[(size_t)(m + i) * c + b + j] = V[(size_t)i * b + j];
+        } else {
+            if (start != ORC_START_RIGHT)
+                for (int i = 0; i < m; ++i)
+                    X0[(size_t)i * c + j] = (start == ORC_START_AUG ? h : 1.0) * U[(size_t)i * b + j];
+            if (start != ORC_START_LEFT)
+                for (int i = 0; i < n; ++i)
+                    X0[(size_t)(m + i) * c + j] = (start == ORC_START_AUG ? h : 1.0) * V[(size_t)i * b + j];
+        }
+    }
+    orth(N, c, X0, X);
+    /* Algorithm 2 */
+    for (int l = 0; l < k; ++l) {
+        /* X_l into Q; M_l = X_l^T W~ X_l */
+        for (int i = 0; i < N; ++i)
+            memcpy(Q + (size_t)i * K + (size_t)l * c, X + (size_t)i * c, sizeof(double) * (size_t)c);
+        mm_nn(N, N, c, Wt, X, WX);
+        mm_tn(c, N, c, X, WX, Mb);
+        for (int a = 0; a < c; ++a)
+            for (int e = 0; e < c; ++e)
+                T[(size_t)(l * c + a) * K + l * c + e] = 0.5 * (Mb[(size_t)a * c + e] + Mb[(size_t)e * c + a]);
+        if (l == k - 1) break;
+        /* R_l = W~ X_l - X_l M_l - X_{l-1} B_{l-1}^T */
+        mm_nn(N, c, c, X, Mb, Tm);
+        for (size_t e = 0; e < (size_t)N * c; ++e) R[e] = WX[e] - Tm[e];
+        if (l > 0) {
+            double* Bt = (double*)malloc(sizeof(double) * (size_t)c * c);
+            for (int a = 0; a < c; ++a)
+                for (int e = 0; e < c; ++e) Bt[(size_t)a * c + e] = Bb[(size_t)e * c + a];
+            double* Xp = (double*)malloc(sizeof(double) * (size_t)N * c);
+            take_cols(N, K, (l - 1) * c, c, Q, Xp);
+            mm_nn(N, c, c, Xp, Bt, Tm);
+            for (size_t e = 0; e < (size_t)N * c; ++e) R[e] -= Tm[e];
+            free(Bt);
+            free(Xp);
+        }
+        /* (X_{l+1}, B_l) = qr(R_l), the new block orthogonal to X_1 .. X_l */
+        take_cols(N, K, 0, (l + 1) * c, Q, Qp);
+        qr_complement(N, (l + 1) * c, c, Qp, R, X);
+        mm_tn(c, N, c, X, R, Bb); /* B_l = X_{l+1}^T R_l */
+        for (int a = 0; a < c; ++a)
+            for (int e = 0; e < c; ++e) {
+                T[(size_t)((l + 1) * c + a) * K + l * c + e] = Bb[(size_t)a * c + e];
+                T[(size_t)(l * c + e) * K + (l + 1) * c + a] = Bb[(size_t)a * c + e];
+            }
+    }
+    /* Algorithm 3 */
+    int rc = jacobi_eig(K, T, lam, Z);
+    take_cols(K, K, 0, b, Z, Zb);
+    mm_nn(N, K, b, Q, Zb, Y);
+    const double r2 = sqrt(2.0);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < b; ++j) U[(size_t)i * b + j] = r2 * Y[(size_t)i * b + j];
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < b; ++j) V[(size_t)i * b + j] = r2 * Y[(size_t)(m + i) * b + j];
+    int r = 0;
+    for (int j = 0; j < b; ++j) {
+        S[j] = lam[j];
+        if (lam[j] > eps) ++r;
+    }
+    if (rank) *rank = r;
+    if (A) svt_reconstruct(m, n, b, r, U, S, V, eps, A);
+    free(Wt); free(Q); free(X); free(X0); free(WX); free(R); free(Tm); free(Mb); free(Bb);
+    free(Qp); free(T); free(Z); free(lam); free(Zb); free(Y);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -848,7 +1044,16 @@ static int rpca_core(int m, int n, const double* D, double lambda, const orc_alm
             }
             free(S);
             S = (double*)malloc(sizeof(double) * (size_t)b);
-            orc_blws_step(m, n, W, eps, b, U, V, S, A, &svp);
+            if (o.svt_start == ORC_START_SPLIT && o.k_blocks == 2) {
+                orc_blws_step(m, n, W, eps, b, U, V, S, A, &svp);
+            } else {
+                int rc = orc_lanczos_svt(m, n, W, eps, b, o.svt_start, o.k_blocks, U, V, S, A,
+                                         &svp);
+                if (rc < 0) {
+                    free(Y); free(W); free(U); free(V); free(S);
+                    return rc;
+                }
+            }
             sv = predict_rank(svp, sv, o.sv_step_frac, p);
         }
         if (svp_trace) svp_trace[it - 1] = svp;

@@ -36,6 +36,22 @@ int orc_jacobi_svd(int m, int n, const double* W, double* U, double* S, double* 
 int orc_svt_exact(int m, int n, const double* W, double eps, double* A, double* S_all,
                   int* rank);
 
+/* Start blocks of the literal block Lanczos on [[0, W], [W^T, 0]] (Sec. 4.1). */
+#define ORC_START_SPLIT 0 /* blockdiag(U, V): 2b columns                        */
+#define ORC_START_AUG 1   /* (U; V) / sqrt(2): b columns                        */
+#define ORC_START_LEFT 2  /* (U; 0)                                              */
+#define ORC_START_RIGHT 3 /* (0; V)                                              */
+
+/* Algorithms 2 and 3 literally on the explicitly formed augmented matrix, from
+ * the start block `start` built from U (m x b) and V (n x b), with k blocks
+ * (k * columns of the start block <= m + n) and block reorthogonalisation.
+ * On exit U = sqrt(2) Y_top, V = sqrt(2) Y_bottom for the top b Ritz vectors Y,
+ * S (b) the top b Ritz values (decreasing), *rank = #{S_i > eps}, A (m x n,
+ * may be NULL) = U_r diag(S_r - eps) V_r^T. Returns 1 if the Jacobi EVD of T_k
+ * did not settle in 100 sweeps, < 0 on bad arguments. */
+int orc_lanczos_svt(int m, int n, const double* W, double eps, int b, int start, int k,
+                    double* U, double* V, double* S, double* A, int* rank);
+
 /* One BLWS step (block Lanczos, k = 2, warm start from U, V; split Rayleigh-Ritz).
  * U (m x b) and V (n x b) hold orthonormal columns on entry and the top-b Ritz
  * vectors on exit. S (b) receives the Ritz values (descending); *rank =
@@ -66,6 +82,8 @@ typedef struct {
     uint64_t seed;
     int norm_steps;        /* safety bound on the BLWS steps of the ||D||_2 estimate */
     double norm_rtol;      /* those steps stop once the top value changes less      */
+    int svt_start;         /* BLWS-mode SVT: ORC_START_SPLIT with k_blocks = 2 is    */
+    int k_blocks;          /* the default step; anything else runs orc_lanczos_svt  */
 } orc_alm_opts;
 
 typedef struct {

@@ -476,3 +476,115 @@ def test_mc_svt_table2_rows(m, r, ratio, iters, err):
     assert abs(info["iters"] - iters) <= 6, info["iters"]
     e = _planted_error(out, inst)
     assert err / 1.25 <= e <= err * 1.25, e
+
+
+# ---------------------------------------------------------------------------
+# Sec. 4.1 ablations: Algorithms 2-3 taken literally on [[0, W], [W^T, 0]]
+# from the split, aug, and half-information start blocks, with k blocks.
+# ---------------------------------------------------------------------------
+
+
+def _warm_signed(W, b, delta, seed):
+    """Noisy top-b singular subspaces with the signs of the exact vectors kept
+    (column j of U and of V perturb u_j and v_j): the pairing that makes
+    (U; V) / sqrt(2) close to eigenvectors of the augmented matrix."""
+    U0, _, V0t = np.linalg.svd(W, full_matrices=False)
+    g = np.random.default_rng(seed)
+    m, n = W.shape
+
+    def orth_signed(X):
+        Q, R = np.linalg.qr(X)
+        return Q * np.sign(np.diag(R))
+
+    return (orth_signed(U0[:, :b] + delta * g.standard_normal((m, b))),
+            orth_signed(V0t[:b].T + delta * g.standard_normal((n, b))))
+
+
+def test_lanczos_split_k2_equals_blws_step():
+    """The literal procedure on the explicit augmented matrix from
+    blockdiag(U, V) gives the same Ritz values and SVT as the default step,
+    which works on W only (two separate implementations)."""
+    W, sigma = _spectrum_case()
+    U, V = _warm(W, 8, 1e-3, seed=4)
+    _, _, S1, A1, r1 = oracle.blws_step(W, 3.5, U, V)
+    Ul, Vl, S2, A2, r2 = oracle.lanczos_svt(W, 3.5, U, V, "split", 2)
+    assert r1 == r2
+    assert np.abs(S1 - S2).max() <= 1e-13 * sigma[0]
+    assert np.linalg.norm(A1 - A2) <= 1e-12 * np.linalg.norm(A1)
+    assert np.abs(Ul.T @ Ul - np.eye(8)).max() < 1e-13
+    assert np.abs(Vl.T @ Vl - np.eye(8)).max() < 1e-13
+
+
+@pytest.mark.parametrize("start,k", [("split", 5), ("aug", 10), ("left", 10), ("right", 10)])
+def test_lanczos_full_krylov_space_is_exact(start, k):
+    """k blocks spanning all of R^(m+n): T_k is orthogonally similar to the
+    augmented matrix, whose top eigenvalues are the singular values of W
+    (Theorem 1), so the Ritz values and the SVT are exact."""
+    g = np.random.default_rng(31)
+    m, n, b = 6, 4, 1
+    W = g.standard_normal((m, n))
+    U = np.linalg.qr(g.standard_normal((m, b)))[0]
+    V = np.linalg.qr(g.standard_normal((n, b)))[0]
+    sv = np.linalg.svd(W, compute_uv=False)
+    eps = 0.5 * (sv[0] + sv[1])  # only sigma_1 above the threshold
+    Un, Vn, S, A, r = oracle.lanczos_svt(W, eps, U, V, start, k)
+    assert abs(S[0] - sv[0]) <= 1e-13 * sv[0]
+    Aex, _, rex = oracle.svt_exact(W, eps)
+    assert r == rex == 1
+    assert np.linalg.norm(A - Aex) <= 1e-12 * np.linalg.norm(Aex)
+
+
+@pytest.mark.parametrize("start", ["left", "right"])
+def test_lanczos_half_start_k2_closed_form(start):
+    """From (U; 0) the second block is (0; orth(W^T U)) and both diagonal
+    blocks of T_2 vanish, so T_2 = [[0, R^T], [R, 0]] with W^T U = G R: the Ritz
+    values are the singular values of W^T U (of W V from (0; V))."""
+    g = np.random.default_rng(32)
+    m, n, b = 25, 19, 4
+    W = g.standard_normal((m, n))
+    U = np.linalg.qr(g.standard_normal((m, b)))[0]
+    V = np.linalg.qr(g.standard_normal((n, b)))[0]
+    _, _, S, _, _ = oracle.lanczos_svt(W, 0.0, U, V, start, 2, want_A=False)
+    expect = np.linalg.svd(W.T @ U if start == "left" else W @ V, compute_uv=False)
+    assert np.allclose(S, expect, rtol=1e-13, atol=0)
+
+
+def test_lanczos_aug_start_on_exact_subspaces_is_exact():
+    """With the exact top-b singular pairs, (U; V) / sqrt(2) spans an
+    invariant subspace of the augmented matrix (W V = U S, W^T U = V S): the
+    Ritz values are sigma_1..sigma_b and the SVT is exact."""
+    W, sigma = _spectrum_case()
+    U0, _, V0t = np.linalg.svd(W, full_matrices=False)
+    b = 8  # all eight values above eps = 3.5
+    Un, Vn, S, A, r = oracle.lanczos_svt(W, 3.5, U0[:, :b], V0t[:b].T, "aug", 2)
+    assert np.allclose(S, sigma[:b], rtol=1e-12)
+    Aex, _, rex = oracle.svt_exact(W, 3.5)
+    assert r == rex
+    assert np.linalg.norm(A - Aex) <= 1e-11 * np.linalg.norm(Aex)
+
+
+@pytest.mark.parametrize("start", ["split", "aug", "left", "right"])
+def test_lanczos_ritz_values_rise_with_k(start):
+    """The Krylov spaces are nested in k, so each Ritz value is
+    nondecreasing in k (Cauchy interlacing) and never above sigma_i."""
+    W, sigma = _spectrum_case()
+    U, V = _warm_signed(W, 5, 1e-2, seed=6)
+    prev = None
+    for k in (2, 3, 4):
+        _, _, S, _, _ = oracle.lanczos_svt(W, 0.0, U, V, start, k, want_A=False)
+        assert np.all(S <= sigma[:5] * (1 + 1e-13))
+        if prev is not None:
+            assert np.all(S >= prev - 1e-12 * sigma[0])
+        prev = S
+
+
+def test_lanczos_aug_start_beats_half_starts():
+    """Sec. 4.1: starting from both previous subspaces gives more precise
+    Ritz values than either half-information start at the same k."""
+    W, sigma = _spectrum_case()
+    U, V = _warm_signed(W, 5, 1e-2, seed=7)
+    err = {}
+    for start in ("aug", "left", "right"):
+        _, _, S, _, _ = oracle.lanczos_svt(W, 0.0, U, V, start, 2, want_A=False)
+        err[start] = np.abs(S - sigma[:5]).max()
+    assert err["aug"] < err["left"] and err["aug"] < err["right"], err
