@@ -76,6 +76,10 @@ typedef struct {
                               /* at most min(m, n) / 2 and b_max                        */
     double ladder_tol;        /* BLWS_BF16 solves: W products in BF16 while the relative */
                               /* residual is at or above this, FP32 below (1e-3)         */
+    int svt_start;            /* robust PCA in FP64 only: a start block other than      */
+    int k_blocks;             /* BLWS_START_SPLIT, or k_blocks != 2, runs each SVT by   */
+                              /* blws_svt_lanczos (the Sec. 4.1 ablations); defaults  */
+                              /* BLWS_START_SPLIT and 2 (the default step)               */
 } blws_alm_opts;
 
 typedef struct {
@@ -129,6 +133,35 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
 int blws_svt_noalloc(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, int ldw,
                      double eps, int b, void* U, int ldu, void* V, int ldv, int warm, double* S,
                      int* rank_dev, void* A, int lda, const blws_svt_opts* opts);
+
+/* Start blocks of blws_svt_lanczos (Sec. 4.1). */
+enum {
+    BLWS_START_SPLIT = 0, /* blockdiag(U, V): 2b columns                          */
+    BLWS_START_AUG = 1,   /* (U; V) / sqrt(2): b columns (BLWS as Sec. 4.1 writes it) */
+    BLWS_START_LEFT = 2,  /* (U; 0): the standard half-information starts       */
+    BLWS_START_RIGHT = 3  /* (0; V)                                              */
+};
+
+/* The start-block ablations of Sec. 4.1: one SVT step by Algorithms 2 and 3
+ * taken literally on the augmented matrix [[0, W], [W^T, 0]] (Theorem 1),
+ * never formed, from the start block `start` built from the orthonormal U
+ * (m x b, ldu) and V (n x b, ldv), with k >= 1 blocks and block
+ * reorthogonalisation (each new block orthonormalised against all earlier
+ * ones; 2k - 1 products with W). The Rayleigh-Ritz matrix T_k (k c x k c,
+ * c = 2b for BLWS_START_SPLIT, else b; k c <= 1024 and <= m + n) is
+ * decomposed by the SVD of T_k + c I with c >= its spectral radius. FP64,
+ * device pointers, queued on `stream`.
+ *   On exit U = sqrt(2) Y_top, V = sqrt(2) Y_bottom for the top b Ritz
+ *   vectors Y (orthonormal for the split and half starts; only nearly so for
+ *   BLWS_START_AUG), S (device double[b]) the top b Ritz values in decreasing
+ *   order (possibly negative for the aug start), rank_dev (device int, may
+ *   be NULL) #{S_i > eps}, A (may be NULL, m x n, lda) U_r diag(S_r - eps) V_r^T.
+ * Errors: BLWS_EINVAL for bad sizes or pointers, BLWS_EUNSUPPORTED for
+ * k c above 1024. The default step (blws_svt) is BLWS_START_SPLIT with
+ * k = 2 and its zero blocks skipped: the same Ritz values up to rounding. */
+int blws_svt_lanczos(blws_ctx ctx, void* stream, int m, int n, const double* W, int ldw,
+                     double eps, int b, int start, int k, double* U, int ldu, double* V,
+                     int ldv, double* S, int* rank_dev, double* A, int lda);
 
 /* Robust PCA: min ||A||_* + lambda ||E||_1 s.t. D = A + E, by inexact ALM with
  * one BLWS step per iteration (Sec. 5). lambda <= 0 selects 1/sqrt(max(m, n)).

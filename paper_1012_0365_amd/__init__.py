@@ -139,6 +139,37 @@ class Context:
             rank.data_ptr(), A.data_ptr() if A is not None else None, lda, ctypes.byref(o)))
         return S, rank
 
+    def svt_lanczos(self, W, eps: float, U, V, start: str = "aug", k: int = 2, A=None, S=None,
+                    rank=None):
+        """One SVT step by the literal block Lanczos on [[0, W], [W^T, 0]]
+        (blws_svt_lanczos) from the start block `start` ("split", "aug",
+        "left", "right") with k blocks; float64 only. U, V are updated in place
+        (sqrt(2) times the halves of the top-b Ritz vectors). Returns (S, rank)."""
+        torch = _torch()
+        if W.dtype != torch.float64:
+            raise TypeError("svt_lanczos takes float64 W")
+        ldw = _check_mat(W, "W")
+        ldu = _check_mat(U, "U")
+        ldv = _check_mat(V, "V")
+        m, n = W.shape
+        b = U.shape[1]
+        if U.shape != (m, b) or V.shape != (n, b) or U.dtype != W.dtype or V.dtype != W.dtype:
+            raise ValueError("U must be m x b and V n x b, with W's dtype")
+        if S is None:
+            S = torch.empty(b, dtype=torch.float64, device=W.device)
+        if rank is None:
+            rank = torch.zeros(1, dtype=torch.int32, device=W.device)
+        lda = 0
+        if A is not None:
+            lda = _check_mat(A, "A")
+            if A.shape != (m, n) or A.dtype != W.dtype:
+                raise ValueError("A must be m x n with W's dtype")
+        self._check(self._lib.blws_svt_lanczos(
+            self.handle, self._stream(), m, n, W.data_ptr(), ldw, float(eps), b,
+            _native.STARTS[start], int(k), U.data_ptr(), ldu, V.data_ptr(), ldv, S.data_ptr(),
+            rank.data_ptr(), A.data_ptr() if A is not None else None, lda))
+        return S, rank
+
     # -- robust PCA ----------------------------------------------------------
     def rpca_solve(self, D, lam: float | None = None, opts: AlmOpts | None = None, A=None,
                    E=None, bf16: bool = False):

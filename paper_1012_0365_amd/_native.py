@@ -14,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libblws.so")
 
 BLWS_FP64, BLWS_FP32, BLWS_BF16 = 0, 1, 2
+# start blocks of blws_svt_lanczos (include/blws.h, BLWS_START_*)
+STARTS = {"split": 0, "aug": 1, "left": 2, "right": 3}
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
           -3: "device error", -4: "NaN or Inf encountered", -5: "unsupported"}
 
@@ -38,6 +40,8 @@ class AlmOpts(ctypes.Structure):
         ("norm_rtol", ctypes.c_double),
         ("b_max", ctypes.c_int),
         ("ladder_tol", ctypes.c_double),
+        ("svt_start", ctypes.c_int),
+        ("k_blocks", ctypes.c_int),
     ]
 
 
@@ -113,6 +117,8 @@ SIGNATURES = {
     "blws_default_svt_opts": (None, [ctypes.POINTER(SvtOpts)]),
     "blws_svt": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, _i, _vp, _i, _vp, _i, _i, _vp, _vp, _vp,
                       _i, ctypes.POINTER(SvtOpts)]),
+    "blws_svt_lanczos": (_i, [_vp, _vp, _i, _i, _vp, _i, _d, _i, _i, _i, _vp, _i, _vp, _i, _vp,
+                              _vp, _vp, _i]),
     "blws_svt_noalloc": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, _i, _vp, _i, _vp, _i, _i, _vp,
                               _vp, _vp, _i, ctypes.POINTER(SvtOpts)]),
     "blws_rpca_solve": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _d, ctypes.POINTER(AlmOpts), _vp, _i,

@@ -14,7 +14,7 @@ OUT = os.path.join(HERE, "libblws.so")
 OBJ = os.path.join(HERE, "_build")
 ARCH = os.environ.get("BLWS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "engine.hip", "server.hip", "tuning.hip"]
+SOURCES = ["k_gemm.hip", "k_gemm_lp.hip", "k_dense.hip", "k_svd.hip", "k_elem.hip", "k_sparse.hip", "k_lanczos.hip", "engine.hip", "server.hip", "tuning.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -179,6 +179,17 @@ void zero_bytes(void* p, size_t bytes, hipStream_t s);
 // rank_out[0] = #{S_i > eps, i < b}.
 void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t s);
 
+// Literal block Lanczos on [[0, W], [W^T, 0]] (k_lanczos.hip): M = S + S^T and
+// Bt = B^T (c x c); T (K x K, K = k c) = T_k + shift I with T_k block
+// tridiagonal from Ms (k blocks M_l) and Bs (k - 1 blocks B_l, below the
+// diagonal), shift (device scalar, written) the largest absolute row sum of
+// T_k; lam[i] = sig[i] - shift (i < b).
+void lanczos_sym(int c, const double* S, double* M, hipStream_t s);
+void lanczos_transpose(int c, const double* B, double* Bt, hipStream_t s);
+void lanczos_assemble(int k, int c, const double* Ms, const double* Bs, double* shift, double* T,
+                      hipStream_t s);
+void lanczos_eigvals(int b, const double* sig, const double* shift, double* lam, hipStream_t s);
+
 // Sum of squares and max |.| of an m x n matrix: two-pass, deterministic.
 // out[0] = sum of squares, out[1] = max abs. scratch >= norms_scratch_elems().
 template <typename T>

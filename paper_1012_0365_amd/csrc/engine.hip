@@ -168,6 +168,8 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->norm_rtol = 1e-13;
     o->b_max = 512;
     o->ladder_tol = 1e-3;
+    o->svt_start = BLWS_START_SPLIT;
+    o->k_blocks = 2;
 }
 
 void blws_default_svt_opts(blws_svt_opts* o)
@@ -202,6 +204,38 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
                                 (float*)V, ldv, warm, S, rank_dev, (float*)A, lda, o);
     else
         throw BlwsError{BLWS_EUNSUPPORTED, "blws_svt: precision not supported"};
+    return BLWS_OK;
+    ABI_END
+}
+
+int blws_svt_lanczos(blws_ctx ctx, void* stream, int m, int n, const double* W, int ldw,
+                     double eps, int b, int start, int k, double* U, int ldu, double* V,
+                     int ldv, double* S, int* rank_dev, double* A, int lda)
+{
+    ABI_BEGIN(ctx)
+    BLWS_REQUIRE(m >= 2 && n >= 2 && b >= 1 && k >= 1 && 2 * b <= (m < n ? m : n), BLWS_EINVAL,
+                 "blws_svt_lanczos: need m, n >= 2, k >= 1 and 1 <= b <= min(m, n) / 2");
+    BLWS_REQUIRE(start >= BLWS_START_SPLIT && start <= BLWS_START_RIGHT, BLWS_EINVAL,
+                 "blws_svt_lanczos: unknown start block");
+    BLWS_REQUIRE(W && U && V && S, BLWS_EINVAL, "blws_svt_lanczos: null W, U, V or S");
+    BLWS_REQUIRE(ldw >= n && ldu >= b && ldv >= b && (!A || lda >= n), BLWS_EINVAL,
+                 "blws_svt_lanczos: leading dimension too small");
+    BLWS_REQUIRE(std::isfinite(eps) && eps >= 0.0, BLWS_EINVAL,
+                 "blws_svt_lanczos: eps must be >= 0");
+    const long long K = (long long)k * blws::lz_cols(start, b);
+    BLWS_REQUIRE(K <= m + n, BLWS_EINVAL, "blws_svt_lanczos: k blocks exceed m + n columns");
+    BLWS_REQUIRE(K <= 1024, BLWS_EUNSUPPORTED, "blws_svt_lanczos: k c above 1024");
+    hipStream_t s = (hipStream_t)stream;
+    cx.ensure(blws::lanczos_ws_bytes(m, n, b, start, k));
+    Carver c(cx.ws);
+    blws::LanczosWs w;
+    w.carve(c, m, n, b, start, k);
+    blws::zero_bytes(w.nflag, 4 * sizeof(int), s);
+    const blws::Op<double> op{W, ldw, nullptr, nullptr};
+    blws_svt_opts so;
+    blws_default_svt_opts(&so);
+    blws::lanczos_step(cx, w, s, m, n, op, eps, b, start, k, U, ldu, V, ldv, S, rank_dev, so.seed);
+    if (A) blws::svt_reconstruct<double>(&cx.timer, m, n, b, U, ldu, V, ldv, S, eps, A, lda, s);
     return BLWS_OK;
     ABI_END
 }

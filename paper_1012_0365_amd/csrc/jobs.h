@@ -15,6 +15,7 @@
 #include <memory>
 #include <string>
 
+#include "lanczos.h"
 #include "step.h"
 
 namespace blws {
@@ -86,6 +87,8 @@ struct RpcaJob : Job {
     size_t mn;
     // workspace
     StepWs<T> w;
+    bool abl = false;  // each SVT by the literal block Lanczos (Sec. 4.1 ablations)
+    LanczosWs lw;
     T *Y = nullptr, *Wb = nullptr, *U = nullptr, *V = nullptr;
     unsigned short* Wh = nullptr;
     double *S = nullptr, *part = nullptr, *scal = nullptr;
@@ -106,6 +109,11 @@ struct RpcaJob : Job {
     {
         p = m < n ? m : n;
         bmax = (p / 2 < o.b_max) ? p / 2 : o.b_max;
+        abl = o.svt_start != LZ_START_SPLIT || o.k_blocks != 2;
+        if (abl) {  // k blocks of lz_cols(start, b) columns: at most 1024 and m + n
+            const int lim = (m + n < 1024 ? m + n : 1024) / (o.k_blocks * lz_cols(o.svt_start, 1));
+            if (bmax > lim) bmax = lim;
+        }
         if (lambda <= 0.0) lambda = 1.0 / std::sqrt((double)(m > n ? m : n));
         mn = (size_t)m * n;
         sv = o.sv0;
@@ -116,6 +124,10 @@ struct RpcaJob : Job {
     void layout(Carver& c)
     {
         w.carve(c, m, n, bmax);
+        if (abl) {
+            lw.carve(c, m, n, bmax, o.svt_start, o.k_blocks);
+            lw.nflag = w.nflag;  // one breakdown / timeout record for the job
+        }
         Y = c.take<T>(mn);
         Wb = c.take<T>(mn);
         Wh = c.take<unsigned short>(ladder ? mn : 1);
@@ -183,7 +195,15 @@ struct RpcaJob : Job {
         }
         const bool use_bf = !refine && bf;
         const Op<T> opW{Wb, n, nullptr, use_bf ? Wh : nullptr};
-        svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        if constexpr (std::is_same<T, double>::value) {
+            if (abl)
+                lanczos_step(cx, lw, s, m, n, opW, eps, b, o.svt_start, o.k_blocks, U, bmax, V,
+                             bmax, S, rank_dev, o.seed);
+            else
+                svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        } else {
+            svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+        }
         mu_next = next_mu(o, mu, mu_bar);
         alm_epilogue<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, lambda, mu, mu_next, D, ldd,
                         Y, E, lde, Wb, use_bf ? Wh : nullptr, (T*)nullptr, 0, part, s);
@@ -797,6 +817,15 @@ inline void check_alm_opts(const blws_alm_opts& o, const std::string& who)
                      o.ladder_tol >= 0.0,
                  BLWS_EINVAL, who + ": bad options");
     BLWS_REQUIRE(o.b_max <= 512, BLWS_EUNSUPPORTED, who + ": b_max above 512");
+    BLWS_REQUIRE(o.svt_start >= LZ_START_SPLIT && o.svt_start <= LZ_START_RIGHT &&
+                     o.k_blocks >= 1,
+                 BLWS_EINVAL, who + ": bad svt_start or k_blocks");
+}
+
+// The Sec. 4.1 ablations (svt_start, k_blocks) run in FP64 robust PCA only.
+inline bool alm_opts_ablation(const blws_alm_opts& o)
+{
+    return o.svt_start != LZ_START_SPLIT || o.k_blocks != 2;
 }
 
 inline std::unique_ptr<Job> make_rpca_job(int prec, int m, int n, const void* D, int ldd,
@@ -812,6 +841,8 @@ inline std::unique_ptr<Job> make_rpca_job(int prec, int m, int n, const void* D,
     blws_default_alm_opts(&o);
     if (opts) o = *opts;
     check_alm_opts(o, who);
+    BLWS_REQUIRE(prec == BLWS_FP64 || !alm_opts_ablation(o), BLWS_EUNSUPPORTED,
+                 who + ": svt_start / k_blocks ablations run in FP64 only");
     if (prec == BLWS_FP64)
         return std::unique_ptr<Job>(new RpcaJob<double>(m, n, (const double*)D, ldd, lambda, o,
                                                         (double*)A, lda, (double*)E, lde, false));
@@ -836,6 +867,8 @@ inline std::unique_ptr<Job> make_mc_job(int prec, int m, int n, int nnz, const i
     blws_default_mc_opts(&o);
     if (opts) o = *opts;
     check_alm_opts(o, who);
+    BLWS_REQUIRE(!alm_opts_ablation(o), BLWS_EUNSUPPORTED,
+                 who + ": svt_start / k_blocks ablations run in robust PCA only");
     if (prec == BLWS_FP64)
         return std::unique_ptr<Job>(new McJob<double>(m, n, nnz, row_ptr, col_idx,
                                                       (const double*)values, o, r_cap, (double*)U,
