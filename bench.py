@@ -260,7 +260,7 @@ def bench_rpca(args):
 
     if not args.no_legs:
         out["legs"] = rpca_legs(args, ctx, D if args.prec == "f64" else D.double(),
-                                total / args.steps)
+                                total / args.steps, A0)
 
     if not args.no_plain:
         # Plain comparator: the same ALM with a full SVD per iteration on the same
@@ -337,17 +337,15 @@ def timed_solves(ctx, D, reps, **kw):
     return sorted(ts)[len(ts) // 2], info, A, E
 
 
-def svt_snapshot_leg(ctx, D):
-    """SVT calls/s on the state of the n = 2000 solve at iteration 15 (b = 112):
-    14 ALM iterations driven from here (blws_svt plus the elementwise updates
-    in torch, outside any timed region) give W, eps and the warm block; then
-    back-to-back blws_svt calls on that W, each fed the previous call's Ritz
-    vectors as its warm block."""
+def snapshot_state(ctx, D):
+    """The state of the n = 2000 solve at iteration 15: 14 ALM iterations
+    driven from here (blws_svt plus the elementwise updates in torch, outside
+    any timed region) give W and eps of iteration 15 and the warm block (U, V)
+    of width b that iteration 14's step returned."""
     import torch
 
     m, n = D.shape
     lam = 1.0 / math.sqrt(max(m, n))
-    dn = float(torch.linalg.norm(D))
     s1 = float(torch.linalg.matrix_norm(D, 2))
     J = max(s1, float(D.abs().max()) / lam)
     Y = D / J
@@ -360,7 +358,7 @@ def svt_snapshot_leg(ctx, D):
         bn = min(((sv + 15) // 16) * 16, min(m, n) // 2)
         cold = b == 0 or bn != b
         if cold:
-            # a cold block of the new width (this leg measures the steady
+            # a cold block of the new width (this state is for the steady
             # state, not the block-resize rule)
             U = torch.empty(m, bn, dtype=D.dtype, device=D.device)
             V = torch.empty(n, bn, dtype=D.dtype, device=D.device)
@@ -376,15 +374,29 @@ def svt_snapshot_leg(ctx, D):
     W = (D - E + Y / mu).contiguous()
     eps = 1.0 / mu
     bn = min(((sv + 15) // 16) * 16, min(m, n) // 2)
-    S = torch.empty(bn, dtype=torch.float64, device=D.device)
-    rank = torch.zeros(1, dtype=torch.int32, device=D.device)
     A = torch.empty_like(W)
     if bn != b:
         U = torch.empty(m, bn, dtype=D.dtype, device=D.device)
         V = torch.empty(n, bn, dtype=D.dtype, device=D.device)
-        ctx.svt(W, eps, U, V, warm=False, A=A, S=S, rank=rank)
-    b = bn
-    for _ in range(5):  # settle the warm block on this W
+        ctx.svt(W, eps, U, V, warm=False, A=A)
+    torch.cuda.synchronize()
+    return W, eps, U, V
+
+
+def svt_snapshot_leg(ctx, state):
+    """SVT calls/s on the iteration-15 state of the n = 2000 solve (b = 112):
+    five blws_svt calls on that W settle the warm block, then back-to-back
+    calls, each fed the previous call's Ritz vectors as its warm block."""
+    import torch
+
+    W, eps, U0, V0 = state
+    U, V = U0.clone(), V0.clone()
+    m, n = W.shape
+    b = U.shape[1]
+    S = torch.empty(b, dtype=torch.float64, device=W.device)
+    rank = torch.zeros(1, dtype=torch.int32, device=W.device)
+    A = torch.empty_like(W)
+    for _ in range(5):
         ctx.svt(W, eps, U, V, A=A, S=S, rank=rank)
     torch.cuda.synchronize()
     calls = 40
@@ -398,6 +410,63 @@ def svt_snapshot_leg(ctx, D):
     return {"calls_per_s": calls / el, "us_per_call": 1e6 * el / calls, "b": b, "rank": r,
             "gflop_per_s": flops * calls / el / 1e9,
             "flops_per_call": flops, "note": "W and the warm block of iteration 15"}
+
+
+ABLATIONS = [("split", 2), ("aug", 2), ("left", 2), ("right", 2), ("aug", 3), ("split", 3)]
+
+
+def ablation_leg(ctx, state, D, A0):
+    """The Sec. 4.1 start-block ablations at n = 2000 (blws_svt_lanczos).
+    Per call, on the iteration-15 state and from its warm block: the error of
+    the top Ritz values and of A = T_eps(W) against a full FP64 SVD of W
+    (torch.linalg.svd, a measurement reference only), the rank, the W-products
+    and the time per call. Then whole robust-PCA solves with every SVT taken
+    this way: iterations, time and the error against the planted A0."""
+    import torch
+
+    import paper_1012_0365_amd as blws
+
+    W, eps, U0, V0 = state
+    b = U0.shape[1]
+    Uf, sf, Vhf = torch.linalg.svd(W, full_matrices=False)
+    r_ex = int((sf > eps).sum().item())
+    A_ex = (Uf[:, :r_ex] * (sf[:r_ex] - eps)) @ Vhf[:r_ex]
+    na = float(torch.linalg.norm(A_ex))
+    out = {"config": ("W and eps of iteration 15 of the n = 2000 solve, warm block from "
+                      "iteration 14's step"),
+           "b": b, "exact_rank": r_ex, "per_call": {}, "solves": {}}
+    A = torch.empty_like(W)
+
+    def measure(name, call, products):
+        U, V = U0.clone(), V0.clone()
+        S, rank = call(U, V)
+        torch.cuda.synchronize()
+        r = int(rank.item())
+        q = min(b, r_ex)
+        serr = float(((S[:q] - sf[:q]).abs().max() / sf[0]).item())
+        aerr = float(torch.linalg.norm(A - A_ex).item() / na)
+        reps = 10
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            call(U, V)
+        torch.cuda.synchronize()
+        out["per_call"][name] = {"sigma_err_rel_s1": serr, "A_err_rel": aerr, "rank": r,
+                                 "w_products": products,
+                                 "ms_per_call": 1e3 * (time.perf_counter() - t1) / reps}
+
+    measure("default_step", lambda U, V: ctx.svt(W, eps, U, V, A=A), 3)
+    for start, k in ABLATIONS:
+        measure(f"{start}_k{k}",
+                lambda U, V, st=start, kk=k: ctx.svt_lanczos(W, eps, U, V, start=st, k=kk, A=A),
+                2 * k - 1)
+    na0 = float(torch.linalg.norm(A0))
+    for start, k in [("aug", 2), ("split", 3), ("left", 2)]:
+        opts = blws.default_alm_opts(svt_start=blws.STARTS[start], k_blocks=k)
+        t, info, Ah, _ = timed_solves(ctx, D, 1, opts=opts)
+        out["solves"][f"{start}_k{k}"] = {
+            "solve_s": t, "iters": info["iters"], "status": info["status"], "rank": info["rank"],
+            "rel_err_vs_A0": float(torch.linalg.norm(Ah - A0).item() / na0)}
+    return out
 
 
 def plain_alm_leg(D, iters_total, iters_timed=3):
@@ -432,7 +501,7 @@ def plain_alm_leg(D, iters_total, iters_timed=3):
                       f"x {iters_total} iterations"}
 
 
-def rpca_legs(args, ctx, D64, fp64_s):
+def rpca_legs(args, ctx, D64, fp64_s, A0):
     """Extra measurements beside the headline FP64 line (each bounded)."""
     import torch
 
@@ -452,17 +521,65 @@ def rpca_legs(args, ctx, D64, fp64_s):
     def low_prec():
         out = {}
         D32 = D64.float()
-        for prec in ("f32", "bf16"):
-            timed_solves(ctx, D32, 1, bf16=prec == "bf16")
-            t, info, A, E = timed_solves(ctx, D32, 3, bf16=prec == "bf16")
+        for prec in ("f32", "bf16", "bf16_x3"):
+            kw = {"bf16": prec != "f32"}
+            if prec == "bf16_x3":  # BF16, then BF16 x 3 down to 1e-6, then FP32
+                kw["opts"] = blws.default_alm_opts(ladder3_tol=1e-6)
+            timed_solves(ctx, D32, 1, **kw)
+            t, info, A, E = timed_solves(ctx, D32, 3, **kw)
             err, _ = golden_error("rpca_n2000_s0", A, E)
             out[prec] = {"solve_s": t, "solves_per_s": 1.0 / t, "iters": info["iters"],
-                         "iters_bf16": info["iters_bf16"], "status": info["status"],
+                         "iters_bf16": info["iters_bf16"],
+                         "iters_bf16x3": info["iters_bf16x3"], "status": info["status"],
                          "rel_err_vs_oracle_samples": err, "vs_f64_speed": fp64_s / t}
         return out
 
+    def w_products():
+        """W V at the benchmark shape (2000 x 2000 times 2000 x 112) in each
+        product mode, 20 back-to-back launches each."""
+        import numpy as np
+
+        m, n = D64.shape
+        b = 112
+        X = torch.randn(n, b, dtype=torch.float64, device=D64.device)
+        W32, X32 = D64.float(), X.float()
+        hi = torch.empty(m, n, dtype=torch.int16, device=D64.device)
+        lo = torch.empty_like(hi)
+        # the split of W in torch: hi = bf16(W) (nearest even), lo = bf16(W - hi)
+        hb = W32.to(torch.bfloat16)
+        hi.copy_(hb.view(torch.int16))
+        lo.copy_((W32 - hb.float()).to(torch.bfloat16).view(torch.int16))
+        C64 = torch.empty(m, b, dtype=torch.float64, device=D64.device)
+        C32 = torch.empty(m, b, dtype=torch.float32, device=D64.device)
+        ref = D64 @ X
+        modes = {
+            "f64": (lambda: ctx.gemm_f64(D64, X, C64), 8.0, C64),
+            "f32": (lambda: ctx.gemm_lp(W32, X32, C32), 4.0, C32),
+            "bf16": (lambda: ctx.gemm_lp(hi, X32, C32), 2.0, C32),
+            "bf16_x3": (lambda: ctx.gemm_bf16x3(hi, lo, X32, C32), 4.0, C32),
+        }
+        out = {"shape": "W (2000 x 2000) times X (2000 x 112)"}
+        for name, (fn, wbytes, C) in modes.items():
+            fn()
+            torch.cuda.synchronize()
+            err = float(torch.linalg.norm(C.double() - ref) / torch.linalg.norm(ref))
+            reps = 20
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize()
+            us = 1e6 * (time.perf_counter() - t1) / reps
+            out[name] = {"us": us, "rel_err": err,
+                         "hbm_GB_per_s": wbytes * m * n / (us * 1e3),
+                         "tflop_per_s": 2.0 * m * n * b / (us * 1e6)}
+        return out
+
     leg("n2000_low_precision", low_prec)
-    leg("svt_snapshot_n2000_f64", lambda: svt_snapshot_leg(ctx, D64))
+    leg("w_products_n2000", w_products)
+    state = snapshot_state(ctx, D64)
+    leg("svt_snapshot_n2000_f64", lambda: svt_snapshot_leg(ctx, state))
+    leg("ablations_sec41_n2000_f64", lambda: ablation_leg(ctx, state, D64, A0))
+    del state
 
     def n4000():
         inst = synth.rpca_instance(4000, 4000, 200, 0.10, AMP, 0)

@@ -17,12 +17,17 @@
  *    queued on it; the solvers block the calling thread until their result is
  *    complete, blws_svt returns as soon as its work is queued.
  *  - Element type of the W/D/U/V/A/E buffers: double for BLWS_FP64, float for
- *    BLWS_FP32 and BLWS_BF16. Singular values S are always double. In BLWS_FP32
- *    the products with W run on FP32 matrix cores; BLWS_BF16 (robust PCA only)
- *    is the precision ladder: the products with W run in BF16 (FP32
- *    accumulation) while the residual is large, then in FP32, and a last BF16
- *    iterate is refined by one FP32 step. Gram matrices, Cholesky factors, the
- *    projected SVD and the reconstruction of A are FP64 in every mode.
+ *    BLWS_FP32, BLWS_BF16 and BLWS_BF16X3. Singular values S are always double.
+ *    In BLWS_FP32 the products with W run on FP32 matrix cores; BLWS_BF16
+ *    (robust PCA only) is the precision ladder: the products with W run in BF16
+ *    (FP32 accumulation) while the residual is large, then (ladder3_tol > 0) in
+ *    split-precision BF16 x 3, then in FP32, and a last reduced-precision
+ *    iterate is refined by one FP32 step. BLWS_BF16X3 (blws_svt only) runs the
+ *    products of one step in BF16 x 3: W = W_hi + W_lo and the block likewise
+ *    split into two BF16 halves, W_hi X_hi + W_hi X_lo + W_lo X_hi on BF16
+ *    matrix cores with FP32 accumulation (about 16 significant bits). Gram
+ *    matrices, Cholesky factors, the projected SVD and the reconstruction of A
+ *    are FP64 in every mode.
  *  - Return value: a blws_status. Arguments are validated before any work is
  *    queued, so an error leaves every output untouched. No call aborts, exits
  *    or throws. blws_last_error() gives a detail message for the last failure.
@@ -39,7 +44,7 @@ extern "C" {
 
 typedef struct blws_ctx_s* blws_ctx;
 
-typedef enum { BLWS_FP64 = 0, BLWS_FP32 = 1, BLWS_BF16 = 2 } blws_precision;
+typedef enum { BLWS_FP64 = 0, BLWS_FP32 = 1, BLWS_BF16 = 2, BLWS_BF16X3 = 3 } blws_precision;
 
 typedef enum {
     BLWS_OK = 0,
@@ -80,6 +85,10 @@ typedef struct {
     int k_blocks;             /* BLWS_START_SPLIT, or k_blocks != 2, runs each SVT by   */
                               /* blws_svt_lanczos (the Sec. 4.1 ablations); defaults  */
                               /* BLWS_START_SPLIT and 2 (the default step)               */
+    double ladder3_tol;       /* BLWS_BF16 robust PCA: > 0 adds a split-precision phase  */
+                              /* after the BF16 one, W products in BF16 x 3 (W = W_hi +  */
+                              /* W_lo, block likewise, three BF16 products) while the    */
+                              /* residual is at or above this, FP32 below (0: off)       */
 } blws_alm_opts;
 
 typedef struct {
@@ -94,6 +103,7 @@ typedef struct {
     double seconds;           /* wall time of the solve, measured on the host           */
     int iters_bf16;           /* iterations whose W products ran in BF16 (BLWS_BF16)    */
     int refined;              /* 1 if a final FP32 step refined a BF16 last iterate     */
+    int iters_bf16x3;         /* iterations whose W products ran in BF16 x 3            */
 } blws_solve_info;
 
 /* Create a context on HIP device `device` (its workspace grows on demand). */
@@ -261,6 +271,16 @@ int blws_gemm_f64(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K, 
  * B is K x N (ldb). Asynchronous on `stream`. */
 int blws_gemm_lp(blws_ctx ctx, void* stream, int bf16, int trans_a, int M, int N, int K,
                  const void* A, int lda, const float* B, int ldb, float* C, int ldc);
+
+/* Diagnostic: C (M x N, float) = op(A) B in split-precision BF16 x 3, the
+ * kernel of the BLWS_BF16X3 W products: A_hi, A_lo (BF16 bits as uint16, the
+ * same layout and lda; A = A_hi + A_lo), B float split on the way in into
+ * b_hi = bf16(b), b_lo = bf16(b - b_hi); C = A_hi B_hi + A_hi B_lo + A_lo B_hi
+ * with FP32 accumulation. op(A) = A (M x K) or A^T (A is K x M). Asynchronous
+ * on `stream`. */
+int blws_gemm_bf16x3(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K,
+                     const void* A_hi, const void* A_lo, int lda, const float* B, int ldb,
+                     float* C, int ldc);
 
 /* SVD of a small dense N x N FP64 matrix B (ldb) on the device: U_B (N x N),
  * V_B (N x N) row-major with ld = N, S (N) decreasing, sign chosen so that the

@@ -38,6 +38,10 @@ def _prec_of(t) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}: use float64 or float32")
 
 
+# start blocks of svt_lanczos and of the svt_start option (Sec. 4.1)
+STARTS = _native.STARTS
+
+
 def _check_mat(t, name: str):
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
@@ -105,14 +109,19 @@ class Context:
 
     # -- the BLWS SVT step ---------------------------------------------------
     def svt(self, W, eps: float, U, V, warm: bool = True, A=None, S=None, seed: int = 20101202,
-            pow_steps: int = 2, rank=None, noalloc: bool = False):
+            pow_steps: int = 2, rank=None, noalloc: bool = False, bf16x3: bool = False):
         """A = T_eps(W) by one BLWS step. U (m x b), V (n x b) are updated in
         place with the top-b Ritz vectors. Returns (S, rank) as device tensors
         (S: float64 [b], rank: int32 [1]; pass them in to reuse buffers).
         noalloc=True calls blws_svt_noalloc (the library's static scratch, no
-        device allocation inside the call)."""
+        device allocation inside the call). bf16x3=True (float32 W) runs the W
+        products in split-precision BF16 x 3 (BLWS_BF16X3)."""
         torch = _torch()
         prec = _prec_of(W)
+        if bf16x3:
+            if prec != _native.BLWS_FP32:
+                raise TypeError("BF16 x 3 products take float32 W")
+            prec = _native.BLWS_BF16X3
         ldw = _check_mat(W, "W")
         ldu = _check_mat(U, "U")
         ldv = _check_mat(V, "V")
@@ -264,6 +273,21 @@ class Context:
         self._check(self._lib.blws_gemm_lp(self.handle, self._stream(), int(bf), int(trans_a),
                                            M, N, K, A.data_ptr(), lda, B.data_ptr(), ldb,
                                            C.data_ptr(), ldc))
+
+    def gemm_bf16x3(self, A_hi, A_lo, B, C, trans_a: bool = False):
+        """C = op(A) B in split-precision BF16 x 3 (A_hi, A_lo int16 tensors
+        holding the BF16 halves of A; B, C float32)."""
+        torch = _torch()
+        lda, ldb, ldc = _check_mat(A_hi, "A_hi"), _check_mat(B, "B"), _check_mat(C, "C")
+        if _check_mat(A_lo, "A_lo") != lda or A_lo.shape != A_hi.shape:
+            raise ValueError("A_hi and A_lo must have the same shape and layout")
+        if A_hi.dtype != torch.int16 or A_lo.dtype != torch.int16:
+            raise TypeError("A_hi and A_lo hold BF16 bits as int16")
+        M, N = C.shape
+        K = B.shape[0]
+        self._check(self._lib.blws_gemm_bf16x3(self.handle, self._stream(), int(trans_a), M, N,
+                                               K, A_hi.data_ptr(), A_lo.data_ptr(), lda,
+                                               B.data_ptr(), ldb, C.data_ptr(), ldc))
 
     def small_svd_f64(self, B):
         torch = _torch()

@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libblws.so")
 
-BLWS_FP64, BLWS_FP32, BLWS_BF16 = 0, 1, 2
+BLWS_FP64, BLWS_FP32, BLWS_BF16, BLWS_BF16X3 = 0, 1, 2, 3
 # start blocks of blws_svt_lanczos (include/blws.h, BLWS_START_*)
 STARTS = {"split": 0, "aug": 1, "left": 2, "right": 3}
 STATUS = {0: "ok", 1: "not converged", -1: "invalid argument", -2: "out of device memory",
@@ -42,6 +42,7 @@ class AlmOpts(ctypes.Structure):
         ("ladder_tol", ctypes.c_double),
         ("svt_start", ctypes.c_int),
         ("k_blocks", ctypes.c_int),
+        ("ladder3_tol", ctypes.c_double),
     ]
 
 
@@ -74,6 +75,7 @@ class SolveInfo(ctypes.Structure):
         ("seconds", ctypes.c_double),
         ("iters_bf16", ctypes.c_int),
         ("refined", ctypes.c_int),
+        ("iters_bf16x3", ctypes.c_int),
     ]
 
     def as_dict(self) -> dict:
@@ -132,6 +134,7 @@ SIGNATURES = {
     "blws_fill_uniform": (_i, [_vp, _vp, _i, _i, _vp, _i, _ull, _ull]),
     "blws_gemm_f64": (_i, [_vp, _vp, _i, _i, _i, _i, _d, _vp, _i, _vp, _i, _d, _vp, _i]),
     "blws_gemm_lp": (_i, [_vp, _vp, _i, _i, _i, _i, _i, _vp, _i, _vp, _i, _vp, _i]),
+    "blws_gemm_bf16x3": (_i, [_vp, _vp, _i, _i, _i, _i, _vp, _vp, _i, _vp, _i, _vp, _i]),
     "blws_small_svd_f64": (_i, [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp]),
     "blws_cold_block": (_i, [_vp, _vp, _i, _i, _i, _vp, _i, _i, _i, _ull, _ull, _vp, _i, _vp,
                              _i]),

@@ -116,11 +116,17 @@ void gemm_lp_grouped(const WProduct* ps, int n, hipStream_t s);
 // (bf16 = true: A holds BF16 bits, B is rounded to BF16), FP32 accumulation:
 // C (M x N, float) = op(A) B. `partial` holds gemm_lp_partial_elems floats.
 size_t gemm_lp_partial_elems(int M, int N, int K);
+// A_lo non-null (BF16 mode only): split-precision BF16 x 3, A holding the high
+// and A_lo the low BF16 halves of the FP32 matrix (A_hi + A_lo), B split the
+// same way on the fly: C = A_hi B_hi + A_hi B_lo + A_lo B_hi.
 void gemm_lp(Timer* tm, const char* family, bool bf16, bool trans_a, int M, int N, int K,
              const void* A, int lda, const float* B, int ldb, float* C, int ldc, float* partial,
-             size_t partial_elems, hipStream_t s);
+             size_t partial_elems, hipStream_t s, const unsigned short* A_lo = nullptr);
 // Y[e] = BF16(X[e]) for e < count (round to nearest even).
 void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s);
+// Hi = BF16(X), Lo = BF16(X - Hi) over rows x cols (all with leading dimension ld).
+void split_bf16x2(int rows, int cols, const float* X, int ld, unsigned short* Hi,
+                  unsigned short* Lo, hipStream_t s);
 
 // Scaled LDL^T / Cholesky with breakdown detection on an n x n Gram matrix:
 // writes Rinv (n x n, ld n) such that X * Rinv has orthonormal columns when
@@ -205,14 +211,15 @@ void rpca_init(int m, int n, const T* D, int ldd, double J, double mu, T* Y, T* 
 // a = sum_{k < r} U[i][k] (S[k] - eps) V[j][k] with r = #{S_k > eps} (k < b);
 // t = d - a + y / mu;  e = shrink(t, lam / mu);  z = d - a - e;
 // y' = y + mu z;  w' = d - e + y' / mu_next.
-// Writes E, Y, W (and its BF16 copy Wh when non-null), and per-workgroup
-// partial sums of z^2 into `partials`
+// Writes E, Y, W (and its BF16 copy Wh when non-null, with the low half
+// Wl = BF16(W - Wh) of the split-precision copy when Wl is non-null too), and
+// per-workgroup partial sums of z^2 into `partials`
 // (size alm_partials(m, n)); A_out (may be null) receives a.
 template <typename T>
 void alm_epilogue(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
                   const double* S, double eps, double lam, double mu, double mu_next,
                   const T* D, int ldd, T* Y, T* E, int lde, T* W, unsigned short* Wh, T* A_out,
-                  int lda, double* partials, hipStream_t s);
+                  int lda, double* partials, hipStream_t s, unsigned short* Wl = nullptr);
 size_t alm_partials(int m, int n);
 // A = U_r diag(S_r - eps) V_r^T only.
 template <typename T>

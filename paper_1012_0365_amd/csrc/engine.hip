@@ -170,6 +170,7 @@ void blws_default_alm_opts(blws_alm_opts* o)
     o->ladder_tol = 1e-3;
     o->svt_start = BLWS_START_SPLIT;
     o->k_blocks = 2;
+    o->ladder3_tol = 0.0;
 }
 
 void blws_default_svt_opts(blws_svt_opts* o)
@@ -199,9 +200,10 @@ int blws_svt(blws_ctx ctx, void* stream, int prec, int m, int n, const void* W, 
     if (prec == BLWS_FP64)
         blws::svt_call_t<double>(cx, s, m, n, (const double*)W, ldw, eps, b, (double*)U, ldu,
                                  (double*)V, ldv, warm, S, rank_dev, (double*)A, lda, o);
-    else if (prec == BLWS_FP32)
+    else if (prec == BLWS_FP32 || prec == BLWS_BF16X3)
         blws::svt_call_t<float>(cx, s, m, n, (const float*)W, ldw, eps, b, (float*)U, ldu,
-                                (float*)V, ldv, warm, S, rank_dev, (float*)A, lda, o);
+                                (float*)V, ldv, warm, S, rank_dev, (float*)A, lda, o,
+                                prec == BLWS_BF16X3);
     else
         throw BlwsError{BLWS_EUNSUPPORTED, "blws_svt: precision not supported"};
     return BLWS_OK;
@@ -406,6 +408,23 @@ int blws_gemm_lp(blws_ctx ctx, void* stream, int bf16, int trans_a, int M, int N
     cx.ensure((pe + 1) * sizeof(float) + 256);
     blws::gemm_lp(&cx.timer, "gemm_diag", bf16 != 0, trans_a != 0, M, N, K, A, lda, B, ldb, C,
                   ldc, (float*)cx.ws, pe + 1, (hipStream_t)stream);
+    return BLWS_OK;
+    ABI_END
+}
+
+int blws_gemm_bf16x3(blws_ctx ctx, void* stream, int trans_a, int M, int N, int K,
+                     const void* A_hi, const void* A_lo, int lda, const float* B, int ldb,
+                     float* C, int ldc)
+{
+    ABI_BEGIN(ctx)
+    BLWS_REQUIRE(M >= 0 && N >= 0 && K >= 1 && A_hi && A_lo && B && C, BLWS_EINVAL,
+                 "blws_gemm_bf16x3: bad arguments");
+    BLWS_REQUIRE(ldb >= N && ldc >= N && lda >= (trans_a ? M : K), BLWS_EINVAL,
+                 "blws_gemm_bf16x3: leading dimension too small");
+    const size_t pe = blws::gemm_lp_partial_elems(M, N, K);
+    cx.ensure((pe + 1) * sizeof(float) + 256);
+    blws::gemm_lp(&cx.timer, "gemm_diag", true, trans_a != 0, M, N, K, A_hi, lda, B, ldb, C, ldc,
+                  (float*)cx.ws, pe + 1, (hipStream_t)stream, (const unsigned short*)A_lo);
     return BLWS_OK;
     ABI_END
 }

@@ -90,7 +90,7 @@ struct RpcaJob : Job {
     bool abl = false;  // each SVT by the literal block Lanczos (Sec. 4.1 ablations)
     LanczosWs lw;
     T *Y = nullptr, *Wb = nullptr, *U = nullptr, *V = nullptr;
-    unsigned short* Wh = nullptr;
+    unsigned short *Wh = nullptr, *Wl = nullptr;
     double *S = nullptr, *part = nullptr, *scal = nullptr;
     int* rank_dev = nullptr;
     long long* nnz_scr = nullptr;
@@ -99,8 +99,11 @@ struct RpcaJob : Job {
     enum Phase { NORMS, SPEC, ALM, REFINE, FINISH } phase = NORMS;
     double dnorm = 0.0, s1 = 0.0, prev = 0.0, mu = 0.0, mu_bar = 0.0, mu_next = 0.0;
     double rel = INFINITY, rel_prev = INFINITY, eps = 0.0;
-    int t = 0, sv = 0, b = 0, svp = 0, it = 0, iters_bf = 0, np = 0;
-    bool bf = false, last_bf = false, refined = false;
+    int t = 0, sv = 0, b = 0, svp = 0, it = 0, iters_bf = 0, iters_x3 = 0, np = 0;
+    // precision ladder: BF16 products (bf), then split-precision BF16 x 3
+    // products (x3, when ladder3_tol > 0), then FP32; last_red: the last
+    // iterate came from reduced-precision products
+    bool bf = false, x3 = false, x3_on = false, last_red = false, refined = false;
 
     RpcaJob(int m_, int n_, const T* D_, int ldd_, double lambda_, const blws_alm_opts& o_, T* A_,
             int lda_, T* E_, int lde_, bool ladder_)
@@ -118,6 +121,7 @@ struct RpcaJob : Job {
         mn = (size_t)m * n;
         sv = o.sv0;
         bf = ladder;
+        x3_on = ladder && o.ladder3_tol > 0.0;
         np = (int)alm_partials(m, n);
     }
 
@@ -131,6 +135,7 @@ struct RpcaJob : Job {
         Y = c.take<T>(mn);
         Wb = c.take<T>(mn);
         Wh = c.take<unsigned short>(ladder ? mn : 1);
+        Wl = c.take<unsigned short>(x3_on ? mn : 1);
         U = c.take<T>((size_t)m * bmax);
         V = c.take<T>((size_t)n * bmax);
         S = c.take<double>(bmax);
@@ -190,11 +195,13 @@ struct RpcaJob : Job {
                 grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)it + 1);
             }
             b = bn;
-            last_bf = bf;
+            last_red = bf || x3;
             iters_bf += bf ? 1 : 0;
+            iters_x3 += (!bf && x3) ? 1 : 0;
         }
-        const bool use_bf = !refine && bf;
-        const Op<T> opW{Wb, n, nullptr, use_bf ? Wh : nullptr};
+        const bool use_bf = !refine && bf, use_x3 = !refine && !bf && x3;
+        const Op<T> opW{Wb, n, nullptr, (use_bf || use_x3) ? Wh : nullptr,
+                        use_x3 ? Wl : nullptr};
         if constexpr (std::is_same<T, double>::value) {
             if (abl)
                 lanczos_step(cx, lw, s, m, n, opW, eps, b, o.svt_start, o.k_blocks, U, bmax, V,
@@ -205,8 +212,10 @@ struct RpcaJob : Job {
             svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         }
         mu_next = next_mu(o, mu, mu_bar);
+        // the copies the next iteration's products may read
         alm_epilogue<T>(&cx.timer, m, n, b, U, bmax, V, bmax, S, eps, lambda, mu, mu_next, D, ldd,
-                        Y, E, lde, Wb, use_bf ? Wh : nullptr, (T*)nullptr, 0, part, s);
+                        Y, E, lde, Wb, (use_bf || use_x3) ? Wh : nullptr, (T*)nullptr, 0, part, s,
+                        ((use_bf || use_x3) && x3_on) ? Wl : nullptr);
         queue_readback(cx, s);
     }
 
@@ -269,8 +278,12 @@ struct RpcaJob : Job {
                 mu = o.mu0_scale / s1;
                 mu_bar = mu * o.mu_max_factor;
                 rpca_init<T>(m, n, D, ldd, J, mu, Y, E, lde, Wb, s);
-                if constexpr (std::is_same<T, float>::value)
-                    if (ladder) to_bf16((long long)mn, Wb, Wh, s);
+                if constexpr (std::is_same<T, float>::value) {
+                    if (x3_on)
+                        split_bf16x2(m, n, Wb, n, Wh, Wl, s);
+                    else if (ladder)
+                        to_bf16((long long)mn, Wb, Wh, s);
+                }
                 it = 1;
                 queue_iteration(cx, s, false);
                 phase = ALM;
@@ -279,12 +292,17 @@ struct RpcaJob : Job {
             case ALM: {
                 read_iteration(hrb);
                 sv = predict_rank(svp, sv, o.sv_step_frac, p);
-                if (bf && (rel < o.ladder_tol || (it >= 3 && rel >= rel_prev))) bf = false;
+                if (x3 && (rel < o.ladder3_tol || rel >= rel_prev)) x3 = false;
+                if (bf && (rel < o.ladder_tol || (it >= 3 && rel >= rel_prev))) {
+                    bf = false;
+                    x3 = x3_on && rel >= o.ladder3_tol;
+                }
                 rel_prev = rel;
                 if (rel < o.tol) {
-                    if (last_bf) {
-                        // the last iterate came from BF16 products: one more ALM
-                        // step with FP32 products (FP64 Rayleigh-Ritz and reconstruction)
+                    if (last_red) {
+                        // the last iterate came from BF16 or BF16 x 3 products: one
+                        // more ALM step with FP32 products (FP64 Rayleigh-Ritz and
+                        // reconstruction)
                         refined = true;
                         queue_iteration(cx, s, true);
                         phase = REFINE;
@@ -316,6 +334,7 @@ struct RpcaJob : Job {
                 info.rel_residual = rel;
                 info.norm2_D = s1;
                 info.iters_bf16 = iters_bf;
+                info.iters_bf16x3 = iters_x3;
                 info.refined = refined ? 1 : 0;
                 status = info.status;
                 done = true;
@@ -814,7 +833,7 @@ inline void check_alm_opts(const blws_alm_opts& o, const std::string& who)
     BLWS_REQUIRE(o.tol > 0.0 && o.max_iter >= 1 && o.rho >= 1.0 && o.mu0_scale > 0.0 &&
                      o.mu_max_factor >= 1.0 && o.sv0 >= 1 && o.b_round >= 1 &&
                      o.norm_steps >= 1 && o.sv_step_frac >= 0.0 && o.b_max >= 1 &&
-                     o.ladder_tol >= 0.0,
+                     o.ladder_tol >= 0.0 && o.ladder3_tol >= 0.0,
                  BLWS_EINVAL, who + ": bad options");
     BLWS_REQUIRE(o.b_max <= 512, BLWS_EUNSUPPORTED, who + ": b_max above 512");
     BLWS_REQUIRE(o.svt_start >= LZ_START_SPLIT && o.svt_start <= LZ_START_RIGHT &&
@@ -915,18 +934,27 @@ inline std::unique_ptr<Job> make_mc_svt_job(int prec, int m, int n, int nnz, con
 template <typename T>
 void svt_call_t(Context& cx, hipStream_t s, int m, int n, const T* W, int ldw, double eps, int b,
                 T* U, int ldu, T* V, int ldv, int warm, double* S, int* rank_dev, T* A, int lda,
-                const blws_svt_opts& o)
+                const blws_svt_opts& o, bool x3 = false)
 {
     StepWs<T> w;
+    unsigned short *Wh = nullptr, *Wl = nullptr;
+    const size_t wcopy = x3 ? (size_t)m * ldw : 0;  // BF16 x 3: the two halves of W
     {
         Carver dry(nullptr);
         w.carve(dry, m, n, b);
+        dry.take<unsigned short>(wcopy);
+        dry.take<unsigned short>(wcopy);
         cx.ensure(dry.off + 256);
     }
     Carver c(cx.ws);
     w.carve(c, m, n, b);
+    if (x3) {
+        Wh = c.take<unsigned short>(wcopy);
+        Wl = c.take<unsigned short>(wcopy);
+        if constexpr (std::is_same<T, float>::value) split_bf16x2(m, n, W, ldw, Wh, Wl, s);
+    }
     zero_bytes(w.nflag, 4 * sizeof(int), s);
-    const Op<T> op{W, ldw, nullptr, nullptr};
+    const Op<T> op{W, ldw, nullptr, Wh, Wl};
     if (!warm) cold_block<T>(cx, w, s, m, n, op, b, o.pow_steps, o.seed, 1, U, ldu, V, ldv);
     svt_step<T>(cx, w, s, m, n, op, eps, b, U, ldu, V, ldv, S, rank_dev, o.seed);
     if (A) svt_reconstruct<T>(&cx.timer, m, n, b, U, ldu, V, ldv, S, eps, A, lda, s);

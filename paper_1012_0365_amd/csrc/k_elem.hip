@@ -51,8 +51,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     int m, int n, int b, const T* __restrict__ U, int ldu, const T* __restrict__ V, int ldv,
     const double* __restrict__ S, double eps, double lam, double mu, double mu_next,
     const T* __restrict__ D, int ldd, T* __restrict__ Y, T* __restrict__ E, int lde,
-    T* __restrict__ W, unsigned short* __restrict__ Wh, T* __restrict__ A_out, int lda,
-    double* __restrict__ partials)
+    T* __restrict__ W, unsigned short* __restrict__ Wh, unsigned short* __restrict__ Wl,
+    T* __restrict__ A_out, int lda, double* __restrict__ partials)
 {
     __shared__ double Us[EBK][TILE + 1];
     __shared__ double Vs[EBK][TILE + 1];
@@ -168,7 +168,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
                 Y[ye] = (T)y2;
                 const T wn = (T)(d - e + y2 / mu_next);
                 W[ye] = wn;
-                if (Wh) Wh[ye] = bf16_rne((float)wn);
+                if (Wh) {
+                    const unsigned short h = bf16_rne((float)wn);
+                    Wh[ye] = h;
+                    // low half of the split-precision copy: W - W_hi in BF16
+                    if (Wl) Wl[ye] = bf16_rne((float)wn - __uint_as_float((unsigned)h << 16));
+                }
                 if (A_out) A_out[(size_t)row * lda + col] = (T)a;
                 zz += z * z;
             }
@@ -313,14 +318,15 @@ template <typename T>
 void alm_epilogue(Timer* tm, int m, int n, int b, const T* U, int ldu, const T* V, int ldv,
                   const double* S, double eps, double lam, double mu, double mu_next, const T* D,
                   int ldd, T* Y, T* E, int lde, T* W, unsigned short* Wh, T* A_out, int lda,
-                  double* partials, hipStream_t s)
+                  double* partials, hipStream_t s, unsigned short* Wl)
 {
     dim3 grid((n + TILE - 1) / TILE, (m + TILE - 1) / TILE);
     // algorithmic traffic: read D, Y; write E, Y, W (A itself is never stored)
     TimedLaunch tl(tm, "alm_epilogue", s, 2.0 * m * (double)n * b,
                    5.0 * sizeof(T) * (double)m * n);
     hipLaunchKernelGGL((svt_tile_kernel<T, 0>), grid, dim3(256), 0, s, m, n, b, U, ldu, V, ldv, S,
-                       eps, lam, mu, mu_next, D, ldd, Y, E, lde, W, Wh, A_out, lda, partials);
+                       eps, lam, mu, mu_next, D, ldd, Y, E, lde, W, Wh, Wl, A_out, lda,
+                       partials);
 }
 
 template <typename T>
@@ -332,7 +338,8 @@ void svt_reconstruct(Timer* tm, int m, int n, int b, const T* U, int ldu, const 
                    sizeof(T) * (double)m * n);
     hipLaunchKernelGGL((svt_tile_kernel<T, 1>), grid, dim3(256), 0, s, m, n, b, U, ldu, V, ldv, S,
                        eps, 0.0, 1.0, 1.0, (const T*)nullptr, 0, (T*)nullptr, (T*)nullptr, 0,
-                       (T*)nullptr, (unsigned short*)nullptr, A, lda, (double*)nullptr);
+                       (T*)nullptr, (unsigned short*)nullptr, (unsigned short*)nullptr, A, lda,
+                       (double*)nullptr);
 }
 
 // The per-iteration readback gathered by one kernel: the summed partials, and
@@ -377,7 +384,7 @@ void count_nonzeros(int m, int n, const T* X, int ldx, long long* out, long long
     template void alm_epilogue<T>(Timer*, int, int, int, const T*, int, const T*, int,          \
                                   const double*, double, double, double, double, const T*, int, \
                                   T*, T*, int, T*, unsigned short*, T*, int, double*,           \
-                                  hipStream_t);                                                 \
+                                  hipStream_t, unsigned short*);                                \
     template void svt_reconstruct<T>(Timer*, int, int, int, const T*, int, const T*, int,       \
                                      const double*, double, T*, int, hipStream_t);             \
     template void count_nonzeros<T>(int, int, const T*, int, long long*, long long*,            \

@@ -159,12 +159,23 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_f32_kernel(int M, int N, int K
 // BF16 mode: A is BF16 bits (the W copy), B float rounded to BF16 into LDS.
 // LDS row-major in k (8 consecutive k per lane fragment); BK = 64 (2 MFMA
 // steps of k = 32). As: 64 x 72, Bs: 16 nt x 72 shorts of LDS.
+//
+// X3 (split-precision BF16 x 3): A = A_hi + A_lo (two BF16 copies) and each
+// B element b = b_hi + b_lo with b_hi = bf16(b), b_lo = bf16(b - b_hi), split
+// on the way into LDS (Al, Bl beside As, Bs); each k-step accumulates
+// A_lo B_hi, A_hi B_lo, then A_hi B_hi in FP32 (the A_lo B_lo term, below
+// 2^-18 of |A||B|, is dropped): about 16 significant bits per product in
+// place of 8, at three BF16 MFMAs per step.
 constexpr int BF_BK = 64, BF_LDK = BF_BK + 8;
-template <bool TRANS, int NT>
-__device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned short* Bs, int bx,
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+template <bool TRANS, int NT, bool X3 = false>
+__device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned short* Bs,
+                                                unsigned short* Al, unsigned short* Bl, int bx,
                                                 int by, int bz, int nt, int M, int N, int K,
                                                 int kchunk, const unsigned short* __restrict__ A,
-                                                int lda, const float* __restrict__ B, int ldb,
+                                                const unsigned short* __restrict__ Alo, int lda,
+                                                const float* __restrict__ B, int ldb,
                                                 float* __restrict__ C, int ldc,
                                                 float* __restrict__ partial)
 {
@@ -180,7 +191,7 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
 
     // the next stage's tiles load into registers while the current one is used
     constexpr int NB = (BK * 16 * NT + LNTHREADS - 1) / LNTHREADS;
-    unsigned short ra[16];
+    unsigned short ra[16], rl[X3 ? 16 : 1];
     float rb[NB];  // rounded to BF16 when stored to LDS, not as it arrives
     auto fetch = [&](int k0) {
         if (!TRANS) {
@@ -189,7 +200,9 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gk = k0 + kq + u;
-                ra[u] = (gr < M && gk < ke) ? A[(size_t)gr * lda + gk] : (unsigned short)0;
+                const bool in = gr < M && gk < ke;
+                ra[u] = in ? A[(size_t)gr * lda + gk] : (unsigned short)0;
+                if constexpr (X3) rl[u] = in ? Alo[(size_t)gr * lda + gk] : (unsigned short)0;
             }
         } else {
             const int kr = tid >> 2, rq = (tid & 3) * 16;
@@ -197,7 +210,9 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const int gr = r0 + rq + u;
-                ra[u] = (gr < M && gk < ke) ? A[(size_t)gk * lda + gr] : (unsigned short)0;
+                const bool in = gr < M && gk < ke;
+                ra[u] = in ? A[(size_t)gk * lda + gr] : (unsigned short)0;
+                if constexpr (X3) rl[u] = in ? Alo[(size_t)gk * lda + gr] : (unsigned short)0;
             }
         }
 #pragma unroll
@@ -213,27 +228,45 @@ __device__ __forceinline__ void gemm_bf16_block(unsigned short* As, unsigned sho
         if (!TRANS) {
             const int row = tid >> 2, kq = (tid & 3) * 16;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) As[row * LDK + kq + u] = ra[u];
+            for (int u = 0; u < 16; ++u) {
+                As[row * LDK + kq + u] = ra[u];
+                if constexpr (X3) Al[row * LDK + kq + u] = rl[u];
+            }
         } else {
             const int kr = tid >> 2, rq = (tid & 3) * 16;
 #pragma unroll
-            for (int u = 0; u < 16; ++u) As[(rq + u) * LDK + kr] = ra[u];
+            for (int u = 0; u < 16; ++u) {
+                As[(rq + u) * LDK + kr] = ra[u];
+                if constexpr (X3) Al[(rq + u) * LDK + kr] = rl[u];
+            }
         }
 #pragma unroll
         for (int u = 0; u < NB; ++u) {
             const int e = tid + LNTHREADS * u;
             const int kr = e / BN, cc = e - kr * BN;
-            if (e < BK * BN) Bs[cc * LDK + kr] = f2bf(rb[u]);
+            if (e < BK * BN) {
+                const unsigned short hi = f2bf(rb[u]);
+                Bs[cc * LDK + kr] = hi;
+                if constexpr (X3) Bl[cc * LDK + kr] = f2bf(rb[u] - bf2f(hi));
+            }
         }
         __syncthreads();
         if (k0 + BK < ke) fetch(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK / 32; ++kk) {
-            const s8 a = *(const s8*)&As[(wave * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4)];
+            const int ao = (wave * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4);
+            const s8 a = *(const s8*)&As[ao];
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 if (j >= nt) break;  // uniform
-                const s8 bv = *(const s8*)&Bs[(j * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4)];
+                const int bo = (j * 16 + (lane & 15)) * LDK + kk * 32 + 8 * (lane >> 4);
+                const s8 bv = *(const s8*)&Bs[bo];
+                if constexpr (X3) {
+                    const s8 al = *(const s8*)&Al[ao];
+                    const s8 bl = *(const s8*)&Bl[bo];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bv, acc[j], 0, 0, 0);
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl, acc[j], 0, 0, 0);
+                }
                 acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bv, acc[j], 0, 0, 0);
             }
         }
@@ -265,8 +298,22 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_kernel(
 {
     __shared__ __attribute__((aligned(16))) unsigned short As[LBM * BF_LDK];
     __shared__ __attribute__((aligned(16))) unsigned short Bs[16 * NT * BF_LDK];
-    gemm_bf16_block<TRANS, NT>(As, Bs, blockIdx.x, blockIdx.y, blockIdx.z, NT, M, N, K, kchunk, A,
-                               lda, B, ldb, C, ldc, partial);
+    gemm_bf16_block<TRANS, NT>(As, Bs, nullptr, nullptr, blockIdx.x, blockIdx.y, blockIdx.z, NT,
+                               M, N, K, kchunk, A, nullptr, lda, B, ldb, C, ldc, partial);
+}
+
+template <bool TRANS, int NT>
+__global__ __launch_bounds__(LNTHREADS) void gemm_bf16x3_kernel(
+    int M, int N, int K, int kchunk, const unsigned short* __restrict__ A,
+    const unsigned short* __restrict__ Alo, int lda, const float* __restrict__ B, int ldb,
+    float* __restrict__ C, int ldc, float* __restrict__ partial)
+{
+    __shared__ __attribute__((aligned(16))) unsigned short As[LBM * BF_LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Al[LBM * BF_LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bs[16 * NT * BF_LDK];
+    __shared__ __attribute__((aligned(16))) unsigned short Bl[16 * NT * BF_LDK];
+    gemm_bf16_block<TRANS, NT, true>(As, Bs, Al, Bl, blockIdx.x, blockIdx.y, blockIdx.z, NT, M, N,
+                                     K, kchunk, A, Alo, lda, B, ldb, C, ldc, partial);
 }
 
 // FP32 partial sums of split s, added in split order in FP64
@@ -346,11 +393,13 @@ __global__ __launch_bounds__(LNTHREADS) void gemm_bf16_grouped_kernel(GroupLp g)
     const GroupLp::Prob& P = g.p[q];
     float* part = P.splits > 1 ? P.partial : nullptr;
     if (P.trans)
-        gemm_bf16_block<true, 8>(As, Bs, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
-                                 (const unsigned short*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+        gemm_bf16_block<true, 8>(As, Bs, nullptr, nullptr, bx, by, bz, P.nt, P.M, P.N, P.K,
+                                 P.kchunk, (const unsigned short*)P.A, nullptr, P.lda, P.B, P.ldb,
+                                 P.C, P.ldc, part);
     else
-        gemm_bf16_block<false, 8>(As, Bs, bx, by, bz, P.nt, P.M, P.N, P.K, P.kchunk,
-                                  (const unsigned short*)P.A, P.lda, P.B, P.ldb, P.C, P.ldc, part);
+        gemm_bf16_block<false, 8>(As, Bs, nullptr, nullptr, bx, by, bz, P.nt, P.M, P.N, P.K,
+                                  P.kchunk, (const unsigned short*)P.A, nullptr, P.lda, P.B, P.ldb,
+                                  P.C, P.ldc, part);
 }
 
 struct GroupRedLp {
@@ -373,6 +422,24 @@ __global__ void reduce_f32_grouped_kernel(GroupRedLp g)
         const double acc = sum_splits_f32(P.partial, total, e, P.S);
         const int row = (int)(e / P.N), col = (int)(e - (size_t)row * P.N);
         P.C[(size_t)row * P.ldc + col] = (float)acc;
+    }
+}
+
+// Hi[r][c] = bf16(X[r][c]), Lo[r][c] = bf16(X[r][c] - Hi[r][c]) (rows x cols, the
+// same ld for all three)
+__global__ void split_bf16x2_kernel(int rows, int cols, const float* __restrict__ X, int ld,
+                                    unsigned short* __restrict__ Hi,
+                                    unsigned short* __restrict__ Lo)
+{
+    const long long total = (long long)rows * cols;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const int r = (int)(e / cols), c = (int)(e - (long long)r * cols);
+        const size_t i = (size_t)r * ld + c;
+        const float x = X[i];
+        const unsigned short h = f2bf(x);
+        Hi[i] = h;
+        Lo[i] = f2bf(x - bf2f(h));
     }
 }
 
@@ -423,21 +490,32 @@ size_t gemm_lp_partial_elems(int M, int N, int K)
 
 void gemm_lp(Timer* tm, const char* family, bool bf16, bool trans_a, int M, int N, int K,
              const void* A, int lda, const float* B, int ldb, float* C, int ldc, float* partial,
-             size_t partial_elems, hipStream_t s)
+             size_t partial_elems, hipStream_t s, const unsigned short* A_lo)
 {
     if (M <= 0 || N <= 0) return;
     BLWS_REQUIRE(K > 0, BLWS_EINVAL, "gemm_lp: K must be positive");
+    BLWS_REQUIRE(!A_lo || bf16, BLWS_EINVAL, "gemm_lp: a low BF16 half needs the BF16 mode");
     const PlanLp p = make_plan_lp(M, N, K, bf16 ? 64 : 32);
     const bool split = p.splits > 1;
     BLWS_REQUIRE(!split || (partial && partial_elems >= (size_t)p.splits * M * N), BLWS_ENOMEM,
                  "gemm_lp: split-K scratch too small");
-    TimedLaunch tl(tm, family, s, 2.0 * M * N * (double)K,
-                   (bf16 ? 2.0 : 4.0) * (double)M * K + 4.0 * ((double)K * N + (double)M * N));
+    TimedLaunch tl(tm, family, s, (A_lo ? 6.0 : 2.0) * M * N * (double)K,
+                   (A_lo ? 4.0 : bf16 ? 2.0 : 4.0) * (double)M * K +
+                       4.0 * ((double)K * N + (double)M * N));
     dim3 grid(p.gx, p.gy, p.splits), block(LNTHREADS);
     float* part = split ? partial : nullptr;
 #define BLWS_LP_CASE(NTV)                                                                      \
     case NTV:                                                                                  \
-        if (bf16) {                                                                            \
+        if (A_lo) {                                                                            \
+            if (trans_a)                                                                       \
+                hipLaunchKernelGGL((gemm_bf16x3_kernel<true, NTV>), grid, block, 0, s, M, N,   \
+                                   K, p.kchunk, (const unsigned short*)A, A_lo, lda, B, ldb, C, \
+                                   ldc, part);                                                 \
+            else                                                                               \
+                hipLaunchKernelGGL((gemm_bf16x3_kernel<false, NTV>), grid, block, 0, s, M, N,  \
+                                   K, p.kchunk, (const unsigned short*)A, A_lo, lda, B, ldb, C, \
+                                   ldc, part);                                                 \
+        } else if (bf16) {                                                                     \
             if (trans_a)                                                                       \
                 hipLaunchKernelGGL((gemm_bf16_kernel<true, NTV>), grid, block, 0, s, M, N, K,  \
                                    p.kchunk, (const unsigned short*)A, lda, B, ldb, C, ldc,     \
@@ -536,6 +614,18 @@ void gemm_lp_grouped(const WProduct* ps, int n, hipStream_t s)
         r.start[nr] = rblocks;
         hipLaunchKernelGGL(reduce_f32_grouped_kernel, dim3(rblocks), dim3(256), 0, s, r);
     }
+}
+
+void split_bf16x2(int rows, int cols, const float* X, int ld, unsigned short* Hi,
+                  unsigned short* Lo, hipStream_t s)
+{
+    const long long total = (long long)rows * cols;
+    if (total <= 0) return;
+    long long blocks = (total + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(split_bf16x2_kernel, dim3((unsigned)blocks), dim3(256), 0, s, rows, cols, X,
+                       ld, Hi, Lo);
+    HIP_TRY(hipGetLastError());
 }
 
 void to_bf16(long long count, const float* X, unsigned short* Y, hipStream_t s)

@@ -525,6 +525,8 @@ struct Op {
     int ldw = 0;
     const McOp<T>* mc = nullptr;
     const unsigned short* Wh = nullptr;  // BF16 copy of W (ld ldw): products in BF16
+    // with Wh, the low half BF16(W - Wh) (ld ldw): split-precision BF16 x 3 products
+    const unsigned short* Wl = nullptr;
 };
 
 // out (rows x c) = W X (trans = false: X is n x c, rows = m) or W^T X
@@ -541,7 +543,7 @@ void op_apply(Context& cx, StepWs<T>& w, hipStream_t s, const Op<T>& op, int m, 
             const bool bf = op.Wh != nullptr;
             gemm_lp(tm, "gemm_w", bf, trans, rows, c, inner,
                     bf ? (const void*)op.Wh : (const void*)op.W, op.ldw, X, ldx, out, ldo,
-                    (float*)w.partial, 2 * w.partial_elems, s);
+                    (float*)w.partial, 2 * w.partial_elems, s, bf ? op.Wl : nullptr);
         } else {
             gemm<T, T, T>(tm, "gemm_w", trans, rows, c, inner, 1.0, op.W, op.ldw, X, ldx, 0.0,
                           (const T*)nullptr, 0, out, ldo, w.partial, w.partial_elems, s);
@@ -611,7 +613,7 @@ void svt_step_pair1_two_streams(Context& cx, StepWs<T>& w, hipStream_t s, int m,
     // products with the start block: P = W V, Q = W^T U (the low-rank
     // coefficients of the matrix-completion operator have one buffer: there
     // Q waits for P)
-    const bool grouped = cx.group && W.W;
+    const bool grouped = cx.group && W.W && !W.Wl;  // BF16 x 3 products are not grouped
     if (grouped) {
         // the request server groups these with other solves' products
         const WProduct pr[2] = {dense_wproduct<T>(w, W, m, n, false, V, ldv, b, w.PH, b2),
@@ -677,7 +679,7 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
         svt_step_pair1_two_streams<T>(cx, w, s, m, n, W, b, U, ldu, V, ldv, seed);
     }
     // the last product of the pass: H = W G
-    if (cx.group && W.W && !cx.single_stream) {
+    if (cx.group && W.W && !W.Wl && !cx.single_stream) {
         const WProduct pr = dense_wproduct<T>(w, W, m, n, false, w.VG + b, b2, b, w.PH + b, b2);
         cx.group->submit(&pr, &s, 1);
     } else {
