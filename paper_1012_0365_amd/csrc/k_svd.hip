@@ -1688,6 +1688,32 @@ __device__ __forceinline__ double readlane_f64(double x, int l)
                       (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l));
 }
 
+// Sums over the 64 lanes of sixteen values at once: lane c (c = lane % 16) of
+// every row ends with the total of v[c]. Reduce-scatter within each 16-lane
+// row (each level keeps the half of the remaining values that the lane's bit
+// selects and adds the partner's copy of it: DPP rotation by 8 pairs c with
+// c ^ 8, the half-row mirror pairs c with 7 - c across bit 2, quad
+// permutations pair c with c ^ 2 and c ^ 1), then the row and half sums
+// (the same bits in every lane of the index). 15 exchanges in place of
+// sixteen full reductions.
+__device__ __forceinline__ double lane_transpose_sum16(const double (&v)[16])
+{
+    const int c = threadIdx.x & 15;
+    const bool b3 = (c & 8) != 0, b2 = (c & 4) != 0, b1 = (c & 2) != 0, b0 = (c & 1) != 0;
+    double u[8], t[4], p2[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+        u[j] = (b3 ? v[j + 8] : v[j]) + dpp_move<0x128>(b3 ? v[j] : v[j + 8]);  // row_ror:8
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        t[j] = (b2 ? u[j + 4] : u[j]) + dpp_move<0x141>(b2 ? u[j] : u[j + 4]);  // row_half_mirror
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+        p2[j] = (b1 ? t[j + 2] : t[j]) + dpp_move<0x4E>(b1 ? t[j] : t[j + 2]);  // quad_perm [2,3,0,1]
+    const double r = (b0 ? p2[1] : p2[0]) + dpp_move<0xB1>(b0 ? p2[0] : p2[1]);  // quad_perm [1,0,3,2]
+    return halves_sum(rows_pair_sum(r));
+}
+
 // QR of an H x 16 panel held by ONE wavefront: lane l owns rows l + 64 r
 // (r < R). On return P holds the reflector vectors below the diagonal
 // (column q, rows > q), the triangular factor on and above it, tau[q] the
@@ -1714,16 +1740,34 @@ __device__ __forceinline__ void panel_qr_wave(int H, double (&P)[R][TS_NB], doub
             const int i = lane + 64 * r;
             y[r] = (i == q) ? 1.0 : ((i > q && i < H) ? P[r][q] * sc : 0.0);
         }
+        // the trailing columns' dot products, then their sums: one transposed
+        // sum of all sixteen while the panel is short (R <= 4; with more rows
+        // per lane the sixteen partial sums beside the panel exceed the
+        // registers), else one full reduction per column
         double w[TS_NB];
+        if constexpr (R <= 4) {
 #pragma unroll
-        for (int c = q + 1; c < TS_NB; ++c) {
-            double p = 0.0;
+            for (int c = 0; c < TS_NB; ++c) {
+                double p = 0.0;
+                if (c > q)
 #pragma unroll
-            for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
-            w[c] = p;
+                    for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
+                w[c] = p;
+            }
+            const double wsum = lane_transpose_sum16(w);
+#pragma unroll
+            for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * readlane_f64(wsum, c);
+        } else {
+#pragma unroll
+            for (int c = q + 1; c < TS_NB; ++c) {
+                double p = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
+                w[c] = p;
+            }
+#pragma unroll
+            for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * wave_sum64(w[c]);
         }
-#pragma unroll
-        for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * wave_sum64(w[c]);
 #pragma unroll
         for (int c = q + 1; c < TS_NB; ++c)
 #pragma unroll
@@ -1767,14 +1811,20 @@ __global__ __launch_bounds__(256) void ts_stage1_kernel(int N, int k0, int ntile
         return TRANS ? (size_t)(k0 + TS_NB + TS_NB * t + q) * N + (k0 + TS_NB + i)
                      : (size_t)(k0 + i) * N + (k0 + TS_NB + TS_NB * t + q);
     };
-    // panel into Ys and the tile into Xs by all four wavefronts (row-major
-    // panel: 16 consecutive doubles per row; transposed: along the rows)
+    // the panel into Ys by all four wavefronts (row-major panel: 16
+    // consecutive doubles per row; transposed: along the rows); the tile into
+    // Xs by wavefronts 1-3 while wavefront 0 factorises the panel
     for (int e = tid; e < H * TS_NB; e += 256) {
         const int i = TRANS ? e % H : e >> 4, q = TRANS ? e / H : e & 15;
         Ys[i][q] = A[pidx(i, q)];
-        if (has_tile) Xs[i][q] = A[tidx(i, q)];
     }
     __syncthreads();
+    if (wave != 0 && has_tile) {
+        for (int e = tid - 64; e < H * TS_NB; e += 192) {
+            const int i = TRANS ? e % H : e >> 4, q = TRANS ? e / H : e & 15;
+            Xs[i][q] = A[tidx(i, q)];
+        }
+    }
     if (wave == 0) {
         double P[R][TS_NB];
 #pragma unroll
@@ -1844,19 +1894,27 @@ __global__ __launch_bounds__(256) void ts_stage1_kernel(int N, int k0, int ntile
         Ws[p][c] = ((Wp[0][p][c] + Wp[1][p][c]) + Wp[2][p][c]) + Wp[3][p][c];
     }
     __syncthreads();
-    // T (forward, columnwise): T[q][q] = tau_q, T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q]
+    // T of the block reflector I - Y T Y^T (upper triangular): T^{-1} =
+    // diag(1 / tau) + (strictly upper part of G = Y^T Y), so lane j of
+    // wavefront 0 finds column j by back-substitution, x_j = tau_j and
+    // x_i = -tau_i sum_{k > i} G[i][k] x_k for i < j (no division; a zero tau
+    // gives a zero column, the identity reflector). The same T as the
+    // column-by-column recurrence T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q].
     if (wave == 0) {
-        for (int q = 0; q < TS_NB; ++q) {
-            const double tq = taus[q];
-            double v = 0.0;
-            if (lane < q) {
-                for (int r = lane; r < q; ++r) v += Tm[lane][r] * Gs[r][q];
-                v *= -tq;
+        if (lane < TS_NB) {
+            double x[TS_NB];
+#pragma unroll
+            for (int i = TS_NB - 1; i >= 0; --i) {
+                double acc = 0.0;
+#pragma unroll
+                for (int k = i + 1; k < TS_NB; ++k) acc = fma(Gs[i][k], x[k], acc);
+                x[i] = lane == i ? taus[i] : (lane > i ? -taus[i] * acc : 0.0);
             }
-            if (lane < TS_NB) Tm[lane][q] = lane < q ? v : (lane == q ? tq : 0.0);
-            __builtin_amdgcn_s_waitcnt(0);
-            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int i = 0; i < TS_NB; ++i) Tm[i][lane] = x[i];
         }
+        __builtin_amdgcn_s_waitcnt(0);
+        __builtin_amdgcn_wave_barrier();
         if (blockIdx.x == 0)
             for (int e = lane; e < TS_NB * TS_NB; e += 64) Tblk[e] = Tm[e >> 4][e & 15];
     }
@@ -2043,58 +2101,74 @@ __global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __
 
 // Back-transformation through the stage-2 reflectors: X <- H_1 ... H_T X for
 // the first nv columns of UB (left reflectors u, side 0) or VB (right
-// reflectors v, side 1), the last slot first; grid (ceil(nv / 4), 2), one
-// wavefront per column (kept in LDS), its four 16-lane groups applying the
-// tasks of one slot (disjoint rows) four at a time. The reflectors of
-// TS_BCH slots at a time are staged in LDS by the whole workgroup (slot t's
-// task i at [t - t0][i - lo(t)]).
-constexpr int TS_BCH = 32;
-__global__ __launch_bounds__(256) void ts_back2_kernel(int N, int nv, const double* __restrict__ rec,
+// reflectors v, side 1), H_1 .. H_T in the order stage 2 ran them. The
+// reflectors of one sweep act on disjoint 16-row blocks, and any two that
+// share rows ran in sweep order (task (i, j) in slot 2 i + j, and a task
+// (i', j') with i' > i overlapping it has j' >= j - 1), so the product is
+// applied one sweep at a time, the last sweep first: N - 1 dependent steps,
+// each with all blocks of the sweep at once. grid (ceil(nv / TS_BCOL), 2): a
+// workgroup holds TS_BCOL columns in LDS; its sixteen 16-lane groups take the
+// (block, column) pairs of a sweep in turn, the next sweep's reflector
+// entries loading into registers meanwhile.
+constexpr int TS_BCOL = 4, TS_BROUNDS = 7;
+static_assert(((TS_MAXN - 2) / TS_NB + 1) * TS_BCOL <= 16 * TS_BROUNDS,
+              "a sweep's (block, column) pairs must fit the rounds");
+__global__ __launch_bounds__(256) void ts_back3_kernel(int N, int nv, const double* __restrict__ rec,
                                                        double* __restrict__ UB,
                                                        double* __restrict__ VB, int ld)
 {
-    __shared__ double xs[4][TS_MAXN];
-    __shared__ double hs[TS_BCH][TS_NB][TS_NB + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, l = lane & 15;
-    const int side = blockIdx.y, col = blockIdx.x * 4 + wave;
+    __shared__ double xs[TS_BCOL][TS_MAXN];
+    const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
+    const int side = blockIdx.y, col0 = blockIdx.x * TS_BCOL;
+    const int ncol = min(TS_BCOL, nv - col0);
     double* X = side == 0 ? UB : VB;
     const int hoff = side == 0 ? 17 : 0;
-    const bool act = col < nv;  // uniform per wavefront
-    if (act)
-        for (int i = lane; i < N; i += 64) xs[wave][i] = X[(size_t)i * ld + col];
+    for (int e = tid; e < ncol * N; e += 256) {
+        const int c = e / N, i = e - c * N;
+        xs[c][i] = X[(size_t)i * ld + col0 + c];
+    }
     const int jmax = ts_jmax(N);
-    const int nslot = max(2 * (N - 2), jmax - 1) + 1;
-    auto lo_of = [&](int t) { return max(0, (t - jmax + 2) >> 1); };
-    for (int t1 = nslot - 1; t1 >= 0; t1 -= TS_BCH) {
-        const int t0 = max(0, t1 - TS_BCH + 1);
-        __syncthreads();  // the previous chunk's reflectors are no longer read
-        for (int e = tid; e < (t1 - t0 + 1) * TS_NB * (TS_NB + 1); e += 256) {
-            const int ts = e / (TS_NB * (TS_NB + 1)), rem = e - ts * (TS_NB * (TS_NB + 1));
-            const int k = rem / (TS_NB + 1), c = rem - k * (TS_NB + 1);
-            const int t = t0 + ts, i = lo_of(t) + k, j = t - 2 * i;
-            const bool ok = i <= min(t >> 1, N - 2) && j >= 0 && j < ts_nsteps(N, i);
-            hs[ts][k][c] = ok ? rec[((size_t)i * jmax + j) * TS_REC + hoff + c] : 0.0;
+    // round r of a sweep: unit u = grp + 16 r, block u / TS_BCOL, column u % TS_BCOL
+    double hn[TS_BROUNDS], tn[TS_BROUNDS];
+    auto fetch = [&](int i) {
+        const int ns = ts_nsteps(N, i);
+#pragma unroll
+        for (int r = 0; r < TS_BROUNDS; ++r) {
+            const int u = grp + 16 * r, j = u / TS_BCOL;
+            const bool ok = j < ns && u % TS_BCOL < ncol;
+            const double* rr = rec + ((size_t)i * jmax + (ok ? j : 0)) * TS_REC + hoff;
+            hn[r] = ok ? rr[l] : 0.0;
+            tn[r] = ok ? rr[TS_NB] : 0.0;
         }
-        __syncthreads();
-        if (!act) continue;
-        for (int t = t1; t >= t0; --t) {
-            const int hi = min(t >> 1, N - 2), lo = lo_of(t);
-            for (int i = hi - g; i >= lo; i -= 4) {  // uniform per 16-lane group
-                const int j = t - 2 * i;
-                if (j >= ts_nsteps(N, i)) continue;
+    };
+    fetch(N - 2);
+    __syncthreads();
+    for (int i = N - 2; i >= 0; --i) {
+        double h[TS_BROUNDS], tau[TS_BROUNDS];
+#pragma unroll
+        for (int r = 0; r < TS_BROUNDS; ++r) {
+            h[r] = hn[r];
+            tau[r] = tn[r];
+        }
+        if (i > 0) fetch(i - 1);
+        const int ns = ts_nsteps(N, i);
+#pragma unroll
+        for (int r = 0; r < TS_BROUNDS; ++r) {
+            const int u = grp + 16 * r, j = u / TS_BCOL, c = u % TS_BCOL;
+            if (j < ns && c < ncol) {  // uniform per 16-lane group
                 const int c0 = i + 1 + TS_NB * j;
                 const int L = min(TS_NB, N - c0);
-                const double* hr = hs[t - t0][i - lo];
-                const double h = hr[l], tau = hr[TS_NB];
-                const double xv = l < L ? xs[wave][c0 + l] : 0.0;
-                const double dt = tau * row_sum16(h * xv);
-                if (l < L) xs[wave][c0 + l] = xv - dt * h;
+                const double xv = l < L ? xs[c][c0 + l] : 0.0;
+                const double dt = tau[r] * row_sum16(h[r] * xv);
+                if (l < L) xs[c][c0 + l] = xv - dt * h[r];
             }
         }
+        lds_barrier();  // LDS only: the next sweep's loads stay in flight
     }
-    if (act)
-        for (int i = lane; i < N; i += 64) X[(size_t)i * ld + col] = xs[wave][i];
+    for (int e = tid; e < ncol * N; e += 256) {
+        const int c = e / N, i = e - c * N;
+        X[(size_t)i * ld + col0 + c] = xs[c][i];
+    }
 }
 
 }  // namespace
@@ -2181,8 +2255,8 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         {
             TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
             const int blocks = (nv + 3) / 4;
-            hipLaunchKernelGGL(ts_back2_kernel, dim3(blocks, 2), dim3(256), 0, s, N, nv, rec, UB, VB,
-                               N);
+            hipLaunchKernelGGL(ts_back3_kernel, dim3((nv + TS_BCOL - 1) / TS_BCOL, 2), dim3(256), 0,
+                               s, N, nv, rec, UB, VB, N);
             if (N <= BT_MAXN)
                 hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0,
                                    s, N, nv, VL, VR, Tall, UB, VB, N, TS_NB);
