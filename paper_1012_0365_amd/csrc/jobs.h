@@ -33,6 +33,9 @@ struct Job {
     bool done = false;
     int status = BLWS_OK;
     blws_solve_info info{};
+    // set by a tick that queued work after its readback: the readback is
+    // complete once this event is (else once the stream is idle)
+    hipEvent_t readback_done = nullptr;
 };
 
 // Wait for the work queued on s by polling it: a blocking wait can add a
@@ -47,15 +50,44 @@ inline void poll_stream(hipStream_t s)
     }
 }
 
+inline void poll_event(hipEvent_t e)
+{
+    for (;;) {
+        const hipError_t r = hipEventQuery(e);
+        if (r == hipSuccess) return;
+        if (r != hipErrorNotReady) HIP_TRY(r);
+        std::this_thread::yield();
+    }
+}
+
 inline void run_blocking(Job& job, Context& cx, hipStream_t s)
 {
     const auto t0 = std::chrono::steady_clock::now();
     cx.fix_calls = 0;
     cx.fix_calls_aux = 0;
     cx.ensure(job.workspace_bytes());
+    // the solve may queue work ahead of its readbacks: off again on every
+    // exit, and nothing of it left running (an error can end the loop early)
+    struct Spec {
+        Context& cx;
+        hipStream_t s;
+        Spec(Context& c, hipStream_t st) : cx(c), s(st)
+        {
+            cx.speculate = !cx.single_stream && !cx.group;
+        }
+        ~Spec()
+        {
+            cx.speculate = false;
+            (void)hipStreamSynchronize(s);
+        }
+    } spec(cx, s);
     job.start(cx, s);
     while (!job.done) {
-        poll_stream(s);
+        if (job.readback_done)
+            poll_event(job.readback_done);
+        else
+            poll_stream(s);
+        job.readback_done = nullptr;
         job.advance(cx, s);
     }
     HIP_TRY(hipStreamSynchronize(s));
@@ -98,12 +130,16 @@ struct RpcaJob : Job {
     // state
     enum Phase { NORMS, SPEC, ALM, REFINE, FINISH } phase = NORMS;
     double dnorm = 0.0, s1 = 0.0, prev = 0.0, mu = 0.0, mu_bar = 0.0, mu_next = 0.0;
-    double rel = INFINITY, rel_prev = INFINITY, eps = 0.0;
+    double rel = INFINITY, rel_prev = INFINITY, rel_old = INFINITY, eps = 0.0;
     int t = 0, sv = 0, b = 0, svp = 0, it = 0, iters_bf = 0, iters_x3 = 0, np = 0;
     // precision ladder: BF16 products (bf), then split-precision BF16 x 3
     // products (x3, when ladder3_tol > 0), then FP32; last_red: the last
     // iterate came from reduced-precision products
     bool bf = false, x3 = false, x3_on = false, last_red = false, refined = false;
+    // the next iteration's products already queued (after the readback) for
+    // block width spec_b and products in BF16 (spec_bf) or BF16 x 3 (spec_x3)
+    bool spec = false, spec_bf = false, spec_x3 = false;
+    int spec_b = 0, prev_b = 0;
 
     RpcaJob(int m_, int n_, const T* D_, int ldd_, double lambda_, const blws_alm_opts& o_, T* A_,
             int lda_, T* E_, int lde_, bool ladder_)
@@ -185,6 +221,11 @@ struct RpcaJob : Job {
     void queue_iteration(Context& cx, hipStream_t s, bool refine)
     {
         eps = 1.0 / mu;
+        // the products queued ahead are this iteration's when the width and
+        // the product precision came out as assumed
+        const bool have = spec && !refine && !abl && block_width(sv, o, p) == spec_b &&
+                          spec_b == b && bf == spec_bf && (!bf && x3) == spec_x3;
+        spec = false;
         if (!refine) {
             const int bn = block_width(sv, o, p);
             const Op<T> opW0{Wb, n, nullptr, nullptr};
@@ -194,6 +235,7 @@ struct RpcaJob : Job {
                 grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)it);
                 grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)it + 1);
             }
+            prev_b = b;
             b = bn;
             last_red = bf || x3;
             iters_bf += bf ? 1 : 0;
@@ -202,14 +244,17 @@ struct RpcaJob : Job {
         const bool use_bf = !refine && bf, use_x3 = !refine && !bf && x3;
         const Op<T> opW{Wb, n, nullptr, (use_bf || use_x3) ? Wh : nullptr,
                         use_x3 ? Wl : nullptr};
+        bool lz = false;
         if constexpr (std::is_same<T, double>::value) {
-            if (abl)
+            if (abl) {
                 lanczos_step(cx, lw, s, m, n, opW, eps, b, o.svt_start, o.k_blocks, U, bmax, V,
                              bmax, S, rank_dev, o.seed);
-            else
-                svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
-        } else {
-            svt_step<T>(cx, w, s, m, n, opW, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
+                lz = true;
+            }
+        }
+        if (!lz) {
+            if (!have) svt_step_products<T>(cx, w, s, m, n, opW, b, U, bmax, V, bmax, o.seed);
+            svt_step_finish<T>(cx, w, s, m, n, eps, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         }
         mu_next = next_mu(o, mu, mu_bar);
         // the copies the next iteration's products may read
@@ -217,6 +262,28 @@ struct RpcaJob : Job {
                         Y, E, lde, Wb, (use_bf || use_x3) ? Wh : nullptr, (T*)nullptr, 0, part, s,
                         ((use_bf || use_x3) && x3_on) ? Wl : nullptr);
         queue_readback(cx, s);
+        // While the host reads this iteration's result, the GPU can already
+        // run the next one's products: they read W, U and V as this iteration
+        // leaves them and write only the step's scratch, so they are simply
+        // queued again when the result changes the width or the precision
+        // (or are left unused when the solve stops).
+        // Only where it is likely to be used: the width unchanged since the
+        // last iteration (the rank rule has settled) and, by the residual's
+        // last ratio, neither a stop nor a precision switch expected next.
+        const double guess = rel_old > 0.0 && std::isfinite(rel_old) ? rel * (rel / rel_old) : rel;
+        const bool likely = b == prev_b && guess >= o.tol && !(bf && guess < o.ladder_tol) &&
+                            !(!bf && x3 && guess < o.ladder3_tol);
+        if (cx.speculate && !abl && !refine && likely) {
+            if (!cx.ev_rb) HIP_TRY(hipEventCreateWithFlags(&cx.ev_rb, hipEventDisableTiming));
+            HIP_TRY(hipEventRecord(cx.ev_rb, s));
+            readback_done = cx.ev_rb;
+            const Op<T> opN{Wb, n, nullptr, (bf || x3) ? Wh : nullptr, (!bf && x3) ? Wl : nullptr};
+            svt_step_products<T>(cx, w, s, m, n, opN, b, U, bmax, V, bmax, o.seed);
+            spec = true;
+            spec_b = b;
+            spec_bf = bf;
+            spec_x3 = !bf && x3;
+        }
     }
 
     void queue_finish(Context& cx, hipStream_t s)
@@ -297,6 +364,7 @@ struct RpcaJob : Job {
                     bf = false;
                     x3 = x3_on && rel >= o.ladder3_tol;
                 }
+                rel_old = rel_prev;
                 rel_prev = rel;
                 if (rel < o.tol) {
                     if (last_red) {

@@ -221,6 +221,11 @@ struct Context {
     hipStream_t aux = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     std::unique_ptr<AuxWorker> worker;  // issues the second stream's launches
+    // a blocking solve may queue the next iteration's products before the
+    // host has read the current one's result (see RpcaJob); ev_rb marks the
+    // end of the readback it then waits for
+    bool speculate = false;
+    hipEvent_t ev_rb = nullptr;
 
     void ensure_aux()
     {
@@ -239,9 +244,10 @@ struct Context {
         }
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
+        if (ev_rb) (void)hipEventDestroy(ev_rb);
         if (aux) (void)hipStreamDestroy(aux);
         aux = nullptr;
-        ev_fork = ev_join = nullptr;
+        ev_fork = ev_join = ev_rb = nullptr;
     }
     // cx.aux waits for the work queued so far on s
     void fork(hipStream_t s)
@@ -659,10 +665,13 @@ void svt_step_pair1_two_streams(Context& cx, StepWs<T>& w, hipStream_t s, int m,
 // Rayleigh-Ritz matrix on the two blocks is, up to a permutation,
 // [[0, B], [B^T, 0]] with B = [U, F]^T W [V, G] = [U, F]^T [W V, W G], whose
 // SVD gives the Ritz values and vectors.
+//
+// In two parts: the products (the new blocks and B, written to the step's
+// scratch only; U and V are read) and the rest (SVD of B, Ritz vectors into
+// U and V, S, the count above eps).
 template <typename T>
-void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
-              double eps, int b, T* U, int ldu, T* V, int ldv, double* S, int* rank_dev,
-              uint64_t seed)
+void svt_step_products(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
+                       int b, const T* U, int ldu, const T* V, int ldv, uint64_t seed)
 {
     Timer* tm = &cx.timer;
     const int b2 = 2 * b;
@@ -688,6 +697,14 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     // B = [U, F]^T [P, H] in FP64
     gemm<T, T, double>(tm, "gemm_ts", true, b2, b2, m, 1.0, w.UF, b2, w.PH, b2, 0.0,
                        (const double*)nullptr, 0, w.Bm, b2, w.partial, w.partial_elems, s);
+}
+
+template <typename T>
+void svt_step_finish(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, double eps, int b,
+                     T* U, int ldu, T* V, int ldv, double* S, int* rank_dev, uint64_t seed)
+{
+    Timer* tm = &cx.timer;
+    const int b2 = 2 * b;
     {
         const OrthWs<double> ow{w.D1, w.D2, w.Cp, w.Gr, w.Ri, w.chol, w.partial,
                                 w.partial_elems, w.flags, w.nflag};
@@ -710,6 +727,15 @@ void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T
     }
     copy2d<double, double>(1, b, w.Sall, b2, S, b, s);
     if (rank_dev) count_above(b, S, eps, rank_dev, s);
+}
+
+template <typename T>
+void svt_step(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, const Op<T>& W,
+              double eps, int b, T* U, int ldu, T* V, int ldv, double* S, int* rank_dev,
+              uint64_t seed)
+{
+    svt_step_products<T>(cx, w, s, m, n, W, b, U, ldu, V, ldv, seed);
+    svt_step_finish<T>(cx, w, s, m, n, eps, b, U, ldu, V, ldv, S, rank_dev, seed);
 }
 
 // Cold block: V = orth(random n x b) refined by pow_steps power half-step
