@@ -139,6 +139,19 @@ void chol_inv(Timer* tm, int n, const double* G, int ldg, double* Rinv, int* fla
               int* nflag, double eta, double ni_tol, double* scratch, hipStream_t s);
 size_t chol_scratch_elems(int n);
 
+// The columns j of Q (rows x c, ldq, c <= 128) with flags0[j] or flags1[j]
+// set (the dependent columns of a chunk's two Cholesky-QR passes, zero in Q)
+// re-formed from src (the chunk as the first pass saw it, lds) by classical
+// Gram-Schmidt with reorthogonalisation against Xa (rows x ba), Xb (rows x bb)
+// and the finished columns of Q, normalised; a column in that span to
+// rounding is replaced by the draws uniform_pm1(seed, (sid << 40) + 4096 i +
+// j) orthogonalised the same way. xv: rows doubles of scratch. nflag += the
+// columns flagged by the second pass only. No work when nothing is flagged.
+template <typename T>
+void orth_fallback(Timer* tm, int rows, int c, const int* flags0, const int* flags1, const T* src,
+                   int lds, T* Q, int ldq, const T* Xa, int lda, int ba, const T* Xb, int ldb,
+                   int bb, double* xv, int* nflag, uint64_t seed, uint64_t sid, hipStream_t s);
+
 // Two Cholesky-QR passes on X0 and X1 (rows x c each, leading dimension ld,
 // rows <= 512, c <= 128) in place, one workgroup per matrix: dependent
 // columns of the first pass redrawn (stream ids sid0, sid1), counted in nflag.

@@ -444,8 +444,9 @@ int blws_small_svd_f64(blws_ctx ctx, void* stream, int N, const double* B, int l
         w.Gr = c.take<double>((size_t)N * N);
         w.Ri = c.take<double>((size_t)N * N);
         w.chol = c.take<double>(blws::chol_scratch_elems(N) + 1);
-        w.flags = c.take<int>((size_t)N);
+        w.flags = c.take<int>((size_t)2 * N);
         w.nflag = c.take<int>(4);
+        w.xv = c.take<double>((size_t)N);
         size_t pe = blws::gemm_partial_elems(N, N, N);
         w.partial_elems = pe;
         w.partial = c.take<double>(pe + 1);

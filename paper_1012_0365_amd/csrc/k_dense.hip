@@ -553,6 +553,171 @@ __global__ void count_above_kernel(int b, const double* S, double eps, int* out)
     if (threadIdx.x == 0) out[0] = cnt;
 }
 
+// ---------------------------------------------------------------------------
+// Columns of a Cholesky-QR block that the Gram matrix cannot resolve.
+//
+// A column whose scaled pivot is <= eta (the squared sine of the angle between
+// the column and the span of the ones before it) is known to the Gram matrix
+// only to about c u / sin^2, so the Cholesky-QR passes give it a zero column.
+// This pass re-forms each such column j from the vectors themselves: x_j as
+// the first pass saw it is orthogonalised by classical Gram-Schmidt against
+// the blocks the chunk is projected out of and against every finished column
+// of the result, the pass repeated while it removes more than half of the
+// norm squared (at most three: "twice is enough" with Kahan's test), and
+// normalised. Its direction is then accurate to about u / sin, so the span of
+// the result holds x_j to rounding, as a Householder QR of the block would.
+// When the residual is below keep_tol |x_j| (x_j in the span to rounding:
+// exact breakdown), the counter-based draws uniform_pm1(seed, (sid << 40) +
+// 4096 i + j) take the column's place and are orthogonalised the same way.
+// One workgroup; it returns at once when no column is flagged.
+// ---------------------------------------------------------------------------
+constexpr int FB_MAXW = 2048;  // widest basis [Xa, Xb, Q] the pass handles
+
+// sum over the workgroup of one value per wavefront (the same in all its
+// lanes); every thread adds the 16 partial sums in the same order
+__device__ __forceinline__ double fb_wave_total(double v, double* red)
+{
+    const int tid = threadIdx.x;
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += red[w];
+    return t;
+}
+
+__device__ __forceinline__ double fb_wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void orth_fallback_kernel(
+    int rows, int c, const int* __restrict__ flags0, const int* __restrict__ flags1,
+    const T* __restrict__ src, int lds, T* Q, int ldq, const T* __restrict__ Xa, int lda, int ba,
+    const T* __restrict__ Xb, int ldb, int bb, double* xv, int* nflag, double keep_tol,
+    uint64_t seed, uint64_t sid)
+{
+    __shared__ double coef[FB_MAXW];
+    __shared__ double xs[1024];
+    __shared__ double red[16];
+    __shared__ int fl[128];  // 1: a column still to re-form; 0: a finished column
+    __shared__ int nfl, nnew;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid == 0) {
+        nfl = 0;
+        nnew = 0;
+    }
+    __syncthreads();
+    if (tid < c) {
+        const int f0 = flags0[tid] != 0, f1 = flags1[tid] != 0;
+        fl[tid] = f0 | f1;
+        if (f0 | f1) atomicAdd(&nfl, 1);
+        if (f1 && !f0) atomicAdd(&nnew, 1);  // the first pass counted its own
+    }
+    __syncthreads();
+    if (nfl == 0) return;
+    if (tid == 0 && nnew) atomicAdd(nflag, nnew);
+    const int W = ba + bb + c;
+    // basis column k: Xa (k < ba), Xb (k < ba + bb), then the chunk's columns
+    auto column = [&](int k, const T*& p, int& ld) -> bool {
+        if (k < ba) {
+            p = Xa + k;
+            ld = lda;
+            return true;
+        }
+        if (k < ba + bb) {
+            p = Xb + (k - ba);
+            ld = ldb;
+            return true;
+        }
+        if (k < W) {
+            p = Q + (k - ba - bb);
+            ld = ldq;
+            return !fl[k - ba - bb];
+        }
+        p = nullptr;
+        ld = 0;
+        return false;
+    };
+    for (int j = 0; j < c; ++j) {
+        if (!fl[j]) continue;  // uniform: LDS
+        double nn = 0.0;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            double n0 = 0.0;
+            for (int r = tid; r < rows; r += 1024) {
+                const double v =
+                    attempt == 0
+                        ? (double)src[(size_t)r * lds + j]
+                        : uniform_pm1(seed, (sid << 40) + (uint64_t)r * 4096ULL + (uint64_t)j);
+                xv[r] = v;
+                n0 += v * v;
+            }
+            n0 = fb_wave_total(fb_wave_sum(n0), red);
+            double prev = n0;
+            nn = n0;
+            for (int pass = 0; pass < 3; ++pass) {
+                // coef[k] = (basis column k)^T x, zero for the columns left out
+                const T *p0, *p1;
+                int l0, l1;
+                const bool on0 = column(tid, p0, l0), on1 = column(tid + 1024, p1, l1);
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+                for (int r0 = 0; r0 < rows; r0 += 1024) {
+                    const int len = min(1024, rows - r0);
+                    __syncthreads();  // the previous chunk's readers are done
+                    if (tid < len) xs[tid] = xv[r0 + tid];
+                    __syncthreads();
+                    if (on0) {
+                        int t = 0;
+                        for (; t + 1 < len; t += 2) {
+                            a0 += (double)p0[(size_t)(r0 + t) * l0] * xs[t];
+                            a1 += (double)p0[(size_t)(r0 + t + 1) * l0] * xs[t + 1];
+                        }
+                        if (t < len) a0 += (double)p0[(size_t)(r0 + t) * l0] * xs[t];
+                    }
+                    if (on1) {
+                        int t = 0;
+                        for (; t + 1 < len; t += 2) {
+                            a2 += (double)p1[(size_t)(r0 + t) * l1] * xs[t];
+                            a3 += (double)p1[(size_t)(r0 + t + 1) * l1] * xs[t + 1];
+                        }
+                        if (t < len) a2 += (double)p1[(size_t)(r0 + t) * l1] * xs[t];
+                    }
+                }
+                if (tid < W) coef[tid] = on0 ? a0 + a1 : 0.0;
+                if (tid + 1024 < W) coef[tid + 1024] = on1 ? a2 + a3 : 0.0;
+                __syncthreads();
+                // x <- x - B coef, one row per wavefront at a time
+                double wn = 0.0;
+                for (int r = wave; r < rows; r += 16) {
+                    double a = 0.0;
+                    for (int k = lane; k < ba; k += 64) a += coef[k] * (double)Xa[(size_t)r * lda + k];
+                    for (int k = lane; k < bb; k += 64)
+                        a += coef[ba + k] * (double)Xb[(size_t)r * ldb + k];
+                    for (int k = lane; k < c; k += 64)
+                        a += coef[ba + bb + k] * (double)Q[(size_t)r * ldq + k];
+                    a = fb_wave_sum(a);
+                    const double x = xv[r] - a;
+                    if (lane == 0) xv[r] = x;
+                    wn += x * x;
+                }
+                nn = fb_wave_total(wn, red);
+                const bool enough = nn > 0.5 * prev;
+                prev = nn;
+                if (enough) break;
+            }
+            if (nn > keep_tol * keep_tol * n0) break;  // attempt 1: a draw, kept as it is
+        }
+        const double inv = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+        for (int r = tid; r < rows; r += 1024) Q[(size_t)r * ldq + j] = (T)(xv[r] * inv);
+        __syncthreads();
+        if (tid == 0) fl[j] = 0;
+        __syncthreads();
+    }
+}
+
 int grid_for(size_t total)
 {
     size_t b = (total + 255) / 256;
@@ -632,6 +797,29 @@ void count_above(int b, const double* S, double eps, int* rank_out, hipStream_t 
     hipLaunchKernelGGL(count_above_kernel, dim3(1), dim3(256), 0, s, b, S, eps, rank_out);
 }
 
+template <typename T>
+void orth_fallback(Timer* tm, int rows, int c, const int* flags0, const int* flags1, const T* src,
+                   int lds, T* Q, int ldq, const T* Xa, int lda, int ba, const T* Xb, int ldb,
+                   int bb, double* xv, int* nflag, uint64_t seed, uint64_t sid, hipStream_t s)
+{
+    if (rows <= 0 || c <= 0) return;
+    BLWS_REQUIRE(c <= 128 && ba + bb + c <= FB_MAXW && (ba == 0 || Xa) && (bb == 0 || Xb),
+                 BLWS_EUNSUPPORTED, "orth_fallback: block wider than the pass handles");
+    TimedLaunch tl(tm, "orth_fallback", s, 0.0, 0.0);
+    // below this relative residual the column lies in the span to the
+    // storage precision's rounding, and a draw takes its place
+    const double keep_tol = sizeof(T) == 4 ? 1e-6 : 1e-14;
+    hipLaunchKernelGGL((orth_fallback_kernel<T>), dim3(1), dim3(1024), 0, s, rows, c, flags0,
+                       flags1, src, lds, Q, ldq, Xa, lda, ba, Xb, ldb, bb, xv, nflag, keep_tol,
+                       seed, sid);
+}
+
+template void orth_fallback<double>(Timer*, int, int, const int*, const int*, const double*, int,
+                                    double*, int, const double*, int, int, const double*, int, int,
+                                    double*, int*, uint64_t, uint64_t, hipStream_t);
+template void orth_fallback<float>(Timer*, int, int, const int*, const int*, const float*, int,
+                                   float*, int, const float*, int, int, const float*, int, int,
+                                   double*, int*, uint64_t, uint64_t, hipStream_t);
 template void fill_uniform<double>(int, int, double*, int, uint64_t, uint64_t, hipStream_t);
 template void fill_uniform<float>(int, int, float*, int, uint64_t, uint64_t, hipStream_t);
 template void copy2d<double, double>(int, int, const double*, int, double*, int, hipStream_t);

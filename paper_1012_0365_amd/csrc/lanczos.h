@@ -36,7 +36,7 @@ inline int lz_cols(int start, int b) { return start == LZ_START_SPLIT ? 2 * b : 
 // Scratch of one literal block-Lanczos step (FP64).
 struct LanczosWs {
     double *Q, *WX, *R, *Sm, *Ms, *Bs, *Bt, *Tm, *shift, *UB, *VB, *Sall, *svd;
-    double *T1, *T2, *Cp, *Gr, *Ri, *chol, *partial, *D1, *D2;
+    double *T1, *T2, *Cp, *Gr, *Ri, *chol, *partial, *D1, *D2, *xv;
     int *flags, *nflag;
     size_t partial_elems;
 
@@ -64,7 +64,8 @@ struct LanczosWs {
         chol = cv.take<double>(chol_scratch_elems(w) + 1);
         D1 = cv.take<double>((size_t)K * w);
         D2 = cv.take<double>((size_t)K * w);
-        flags = cv.take<int>((size_t)w);
+        xv = cv.take<double>((size_t)N);
+        flags = cv.take<int>((size_t)2 * w);
         nflag = cv.take<int>(4);
         size_t pe = 0;
         const int shapes[][3] = {{m, c, n}, {n, c, m}, {c, c, m}, {N, c, c}, {c, c, N},
@@ -99,7 +100,7 @@ inline void lanczos_step(Context& cx, LanczosWs& w, hipStream_t s, int m, int n,
     Timer* tm = &cx.timer;
     const int N = m + n, c = lz_cols(start, b), K = k * c;
     const OrthWs<double> ow{w.T1, w.T2, w.Cp, w.Gr, w.Ri, w.chol, w.partial, w.partial_elems,
-                            w.flags, w.nflag};
+                            w.flags, w.nflag, w.xv};
     StepWs<double> pw{};  // op_apply reads only the split-K partials
     pw.partial = w.partial;
     pw.partial_elems = w.partial_elems;
@@ -148,7 +149,7 @@ inline void lanczos_step(Context& cx, LanczosWs& w, hipStream_t s, int m, int n,
     lanczos_assemble(k, c, w.Ms, w.Bs, w.shift, w.Tm, s);
     {
         const OrthWs<double> sw{w.D1, w.D2, w.Cp, w.Gr, w.Ri, w.chol, w.partial, w.partial_elems,
-                                w.flags, w.nflag};
+                                w.flags, w.nflag, w.xv};
         small_svd_dispatch(cx, s, K, b, w.Tm, K, w.UB, w.Sall, w.VB, w.svd, sw, seed);
     }
     lanczos_eigvals(b, w.Sall, w.shift, S, s);

@@ -286,13 +286,13 @@ namespace {
 template <typename T>
 struct StepWs {
     T *UF, *PH, *VG, *Qb, *T1, *T2, *R;
-    double *Cp, *Gr, *Ri, *Bm, *UB, *VB, *Sall, *svd, *chol, *partial, *D1, *D2;
+    double *Cp, *Gr, *Ri, *Bm, *UB, *VB, *Sall, *svd, *chol, *partial, *D1, *D2, *xv;
     int *flags, *nflag;
     size_t partial_elems;
     // the same orthonormalisation scratch and split-K partials again, for work
     // on the second stream (the breakdown counter nflag is shared: atomic)
     T *T1b, *T2b;
-    double *Cpb, *Grb, *Rib, *cholb, *partialb;
+    double *Cpb, *Grb, *Rib, *cholb, *partialb, *xvb;
     int* flagsb;
 
     // second_set = false leaves out the scratch of the second stream (the
@@ -318,7 +318,8 @@ struct StepWs {
         D1 = c.take<double>((size_t)b2 * b);
         D2 = c.take<double>((size_t)b2 * b);
         chol = c.take<double>(chol_scratch_elems(b) + 1);
-        flags = c.take<int>((size_t)b);
+        xv = c.take<double>((size_t)mx);
+        flags = c.take<int>((size_t)2 * b);
         nflag = c.take<int>(4);
         size_t pe = 0;
         const int shapes[][3] = {{m, b, n},  {n, b, m},   {b, b, m},  {b, b, n},
@@ -335,7 +336,7 @@ struct StepWs {
         partial = c.take<double>(pe + 1);
         if (!second_set) {
             T1b = T2b = nullptr;
-            Cpb = Grb = Rib = cholb = partialb = nullptr;
+            Cpb = Grb = Rib = cholb = partialb = xvb = nullptr;
             flagsb = nullptr;
             return;
         }
@@ -345,7 +346,8 @@ struct StepWs {
         Grb = c.take<double>((size_t)b * b);
         Rib = c.take<double>((size_t)b * b);
         cholb = c.take<double>(chol_scratch_elems(b) + 1);
-        flagsb = c.take<int>((size_t)b);
+        xvb = c.take<double>((size_t)mx);
+        flagsb = c.take<int>((size_t)2 * b);
         partialb = c.take<double>(pe + 1);
     }
 
@@ -361,6 +363,7 @@ struct StepWs {
         v.Ri = Rib;
         v.chol = cholb;
         v.flags = flagsb;
+        v.xv = xvb;
         v.partial = partialb;
         return v;
     }
@@ -368,13 +371,15 @@ struct StepWs {
 
 // Scratch of one orthonormalisation: T1, T2 (rows x 128), Cp (b x 128, b the
 // widest block projected against), Gr, Ri (128 x 128), the Cholesky scratch,
-// the breakdown flags (nflag[0] counts them) and the split-K partials.
+// the breakdown flags of the two passes (2 x 128; nflag[0] counts them), the
+// split-K partials and one column of rows doubles for the fallback pass.
 template <typename T>
 struct OrthWs {
     T *T1, *T2;
     double *Cp, *Gr, *Ri, *chol, *partial;
     size_t partial_elems;
     int *flags, *nflag;
+    double* xv;
 };
 
 constexpr int ORTH_CHUNK = 128;  // widest Cholesky-QR block (register Cholesky)
@@ -405,8 +410,11 @@ void project_out(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int n
 
 // One block of at most ORTH_CHUNK columns: project In out of the X blocks,
 // then two Cholesky-QR passes, the X blocks projected out again between them.
-// Columns found dependent in the first pass are replaced by counter-based
-// random draws, which the second projection and pass orthonormalise.
+// A column either pass finds dependent comes out of the passes as zero and is
+// re-formed from the vectors by the fallback pass (orth_fallback): classical
+// Gram-Schmidt with reorthogonalisation of the column as the first pass saw
+// it (kept in T1), or of counter-based draws where that column lies in the
+// span to rounding.
 template <typename T>
 void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx,
                 const T* const* X, const int* ldx, const int* bx, const T* In, int ldin, int c,
@@ -414,28 +422,26 @@ void orth_chunk(Context& cx, const OrthWs<T>& w, hipStream_t s, int rows, int nx
 {
     Timer* tm = &cx.timer;
     project_out<T>(cx, w, s, rows, nx, X, ldx, bx, In, ldin, w.T1, c);
-    T* cur = w.T1;
-    for (int pass = 0; pass < 2; ++pass) {
-        gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, cur, c, cur, c, 0.0,
-                           (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
-        chol_inv(tm, c, w.Gr, c, w.Ri, w.flags, w.nflag, CHOL_ETA, chol_ni_tol<T>(), w.chol, s);
-        if (pass == 1) {
-            gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, cur, c, w.Ri, c, 0.0,
-                               (const T*)nullptr, 0, Out, ldout, w.partial, w.partial_elems, s);
-        } else {
-            // T2 = cur R^{-1}, its dependent columns redrawn in the same launch;
-            // stream ids of the replacement draws: one sequence per stream
-            const uint64_t sid = s == cx.aux ? (1ULL << 21) + (++cx.fix_calls_aux)
-                                             : (1ULL << 20) + (++cx.fix_calls);
-            gemm_apply_flagged<T>(tm, rows, c, cur, c, w.Ri, c, w.T2, c, w.flags, seed, sid, s);
-            if (nx > 0) {
-                project_out<T>(cx, w, s, rows, nx, X, ldx, bx, w.T2, c, w.T1, c);
-                cur = w.T1;
-            } else {
-                cur = w.T2;
-            }
-        }
-    }
+    // pass 1: T2 = T1 R^{-1} (a dependent column has a zero column in R^{-1})
+    gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, w.T1, c, w.T1, c, 0.0,
+                       (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
+    chol_inv(tm, c, w.Gr, c, w.Ri, w.flags, w.nflag, CHOL_ETA, chol_ni_tol<T>(), w.chol, s);
+    gemm_apply_flagged<T>(tm, rows, c, w.T1, c, w.Ri, c, w.T2, c, (const int*)nullptr, 0, 0, s);
+    if (nx > 0) project_out<T>(cx, w, s, rows, nx, X, ldx, bx, w.T2, c, w.T2, c);
+    // pass 2 (its flags after the first pass's; its count goes to a spare slot)
+    gemm<T, T, double>(tm, "gemm_ts", true, c, c, rows, 1.0, w.T2, c, w.T2, c, 0.0,
+                       (const double*)nullptr, 0, w.Gr, c, w.partial, w.partial_elems, s);
+    chol_inv(tm, c, w.Gr, c, w.Ri, w.flags + c, w.nflag + 3, CHOL_ETA, chol_ni_tol<T>(), w.chol,
+             s);
+    gemm<T, double, T>(tm, "gemm_ts", false, rows, c, c, 1.0, w.T2, c, w.Ri, c, 0.0,
+                       (const T*)nullptr, 0, Out, ldout, w.partial, w.partial_elems, s);
+    // stream ids of the replacement draws: one sequence per stream
+    const uint64_t sid = s == cx.aux ? (1ULL << 21) + (++cx.fix_calls_aux)
+                                     : (1ULL << 20) + (++cx.fix_calls);
+    orth_fallback<T>(tm, rows, c, w.flags, w.flags + c, w.T1, c, Out, ldout,
+                     nx > 0 ? X[0] : (const T*)nullptr, nx > 0 ? ldx[0] : 0, nx > 0 ? bx[0] : 0,
+                     nx > 1 ? X[1] : (const T*)nullptr, nx > 1 ? ldx[1] : 0, nx > 1 ? bx[1] : 0,
+                     w.xv, w.nflag, seed, sid, s);
 }
 
 // Orthonormalise `In` (rows x c, ldin) against the orthonormal block X (rows x b0,
@@ -470,7 +476,7 @@ void orth_against(Context& cx, StepWs<T>& sw, hipStream_t s, int rows, int b0, c
                   int ldx, const T* In, int ldin, int c, T* Out, int ldout, uint64_t seed)
 {
     const OrthWs<T> w{sw.T1, sw.T2, sw.Cp, sw.Gr, sw.Ri, sw.chol, sw.partial, sw.partial_elems,
-                      sw.flags, sw.nflag};
+                      sw.flags, sw.nflag, sw.xv};
     orth_against<T>(cx, w, s, rows, b0, X, ldx, In, ldin, c, Out, ldout, seed);
 }
 
@@ -707,7 +713,7 @@ void svt_step_finish(Context& cx, StepWs<T>& w, hipStream_t s, int m, int n, dou
     const int b2 = 2 * b;
     {
         const OrthWs<double> ow{w.D1, w.D2, w.Cp, w.Gr, w.Ri, w.chol, w.partial,
-                                w.partial_elems, w.flags, w.nflag};
+                                w.partial_elems, w.flags, w.nflag, w.xv};
         small_svd_dispatch(cx, s, b2, b, w.Bm, b2, w.UB, w.Sall, w.VB, w.svd, ow, seed);
     }
     // Ritz vectors [U, F] U_B(:, 1:b), [V, G] V_B(:, 1:b), on the two streams

@@ -27,6 +27,7 @@ __all__ = [
     "gaussian",
     "orthonormal",
     "prescribed_spectrum",
+    "ill_conditioned_block",
     "sample_positions",
 ]
 
@@ -97,3 +98,30 @@ def sample_positions(m: int, n: int, count: int, seed: int) -> np.ndarray:
     """Seeded distinct flat positions used for sampled parity checks."""
     count = min(count, m * n)
     return np.sort(rng(seed).choice(m * n, size=count, replace=False))
+
+
+def ill_conditioned_block(m: int, n: int, b: int, kappa: float, side: str, seed: int) -> dict:
+    """A matrix W and a warm block (U, V) whose new Krylov block is
+    ill-conditioned without being singular.
+
+    W = X diag(sigma) Y^T (random orthonormal X, Y) with sigma_1 = 100, ten
+    values from 60 down to 40, a geometric tail from 20 and a last value
+    100 / kappa. side "V": V = [(y_1 + y_p) / sqrt(2), (y_1 - y_p) / sqrt(2),
+    y_2, .., y_{b-1}] and U random, so the first two columns of W V are
+    (sigma_1 x_1 +- sigma_p x_p) / sqrt(2): after the columns are scaled to
+    unit norm, the sine of the angle between them is about 2 / kappa (the
+    left block's condition number is about kappa). side "U": the same with
+    the roles of (U, x) and (V, y) exchanged. Every singular pair above 30 is
+    spanned by both halves of the block, so one step reaches them exactly."""
+    p = min(m, n)
+    sigma = np.r_[100.0, np.linspace(60.0, 40.0, 10), np.geomspace(20.0, 1e-2, p - 12),
+                  100.0 / kappa]
+    W, X, Y = prescribed_spectrum(m, n, sigma, seed)
+    pair = lambda Z: np.c_[(Z[:, 0] + Z[:, p - 1]) / np.sqrt(2.0),
+                           (Z[:, 0] - Z[:, p - 1]) / np.sqrt(2.0), Z[:, 1:b - 1]]
+    if side == "V":
+        U, V = orthonormal(m, b, seed + 1), pair(Y)
+    else:
+        U, V = pair(X), orthonormal(n, b, seed + 1)
+    return {"W": np.ascontiguousarray(W), "U": np.ascontiguousarray(U),
+            "V": np.ascontiguousarray(V), "sigma": sigma}

@@ -3,7 +3,8 @@
 Every request must compute exactly what the blocking solver computes for the
 same arguments, whatever else is in flight: results are compared bit for bit
 with solves run alone, with the W-products of solves stepping together in
-grouped launches and without. Also checked: solves overlap (more than one in flight),
+grouped launches and without, and each served result against the oracle's
+solve of the same problem. Also checked: solves overlap (more than one in flight),
 admission by the memory budget (a budget below one request's workspace runs
 them one at a time), per-request errors, argument checks at submission, and
 polling.
@@ -113,6 +114,59 @@ def test_mix_results_equal_solves_alone(torch, blws, mix, alone):
     assert st["grouped_launches"] > 0 and st["max_group"] >= 2
     assert st["grouped_products"] >= st["grouped_launches"]
     srv.close()
+
+
+def oracle_ref(req):
+    """The oracle's BLWS solve of a request on the values the GPU was given
+    (FP32 requests: their FP32-rounded entries, in FP64), with the library's
+    reading of the ||D||_2 estimate (at most 8 BLWS steps)."""
+    import oracle
+
+    if req[0] == "rpca":
+        return oracle.rpca(req[1].double().cpu().numpy(), mode="blws", norm_steps=8)
+    _, m, n, rp, ci, v = req
+    return oracle.mc(m, n, rp.cpu().numpy(), ci.cpu().numpy(), v.double().cpu().numpy(),
+                     mode="blws", norm_steps=8, **MC_OPTS)
+
+
+def test_served_results_match_oracle(torch, blws, mix):
+    """Each request as served (grouped launches, four in flight) against the
+    oracle's solve of the same problem. FP64 requests follow the oracle's
+    trajectory (same iterations and rank, rounding differences of two FP64
+    implementations only); FP32 and BF16-ladder RPCA requests end within the
+    FP32 bar of 1e-6 of it. The FP32 MC request (400 x 400, 15% sampled,
+    stopped at a relative residual of 1e-6) does not recover its planted rank
+    10: 91 values stay above the threshold, the smallest 0.04 against 442, and
+    over its 93 iterations FP32 rounding moves those near the threshold; it is
+    held to 1e-5, the bar of the other FP32 MC solves stopped at 1e-6."""
+    srv = blws.Server(0, max_slots=4)
+    tickets = [submit(srv, blws, r) for r in mix]
+    served = [srv.wait(t) for t in tickets]
+    srv.close()
+    for i, (req, res) in enumerate(zip(mix, served)):
+        ref = oracle_ref(req)
+        info = res[-1]
+        f64 = (req[1] if req[0] == "rpca" else req[5]).dtype == torch.float64
+        if req[0] == "rpca":
+            A = res[0].double().cpu().numpy()
+            A_or = ref["A"]
+            rank_or = ref["info"]["rank"]
+        else:
+            U, S, V = (x.double().cpu().numpy() for x in res[:3])
+            r = info["rank"]
+            A = (U[:, :r] * S[:r]) @ V[:, :r].T
+            A_or = (ref["U"] * ref["S"]) @ ref["V"].T
+            rank_or = ref["rank"]
+        err = np.linalg.norm(A - A_or) / np.linalg.norm(A_or)
+        print(f"request {i} {req[0]} {tuple(A.shape)} {'f64' if f64 else 'f32'}: iters "
+              f"{info['iters']} (oracle {ref['info']['iters']}), rank {info['rank']} "
+              f"({rank_or}), |A - A_oracle| / |A_oracle| {err:.2e}", flush=True)
+        assert info["status"] == ref["info"]["status"] == 0
+        if f64:
+            assert info["iters"] == ref["info"]["iters"] and info["rank"] == rank_or
+            assert err < 1e-8
+        else:
+            assert err < (1e-6 if req[0] == "rpca" else 1e-5)
 
 
 def test_mix_without_grouping_is_the_same(torch, blws, mix, alone):

@@ -123,10 +123,11 @@ def spectrum_w(m, n, r, seed):
 
 
 # The block widths the solvers run at: b = 112 (the projected matrix is
-# 224 x 224: the one-workgroup bidiagonalisation; one Cholesky-QR block) and
-# b = 208 (416 x 416: the cooperative bidiagonalisation; blocks wider than 128
-# columns, orthonormalised in two chunks with block Gram-Schmidt between them).
-WIDE = [(600, 560, 112, 100, 20.0), (1000, 900, 208, 200, 20.0)]
+# 224 x 224: the one-workgroup bidiagonalisation; one Cholesky-QR block),
+# b = 128 and b = 208 (256 x 256 and 416 x 416: the two-stage reduction; at
+# b = 208 blocks wider than 128 columns, orthonormalised in two chunks with
+# block Gram-Schmidt between them).
+WIDE = [(600, 560, 112, 100, 20.0), (600, 560, 128, 100, 20.0), (1000, 900, 208, 200, 20.0)]
 
 
 @pytest.mark.parametrize("m,n,b,r,eps", WIDE)
@@ -236,6 +237,36 @@ def test_svt_exact_warm_start_breakdown(torch, ctx):
     assert rg == rex
     assert np.linalg.norm(Ag - Aex) <= 1e-11 * np.linalg.norm(Aex)
     assert np.abs(Ug.T @ Ug - np.eye(b)).max() < 1e-12
+
+
+@pytest.mark.parametrize("side", ["V", "U"])
+@pytest.mark.parametrize("kappa", [1e4, 1e6, 1e8, 1e10, 1e12])
+def test_svt_ill_conditioned_krylov_block(torch, ctx, side, kappa):
+    """The new block F0 (side V) or G0 (side U) with condition number kappa
+    after column scaling, not singular. Up to kappa ~ 3e6 the two Cholesky-QR
+    passes keep the near-dependent pair; beyond it the first pass finds the
+    scaled pivot (about 4 / kappa^2) below 1e-13 and the fallback pass
+    re-forms that column from the vectors (Gram-Schmidt with
+    reorthogonalisation), so the block's span holds the pair to rounding as
+    the oracle's Householder QR does. Every singular pair above eps lies in
+    the span, so the values above eps, A and the retained subspaces are
+    those of W and the oracle's."""
+    c = synth.ill_conditioned_block(200, 180, 12, kappa, side, seed=11)
+    W, sig, eps = c["W"], c["sigma"], 30.0
+    gpu = run_gpu(torch, ctx, W, eps, c["U"], c["V"])
+    Ug, Vg, Sg, Ag, rg = gpu
+    Uo, Vo, So, Ao, ro = oracle.blws_step(W, eps, c["U"], c["V"])
+    print(f"ill-conditioned {side} kappa {kappa:.0e}: |dS|/s1 "
+          f"{np.abs(Sg[:rg] - sig[:rg]).max() / sig[0]:.1e}, |A - A_oracle| / |A_oracle| "
+          f"{np.linalg.norm(Ag - Ao) / np.linalg.norm(Ao):.1e}", flush=True)
+    assert rg == ro == 11
+    assert np.abs(Sg[:rg] - sig[:rg]).max() <= 1e-12 * sig[0]
+    assert np.abs(Sg[:rg] - So[:ro]).max() <= 1e-12 * sig[0]
+    assert np.linalg.norm(Ag - Ao) <= 1e-11 * np.linalg.norm(Ao)
+    assert np.abs(Ug.T @ Ug - np.eye(12)).max() < 1e-12
+    assert np.abs(Vg.T @ Vg - np.eye(12)).max() < 1e-12
+    assert np.abs(proj(Ug[:, :rg]) - proj(Uo[:, :ro])).max() < 1e-10
+    assert np.abs(proj(Vg[:, :rg]) - proj(Vo[:, :ro])).max() < 1e-10
 
 
 def test_svt_exactly_low_rank_w(torch, ctx):

@@ -252,6 +252,25 @@ def test_blws_rank_deficient_w():
     assert np.abs(Vn.T @ Vn - np.eye(6)).max() < 1e-12
 
 
+@pytest.mark.parametrize("side", ["V", "U"])
+@pytest.mark.parametrize("kappa", [1e8, 1e12])
+def test_blws_ill_conditioned_krylov_block(side, kappa):
+    """A new block with condition number kappa (not singular): every singular
+    pair above the threshold lies in both halves of the block, so the step's
+    values are the prescribed ones and A is T_eps(W) formed from the
+    prescribed factors, whatever the QR step does with the near-dependent pair."""
+    c = synth.ill_conditioned_block(200, 180, 12, kappa, side, seed=11)
+    W, sig = c["W"], c["sigma"]
+    Un, Vn, S, A, r = oracle.blws_step(W, 30.0, c["U"], c["V"])
+    assert r == 11
+    assert np.abs(S[:r] - sig[:r]).max() <= 1e-13 * sig[0]
+    _, X, Y = synth.prescribed_spectrum(200, 180, sig, seed=11)
+    A_def = (X[:, :r] * (sig[:r] - 30.0)) @ Y[:, :r].T
+    assert np.linalg.norm(A - A_def) <= 1e-12 * np.linalg.norm(A_def)
+    assert np.abs(Un.T @ Un - np.eye(12)).max() < 1e-13
+    assert np.abs(Vn.T @ Vn - np.eye(12)).max() < 1e-13
+
+
 def test_spectral_norm_by_blws():
     # a clear top gap: converged to rounding
     sigma = np.r_[10.0, np.linspace(8.0, 0.1, 59)]
