@@ -3,11 +3,12 @@
 //
 // 1. Golub-Kahan bidiagonalisation B = Q_L Bd Q_R^T. Up to N = 224 in ONE
 //    workgroup, B held in registers: a 32 x 16 thread grid, thread (tr, tc)
-//    owning rows tr + 32a and columns tc + 16c. Up to N = 1024 across
-//    ceil(N / 32) co-resident workgroups holding 32-column slabs, with one
-//    device-wide barrier per column. Each step is a left and a right
-//    Householder reflection; their vectors are written to global memory for
-//    the back-transformation.
+//    owning rows tr + 32a and columns tc + 16c. Up to N = 1024 the first
+//    N - 224 steps run across ceil(N / 32) co-resident workgroups holding
+//    32-column slabs, with one device-wide barrier per step, and the trailing
+//    224 x 224 matrix they leave goes to the one-workgroup kernel. Each step
+//    is a left and a right Householder reflection; their vectors are written
+//    to global memory for the back-transformation.
 // 2. Singular values of Bd by multisection with Sturm counts of B^T B - x^2 I,
 //    taken by the differential stationary qd transform on the squared
 //    bidiagonal entries (exact for entries perturbed in their last places):
@@ -176,6 +177,7 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, int idx, double
 
 struct GkOut {
     int N;
+    int ldv;  // row stride of VL and VR (N, or that of a larger matrix whose trailing part this is)
     double *d, *e, *VL, *tauL, *VR, *tauR;
 };
 
@@ -201,7 +203,9 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
         constexpr int KA = KC / 2;
         const int N = o.N;
         const int tid = threadIdx.x, lane = tid & 63, tr = tid & 31, tc = tid >> 5;
-        const __amdgpu_buffer_rsrc_t rVL = buf_rsrc(o.VL, N * N), rVR = buf_rsrc(o.VR, N * N);
+        const int ldv = o.ldv;
+        const int nv = (N - 1) * ldv + N;  // the reflector rows' extent
+        const __amdgpu_buffer_rsrc_t rVL = buf_rsrc(o.VL, nv), rVR = buf_rsrc(o.VR, nv);
         const int kend = min(16 * KC + 16, N);
         for (int k = 16 * KC; k < kend; ++k) {
             // Lane tests against step k. Here 16 KC <= k < 16 KC + 16, so
@@ -274,9 +278,9 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
                     if (col_eq1(c)) sh.ax = xk;
                 }
             }
-            if (tid > k && tid < N) buf_st(rVL, k * N + tid, sh.xc[tid] * scaleL);
+            if (tid > k && tid < N) buf_st(rVL, k * ldv + tid, sh.xc[tid] * scaleL);
             if (tid == k) {
-                o.VL[(size_t)k * N + k] = 1.0;
+                o.VL[(size_t)k * ldv + k] = 1.0;
                 o.tauL[k] = tauLk;
                 o.d[k] = betaL;
             }
@@ -338,10 +342,10 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
             }
             if (tr < NPC - KC) {  // lane tr stores column tc + 16 (KC + tr) of row k
                 const int j = tc + 16 * (KC + tr);
-                if (j >= k + 2 && j < N) buf_st(rVR, k * N + j, sh.sx[tc * 16 + KC + tr] * scaleR);
+                if (j >= k + 2 && j < N) buf_st(rVR, k * ldv + j, sh.sx[tc * 16 + KC + tr] * scaleR);
             }
             if (tid == 0) {
-                o.VR[(size_t)k * N + k + 1] = 1.0;
+                o.VR[(size_t)k * ldv + k + 1] = 1.0;
                 o.tauR[k] = tauRk;
                 o.e[k] = betaR;
             }
@@ -379,7 +383,9 @@ __device__ __forceinline__ void gk_block(GkShared& sh, const GkOut& o,
 
 // One-workgroup bidiagonalisation for N <= 32 NPR (NPR <= 7): thread
 // (tr, tc) of the 32 x 16 grid owns rows tr + 32a (a < NPR) and columns
-// tc + 16c (c < 2 NPR), 7 x 14 doubles at N = 224.
+// tc + 16c (c < 2 NPR), 7 x 14 doubles at N = 224. Reflector k is row k of
+// VL / VR with stride ldv (N; larger when B is the trailing part of a bigger
+// matrix whose first steps the cooperative kernel took).
 template <int NPR>
 __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __restrict__ B,
                                                         int ldb, double* __restrict__ dout,
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
                                                         double* __restrict__ VL,
                                                         double* __restrict__ tauL,
                                                         double* __restrict__ VR,
-                                                        double* __restrict__ tauR)
+                                                        double* __restrict__ tauR, int ldv)
 {
     constexpr int NPC = 2 * NPR;
     __shared__ GkShared sh;
@@ -407,7 +413,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
         sh.zs[tid] = 0.0;
     }
     __syncthreads();
-    const GkOut o{N, dout, eout, VL, tauL, VR, tauR};
+    const GkOut o{N, ldv, dout, eout, VL, tauL, VR, tauR};
     gk_block<NPR, 0>(sh, o, Br);
 }
 
@@ -516,11 +522,15 @@ __device__ __forceinline__ void transpose_sum32(double (&v)[32], int c)
     transpose_level<1>(v, (c & 1) != 0);
 }
 
+// Steps 0 .. kstop - 1 only when kstop < N: the trailing matrix
+// B[kstop:, kstop:] after them is written to Tout (leading dimension
+// N - kstop), whose bidiagonalisation gives the remaining steps.
 template <int NQ>
 __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
     int N, const double* __restrict__ B, int ldb, double* __restrict__ dout,
     double* __restrict__ eout, double* __restrict__ VL, double* __restrict__ tauL,
-    double* __restrict__ VR, double* __restrict__ tauR, CoopBuf cb)
+    double* __restrict__ VR, double* __restrict__ tauR, CoopBuf cb, int kstop,
+    double* __restrict__ Tout)
 {
     __shared__ double xcol[SVD_MAXN];  // column k, then the left vector
     __shared__ double zs[SVD_MAXN];    // z = B v of the right reflector
@@ -544,7 +554,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
     for (int i = tid; i < N; i += 512) xcol[i] = B[(size_t)i * ldb];
     __syncthreads();
 
-    for (int k = 0; k < N; ++k) {
+    for (int k = 0; k < kstop; ++k) {
         // ---- left reflector of column k (rows k..N-1), formed by every
         // wavefront of every workgroup from the published column (the same
         // loads and the same order everywhere: the same bits). The column
@@ -692,6 +702,14 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
             }
         }
         __syncthreads();  // rowk, zs and sc are rewritten in the next step
+    }
+    if (kstop < N && jv && j >= kstop) {
+        const int nt = N - kstop;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const int i = g + 16 * q;
+            if (i >= kstop && i < N) Tout[(size_t)(i - kstop) * nt + (j - kstop)] = a[q];
+        }
     }
 }
 
@@ -1653,544 +1671,20 @@ __global__ __launch_bounds__(256) void sign_fix_kernel(int N, int nv, double* __
     }
 }
 
-// ---------------------------------------------------------------------------
-// Two-stage bidiagonalisation for GK_MAXN < N <= TS_MAXN, N a multiple of 16.
-//
-// Stage 1 reduces B to upper band form (band width 16) by blocked Householder
-// transformations: for each 16-column panel k0, a QR of the column panel
-// B[k0:, k0:k0+16] whose block reflector I - Y T Y^T is applied to the columns
-// right of it, then an LQ of the row panel B[k0:k0+16, k0+16:] applied to the
-// rows below it. One launch per panel side: every workgroup factorizes the
-// panel itself (one wavefront, the panel in registers; all workgroups form the
-// same bits) and applies the block reflector to its own 16-column (or, on the
-// row side, 16-row) tile with FP64 matrix cores; workgroup 0 stores the
-// reflectors (left: row k of VL from column k; right: row k of VR from column
-// k + 16), their T factors and the triangular factor, which goes to the band.
-// The row side is the column side on the transposed matrix, so one kernel
-// serves both.
-// Stage 2 reduces the band to bidiagonal form by bulge chasing in one
-// workgroup, the band in LDS: sweep i annihilates row i beyond the
-// superdiagonal with a right reflector on columns i+1..i+16, removes the
-// fill below the diagonal with a left reflector, and chases the bulge down
-// 16 rows at a time; task j of sweep i runs in slot 2i + j, so the tasks of
-// one slot touch disjoint rows and columns and run on different wavefronts.
-// The reflectors are recorded for the back-transformation.
-// ---------------------------------------------------------------------------
-constexpr int TS_NB = 16;
-constexpr int TS_MAXN = 416;
-constexpr int TS_BW = 47, TS_BOFF = 15;  // band row r holds columns r - 15 .. r + 31
-constexpr int TS_REC = 34;               // per task: v[16], tau_v, u[16], tau_u
-
-__device__ __forceinline__ double readlane_f64(double x, int l)
-{
-    const unsigned long long u = __double_as_longlong(x);
-    return join_words((unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffu), l),
-                      (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l));
-}
-
-// Sums over the 64 lanes of sixteen values at once: lane c (c = lane % 16) of
-// every row ends with the total of v[c]. Reduce-scatter within each 16-lane
-// row (each level keeps the half of the remaining values that the lane's bit
-// selects and adds the partner's copy of it: DPP rotation by 8 pairs c with
-// c ^ 8, the half-row mirror pairs c with 7 - c across bit 2, quad
-// permutations pair c with c ^ 2 and c ^ 1), then the row and half sums
-// (the same bits in every lane of the index). 15 exchanges in place of
-// sixteen full reductions.
-__device__ __forceinline__ double lane_transpose_sum16(const double (&v)[16])
-{
-    const int c = threadIdx.x & 15;
-    const bool b3 = (c & 8) != 0, b2 = (c & 4) != 0, b1 = (c & 2) != 0, b0 = (c & 1) != 0;
-    double u[8], t[4], p2[2];
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-        u[j] = (b3 ? v[j + 8] : v[j]) + dpp_move<0x128>(b3 ? v[j] : v[j + 8]);  // row_ror:8
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-        t[j] = (b2 ? u[j + 4] : u[j]) + dpp_move<0x141>(b2 ? u[j] : u[j + 4]);  // row_half_mirror
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-        p2[j] = (b1 ? t[j + 2] : t[j]) + dpp_move<0x4E>(b1 ? t[j] : t[j + 2]);  // quad_perm [2,3,0,1]
-    const double r = (b0 ? p2[1] : p2[0]) + dpp_move<0xB1>(b0 ? p2[0] : p2[1]);  // quad_perm [1,0,3,2]
-    return halves_sum(rows_pair_sum(r));
-}
-
-// QR of an H x 16 panel held by ONE wavefront: lane l owns rows l + 64 r
-// (r < R). On return P holds the reflector vectors below the diagonal
-// (column q, rows > q), the triangular factor on and above it, tau[q] the
-// reflector scalars (the same bits in every lane).
-template <int R>
-__device__ __forceinline__ void panel_qr_wave(int H, double (&P)[R][TS_NB], double (&tau)[TS_NB])
-{
-    const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int q = 0; q < TS_NB; ++q) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = lane + 64 * r;
-            s += (i > q && i < H) ? P[r][q] * P[r][q] : 0.0;
-        }
-        const double s2 = wave_sum64(s);
-        const double alpha = readlane_f64(P[0][q], q);
-        double tq, bq, sc;
-        house(alpha, s2, tq, bq, sc);
-        double y[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = lane + 64 * r;
-            y[r] = (i == q) ? 1.0 : ((i > q && i < H) ? P[r][q] * sc : 0.0);
-        }
-        // the trailing columns' dot products, then their sums: one transposed
-        // sum of all sixteen while the panel is short (R <= 4; with more rows
-        // per lane the sixteen partial sums beside the panel exceed the
-        // registers), else one full reduction per column
-        double w[TS_NB];
-        if constexpr (R <= 4) {
-#pragma unroll
-            for (int c = 0; c < TS_NB; ++c) {
-                double p = 0.0;
-                if (c > q)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
-                w[c] = p;
-            }
-            const double wsum = lane_transpose_sum16(w);
-#pragma unroll
-            for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * readlane_f64(wsum, c);
-        } else {
-#pragma unroll
-            for (int c = q + 1; c < TS_NB; ++c) {
-                double p = 0.0;
-#pragma unroll
-                for (int r = 0; r < R; ++r) p += y[r] * P[r][c];
-                w[c] = p;
-            }
-#pragma unroll
-            for (int c = q + 1; c < TS_NB; ++c) w[c] = tq * wave_sum64(w[c]);
-        }
-#pragma unroll
-        for (int c = q + 1; c < TS_NB; ++c)
-#pragma unroll
-            for (int r = 0; r < R; ++r) P[r][c] -= y[r] * w[c];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int i = lane + 64 * r;
-            if (i >= q) P[r][q] = (i == q) ? bq : y[r];
-        }
-        tau[q] = tq;
-    }
-}
-
-// One panel side of stage 1 (see above). grid.x = max(1, ntiles) workgroups
-// of 256 threads; workgroup t < ntiles updates trailing tile t.
-//   TRANS = false: panel (i, q) = A[k0 + i][k0 + q], i < H = N - k0;
-//                  tile t (i, q) = A[k0 + i][k0 + 16 + 16 t + q].
-//   TRANS = true:  panel (i, q) = A[k0 + q][k0 + 16 + i], i < H = N - k0 - 16;
-//                  tile t (i, q) = A[k0 + 16 + 16 t + q][k0 + 16 + i].
-template <int R, bool TRANS>
-__global__ __launch_bounds__(256) void ts_stage1_kernel(int N, int k0, int ntiles,
-                                                        double* __restrict__ A,
-                                                        double* __restrict__ V,
-                                                        double* __restrict__ tauo,
-                                                        double* __restrict__ band,
-                                                        double* __restrict__ Tblk)
-{
-    __shared__ double Ys[TS_MAXN][17];
-    __shared__ double Xs[TS_MAXN][17];
-    __shared__ double Wp[4][16][17], Gp[4][16][17];
-    __shared__ double Ws[16][17], Gs[16][17], Tm[16][17], WT[16][17];
-    __shared__ double taus[TS_NB];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int H = TRANS ? N - k0 - TS_NB : N - k0;
-    const int t = blockIdx.x;
-    const bool has_tile = t < ntiles;
-    auto pidx = [&](int i, int q) -> size_t {
-        return TRANS ? (size_t)(k0 + q) * N + (k0 + TS_NB + i) : (size_t)(k0 + i) * N + (k0 + q);
-    };
-    auto tidx = [&](int i, int q) -> size_t {
-        return TRANS ? (size_t)(k0 + TS_NB + TS_NB * t + q) * N + (k0 + TS_NB + i)
-                     : (size_t)(k0 + i) * N + (k0 + TS_NB + TS_NB * t + q);
-    };
-    // the panel into Ys by all four wavefronts (row-major panel: 16
-    // consecutive doubles per row; transposed: along the rows); the tile into
-    // Xs by wavefronts 1-3 while wavefront 0 factorises the panel
-    for (int e = tid; e < H * TS_NB; e += 256) {
-        const int i = TRANS ? e % H : e >> 4, q = TRANS ? e / H : e & 15;
-        Ys[i][q] = A[pidx(i, q)];
-    }
-    __syncthreads();
-    if (wave != 0 && has_tile) {
-        for (int e = tid - 64; e < H * TS_NB; e += 192) {
-            const int i = TRANS ? e % H : e >> 4, q = TRANS ? e / H : e & 15;
-            Xs[i][q] = A[tidx(i, q)];
-        }
-    }
-    if (wave == 0) {
-        double P[R][TS_NB];
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int q = 0; q < TS_NB; ++q) {
-                const int i = lane + 64 * r;
-                P[r][q] = i < H ? Ys[i][q] : 0.0;
-            }
-        double tau[TS_NB];
-        panel_qr_wave<R>(H, P, tau);
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int q = 0; q < TS_NB; ++q) {
-                const int i = lane + 64 * r;
-                if (i < H) Ys[i][q] = i < q ? 0.0 : (i == q ? 1.0 : P[r][q]);
-            }
-        if (lane == 0)
-#pragma unroll
-            for (int q = 0; q < TS_NB; ++q) taus[q] = tau[q];
-        if (blockIdx.x == 0) {
-            const int off = TRANS ? k0 + TS_NB : k0;
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int q = 0; q < TS_NB; ++q) {
-                    const int i = lane + 64 * r;
-                    if (i >= q && i < H)
-                        V[(size_t)(k0 + q) * N + off + i] = i == q ? 1.0 : P[r][q];
-                    // triangular factor (rows i <= q) into the band: the
-                    // upper triangle of the diagonal block, or (row side) the
-                    // lower triangle of the block right of it
-                    if (i <= q) {
-                        if (TRANS)
-                            band[(size_t)(k0 + q) * TS_BW + (TS_NB + i - q + TS_BOFF)] = P[r][q];
-                        else
-                            band[(size_t)(k0 + i) * TS_BW + (q - i + TS_BOFF)] = P[r][q];
-                    }
-                }
-            if (lane == 0)
-#pragma unroll
-                for (int q = 0; q < TS_NB; ++q) tauo[k0 + q] = tau[q];
-        }
-    }
-    __syncthreads();
-    // G = Y^T Y and W = Y^T X, the rows split over the four wavefronts
-    {
-        d4 ag = d4{0.0, 0.0, 0.0, 0.0}, aw = d4{0.0, 0.0, 0.0, 0.0};
-        for (int kb = 4 * wave; kb < H; kb += 16) {
-            const int i = kb + (lane >> 4);
-            const double a = i < H ? Ys[i][lane & 15] : 0.0;
-            const double b = (i < H && has_tile) ? Xs[i][lane & 15] : 0.0;
-            ag = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, ag, 0, 0, 0);
-            aw = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, aw, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Gp[wave][(lane >> 4) + 4 * r][lane & 15] = ag[r];
-            Wp[wave][(lane >> 4) + 4 * r][lane & 15] = aw[r];
-        }
-    }
-    __syncthreads();
-    {
-        const int p = tid >> 4, c = tid & 15;
-        Gs[p][c] = ((Gp[0][p][c] + Gp[1][p][c]) + Gp[2][p][c]) + Gp[3][p][c];
-        Ws[p][c] = ((Wp[0][p][c] + Wp[1][p][c]) + Wp[2][p][c]) + Wp[3][p][c];
-    }
-    __syncthreads();
-    // T of the block reflector I - Y T Y^T (upper triangular): T^{-1} =
-    // diag(1 / tau) + (strictly upper part of G = Y^T Y), so lane j of
-    // wavefront 0 finds column j by back-substitution, x_j = tau_j and
-    // x_i = -tau_i sum_{k > i} G[i][k] x_k for i < j (no division; a zero tau
-    // gives a zero column, the identity reflector). The same T as the
-    // column-by-column recurrence T[0:q, q] = -tau_q T[0:q, 0:q] G[0:q, q].
-    if (wave == 0) {
-        if (lane < TS_NB) {
-            double x[TS_NB];
-#pragma unroll
-            for (int i = TS_NB - 1; i >= 0; --i) {
-                double acc = 0.0;
-#pragma unroll
-                for (int k = i + 1; k < TS_NB; ++k) acc = fma(Gs[i][k], x[k], acc);
-                x[i] = lane == i ? taus[i] : (lane > i ? -taus[i] * acc : 0.0);
-            }
-#pragma unroll
-            for (int i = 0; i < TS_NB; ++i) Tm[i][lane] = x[i];
-        }
-        __builtin_amdgcn_s_waitcnt(0);
-        __builtin_amdgcn_wave_barrier();
-        if (blockIdx.x == 0)
-            for (int e = lane; e < TS_NB * TS_NB; e += 64) Tblk[e] = Tm[e >> 4][e & 15];
-    }
-    __syncthreads();
-    if (!has_tile) return;  // uniform per workgroup
-    // WT = T^T W
-    {
-        const int p = tid >> 4, c = tid & 15;
-        double sm = 0.0;
-#pragma unroll
-        for (int q = 0; q < TS_NB; ++q)
-            if (q <= p) sm += Tm[q][p] * Ws[q][c];
-        WT[p][c] = sm;
-    }
-    __syncthreads();
-    // X <- X - Y WT over 16-row tiles
-    for (int rt = wave; 16 * rt < H; rt += 4) {
-        d4 acc = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-            const int i = 16 * rt + (lane & 15);
-            const double a = i < H ? Ys[i][4 * kk + (lane >> 4)] : 0.0;
-            const double b = WT[4 * kk + (lane >> 4)][lane & 15];
-            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * rt + (lane >> 4) + 4 * r;
-            if (row < H) Xs[row][lane & 15] -= acc[r];
-        }
-    }
-    __syncthreads();
-    for (int e = tid; e < H * TS_NB; e += 256) {
-        const int i = e >> 4, q = e & 15;
-        A[tidx(i, q)] = Xs[i][q];
-    }
-}
-
-// Workgroup barrier that waits only for this wavefront's LDS operations (not
-// for its global stores, which nothing in the workgroup reads back).
-__device__ __forceinline__ void lds_barrier()
-{
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
-}
-
-__device__ __forceinline__ int ts_jmax(int N) { return (N - 2) / TS_NB + 1; }
-__device__ __forceinline__ int ts_nsteps(int N, int i) { return (N - 2 - i) / TS_NB + 1; }
-
-// Stage 2: band (global, rows of TS_BW) -> bidiagonal d, e; reflectors of
-// task (i, j) at rec[(i * jmax + j) * TS_REC]. One workgroup of 1024 threads;
-// in slot t the wavefront i % 16 runs task (i, t - 2 i).
-//
-// A task's 16 x 32 block is held one row (right reflector: rows r0 .. r0 + 31,
-// columns c0 .. c0 + 15) or one column (left reflector: columns c0 .. c0 + 31,
-// rows c0 .. c0 + 15) per 32-lane half-wavefront position, each half owning
-// eight of the 16 reflector entries: the dot products are eight in-lane
-// products plus one cross-half sum, and the reflector itself is read by every
-// lane from LDS (a broadcast). Positions outside the block (past N - 1, or past
-// the task's last row or column) still read inside the array, which has 16
-// spare rows, and drop the value; their stores go to one spare word.
-constexpr int TS_S2_WORDS = (TS_MAXN + TS_NB) * TS_BW + 1;
-constexpr int TS_TRASH = TS_S2_WORDS - 1;
-__device__ __forceinline__ int ts_idx(int r, int c) { return r * (TS_BW - 1) + c + TS_BOFF; }
-
-__global__ __launch_bounds__(1024) void ts_stage2_kernel(int N, const double* __restrict__ band,
-                                                         double* __restrict__ dout,
-                                                         double* __restrict__ eout,
-                                                         double* __restrict__ rec)
-{
-    __shared__ double bd[TS_S2_WORDS];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int h = lane >> 5, q = lane & 31;
-    for (int e = tid; e < N * TS_BW; e += 1024) bd[e] = band[e];
-    for (int e = N * TS_BW + tid; e < TS_S2_WORDS; e += 1024) bd[e] = 0.0;
-    __syncthreads();
-    const int jmax = ts_jmax(N);
-    const int nslot = max(2 * (N - 2), jmax - 1) + 1;
-    for (int t = 0; t < nslot; ++t) {
-        // the sweep of this wavefront in slot t: i = wave (mod 16) with
-        // 0 <= t - 2 i < nsteps(i)
-        const int hi = min(t >> 1, N - 2);
-        const int i = hi - ((hi - wave) & 15);
-        const int j = t - 2 * i;
-        const bool has = i >= 0 && j < ts_nsteps(N, i);  // uniform per wavefront
-        const int c0 = i + 1 + TS_NB * j;
-        const int c1 = min(c0 + TS_NB - 1, N - 1);
-        const int L = c1 - c0 + 1;
-        if (has) {
-            double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
-            // right reflector on columns c0..c1 of row r0, applied to rows
-            // r0..c1; lane (h, q) holds row r0 + q, columns c0 + 8 h + k
-            const int r0 = j == 0 ? i : i + 1 + TS_NB * (j - 1);
-            const int nr = c1 - r0 + 1;
-            const double alpha = bd[ts_idx(r0, c0)];
-            const double* xr = bd + ts_idx(r0, c0 + 8 * h);
-            const double* ar = bd + ts_idx(r0 + q, c0 + 8 * h);
-            double x[8], a[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const double xv = xr[k], av = ar[k];
-                const bool in = 8 * h + k < L;
-                x[k] = (in & ((h | k) != 0)) ? xv : 0.0;
-                a[k] = (in & (q < nr)) ? av : 0.0;
-            }
-            double s2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s2 = fma(x[k], x[k], s2);
-            s2 = halves_sum(s2);
-            double tv, bv, sc;
-            house(alpha, s2, tv, bv, sc);
-            double v[8], d = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                v[k] = (h | k) ? x[k] * sc : 1.0;
-                d = fma(a[k], v[k], d);
-            }
-            const double dt = tv * halves_sum(d);
-            double* wr = bd + ts_idx(r0 + q, c0 + 8 * h);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const bool in = (8 * h + k < L) & (q < nr);
-                const double nv = q == 0 ? ((h | k) ? 0.0 : bv) : fma(-dt, v[k], a[k]);
-                *(in ? wr + k : bd + TS_TRASH) = nv;
-            }
-            if (q == 0) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) rc[8 * h + k] = v[k];
-                if (h == 0) rc[16] = tv;
-            }
-        }
-        // the right reflectors of a slot before its left reflectors: task (i, j)
-        // ends its row r0 in column c0, which the left reflector of task
-        // (i + 1, j - 2) in the same slot then updates
-        lds_barrier();
-        if (has) {
-            double* rc = rec + ((size_t)i * jmax + j) * TS_REC;
-            // left reflector on rows c0..c1 of column c0, applied to columns
-            // c0..c0 + nc - 1; lane (h, q) holds column c0 + q, rows c0 + 8 h + k
-            const int nc = min(c1 + TS_NB, N - 1) - c0 + 1;
-            const double alpha = bd[ts_idx(c0, c0)];
-            const double* xr = bd + ts_idx(c0 + 8 * h, c0);
-            const double* ar = bd + ts_idx(c0 + 8 * h, c0 + q);
-            double x[8], a[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const double xv = xr[k * (TS_BW - 1)], av = ar[k * (TS_BW - 1)];
-                const bool in = 8 * h + k < L;
-                x[k] = (in & ((h | k) != 0)) ? xv : 0.0;
-                a[k] = (in & (q < nc)) ? av : 0.0;
-            }
-            double s2 = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s2 = fma(x[k], x[k], s2);
-            s2 = halves_sum(s2);
-            double tu, bu, sc;
-            house(alpha, s2, tu, bu, sc);
-            double u[8], d = 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                u[k] = (h | k) ? x[k] * sc : 1.0;
-                d = fma(a[k], u[k], d);
-            }
-            const double dt = tu * halves_sum(d);
-            double* wr = bd + ts_idx(c0 + 8 * h, c0 + q);
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                const bool in = (8 * h + k < L) & (q < nc);
-                const double nv = q == 0 ? ((h | k) ? 0.0 : bu) : fma(-dt, u[k], a[k]);
-                *(in ? wr + k * (TS_BW - 1) : bd + TS_TRASH) = nv;
-            }
-            if (q == 0) {
-#pragma unroll
-                for (int k = 0; k < 8; ++k) rc[17 + 8 * h + k] = u[k];
-                if (h == 0) rc[33] = tu;
-            }
-        }
-        lds_barrier();
-    }
-    for (int r = tid; r < N; r += 1024) {
-        dout[r] = bd[ts_idx(r, r)];
-        if (r + 1 < N) eout[r] = bd[ts_idx(r, r + 1)];
-    }
-}
-
-// Back-transformation through the stage-2 reflectors: X <- H_1 ... H_T X for
-// the first nv columns of UB (left reflectors u, side 0) or VB (right
-// reflectors v, side 1), H_1 .. H_T in the order stage 2 ran them. The
-// reflectors of one sweep act on disjoint 16-row blocks, and any two that
-// share rows ran in sweep order (task (i, j) in slot 2 i + j, and a task
-// (i', j') with i' > i overlapping it has j' >= j - 1), so the product is
-// applied one sweep at a time, the last sweep first: N - 1 dependent steps,
-// each with all blocks of the sweep at once. grid (ceil(nv / TS_BCOL), 2): a
-// workgroup holds TS_BCOL columns in LDS; its sixteen 16-lane groups take the
-// (block, column) pairs of a sweep in turn, the next sweep's reflector
-// entries loading into registers meanwhile.
-constexpr int TS_BCOL = 4, TS_BROUNDS = 7;
-static_assert(((TS_MAXN - 2) / TS_NB + 1) * TS_BCOL <= 16 * TS_BROUNDS,
-              "a sweep's (block, column) pairs must fit the rounds");
-__global__ __launch_bounds__(256) void ts_back3_kernel(int N, int nv, const double* __restrict__ rec,
-                                                       double* __restrict__ UB,
-                                                       double* __restrict__ VB, int ld)
-{
-    __shared__ double xs[TS_BCOL][TS_MAXN];
-    const int tid = threadIdx.x, grp = tid >> 4, l = tid & 15;
-    const int side = blockIdx.y, col0 = blockIdx.x * TS_BCOL;
-    const int ncol = min(TS_BCOL, nv - col0);
-    double* X = side == 0 ? UB : VB;
-    const int hoff = side == 0 ? 17 : 0;
-    for (int e = tid; e < ncol * N; e += 256) {
-        const int c = e / N, i = e - c * N;
-        xs[c][i] = X[(size_t)i * ld + col0 + c];
-    }
-    const int jmax = ts_jmax(N);
-    // round r of a sweep: unit u = grp + 16 r, block u / TS_BCOL, column u % TS_BCOL
-    double hn[TS_BROUNDS], tn[TS_BROUNDS];
-    auto fetch = [&](int i) {
-        const int ns = ts_nsteps(N, i);
-#pragma unroll
-        for (int r = 0; r < TS_BROUNDS; ++r) {
-            const int u = grp + 16 * r, j = u / TS_BCOL;
-            const bool ok = j < ns && u % TS_BCOL < ncol;
-            const double* rr = rec + ((size_t)i * jmax + (ok ? j : 0)) * TS_REC + hoff;
-            hn[r] = ok ? rr[l] : 0.0;
-            tn[r] = ok ? rr[TS_NB] : 0.0;
-        }
-    };
-    fetch(N - 2);
-    __syncthreads();
-    for (int i = N - 2; i >= 0; --i) {
-        double h[TS_BROUNDS], tau[TS_BROUNDS];
-#pragma unroll
-        for (int r = 0; r < TS_BROUNDS; ++r) {
-            h[r] = hn[r];
-            tau[r] = tn[r];
-        }
-        if (i > 0) fetch(i - 1);
-        const int ns = ts_nsteps(N, i);
-#pragma unroll
-        for (int r = 0; r < TS_BROUNDS; ++r) {
-            const int u = grp + 16 * r, j = u / TS_BCOL, c = u % TS_BCOL;
-            if (j < ns && c < ncol) {  // uniform per 16-lane group
-                const int c0 = i + 1 + TS_NB * j;
-                const int L = min(TS_NB, N - c0);
-                const double xv = l < L ? xs[c][c0 + l] : 0.0;
-                const double dt = tau[r] * row_sum16(h[r] * xv);
-                if (l < L) xs[c][c0 + l] = xv - dt * h[r];
-            }
-        }
-        lds_barrier();  // LDS only: the next sweep's loads stay in flight
-    }
-    for (int e = tid; e < ncol * N; e += 256) {
-        const int c = e / N, i = e - c * N;
-        X[(size_t)i * ld + col0 + c] = xs[c][i];
-    }
-}
-
 }  // namespace
 
 bool small_svd_gk_supported(int N) { return N >= 2 && N <= SVD_MAXN; }
 
-static bool two_stage(int N) { return N > GK_MAXN && N <= TS_MAXN && N % TS_NB == 0; }
-
 size_t small_svd_gk_scratch_elems(int N)
 {
-    // d, e, tauL, tauR, the reflector vectors VL, VR, and for the cooperative
-    // bidiagonalisation the published column, partials and barrier counter
+    // d, e, tauL, tauR, the reflector vectors VL, VR, for the cooperative
+    // bidiagonalisation the published column, partials and barrier counter,
+    // the T factors, and beyond GK_MAXN the trailing GK_MAXN x GK_MAXN matrix
+    // the cooperative steps hand to the one-workgroup kernel
     const size_t P = (N + 31) / 32;
     const size_t nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
-    const size_t one = 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
-                       nblk * WY_RB * WY_RB;
-    // two-stage: d, e, tauL, tauR, VL, VR, the working matrix, the band, the
-    // stage-2 reflectors and the T factors
-    const size_t jm = (size_t)((N - 2) / TS_NB + 1);
-    const size_t two = 4 * (size_t)N + 3 * (size_t)N * N + (size_t)N * TS_BW +
-                       (size_t)(N > 1 ? N - 1 : 1) * jm * TS_REC + nblk * WY_RB * WY_RB;
-    return two_stage(N) && two > one ? two : one;
+    return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
+           nblk * WY_RB * WY_RB + (N > GK_MAXN ? (size_t)GK_MAXN * GK_MAXN : 0);
 }
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
@@ -2215,59 +1709,18 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
                                            "gk_bidiag_p7"};
     // bidiagonalisation flops: 4 N^3 - 4 N^3 / 3 (Householder, both sides)
     const double bd_flops = 8.0 / 3.0 * N * (double)N * N;
-    if (two_stage(N)) {
-        const int nblkL = N / TS_NB;
-        double* Aw = VR + (size_t)N * N;
-        double* band = Aw + (size_t)N * N;
-        const int jm = (N - 2) / TS_NB + 1;
-        double* rec = band + (size_t)N * TS_BW;
-        double* Tall = rec + (size_t)(N - 1) * jm * TS_REC;
-        {
-            TimedLaunch tl(tm, "ts_band", s, bd_flops, 16.0 * N * N);
-            copy2d<double, double>(N, N, B, ldb, Aw, N, s);
-            zero_bytes(band, sizeof(double) * (size_t)N * TS_BW, s);
-            for (int p = 0; p < nblkL; ++p) {
-                const int k0 = TS_NB * p;
-                const int nt = (N - k0 - TS_NB) / TS_NB;
-                if (N <= 256) {
-                    hipLaunchKernelGGL((ts_stage1_kernel<4, false>), dim3(nt > 0 ? nt : 1), dim3(256), 0, s,
-                                       N, k0, nt, Aw, VL, tL, band, Tall + (size_t)p * 256);
-                    if (nt > 0)
-                        hipLaunchKernelGGL((ts_stage1_kernel<4, true>), dim3(nt), dim3(256), 0, s, N, k0,
-                                           nt, Aw, VR, tR, band, Tall + (size_t)(nblkL + p) * 256);
-                } else {
-                    hipLaunchKernelGGL((ts_stage1_kernel<7, false>), dim3(nt > 0 ? nt : 1), dim3(256), 0, s,
-                                       N, k0, nt, Aw, VL, tL, band, Tall + (size_t)p * 256);
-                    if (nt > 0)
-                        hipLaunchKernelGGL((ts_stage1_kernel<7, true>), dim3(nt), dim3(256), 0, s, N, k0,
-                                           nt, Aw, VR, tR, band, Tall + (size_t)(nblkL + p) * 256);
-                }
-            }
-        }
-        {
-            TimedLaunch tl(tm, "ts_bulge", s, 0.0, 0.0);
-            hipLaunchKernelGGL(ts_stage2_kernel, dim3(1), dim3(1024), 0, s, N, band, d, e, rec);
-        }
-        {
-            TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
-            hipLaunchKernelGGL(tgk_solve_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S, UB, VB, N);
-        }
-        {
-            TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
-            const int blocks = (nv + 3) / 4;
-            hipLaunchKernelGGL(ts_back3_kernel, dim3((nv + TS_BCOL - 1) / TS_BCOL, 2), dim3(256), 0,
-                               s, N, nv, rec, UB, VB, N);
-            if (N <= BT_MAXN)
-                hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0,
-                                   s, N, nv, VL, VR, Tall, UB, VB, N, TS_NB);
-            else
-                hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s,
-                                   N, nv, VL, VR, Tall, UB, VB, N, TS_NB);
-            hipLaunchKernelGGL(sign_fix_kernel, dim3(blocks), dim3(256), 0, s, N, nv, UB, VB, N);
-        }
-        return;
-    }
     if (N > GK_MAXN) {
+        // The first N - GK_MAXN steps across ceil(N / 32) co-resident
+        // workgroups; the trailing GK_MAXN x GK_MAXN matrix they leave is
+        // then bidiagonalised by the one-workgroup kernel (its steps cost a
+        // workgroup barrier, not a device-wide one), writing its reflectors
+        // into the trailing part of VL and VR.
+        const int kstop = N - GK_MAXN;
+        const int nblk_t = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
+        const int Pt = (N + 31) / 32;
+        double* Tt = VR + (size_t)N * N + 2 * (size_t)N + 2 * (size_t)Pt + 2 * (size_t)Pt * N + 8 +
+                     (size_t)nblk_t * WY_RB * WY_RB;
+        {
         const int NQc = (N + 15) / 16;
         const int qi = NQc <= 20 ? 0 : NQc <= 24 ? 1 : NQc <= 28 ? 2 : NQc <= 32 ? 3
                      : NQc <= 40 ? 4 : NQc <= 48 ? 5 : NQc <= 56 ? 6 : 7;
@@ -2280,8 +1733,9 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         cb.ctr = (unsigned*)(cb.part + 2 * (size_t)P * N);
         cb.err = err;
         zero_bytes(cb.ctr, sizeof(unsigned), s);
-        void* args[] = {(void*)&N,  (void*)&B,  (void*)&ldb, (void*)&d,  (void*)&e,
-                        (void*)&VL, (void*)&tL, (void*)&VR,  (void*)&tR, (void*)&cb};
+        void* args[] = {(void*)&N,  (void*)&B,  (void*)&ldb, (void*)&d,     (void*)&e,
+                        (void*)&VL, (void*)&tL, (void*)&VR,  (void*)&tR,    (void*)&cb,
+                        (void*)&kstop, (void*)&Tt};
         const void* fn = nullptr;
         const int NQ = (N + 15) / 16;
         if (NQ <= 20) fn = (const void*)gk_bidiag_coop_kernel<20>;
@@ -2293,13 +1747,21 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         else if (NQ <= 56) fn = (const void*)gk_bidiag_coop_kernel<56>;
         else fn = (const void*)gk_bidiag_coop_kernel<64>;
         HIP_TRY(hipLaunchCooperativeKernel(fn, dim3(P), dim3(512), args, 0, s));
+        }
+        {
+            const int nt = GK_MAXN;
+            TimedLaunch tl(tm, one_fam[6], s, 8.0 / 3.0 * nt * (double)nt * nt, 16.0 * nt * nt);
+            const size_t off = (size_t)kstop * N + kstop;
+            hipLaunchKernelGGL((gk_bidiag_kernel<7>), dim3(1), dim3(512), 0, s, nt, Tt, nt,
+                               d + kstop, e + kstop, VL + off, tL + kstop, VR + off, tR + kstop, N);
+        }
     } else {
         const int NP = (N + 31) / 32;
         TimedLaunch tl(tm, one_fam[NP - 1], s, bd_flops, 16.0 * N * N);
 #define BLWS_GK_CASE(P)                                                                      \
     case P:                                                                                  \
         hipLaunchKernelGGL((gk_bidiag_kernel<P>), dim3(1), dim3(512), 0, s, N, B, ldb, d, e, VL, \
-                           tL, VR, tR);                                                      \
+                           tL, VR, tR, N);                                                   \
         break;
         switch (NP) {
             BLWS_GK_CASE(1)

@@ -65,8 +65,8 @@ CASES = [
     (131, 97, 8, "left", 4),
     (64, 64, 1, "aug", 2),
     (300, 260, 56, "aug", 4),    # k c = 224: one-workgroup bidiagonalisation
-    (300, 260, 40, "split", 3),  # k c = 240: two-stage reduction
-    (400, 380, 100, "aug", 3),   # k c = 300: cooperative bidiagonalisation
+    (300, 260, 40, "split", 3),  # k c = 240: 16 cooperative steps, then one workgroup
+    (400, 380, 100, "aug", 3),   # k c = 300: 76 cooperative steps, then one workgroup
 ]
 
 

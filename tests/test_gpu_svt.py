@@ -124,9 +124,10 @@ def spectrum_w(m, n, r, seed):
 
 # The block widths the solvers run at: b = 112 (the projected matrix is
 # 224 x 224: the one-workgroup bidiagonalisation; one Cholesky-QR block),
-# b = 128 and b = 208 (256 x 256 and 416 x 416: the two-stage reduction; at
-# b = 208 blocks wider than 128 columns, orthonormalised in two chunks with
-# block Gram-Schmidt between them).
+# b = 128 and b = 208 (256 x 256 and 416 x 416: 32 and 192 cooperative
+# bidiagonalisation steps, then the one-workgroup kernel on the trailing
+# 224 x 224; at b = 208 blocks wider than 128 columns, orthonormalised in two
+# chunks with block Gram-Schmidt between them).
 WIDE = [(600, 560, 112, 100, 20.0), (600, 560, 128, 100, 20.0), (1000, 900, 208, 200, 20.0)]
 
 
