@@ -437,6 +437,10 @@ __global__ __launch_bounds__(512) void gk_bidiag_kernel(int N, const double* __r
 // ---------------------------------------------------------------------------
 constexpr unsigned CO_SPIN_LIMIT = 1u << 22;
 
+// A compiler barrier right after a batch of loads keeps them issued together
+// (otherwise they are folded into loads at their use, each waited on in turn).
+__device__ __forceinline__ void loads_issued() { asm volatile("" ::: "memory"); }
+
 struct CoopBuf {
     double* colpub;  // 2 x N: column k + 1 before the right update
     double* nrm;     // 2 x P: partial sums of squares of row k
@@ -574,13 +578,26 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
                 }
                 if (i < N) s2a += xcol[i] * xcol[i];
             }
+            // the column entries are read 16 row groups at a time, all loads
+            // of a batch issued before any is used; rows outside k < i < N
+            // are masked by a select (xcol beyond N is never written)
             double pw[4] = {0.0, 0.0, 0.0, 0.0}, p0 = 0.0;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (16 * q + 15 < k) continue;  // uniform
-                const int i = g + 16 * q;
-                pw[q & 3] += (i > k && i < N) ? xcol[i] * a[q] : 0.0;
-                if (i == k) p0 = a[q];
+            for (int q0 = 0; q0 < NQ; q0 += 16) {
+                if (16 * q0 + 255 < k) continue;  // uniform
+                double xq[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (q0 + u < NQ) xq[u] = xcol[g + 16 * (q0 + u)];
+                loads_issued();
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int q = q0 + u;
+                    if (q >= NQ) break;
+                    const int i = g + 16 * q;
+                    pw[q & 3] += (i > k && i < N) ? xq[u] * a[q] : 0.0;
+                    if (i == k) p0 = a[q];
+                }
             }
             red[g][c] = (pw[0] + pw[1]) + (pw[2] + pw[3]);
             red0[g][c] = p0;
@@ -613,11 +630,21 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
             __syncthreads();
             const double wj = (jv && j > k) ? wcol[c] : 0.0;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (16 * q + 15 < k) continue;
-                const int i = g + 16 * q;
-                const double vi = (i == k) ? 1.0 : xcol[i] * sl;
-                if (i >= k && i < N) a[q] -= vi * wj;
+            for (int q0 = 0; q0 < NQ; q0 += 16) {
+                if (16 * q0 + 255 < k) continue;  // uniform
+                double xq[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (q0 + u < NQ) xq[u] = xcol[g + 16 * (q0 + u)];
+                loads_issued();
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int q = q0 + u;
+                    if (q >= NQ) break;
+                    const int i = g + 16 * q;
+                    const double vi = (i == k) ? 1.0 : xq[u] * sl;
+                    a[q] = (i >= k && i < N) ? a[q] - vi * wj : a[q];
+                }
             }
         }
         if (k + 1 >= N) break;
@@ -648,13 +675,10 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
                 if (q0 + c < NQ && i >= k + 1 && i < N) st_agent(prow + i, v[0]);
             }
         }
-        if (tid == 0) {
-            double s2 = 0.0;
-            for (int cc = 0; cc < 32; ++cc) {
-                const int jj = 32 * p + cc;
-                if (jj >= k + 2 && jj < N) s2 += rowk[cc] * rowk[cc];
-            }
-            st_agent(cb.nrm + slot * P + p, s2);
+        if (tid < 64) {  // this slab's part of |x|^2, summed over the 32 column lanes
+            const double rv = (c == tid && jv && j >= k + 2) ? rowk[c] : 0.0;
+            const double s2 = half_sum32(rv * rv);
+            if (tid == 0) st_agent(cb.nrm + slot * P + p, s2);
         }
         if (p == ((k + 1) >> 5) && c == ((k + 1) & 31)) {
 #pragma unroll
@@ -668,11 +692,36 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
         // ---- the reflector, z = B v and the next column, from the partials;
         // every thread loads the norms with its partials and forms the
         // reflector itself (same loads, same order: the same bits everywhere)
+        // Up to N = 512 (P <= 16) all of this step's exchange this thread
+        // needs (alpha, the P norms, row k + 1 + tid's P partials and column
+        // entry) is loaded at once, from clamped addresses, before any is
+        // used: one memory round trip instead of one per load. The sums run in
+        // the fixed order q = 0 .. P - 1 either way.
+        constexpr int PB = NQ <= 32 ? (NQ + 1) / 2 : 1;
+        const int i0 = k + 1 + tid;
+        const int ic = i0 < N ? i0 : N - 1;
+        double nb[PB], pb[PB], cp0 = 0.0;
+        if constexpr (NQ <= 32) {
+#pragma unroll
+            for (int q = 0; q < PB; ++q) {
+                const int qc = q < P ? q : P - 1;
+                nb[q] = ld_agent(cb.nrm + slot * P + qc);
+                pb[q] = ld_agent(cb.part + ((size_t)slot * P + qc) * N + ic);
+            }
+            cp0 = ld_agent(cb.colpub + (size_t)slot * N + ic);
+        }
         double tq, scl;
         {
             const double alpha = ld_agent(cb.colpub + (size_t)slot * N + k);
+            loads_issued();
             double s2 = 0.0;
-            for (int q = 0; q < P; ++q) s2 += ld_agent(cb.nrm + slot * P + q);
+            if constexpr (NQ <= 32) {
+#pragma unroll
+                for (int q = 0; q < PB; ++q)
+                    if (q < P) s2 += nb[q];
+            } else {
+                for (int q = 0; q < P; ++q) s2 += ld_agent(cb.nrm + slot * P + q);
+            }
             double tau, beta, scale;
             house(alpha, s2, tau, beta, scale);
             tq = tau;
@@ -682,7 +731,20 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
                 eout[k] = beta;
             }
         }
-        for (int i = k + 1 + tid; i < N; i += 512) {
+        int ibeg = k + 1 + tid;
+        if constexpr (NQ <= 32) {
+            if (i0 < N) {
+                double acc = 0.0;
+#pragma unroll
+                for (int q = 0; q < PB; ++q)
+                    if (q < P) acc += pb[q];
+                const double z = cp0 + scl * acc;
+                zs[i0] = z;
+                xcol[i0] = cp0 - tq * z;
+            }
+            ibeg += 512;
+        }
+        for (int i = ibeg; i < N; i += 512) {
             double acc = 0.0;
             for (int q = 0; q < P; ++q) acc += ld_agent(cb.part + ((size_t)slot * P + q) * N + i);
             const double cp = ld_agent(cb.colpub + (size_t)slot * N + i);
@@ -695,10 +757,20 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
         if (tq != 0.0) {
             const double vj = (jv && j >= k + 1) ? ((j == k + 1) ? 1.0 : rowk[c] * scl) : 0.0;
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (16 * q + 15 < k + 1) continue;
-                const int i = g + 16 * q;
-                if (i >= k + 1 && i < N) a[q] -= tq * zs[i] * vj;
+            for (int q0 = 0; q0 < NQ; q0 += 16) {
+                if (16 * q0 + 255 < k + 1) continue;  // uniform
+                double zq[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u)
+                    if (q0 + u < NQ) zq[u] = zs[g + 16 * (q0 + u)];
+                loads_issued();
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+                    const int q = q0 + u;
+                    if (q >= NQ) break;
+                    const int i = g + 16 * q;
+                    a[q] = (i >= k + 1 && i < N) ? a[q] - tq * zq[u] * vj : a[q];
+                }
             }
         }
         __syncthreads();  // rowk, zs and sc are rewritten in the next step
@@ -715,10 +787,7 @@ __global__ __launch_bounds__(512) void gk_bidiag_coop_kernel(
 
 // The recurrences below read their operands from LDS in blocks of eight,
 // alternating between two register sets: the loads of one block are issued
-// before the previous block is computed. A compiler barrier right after them
-// keeps them there (otherwise they are folded into loads at their use, each
-// waited on in turn).
-__device__ __forceinline__ void loads_issued() { asm volatile("" ::: "memory"); }
+// before the previous block is computed (loads_issued keeps them there).
 
 // Number of singular values of the upper bidiagonal B = (d, e) below sqrt(tau),
 // by the differential stationary qd transform of B^T B - tau I = L D L^T
