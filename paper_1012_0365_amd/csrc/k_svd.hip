@@ -1703,6 +1703,18 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
     }
 }
 
+// QL = QR = I (N x N)
+__global__ void eye2_kernel(int N, double* __restrict__ QL, double* __restrict__ QR)
+{
+    const size_t total = (size_t)N * N;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const double v = (e / N == e % N) ? 1.0 : 0.0;
+        QL[e] = v;
+        QR[e] = v;
+    }
+}
+
 // Sign convention of the singular pairs: the first largest-magnitude entry of
 // the left vector positive (u and v of a pair flip together). One wavefront
 // per column.
@@ -1750,10 +1762,13 @@ size_t small_svd_gk_scratch_elems(int N)
     // bidiagonalisation the published column, partials and barrier counter,
     // the T factors, and beyond GK_MAXN the trailing GK_MAXN x GK_MAXN matrix
     // the cooperative steps hand to the one-workgroup kernel
+    // (up to BT_MAXN also Q_L, Q_R, the bidiagonal's vectors and the
+    // partials of the products that apply Q_L, Q_R to them)
     const size_t P = (N + 31) / 32;
     const size_t nblk = (N + WY_RB - 1) / WY_RB + (N - 1 + WY_RB - 1) / WY_RB;
     return 4 * (size_t)N + 2 * (size_t)N * N + 2 * (size_t)N + 2 * P + 2 * P * N + 8 +
-           nblk * WY_RB * WY_RB + (N > GK_MAXN ? (size_t)GK_MAXN * GK_MAXN : 0);
+           nblk * WY_RB * WY_RB + (N > GK_MAXN ? (size_t)GK_MAXN * GK_MAXN : 0) +
+           (N <= BT_MAXN ? 4 * (size_t)N * N + gemm_partial_elems(N, N, N) + 1 : 0);
 }
 
 // Outputs: S[0..nv), UB, VB (N x N, ld N) with their first nv columns set.
@@ -1851,6 +1866,49 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
     double* Tall = VR + (size_t)N * N + 2 * (size_t)N + 2 * (size_t)((N + 31) / 32) +
                    2 * (size_t)((N + 31) / 32) * N + 8;
     const bool two = s2 != nullptr && ev_a != nullptr && ev_b != nullptr;
+    if (two && N <= BT_MAXN) {
+        // Q_L = H_0 .. H_{N-1} and Q_R formed on the second stream (the
+        // reflectors applied to the identity) while the values and the
+        // bidiagonal's vectors are found; the back-transformation is then
+        // two products UB = Q_L Ubd, VB = Q_R Vbd instead of a chain of
+        // reflector blocks after the vectors.
+        double* QL = Tall + (size_t)nblk * WY_RB * WY_RB +
+                     (N > GK_MAXN ? (size_t)GK_MAXN * GK_MAXN : 0);
+        double* QR = QL + (size_t)N * N;
+        double* Ubd = QR + (size_t)N * N;
+        double* Vbd = Ubd + (size_t)N * N;
+        double* gpart = Vbd + (size_t)N * N;
+        const size_t gpe = gemm_partial_elems(N, N, N);
+        HIP_TRY(hipEventRecord(ev_a, s));
+        HIP_TRY(hipStreamWaitEvent(s2, ev_a, 0));
+        {
+            TimedLaunch tl(tm, "wy_t", s2, 0.0, 0.0);
+            hipLaunchKernelGGL(wy_t_kernel, dim3(nblk), dim3(256), 0, s2, N, VL, tL, VR, tR, Tall);
+        }
+        {
+            TimedLaunch tl(tm, "gk_form_q", s2, 8.0 * N * (double)N * N, 0.0);
+            hipLaunchKernelGGL(eye2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, s2, N, QL, QR);
+            hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((N + 15) / 16, 2), dim3(256), 0, s2,
+                               N, N, VL, VR, Tall, QL, QR, N, 1);
+        }
+        HIP_TRY(hipEventRecord(ev_b, s2));
+        {
+            TimedLaunch tl(tm, "tgk_solve", s, 0.0, 0.0);
+            hipLaunchKernelGGL(tgk_solve_kernel, dim3(nv), dim3(BS_PTS), 0, s, N, d, e, S, Ubd, Vbd,
+                               N);
+        }
+        HIP_TRY(hipStreamWaitEvent(s, ev_b, 0));
+        {
+            TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
+            gemm<double, double, double>(tm, "gemm_ts", false, N, nv, N, 1.0, QL, N, Ubd, N, 0.0,
+                                         (const double*)nullptr, 0, UB, N, gpart, gpe, s);
+            gemm<double, double, double>(tm, "gemm_ts", false, N, nv, N, 1.0, QR, N, Vbd, N, 0.0,
+                                         (const double*)nullptr, 0, VB, N, gpart, gpe, s);
+            hipLaunchKernelGGL(sign_fix_kernel, dim3((nv + 3) / 4), dim3(256), 0, s, N, nv, UB, VB,
+                               N);
+        }
+        return;
+    }
     if (two) {
         HIP_TRY(hipEventRecord(ev_a, s));
         HIP_TRY(hipStreamWaitEvent(s2, ev_a, 0));
