@@ -1592,22 +1592,24 @@ __global__ __launch_bounds__(256) void backtransform_kernel(
     }
 }
 
-// The same back-transformation with matrix cores for N <= BT_MAXN: grid
+// The same back-transformation with matrix cores for N <= MAXN: grid
 // (ceil(nv / 16), 2), workgroup (c, side) holds columns 16 c .. 16 c + 15 of
 // UB (side 0) or VB (side 1) in LDS and applies that side's blocks, last
 // first: W = Y^T X by MFMA with the rows split over the four wavefronts (the
 // partial products summed in LDS in wavefront order), W <- T W, then
 // X <- X - Y W by MFMA over 16-row tiles. The next block's Y is loaded into
-// registers while the current one is applied.
-constexpr int BT_MAXN = 256;
+// registers while the current one is applied. MAXN = 256 (70 KB of LDS) or
+// 512 (151 KB, for 256 < N <= 512).
+constexpr int BT_MAXN = 512;
 typedef double d4 __attribute__((ext_vector_type(4)));
+template <int MAXN>
 __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
     int N, int nv, const double* __restrict__ VL, const double* __restrict__ VR,
     const double* __restrict__ Tall, double* __restrict__ UB, double* __restrict__ VB, int ld,
     int roff)
 {
-    __shared__ double Xs[BT_MAXN][17];
-    __shared__ double Ys[BT_MAXN][17];
+    __shared__ double Xs[MAXN][17];
+    __shared__ double Ys[MAXN][17];
     __shared__ double Wp[4][16][17];
     __shared__ double Ws[16][17];
     __shared__ double WT[16][17];
@@ -1625,17 +1627,35 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
         Xs[i][q] = c0 + q < nv ? X[(size_t)i * ld + c0 + q] : 0.0;
     }
     // the Y block of a step as 16 x N (row q = reflector k0 + q), read along
-    // the reflector rows; at most BT_MAXN * 16 / 256 = 16 values per thread
-    constexpr int PY = BT_MAXN * 16 / 256;
+    // the reflector rows; at most MAXN * 16 / 256 values per thread
+    constexpr int PY = MAXN * 16 / 256;
     double py[PY];
     double pt = 0.0;
     auto prefetch = [&](int st) {
         const int blk = nsteps - 1 - st, k0 = blk * WY_RB;
         const int cnt = (nref - k0) < WY_RB ? (nref - k0) : WY_RB;
+        if constexpr (MAXN > 256) {
+            // launched for N > 256 only: element e + 256 is at most one
+            // reflector row further on
+            int q = tid / N, i = tid - q * N;
 #pragma unroll
-        for (int u = 0; u < PY; ++u) {
-            const int e = tid + 256 * u, q = e / N, i = e - q * N;
-            py[u] = (e < 16 * N && q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i] : 0.0;
+            for (int u = 0; u < PY; ++u) {
+                const int e = tid + 256 * u;
+                py[u] = (e < 16 * N && q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i]
+                                                                      : 0.0;
+                i += 256;
+                if (i >= N) {
+                    i -= N;
+                    ++q;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < PY; ++u) {
+                const int e = tid + 256 * u, q = e / N, i = e - q * N;
+                py[u] = (e < 16 * N && q < cnt && i >= k0 + q + off) ? Vh[(size_t)(k0 + q) * N + i]
+                                                                      : 0.0;
+            }
         }
         pt = Tall[(size_t)(side == 0 ? blk : nblkL + blk) * WY_RB * WY_RB + tid];
     };
@@ -1701,6 +1721,20 @@ __global__ __launch_bounds__(256) void backtransform_mfma_kernel(
         const int i = e >> 4, q = e & 15;
         if (c0 + q < nv) X[(size_t)i * ld + c0 + q] = Xs[i][q];
     }
+}
+
+// The matrix-core back-transformation for N <= BT_MAXN, the smaller LDS
+// form up to 256 (two workgroups per CU).
+void backtransform_mfma(int N, int nv, const double* VL, const double* VR, const double* Tall,
+                        double* UB, double* VB, int ld, int roff, hipStream_t s)
+{
+    const dim3 grid((nv + 15) / 16, 2);
+    if (N <= 256)
+        hipLaunchKernelGGL((backtransform_mfma_kernel<256>), grid, dim3(256), 0, s, N, nv, VL, VR,
+                           Tall, UB, VB, ld, roff);
+    else
+        hipLaunchKernelGGL((backtransform_mfma_kernel<BT_MAXN>), grid, dim3(256), 0, s, N, nv, VL,
+                           VR, Tall, UB, VB, ld, roff);
 }
 
 // QL = QR = I (N x N)
@@ -1888,8 +1922,7 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         {
             TimedLaunch tl(tm, "gk_form_q", s2, 8.0 * N * (double)N * N, 0.0);
             hipLaunchKernelGGL(eye2_kernel, dim3((N * N + 255) / 256), dim3(256), 0, s2, N, QL, QR);
-            hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((N + 15) / 16, 2), dim3(256), 0, s2,
-                               N, N, VL, VR, Tall, QL, QR, N, 1);
+            backtransform_mfma(N, N, VL, VR, Tall, QL, QR, N, 1, s2);
         }
         HIP_TRY(hipEventRecord(ev_b, s2));
         {
@@ -1930,11 +1963,7 @@ void small_svd_gk(Timer* tm, int N, int nv, const double* B, int ldb, double* UB
         TimedLaunch tl(tm, "gk_backtransform", s, 4.0 * N * (double)N * nv, 0.0);
         const int blocks = (nv + 3) / 4;
         if (N <= BT_MAXN)
-            hipLaunchKernelGGL(backtransform_mfma_kernel, dim3((nv + 15) / 16, 2), dim3(256), 0, s,
-                               N, nv, VL, VR, Tall, UB, VB, N, 1);
-        else if (N <= 512)
-            hipLaunchKernelGGL((backtransform_kernel<512, 8>), dim3(blocks, 2), dim3(256), 0, s, N,
-                               nv, VL, VR, Tall, UB, VB, N, 1);
+            backtransform_mfma(N, nv, VL, VR, Tall, UB, VB, N, 1, s);
         else
             hipLaunchKernelGGL((backtransform_kernel<SVD_MAXN, 16>), dim3(blocks, 2), dim3(256), 0,
                                s, N, nv, VL, VR, Tall, UB, VB, N, 1);
