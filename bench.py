@@ -297,9 +297,18 @@ def bench_rpca(args):
             if time.perf_counter() - t1 >= args.cpu_seconds:
                 break
         tc = time.perf_counter() - t1
+        cpu_model = None
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        cpu_model = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
         out["cpu_baseline"] = {
             "value": n_solves / tc, "unit": "solves/s", "cores": min(threads, cores),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model,
             "sample": (f"oracle BLWS inexact ALM (FP64 plain loops, OpenMP), {n_solves} full "
                        f"n=2000 solve(s) of {n_it} iterations in {tc:.1f}s"),
         }
