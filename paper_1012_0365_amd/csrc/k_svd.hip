@@ -18,8 +18,11 @@
 //    factorisation of T - sigma I for a value isolated to 1e-6 relative,
 //    inverse iteration otherwise (close, repeated or zero values), in the
 //    same workgroup that found the value.
-// 4. Back-transformation through the stored reflectors (one workgroup per
-//    column block).
+// 4. Back-transformation through the stored reflectors, in blocks of 16
+//    (compact WY form, matrix cores up to N = 512, one wavefront per column
+//    beyond). With a second stream (the solves) and N <= 512, Q_L and Q_R
+//    are formed from the identity there while steps 2 and 3 run, and the
+//    back-transformation is two products with them.
 #include "blws_common.h"
 
 namespace blws {
