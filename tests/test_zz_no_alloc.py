@@ -1,5 +1,5 @@
 """blws_svt_noalloc (static scratch, no allocation inside the call) against
-blws_svt on the same inputs, two calls in a row with the second smaller, in
+blws_svt on the same inputs, calls in a row each smaller than the last, in
 FP64 (Ritz values above eps to 1e-10 relative, A to 1e-9, ranks equal) and
 FP32 (values to 1e-6 of the largest, A to 1e-5); and its size limit."""
 
@@ -54,9 +54,13 @@ def _run(torch, ctx, W, U, V, eps, dtype, noalloc):
 @pytest.mark.parametrize("dtype_name", ["float64", "float32"])
 def test_noalloc_matches_svt_two_calls(torch, ctx, dtype_name):
     dtype = getattr(torch, dtype_name)
-    # second call smaller than the first: the static scratch keeps the first
-    # call's contents, which must not leak into the second
-    for (m, n, b, r, eps) in [(600, 560, 112, 100, 20.0), (300, 250, 24, 20, 20.0)]:
+    # each call smaller than the one before: the static scratch keeps the
+    # previous call's contents, which must not leak into the next. b = 160
+    # (small SVD of N = 320: cooperative steps, then the one-workgroup kernel,
+    # the back-transformation's 512-row form) on the single stream here
+    # against the two-stream path of blws_svt
+    for (m, n, b, r, eps) in [(700, 650, 160, 140, 20.0), (600, 560, 112, 100, 20.0),
+                              (300, 250, 24, 20, 20.0)]:
         W, U, V = _case(m, n, b, r, seed=m)
         print(f"noalloc {dtype_name} m={m} n={n} b={b}", flush=True)
         Sr, rr, Ar, Ur = _run(torch, ctx, W, U, V, eps, dtype, noalloc=False)
