@@ -67,6 +67,28 @@ def test_rpca_fp64_small_matches_oracle(torch, ctx, small_case):
     assert rel(A, inst["A0"]) < 2e-6
 
 
+def test_rpca_table1_m500_matches_oracle(torch, ctx):
+    """Table 1's m = 500 row (rank 50, 25000 entries corrupted with
+    U[-500, 500], lambda = 1/sqrt(500)): the GPU's FP64 solve follows the
+    oracle's BLWS solve (same iterations, rank and support of E, A to 1e-8) and
+    lands on the paper's row (rank 50, ||E||_0 within a few dozen of 25000,
+    the planted A to 5e-5)."""
+    inst = synth.rpca_instance(500, 500, 50, 0.10, 500.0, 0)
+    bl = oracle.rpca(inst["D"], mode="blws", norm_steps=8)
+    D = torch.tensor(inst["D"], dtype=torch.float64, device="cuda")
+    A, E, info = ctx.rpca_solve(D)
+    torch.cuda.synchronize()
+    A, E = A.cpu().numpy(), E.cpu().numpy()
+    print(f"table 1 m=500: iters {info['iters']} (oracle {bl['info']['iters']}), rank "
+          f"{info['rank']}, nnz(E) {info['nnz_E']}, |A - A0| / |A0| {rel(A, inst['A0']):.2e}",
+          flush=True)
+    assert info["status"] == 0 == bl["info"]["status"]
+    assert info["iters"] == bl["info"]["iters"] and info["rank"] == bl["info"]["rank"] == 50
+    assert info["nnz_E"] == bl["info"]["nnz_E"] and 25000 <= info["nnz_E"] <= 25100
+    assert rel(A, bl["A"]) < 1e-8 and rel(E, bl["E"]) < 1e-8
+    assert rel(A, inst["A0"]) < 5e-5
+
+
 def test_rpca_fp32_small(torch, ctx, small_case):
     inst, ex, bl = small_case
     D = torch.tensor(inst["D"], dtype=torch.float32, device="cuda")
