@@ -45,6 +45,17 @@ PAPER_TABLE1 = {
     3000: {"rel_err": 3.90e-6, "rank": 300, "iters": 30, "time_s": 149.19},
 }
 
+# Table 2, BLWS-SVT columns (same machine): seconds, iterations, relative error
+PAPER_TABLE2 = {
+    (5000, 10): {"time_s": 20.02, "iters": 123, "rel_err": 1.74e-4},
+    (5000, 50): {"time_s": 279.08, "iters": 108, "rel_err": 1.55e-4},
+    (5000, 100): {"time_s": 1175.91, "iters": 122, "rel_err": 1.74e-4},
+    (10000, 10): {"time_s": 42.80, "iters": 123, "rel_err": 1.70e-4},
+    (10000, 50): {"time_s": 736.01, "iters": 110, "rel_err": 1.60e-4},
+    (20000, 10): {"time_s": 101.47, "iters": 124, "rel_err": 1.68e-4},
+    (30000, 10): {"time_s": 171.40, "iters": 125, "rel_err": 1.69e-4},
+}
+
 # MI355X published peaks
 PEAK = {
     "hbm": 8000.0,        # GB/s
@@ -708,10 +719,42 @@ def rpca_legs(args, ctx, D64, fp64_s, A0):
             err = math.sqrt(max(float((S * S).sum()) + nM2 - 2.0 * ip, 0.0) / nM2)
             out[str(m) if m < 30000 else f"{m}_seed{seed}"] = {
                 "nnz": s, "solve_s": t, "iters": info["iters"], "rank": info["rank"],
-                "status": info["status"], "rel_err_vs_planted": err}
+                "status": info["status"], "rel_err_vs_planted": err,
+                "paper_blws_svt": PAPER_TABLE2.get((m, 10))}
         return out
 
     leg("mc_svt_table2_r10", table2)
+
+    def table2_wide():
+        """Table 2's r = 50 and r = 100 rows (s / d_r = 5 and 4), the same host
+        and error measure as the r = 10 rows."""
+        out = {"config": "m x m, rank r, s = c r (2 m - r) samples (c = 5 for r = 50, 4 for "
+                         "r = 100), tau = 5 m, delta = 1.2 m^2 / s, tol 1e-4, FP64"}
+        for m, r, c in [(5000, 50, 5), (5000, 100, 4), (10000, 50, 5)]:
+            s = c * r * (2 * m - r)
+            inst = synth.mc_instance(m, m, r, s / float(m * m), 0)
+            rp = torch.tensor(inst["row_ptr"], dtype=torch.int32, device="cuda")
+            ci = torch.tensor(inst["col_idx"], dtype=torch.int32, device="cuda")
+            vals = torch.tensor(inst["values"], dtype=torch.float64, device="cuda")
+            cap = 2 * r + 64
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            U, S, V, info = ctx.mc_svt_solve(m, m, rp, ci, vals, r_cap=cap)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t1
+            L = torch.tensor(inst["L"], device="cuda")
+            R = torch.tensor(inst["R"], device="cuda")
+            nM2 = float(((L.T @ L) * (R.T @ R)).sum())
+            ip = float((((U * S).T @ L) * (V.T @ R)).sum())
+            err = math.sqrt(max(float((S * S).sum()) + nM2 - 2.0 * ip, 0.0) / nM2)
+            out[f"{m}_r{r}"] = {"nnz": s, "solve_s": t, "iters": info["iters"],
+                                "rank": info["rank"], "status": info["status"],
+                                "rel_err_vs_planted": err,
+                                "paper_blws_svt": PAPER_TABLE2.get((m, r))}
+            del rp, ci, vals, U, S, V, L, R
+        return out
+
+    leg("mc_svt_table2_r50_r100", table2_wide)
     if not args.no_plain:
         leg("plain_alm_n2000_f64", lambda: plain_alm_leg(D64, 23))
 
