@@ -680,7 +680,7 @@ struct McSvtJob : Job {
     McOp<T> mo;
     enum Phase { CHECK, NORMS, SPEC, STEP, FINISH } phase = CHECK;
     double dnorm = 0.0, s1 = 0.0, prev = 0.0, rel = INFINITY;
-    int t = 0, sreq = 1, b = 0, r = 0, it = 0, npart = 0, steps = 0;
+    int t = 0, sreq = 1, b = 0, r = 0, it = 0, npart = 0;
 
     McSvtJob(int m_, int n_, int nnz_, const int* rp, const int* ci, const T* d_,
              const blws_svt_mc_opts& o_, int r_cap_, T* U_, int ldu_, double* S_, T* V_, int ldv_)
@@ -749,11 +749,12 @@ struct McSvtJob : Job {
         if (b == 0) {
             cold_block<T>(cx, w, s, m, n, op, bn, o.pow_steps, o.seed, 1, U, bmax, V, bmax);
         } else if (bn > b) {
-            grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)steps);
-            grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)steps + 1);
+            // generator streams by iteration (the repeated requests of one
+            // iteration draw from its streams), as in the ALM solvers
+            grow_block<T>(cx, w, s, m, b, bn, U, bmax, o.seed, 1000 + 2 * (uint64_t)it);
+            grow_block<T>(cx, w, s, n, b, bn, V, bmax, o.seed, 1000 + 2 * (uint64_t)it + 1);
         }
         b = bn;
-        ++steps;
         svt_step<T>(cx, w, s, m, n, op, tau, b, U, bmax, V, bmax, S, rank_dev, o.seed);
         // the request can still grow unless it reached min(m, n) or the block its cap
         const int need = (sreq >= p || b >= bmax) ? INT_MAX : sreq;

@@ -65,17 +65,19 @@ def _rel_between(Ua, Sa, Va, Ub, Sb, Vb):
     return np.sqrt(max(d2, 0.0)) / np.sqrt(g(Ub, Sb, Vb, Ub, Sb, Vb))
 
 
-CASES = [(300, 260, 5, 6), (5000, 5000, 10, 6)]
+# (m, n, r, s / d_r): the last two at Table 2's r = 50 sampling (s / d_r = 5)
+CASES = [(300, 260, 5, 6), (5000, 5000, 10, 6), (1000, 1000, 50, 5), (2000, 2000, 50, 5)]
 
 
 @pytest.mark.parametrize("m,n,r,ratio", CASES, ids=lambda v: str(v))
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 def test_mc_svt_matches_oracle(torch, blws, ctx, m, n, r, ratio, prec):
     inst = _instance(m, n, r, ratio)
+    cap = 64 if r <= 10 else 2 * r + 64  # room for the block to grow past the rank
     ref = oracle.mc_svt(m, n, inst["row_ptr"], inst["col_idx"], inst["values"], mode="blws",
-                        r_cap=64, norm_steps=GPU_NORM_STEPS)
+                        r_cap=cap, norm_steps=GPU_NORM_STEPS)
     dt = torch.float64 if prec == "f64" else torch.float32
-    U, S, V, info = ctx.mc_svt_solve(m, n, *_dev(torch, inst, dt), r_cap=64)
+    U, S, V, info = ctx.mc_svt_solve(m, n, *_dev(torch, inst, dt), r_cap=cap)
     torch.cuda.synchronize()
     U, S, V = U.double().cpu().numpy(), S.cpu().numpy(), V.double().cpu().numpy()
     err = _rel_between(U, S, V, ref["U"], ref["S"], ref["V"])
