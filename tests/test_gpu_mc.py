@@ -107,6 +107,48 @@ def test_mc_fp64_matches_exact_form(torch, blws, ctx):
     assert np.linalg.norm(A - A_ex) / np.linalg.norm(A_ex) < 1e-6
 
 
+@pytest.fixture(scope="module")
+def wide_case():
+    """Rank 30 at 25% sampling, rho 1.05 (the library's MC default, with which
+    the oracle recovers the planted rank here): the block grows to 32 columns
+    over the solve, so the columns added on widening are drawn as well."""
+    m, n, r, frac, seed = 800, 700, 30, 0.25, 2
+    inst = synth.mc_instance(m, n, r, frac, seed)
+    bl = oracle.mc(m, n, inst["row_ptr"], inst["col_idx"], inst["values"], mode="blws",
+                   r_cap=96, norm_steps=GPU_NORM_STEPS, rho=1.05, tol=1e-8, mu0_scale=1.0)
+    return inst, bl
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mc_rank30_matches_oracle(torch, blws, ctx, wide_case, prec):
+    inst, bl = wide_case
+    m, n = inst["m"], inst["n"]
+    dt = torch.float64 if prec == "f64" else torch.float32
+    rp, ci, vals = _dev(torch, inst, dt)
+    tol = 1e-8 if prec == "f64" else 1e-6
+    U, S, V, info = ctx.mc_solve(m, n, rp, ci, vals,
+                                 opts=blws.default_mc_opts(rho=1.05, tol=tol, mu0_scale=1.0),
+                                 r_cap=96)
+    torch.cuda.synchronize()
+    U, S, V = U.double().cpu().numpy(), S.cpu().numpy(), V.double().cpu().numpy()
+    A = _dense(U, S, V)
+    A_or = _dense(bl["U"], bl["S"], bl["V"])
+    err = np.linalg.norm(A - A_or) / np.linalg.norm(A_or)
+    M = inst["L"] @ inst["R"].T
+    rec = np.linalg.norm(A - M) / np.linalg.norm(M)
+    print(f"mc rank 30 {prec}: iters={info['iters']} (oracle {bl['info']['iters']}) "
+          f"rank={info['rank']} err vs oracle {err:.2e} vs planted {rec:.2e}", flush=True)
+    assert info["status"] == 0 and info["rank"] == bl["rank"] == 30
+    if prec == "f64":
+        # the same algorithm: same trajectory
+        assert info["iters"] == bl["info"]["iters"]
+        assert np.max(np.abs(S - bl["S"]) / bl["S"]) < 1e-8
+        assert err < 1e-8 and rec < 1e-6
+    else:
+        # FP32 stopped at 1e-6 (the FP32 bar of the other MC solves)
+        assert err < 1e-5
+
+
 def test_mc_fp32_small(torch, blws, ctx, case):
     inst, bl = case
     m, n = inst["m"], inst["n"]
