@@ -150,16 +150,25 @@ __global__ __launch_bounds__(256) void seg_sort_kernel(int n, const int* col_ptr
 // One wavefront per row; lanes over the c columns (c <= 512); entries fetched
 // 64 at a time and broadcast; sums in FP64 in entry order. With `perm` the
 // value of position e is val[perm[e]] (the transposed pattern).
-template <typename T>
+template <typename T, int QN>
 __global__ __launch_bounds__(256) void spmm_kernel(int rows, int c, const int* ptr,
                                                    const int* idx, const int* perm, const T* val,
                                                    const T* X, int ldx, T* out, int ldo)
 {
+    // QN = ceil(c / 64) chunks of 64 columns, one value per lane each; the
+    // rows of X for eight samples are loaded before any is used (the gathers,
+    // mostly from L2 and the last-level cache, are what the kernel waits on)
+    constexpr int G = 8;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int i = blockIdx.x * 4 + wave;
     if (i >= rows) return;  // no barriers below
     const int a = ptr[i], z = ptr[i + 1];
-    double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    bool live[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) live[q] = lane + 64 * q < c;
+    double acc[QN];
+#pragma unroll
+    for (int q = 0; q < QN; ++q) acc[q] = 0.0;
     for (int base = a; base < z; base += 64) {
         const int e = base + lane;
         int col = 0;
@@ -169,23 +178,33 @@ __global__ __launch_bounds__(256) void spmm_kernel(int rows, int c, const int* p
             v = (double)val[perm ? perm[e] : e];
         }
         const int cnt = (z - base) < 64 ? (z - base) : 64;
-#pragma unroll 4
-        for (int t = 0; t < cnt; ++t) {
-            const int cc = __shfl(col, t, 64);
-            const double vv = __shfl(v, t, 64);
-            const T* xr = X + (size_t)cc * ldx;
+        int t = 0;
+        for (; t + G <= cnt; t += G) {
+            T xv[G][QN];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int jj = lane + 64 * q;
-                if (jj < c) acc[q] += vv * (double)xr[jj];
+            for (int u = 0; u < G; ++u) {
+                const T* xr = X + (size_t)__shfl(col, t + u, 64) * ldx + lane;
+#pragma unroll
+                for (int q = 0; q < QN; ++q) xv[u][q] = live[q] ? xr[64 * q] : T(0);
             }
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const double vv = __shfl(v, t + u, 64);
+#pragma unroll
+                for (int q = 0; q < QN; ++q) acc[q] += vv * (double)xv[u][q];
+            }
+        }
+        for (; t < cnt; ++t) {
+            const T* xr = X + (size_t)__shfl(col, t, 64) * ldx + lane;
+            const double vv = __shfl(v, t, 64);
+#pragma unroll
+            for (int q = 0; q < QN; ++q)
+                if (live[q]) acc[q] += vv * (double)xr[64 * q];
         }
     }
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int jj = lane + 64 * q;
-        if (jj < c) out[(size_t)i * ldo + jj] = (T)acc[q];
-    }
+    for (int q = 0; q < QN; ++q)
+        if (live[q]) out[(size_t)i * ldo + lane + 64 * q] = (T)acc[q];
 }
 
 // C (r x c, ldc) row k *= (S[k] - eps): the coefficients theta of the low-rank part.
@@ -316,8 +335,23 @@ void spmm(Timer* tm, const char* family, int rows, int c, const int* ptr, const 
                    (double)nnz * (sizeof(int) + sizeof(T) + (perm ? sizeof(int) : 0) +
                                   (double)c * sizeof(T)) +
                        (double)rows * c * sizeof(T));
-    hipLaunchKernelGGL((spmm_kernel<T>), dim3((rows + 3) / 4), dim3(256), 0, s, rows, c, ptr, idx,
-                       perm, val, X, ldx, out, ldo);
+    const dim3 grid((rows + 3) / 4);
+    switch ((c + 63) / 64) {
+#define BLWS_SPMM_CASE(Q)                                                                      \
+    case Q:                                                                                    \
+        hipLaunchKernelGGL((spmm_kernel<T, Q>), grid, dim3(256), 0, s, rows, c, ptr, idx, perm, \
+                           val, X, ldx, out, ldo);                                             \
+        break;
+        BLWS_SPMM_CASE(1)
+        BLWS_SPMM_CASE(2)
+        BLWS_SPMM_CASE(3)
+        BLWS_SPMM_CASE(4)
+        BLWS_SPMM_CASE(5)
+        BLWS_SPMM_CASE(6)
+        BLWS_SPMM_CASE(7)
+        BLWS_SPMM_CASE(8)
+#undef BLWS_SPMM_CASE
+    }
 }
 
 void lr_scale(int r, int c, const double* S, double eps, double* C, int ldc, hipStream_t s)
