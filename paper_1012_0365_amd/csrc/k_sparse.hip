@@ -243,10 +243,21 @@ __global__ __launch_bounds__(256) void mc_update_kernel(
     double zz = 0.0;
     if (i < m) {
         const int a = row_ptr[i], z = row_ptr[i + 1];
+        // V's rows four values per load where they are 16-byte aligned (FP32,
+        // ldv and V's base multiples of 4 values); the sum runs in the same order
+        const bool vec4 = sizeof(T) == 4 && (ldv & 3) == 0 && (((uintptr_t)V) & 15) == 0;
+        const int r4 = vec4 ? (r & ~3) : 0;
         for (int e = a + lane; e < z; e += 64) {
             const T* vr = V + (size_t)col_idx[e] * ldv;
             double s = 0.0;
-            for (int k = 0; k < r; ++k) s += coef[wave][k] * (double)vr[k];
+            for (int k = 0; k < r4; k += 4) {
+                const float4 q = *(const float4*)(vr + k);
+                s += coef[wave][k] * (double)q.x;
+                s += coef[wave][k + 1] * (double)q.y;
+                s += coef[wave][k + 2] * (double)q.z;
+                s += coef[wave][k + 3] * (double)q.w;
+            }
+            for (int k = r4; k < r; ++k) s += coef[wave][k] * (double)vr[k];
             const double dd = (double)d[e];
             const double zv = dd - s;
             const T yn = (T)((double)y[e] + mu * zv);
